@@ -1,0 +1,258 @@
+/*
+ * attn.h -- C interface of the MI355X (gfx950) library for the hot path of the
+ * augmented tree tensor network (aTTN) ground-state search.
+ *
+ * The method (Reinic, Pavesic, Jaschke, Montangero, "The Augmented Tree Tensor
+ * Network Cookbook"):
+ *   |psi_aTTN> = D(u) |psi_TTN>, D(u) = prod_k u_k two-site unitaries on the
+ *   bottom of a binary TTN (Sec. 2, eq. 1).  The ground-state sweep maps the
+ *   Hamiltonian (a sum of local terms stored term by term as a TPO, Sec. 3.3)
+ *   to H' with the disentangler layer contracted into every term (Sec. 4.2,
+ *   algorithm "Contract disentangler layer"), then runs a DMRG sweep of
+ *   single-tensor updates on the TTN (Sec. 4, step 3): QR isometrisation
+ *   (Sec. 3.1), effective operators kept term by term (Sec. 3.3.2), and the
+ *   generalised matvec inside the Lanczos eigensolver (Sec. 4.3.2).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns attn_status: 0 = ATTN_OK, negative = error.  No C++
+ *     exception crosses this interface.  attn_last_error(h) gives a message.
+ *   - Validation errors leave the handle unchanged.  After ATTN_ERR_HIP or
+ *     ATTN_ERR_NUMERIC only attn_last_error and attn_destroy may be called.
+ *   - A handle is not thread-safe; separate handles are independent.
+ *   - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *     default stream).  Work is enqueued asynchronously on that stream; only
+ *     calls that return host scalars synchronise it.
+ *   - Host arrays passed in are borrowed for the duration of the call and
+ *     copied.  Device pointers passed in (attn_heff_apply) are owned by the
+ *     caller and must live on the handle's device.
+ *   - Tensors are real, row-major T[l][r][p]: l = left child leg, r = right
+ *     child leg, p = parent leg.  Node ids are the post-order of the binary
+ *     tree (left subtree, right subtree, node); the root is n_sites - 2 and
+ *     its parent leg has dimension 1.  Legs are numbered 0 = l, 1 = r, 2 = p.
+ *   - Bond dimension of the link above a k-site subtree: min(m, d^k, d^(N-k)).
+ */
+#ifndef ATTN_H
+#define ATTN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t attn_status;
+
+#define ATTN_OK                  0
+#define ATTN_ERR_ARG            -1   /* null pointer, out-of-range or duplicate value */
+#define ATTN_ERR_NOT_UNITARY    -2   /* ||u^T u - 1||_max > 1e-12 for a disentangler */
+#define ATTN_ERR_NOT_HERMITIAN  -3   /* a term's operator is not symmetric (1e-12) */
+#define ATTN_ERR_DE_OVERLAP     -4   /* a site belongs to two disentanglers */
+#define ATTN_ERR_DE_RESTRICTION -5   /* ATTN_DE_STRICT: a placement restriction is broken */
+#define ATTN_ERR_OOM            -6   /* device or host allocation failed */
+#define ATTN_ERR_HIP            -7   /* a HIP runtime call failed */
+#define ATTN_ERR_STATE          -8   /* call not valid in the current state (see each call) */
+#define ATTN_ERR_SHAPE          -9   /* buffer length does not match the tensor size */
+#define ATTN_ERR_NUMERIC       -10   /* NaN / Inf, or a factorisation broke down */
+#define ATTN_ERR_UNSUPPORTED   -11   /* valid input outside what this build implements */
+
+/* attn_problem.flags */
+#define ATTN_DE_STRICT     1u  /* enforce both placement restrictions of Sec. 6.1.1 */
+#define ATTN_HOST_ONLY     2u  /* build host-side structures only, touch no GPU */
+#define ATTN_DRYRUN        4u  /* build every device work list against a fake address
+                                  space without touching the GPU (for attn_validate) */
+
+typedef enum attn_dtype {
+  ATTN_F64 = 0,     /* FP64 operands, FP64 accumulation */
+  ATTN_F32 = 1,     /* FP32 operands on MFMA, FP32 accumulation */
+  ATTN_BF16X2 = 2   /* operands split hi+lo in BF16, three products, FP32 accumulation */
+} attn_dtype;
+
+/*
+ * The problem: a lattice Hamiltonian as a sum of local terms (Sec. 3.3), a
+ * binary tree over the sites in `leaf_order` (Sec. 3.1), bond dimension m and
+ * a layer of two-site disentanglers (Sec. 3.2).
+ *
+ *   n_sites, d, m     number of sites (>= 2), local dimension (>= 2), maximal
+ *                     bond dimension (>= 1).
+ *   leaf_order        [n_sites] permutation of 0..n_sites-1: site at each leaf.
+ *   n_terms           number of terms.
+ *   term_nsites       [n_terms] sites per term, 1..4.
+ *   term_sites        concatenated site ids of every term (distinct per term).
+ *   term_ops          concatenated d x d row-major real operators, one per
+ *                     site of every term, in the order of term_sites.
+ *   term_coef         [n_terms] real coefficient; term = coef * (op_0 x op_1 ..).
+ *   n_de              number of disentanglers.
+ *   de_sites          [n_de][2] site pairs (no site in two pairs).
+ *   de_u              [n_de][d*d][d*d] row-major real orthogonal matrices acting on
+ *                     |s_a s_b> with the first listed site the major index.
+ *   flags             ATTN_DE_STRICT, ATTN_HOST_ONLY.
+ *   device            HIP device ordinal for all device memory of the handle.
+ */
+typedef struct attn_problem {
+  int32_t n_sites, d, m;
+  const int32_t* leaf_order;
+  int32_t n_terms;
+  const int32_t* term_nsites;
+  const int32_t* term_sites;
+  const double* term_ops;
+  const double* term_coef;
+  int32_t n_de;
+  const int32_t* de_sites;
+  const double* de_u;
+  uint32_t flags;
+  int32_t device;
+} attn_problem;
+
+typedef struct attn_handle attn_handle;
+
+/* Local eigensolver options (Sec. 4.3.2: Lanczos inside the sweep). */
+#define ATTN_SOLVER_LANCZOS  0
+#define ATTN_SOLVER_DAVIDSON 1
+#define ATTN_PRECOND_NONE    0
+#define ATTN_PRECOND_JACOBI  1
+#define ATTN_PRECOND_LEARNED 2
+
+typedef struct attn_solver_opts {
+  int32_t solver;      /* ATTN_SOLVER_LANCZOS (default) or ATTN_SOLVER_DAVIDSON */
+  int32_t krylov_k;    /* Lanczos: number of matvecs k (capped at the tensor size);
+                          Davidson: maximal subspace size */
+  double tol;          /* Davidson: residual norm tolerance; Lanczos: unused */
+  int32_t precision;   /* attn_dtype of the H_eff contractions; Krylov stays FP64 */
+  int32_t precond;     /* Davidson preconditioner: NONE, JACOBI or LEARNED */
+  int32_t max_iter;    /* Davidson: maximal number of matvecs */
+  int32_t restart;     /* Davidson: vectors kept at a restart */
+} attn_solver_opts;
+
+typedef struct attn_sweep_opts {
+  attn_solver_opts solver;
+  int32_t use_graphs;  /* reserved, 0 */
+} attn_sweep_opts;
+
+/*
+ * a1. Rotated TPO build (Sec. 4.2, algorithm "Contract disentangler layer"):
+ * validates the problem, builds the tree and bond dimensions, contracts the
+ * disentanglers touching each term into it (h' = U^T h U on the extended
+ * support), factorises every rotated term across each tree link it crosses
+ * (operator-Schmidt decompositions: minimal TPO bonds, at most d^2 for a term
+ * touching one disentangler, d^4 for two), classifies terms per node as local
+ * (summed into one operator per leg) or crossing, and allocates all device
+ * storage.  Tensors must then be given with attn_init_state or attn_set_tensor.
+ * *out is owned by the caller; release it with attn_destroy.
+ * Errors: ARG, NOT_UNITARY, NOT_HERMITIAN, DE_OVERLAP, DE_RESTRICTION
+ * (strict mode), UNSUPPORTED (supports beyond 6 sites), OOM, HIP.
+ */
+attn_status attn_build_tpo(const attn_problem* p, attn_handle** out);
+
+/* Release every resource of the handle.  NULL is accepted. */
+attn_status attn_destroy(attn_handle* h);
+
+/* Message of the last error on this handle (owned by h); "" if none.
+ * With h == NULL: the last error of a failed attn_build_tpo in this thread. */
+const char* attn_last_error(const attn_handle* h);
+
+/* Structure of node `node`: dims[3] = (m_l, m_r, m_p); *n_cross = number of
+ * crossing terms; *flops = algorithmic flops of one matvec (summed local legs
+ * 2 m_j M, two-leg terms 2 M t (m_a + m_b), three-leg terms the cheapest chain
+ * 2 M (t_a m_a + t_a t_c m_b + t_c m_c); M = m_l m_r m_p, t = minimal bonds).
+ * Any output pointer may be NULL.  Works on host-only handles.  Errors: ARG. */
+attn_status attn_node_info(const attn_handle* h, int32_t node, int32_t dims[3],
+                           int32_t* n_cross, double* flops);
+
+/* Tree and storage summary: n_nodes, root id, total device bytes of
+ * effective-operator storage.  Any pointer may be NULL. */
+attn_status attn_tree_info(const attn_handle* h, int32_t* n_nodes, int32_t* root,
+                           int64_t* env_bytes);
+
+/* Initial state (reading of the paper's random start): `raw` holds one block of
+ * m_l*m_r*m_p values per node in post-order (concatenated, row-major).  Every
+ * non-root block, viewed as an (m_l m_r) x m_p matrix, is replaced by Q of its
+ * QR decomposition with diag(R) >= 0; the root block is normalised.  The
+ * isometry centre is the root and all effective operators toward it are built.
+ * Synchronises the stream.  Errors: SHAPE (len), STATE (host-only), NUMERIC, HIP. */
+attn_status attn_init_state(attn_handle* h, const double* raw, int64_t len, void* stream);
+
+/* Load / read back T_node (host buffer of exactly m_l*m_r*m_p doubles).
+ * attn_set_tensor invalidates every effective operator that depends on the
+ * node; the node keeps its isometry direction.  attn_get_tensor synchronises.
+ * Errors: ARG, SHAPE, STATE (host-only), HIP. */
+attn_status attn_set_tensor(attn_handle* h, int32_t node, const double* host, int64_t len);
+attn_status attn_get_tensor(attn_handle* h, int32_t node, double* host, int64_t len);
+
+/* Current isometry centre (node id). */
+attn_status attn_get_center(const attn_handle* h, int32_t* node);
+
+/*
+ * a2. Effective-operator update (Sec. 3.3.2): renormalise every term through
+ * T_node onto the link at leg `leg` (0 = l, 1 = r, 2 = p), in the direction
+ * pointing away from `node`.  Terms confined to node's side are summed into
+ * the link's local operator; terms reaching across it keep one m x m block per
+ * TPO bond index.  Requires T_node isometric toward `leg` and the node's two
+ * other incoming effective operators current.  Child legs that are sites
+ * carry no tensor: leg must lead to a tree node.
+ * Errors: ARG, STATE (not isometric toward leg / stale inputs / host-only), HIP.
+ */
+attn_status attn_update_env(attn_handle* h, int32_t node, int32_t leg, void* stream);
+
+/*
+ * a3. H_eff matvec (Sec. 3.3.2 and 4.3.2): y <- H_eff(node) x, with
+ * H_eff = E_l x 1 x 1 + 1 x E_r x 1 + 1 x 1 x E_p + sum over crossing terms of
+ * their leg blocks contracted into x over the TPO bonds.  x and y are device
+ * pointers of M = m_l m_r m_p elements, row-major [l][r][p]: double for
+ * ATTN_F64, float for ATTN_F32 and ATTN_BF16X2 (split into hi/lo inside).
+ * They must not alias.  Asynchronous on `stream`.
+ * Errors: STATE (node is not the centre, or its incoming effective operators
+ * are stale, or host-only), ARG (NULL pointer or dtype), HIP.
+ */
+attn_status attn_heff_apply(attn_handle* h, int32_t node, int32_t dtype, const void* x,
+                            void* y, void* stream);
+
+/*
+ * a4. Local eigensolve: lowest eigenpair of H_eff(node), warm-started from
+ * T_node.  Lanczos: k = min(opts->krylov_k, M) matvecs, three-term recurrence
+ * plus two passes of classical Gram-Schmidt in FP64, stop when
+ * beta_j <= 1e-14 max|alpha|; lowest eigenpair of the tridiagonal matrix; the
+ * normalised Ritz vector (sign: non-negative overlap with the start vector)
+ * replaces T_node.  Davidson (optional form): Jacobi or learned pointwise
+ * preconditioner, stops at residual norm <= tol.  Synchronises `stream` and
+ * returns theta and the number of matvecs.  opts may be NULL (Lanczos, k = 20,
+ * FP64).  Errors: STATE (as heff_apply), NUMERIC (non-finite values), HIP.
+ */
+attn_status attn_eigsolve_node(attn_handle* h, int32_t node, const attn_solver_opts* opts,
+                               double* theta, int32_t* n_matvec, void* stream);
+
+/*
+ * a5. Isometrisation (Sec. 3.1): move the centre from `from` to the adjacent
+ * node `to`.  QR of T_from matricised (other two legs) x (leg toward `to`),
+ * with diag(R) >= 0; Q replaces T_from, R is absorbed into T_to along that
+ * link.  Does not update effective operators: follow with
+ * attn_update_env(from, leg toward to).
+ * Errors: ARG (not adjacent), STATE (from is not the centre), NUMERIC, HIP.
+ */
+attn_status attn_isometrize(attn_handle* h, int32_t from, int32_t to, void* stream);
+
+/*
+ * a6. Sweep (Sec. 4, step 3): n_sweeps sweeps over all nodes in post-order;
+ * the centre moves link by link (attn_isometrize then attn_update_env) and
+ * every node is optimised with attn_eigsolve_node.  energies[s] = theta at the
+ * last node of sweep s, seconds[s] = wall time of sweep s (device synchronised).
+ * Output arrays are caller-owned, n_sweeps entries each (either may be NULL).
+ * Errors: any of the calls above.
+ */
+attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* opts,
+                       double* energies, double* seconds);
+
+/* Checks on the host that every work unit of every device work list of the
+ * handle reads and writes only inside the buffer it was built for.  Meant for
+ * ATTN_DRYRUN handles (no GPU needed).  Errors: STATE (message names the first
+ * violation), ARG. */
+attn_status attn_validate(const attn_handle* h);
+
+/* Counters since the handle was built: matvecs, env updates, QR moves. */
+attn_status attn_counters(const attn_handle* h, int64_t* n_matvec, int64_t* n_env,
+                          int64_t* n_qr);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATTN_H */

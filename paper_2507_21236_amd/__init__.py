@@ -1,0 +1,84 @@
+"""MI355X (gfx950) library for the hot path of the augmented tree tensor
+network ground-state search: rotated TPO build, effective-operator updates,
+H_eff matvec, local Lanczos eigensolve, QR isometrisation and sweeps.
+
+The compute path is the C library ``libattn.so`` (hand-written HIP kernels);
+``_lib`` marshals arguments into it and ``AttnHandle`` is a small convenience
+wrapper around one handle.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib
+from ._lib import (ATTN_F64, ATTN_F32, ATTN_BF16X2, ATTN_DE_STRICT, ATTN_HOST_ONLY, ATTN_DRYRUN,
+                   AttnError, solver_opts)
+
+
+class AttnHandle:
+    """One problem instance on one device (owns an attn_handle)."""
+
+    def __init__(self, problem, flags=0, device=0):
+        nsites, sites, ops, coef = problem.flat_terms()
+        self.problem = problem
+        self.h = _lib.attn_build_tpo(problem.n_sites, problem.d, problem.m, problem.leaf_order,
+                                     nsites, sites, ops, coef,
+                                     np.asarray(problem.de_sites, dtype=np.int32).reshape(-1, 2),
+                                     problem.de_u, flags=flags, device=device)
+        self.n_nodes, self.root, self.env_bytes = _lib.attn_tree_info(self.h)
+
+    def close(self):
+        if self.h:
+            _lib.attn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def node_info(self, n):
+        return _lib.attn_node_info(self.h, n)
+
+    def init_state(self, raw=None, stream=None):
+        raw = self.problem.raw_concat() if raw is None else raw
+        _lib.attn_init_state(self.h, raw, stream)
+
+    def get_tensor(self, n):
+        return _lib.attn_get_tensor(self.h, n)
+
+    def set_tensor(self, n, t):
+        _lib.attn_set_tensor(self.h, n, t)
+
+    @property
+    def center(self):
+        return _lib.attn_get_center(self.h)
+
+    def isometrize(self, frm, to, stream=None):
+        _lib.attn_isometrize(self.h, frm, to, stream)
+
+    def update_env(self, node, leg, stream=None):
+        _lib.attn_update_env(self.h, node, leg, stream)
+
+    def heff_apply(self, node, x, y, dtype=ATTN_F64, stream=None):
+        """x, y: torch tensors on the handle's device (float64 for ATTN_F64,
+        float32 otherwise), M elements each."""
+        _lib.attn_heff_apply(self.h, node, dtype, x.data_ptr(), y.data_ptr(), stream)
+
+    def eigsolve(self, node, opts=None, stream=None):
+        return _lib.attn_eigsolve_node(self.h, node, opts, stream)
+
+    def sweep(self, n_sweeps, opts=None):
+        return _lib.attn_sweep(self.h, n_sweeps, opts)
+
+    def validate(self):
+        _lib.attn_validate(self.h)
+
+    def counters(self):
+        return _lib.attn_counters(self.h)
+
+    # tree helpers (structure only)
+    def path_moves(self, target):
+        """Sequence of (from, to, leg) moves that bring the centre to target."""
+        return None

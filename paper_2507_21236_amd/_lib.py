@@ -1,0 +1,214 @@
+"""ctypes binding of libattn.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls; all work of
+the hot path runs in the library's HIP kernels.  Device buffers are passed as
+raw pointers (``tensor.data_ptr()``) and streams as ``hipStream_t`` values
+(``torch.cuda.current_stream().cuda_stream``).  If the library has not been
+built, importing this module raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libattn.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python paper_2507_21236_amd/build.py` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+ATTN_OK = 0
+ERRORS = {
+    -1: "ATTN_ERR_ARG", -2: "ATTN_ERR_NOT_UNITARY", -3: "ATTN_ERR_NOT_HERMITIAN",
+    -4: "ATTN_ERR_DE_OVERLAP", -5: "ATTN_ERR_DE_RESTRICTION", -6: "ATTN_ERR_OOM",
+    -7: "ATTN_ERR_HIP", -8: "ATTN_ERR_STATE", -9: "ATTN_ERR_SHAPE", -10: "ATTN_ERR_NUMERIC",
+    -11: "ATTN_ERR_UNSUPPORTED",
+}
+ATTN_DE_STRICT = 1
+ATTN_HOST_ONLY = 2
+ATTN_DRYRUN = 4
+ATTN_F64, ATTN_F32, ATTN_BF16X2 = 0, 1, 2
+ATTN_SOLVER_LANCZOS, ATTN_SOLVER_DAVIDSON = 0, 1
+ATTN_PRECOND_NONE, ATTN_PRECOND_JACOBI, ATTN_PRECOND_LEARNED = 0, 1, 2
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class attn_problem(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("d", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("leaf_order", _i32p), ("n_terms", ctypes.c_int32), ("term_nsites", _i32p),
+                ("term_sites", _i32p), ("term_ops", _f64p), ("term_coef", _f64p),
+                ("n_de", ctypes.c_int32), ("de_sites", _i32p), ("de_u", _f64p),
+                ("flags", ctypes.c_uint32), ("device", ctypes.c_int32)]
+
+
+class attn_solver_opts(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int32), ("krylov_k", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("restart", ctypes.c_int32)]
+
+
+class attn_sweep_opts(ctypes.Structure):
+    _fields_ = [("solver", attn_solver_opts), ("use_graphs", ctypes.c_int32)]
+
+
+_H = ctypes.c_void_p
+_proto = {
+    "attn_build_tpo": (ctypes.c_int32, [ctypes.POINTER(attn_problem), ctypes.POINTER(_H)]),
+    "attn_destroy": (ctypes.c_int32, [_H]),
+    "attn_last_error": (ctypes.c_char_p, [_H]),
+    "attn_node_info": (ctypes.c_int32, [_H, ctypes.c_int32, _i32p, _i32p, _f64p]),
+    "attn_tree_info": (ctypes.c_int32, [_H, _i32p, _i32p, ctypes.POINTER(ctypes.c_int64)]),
+    "attn_init_state": (ctypes.c_int32, [_H, _f64p, ctypes.c_int64, ctypes.c_void_p]),
+    "attn_set_tensor": (ctypes.c_int32, [_H, ctypes.c_int32, _f64p, ctypes.c_int64]),
+    "attn_get_tensor": (ctypes.c_int32, [_H, ctypes.c_int32, _f64p, ctypes.c_int64]),
+    "attn_get_center": (ctypes.c_int32, [_H, _i32p]),
+    "attn_update_env": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "attn_heff_apply": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "attn_eigsolve_node": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.POINTER(attn_solver_opts),
+                                            _f64p, _i32p, ctypes.c_void_p]),
+    "attn_isometrize": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "attn_sweep": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.POINTER(attn_sweep_opts), _f64p,
+                                    _f64p]),
+    "attn_validate": (ctypes.c_int32, [_H]),
+    "attn_counters": (ctypes.c_int32, [_H, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64)]),
+}
+for _name, (_res, _args) in _proto.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = sorted(_proto)
+
+
+class AttnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code, h):
+    if code != ATTN_OK:
+        raise AttnError(code, (_lib.attn_last_error(h) or b"").decode())
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def attn_build_tpo(n_sites, d, m, leaf_order, term_nsites, term_sites, term_ops, term_coef,
+                   de_sites, de_u, flags=0, device=0):
+    """Returns an opaque handle (int).  Arrays are copied by the library."""
+    keep = [_arr(leaf_order, np.int32), _arr(term_nsites, np.int32), _arr(term_sites, np.int32),
+            _arr(term_ops, np.float64), _arr(term_coef, np.float64),
+            _arr(np.asarray(de_sites).reshape(-1), np.int32),
+            _arr(np.asarray(de_u).reshape(-1), np.float64)]
+    p = attn_problem(n_sites, d, m, keep[0].ctypes.data_as(_i32p), len(keep[1]),
+                     keep[1].ctypes.data_as(_i32p), keep[2].ctypes.data_as(_i32p),
+                     keep[3].ctypes.data_as(_f64p), keep[4].ctypes.data_as(_f64p),
+                     len(keep[5]) // 2, keep[5].ctypes.data_as(_i32p),
+                     keep[6].ctypes.data_as(_f64p), flags, device)
+    h = _H()
+    code = _lib.attn_build_tpo(ctypes.byref(p), ctypes.byref(h))
+    if code != ATTN_OK:
+        raise AttnError(code, (_lib.attn_last_error(None) or b"").decode())
+    return h.value
+
+
+def attn_destroy(h):
+    _check(_lib.attn_destroy(h), h)
+
+
+def attn_last_error(h):
+    return (_lib.attn_last_error(h) or b"").decode()
+
+
+def attn_node_info(h, node):
+    dims = (ctypes.c_int32 * 3)()
+    nc = ctypes.c_int32()
+    fl = ctypes.c_double()
+    _check(_lib.attn_node_info(h, node, dims, ctypes.byref(nc), ctypes.byref(fl)), h)
+    return tuple(dims), nc.value, int(fl.value)
+
+
+def attn_tree_info(h):
+    nn, root, eb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(_lib.attn_tree_info(h, ctypes.byref(nn), ctypes.byref(root), ctypes.byref(eb)), h)
+    return nn.value, root.value, eb.value
+
+
+def attn_init_state(h, raw, stream=None):
+    raw = _arr(raw, np.float64)
+    _check(_lib.attn_init_state(h, raw.ctypes.data_as(_f64p), raw.size, stream), h)
+
+
+def attn_set_tensor(h, node, host):
+    host = _arr(host, np.float64)
+    _check(_lib.attn_set_tensor(h, node, host.ctypes.data_as(_f64p), host.size), h)
+
+
+def attn_get_tensor(h, node):
+    dims, _, _ = attn_node_info(h, node)
+    out = np.zeros(dims, dtype=np.float64)
+    _check(_lib.attn_get_tensor(h, node, out.ctypes.data_as(_f64p), out.size), h)
+    return out
+
+
+def attn_get_center(h):
+    c = ctypes.c_int32()
+    _check(_lib.attn_get_center(h, ctypes.byref(c)), h)
+    return c.value
+
+
+def attn_update_env(h, node, leg, stream=None):
+    _check(_lib.attn_update_env(h, node, leg, stream), h)
+
+
+def attn_heff_apply(h, node, dtype, x_ptr, y_ptr, stream=None):
+    _check(_lib.attn_heff_apply(h, node, dtype, x_ptr, y_ptr, stream), h)
+
+
+def solver_opts(solver=ATTN_SOLVER_LANCZOS, krylov_k=20, tol=1e-7, precision=ATTN_F64,
+                precond=ATTN_PRECOND_NONE, max_iter=200, restart=8):
+    return attn_solver_opts(solver, krylov_k, tol, precision, precond, max_iter, restart)
+
+
+def attn_eigsolve_node(h, node, opts=None, stream=None):
+    th = ctypes.c_double()
+    nmv = ctypes.c_int32()
+    _check(_lib.attn_eigsolve_node(h, node, ctypes.byref(opts) if opts is not None else None,
+                                   ctypes.byref(th), ctypes.byref(nmv), stream), h)
+    return th.value, nmv.value
+
+
+def attn_isometrize(h, frm, to, stream=None):
+    _check(_lib.attn_isometrize(h, frm, to, stream), h)
+
+
+def attn_sweep(h, n_sweeps, opts=None):
+    e = np.zeros(n_sweeps)
+    s = np.zeros(n_sweeps)
+    so = attn_sweep_opts(opts if opts is not None else solver_opts(), 0)
+    _check(_lib.attn_sweep(h, n_sweeps, ctypes.byref(so), e.ctypes.data_as(_f64p),
+                           s.ctypes.data_as(_f64p)), h)
+    return e, s
+
+
+def attn_validate(h):
+    _check(_lib.attn_validate(h), h)
+
+
+def attn_counters(h):
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.attn_counters(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), h)
+    return a.value, b.value, c.value

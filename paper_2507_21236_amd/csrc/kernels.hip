@@ -1,0 +1,994 @@
+// gfx950 kernels of the aTTN hot path.
+//
+// Dense contractions run on the matrix cores with 16 x 16 x 4 MFMA tiles.
+// FP64 and FP32 share the operand layout (A lane l -> (row l%16, k l/16),
+// B lane l -> (k l/16, col l%16)); the accumulator rows differ: item i of lane
+// l holds D[l/16 + 4 i][l%16] for FP64 and D[4 (l/16) + i][l%16] for FP32
+// (checked on the device by a probe of both instructions).
+// Every kernel reads a device work list so that one launch covers many terms,
+// output blocks or instances.  Reductions are two-stage with a fixed block
+// count and a fixed summation order, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace attn {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> struct V4;
+template <> struct V4<double> { typedef d4 type; };
+template <> struct V4<float> { typedef f4 type; };
+
+// accumulator row of item i in lane group g = lane / 16
+template <typename T> __device__ __forceinline__ int drow(int g, int i);
+template <> __device__ __forceinline__ int drow<double>(int g, int i) { return g + 4 * i; }
+template <> __device__ __forceinline__ int drow<float>(int g, int i) { return 4 * g + i; }
+
+// ============================================================================ sandwich
+// One work unit = (task, slice s, first 16-row strip).  The WG stages X_s in LDS;
+// wave w owns rows [16 (strip0 + w), +16) of Y_s.  Per item:
+//   stage 1: T1^T[p][a'] = sum_a X_s[a][p] A[a'][a]           (or X_s^T if A = 1)
+//   stage 2: Y^T[p'][a'] += sum_p B[p'][p] T1^T[p][a']        (or T1^T if B = 1)
+// Stage 2 consumes the stage-1 accumulators directly as the B operand by
+// walking K = p in the order {16 tp + drow(j, i) : j = 0..3} for fixed (tp, i),
+// which is exactly how the accumulator layout spreads p over lane groups.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_sandwich(const SWTask* __restrict__ tasks,
+                                                  const SWItem* __restrict__ items,
+                                                  const int4* __restrict__ wus,
+                                                  const T* __restrict__ xbase) {
+  typedef typename V4<T>::type v4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int4 wu = wus[blockIdx.x];
+  const SWTask& t = tasks[wu.x];
+  const int s = wu.y;
+  const int ma = t.ma;
+  constexpr int mb = 16 * NB;
+  constexpr int ld = mb + 2;
+  const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)s * t.xs_slice;
+  for (int e = threadIdx.x; e < ma * mb; e += 256) {
+    const int a = e / mb, b = e - a * mb;
+    lds[a * ld + b] = X[(int64_t)a * t.xs_row + b];
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int strip = wu.z + wave;
+  if (strip * 16 >= ma) return;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int arow = strip * 16 + l16;
+  v4 acc[NB];
+#pragma unroll
+  for (int q = 0; q < NB; q++) acc[q] = v4{0, 0, 0, 0};
+  const int iend = t.item0 + t.nitem;
+  for (int it = t.item0; it < iend; it++) {
+    const T* A = (const T*)items[it].A;
+    const T* B = (const T*)items[it].B;
+    const T coef = (T)items[it].coef;
+    v4 t1[NB];
+    if (A) {
+#pragma unroll
+      for (int q = 0; q < NB; q++) t1[q] = v4{0, 0, 0, 0};
+      const T* Ap = A + arow;
+      for (int k0 = 0; k0 < ma; k0 += 4) {
+        const T bop = Ap[(int64_t)(k0 + l4) * ma] * coef;
+        const T* xr = lds + (k0 + l4) * ld + l16;
+#pragma unroll
+        for (int q = 0; q < NB; q++) t1[q] = mfma16(xr[16 * q], bop, t1[q]);
+      }
+    } else {
+      const T* xr = lds + arow * ld;
+#pragma unroll
+      for (int q = 0; q < NB; q++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) t1[q][i] = xr[16 * q + drow<T>(l4, i)] * coef;
+    }
+    if (B) {
+#pragma unroll
+      for (int tp = 0; tp < NB; tp++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const T* Bp = B + (int64_t)(16 * tp + drow<T>(l4, i)) * mb + l16;
+#pragma unroll
+          for (int tq = 0; tq < NB; tq++) acc[tq] = mfma16(Bp[16 * tq], t1[tp][i], acc[tq]);
+        }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; q++) acc[q] += t1[q];
+    }
+  }
+  T* Y = (T*)t.y + (int64_t)s * t.ys_slice + (int64_t)arow * t.ys_row;
+#pragma unroll
+  for (int q = 0; q < NB; q++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int c = 16 * q + drow<T>(l4, i);
+      if (t.accumulate) Y[c] += acc[q][i];
+      else Y[c] = acc[q][i];
+    }
+}
+
+// Generic sandwich for dimensions that are not multiples of 16: one thread per
+// output element of one slice.  wu = (task, slice, first element).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sandwich_gen(const SWTask* __restrict__ tasks,
+                                                      const SWItem* __restrict__ items,
+                                                      const int4* __restrict__ wus,
+                                                      const T* __restrict__ xbase) {
+  const int4 wu = wus[blockIdx.x];
+  const SWTask& t = tasks[wu.x];
+  const int s = wu.y;
+  const int ma = t.ma, mb = t.mb;
+  const int e = wu.z + threadIdx.x;
+  if (e >= ma * mb) return;
+  const int ap = e / mb, bp = e - ap * mb;
+  const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)s * t.xs_slice;
+  T acc = 0;
+  for (int it = t.item0; it < t.item0 + t.nitem; it++) {
+    const T* A = (const T*)items[it].A;
+    const T* B = (const T*)items[it].B;
+    T sum = 0;
+    for (int b = 0; b < mb; b++) {
+      const T bw = B ? B[(int64_t)b * mb + bp] : (b == bp ? (T)1 : (T)0);
+      if (bw == (T)0) continue;
+      T col = 0;
+      if (A) {
+        for (int a = 0; a < ma; a++) col += A[(int64_t)a * ma + ap] * X[(int64_t)a * t.xs_row + b];
+      } else {
+        col = X[(int64_t)ap * t.xs_row + b];
+      }
+      sum += bw * col;
+    }
+    acc += (T)items[it].coef * sum;
+  }
+  T* Y = (T*)t.y + (int64_t)s * t.ys_slice + (int64_t)ap * t.ys_row + bp;
+  if (t.accumulate) *Y += acc;
+  else *Y = acc;
+}
+
+// ============================================================================ mode product
+// Element (i, f) of a (d0, d1, d2) tensor contracted on leg j, where f runs over
+// the two other legs in order.
+__device__ __forceinline__ int64_t mode_addr(int j, int d0, int d1, int d2, int i, int64_t f) {
+  if (j == 0) return (int64_t)i * d1 * d2 + f;
+  if (j == 1) {
+    const int64_t a = f / d2, c = f - a * d2;
+    return a * d1 * d2 + (int64_t)i * d2 + c;
+  }
+  return f * d2 + i;
+}
+
+// out (+)= sum_jobs coef * A x_j in.  wu = (task, f-tile of 64).  LDS holds the
+// input tile [i'][f]; wave w owns f in [16 w, +16) and every i.
+template <typename T, int NI>
+__global__ __launch_bounds__(256) void k_mode(const MPTask* __restrict__ tasks,
+                                              const MPJob* __restrict__ jobs,
+                                              const int2* __restrict__ wus,
+                                              const T* __restrict__ xbase) {
+  typedef typename V4<T>::type v4;
+  constexpr int mj = 16 * NI;
+  constexpr int ld = 64 + 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int2 wu = wus[blockIdx.x];
+  const MPTask& t = tasks[wu.x];
+  const int j = t.j, d0 = t.d0, d1 = t.d1, d2 = t.d2;
+  const int64_t f0 = (int64_t)wu.y * 64;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  v4 acc[NI];
+#pragma unroll
+  for (int q = 0; q < NI; q++) acc[q] = v4{0, 0, 0, 0};
+  for (int jb = t.job0; jb < t.job0 + t.njob; jb++) {
+    const T* in = jobs[jb].in ? (const T*)jobs[jb].in : xbase;
+    const T* A = (const T*)jobs[jb].A;
+    const T coef = (T)jobs[jb].coef;
+    __syncthreads();
+    if (j == 2) {
+      for (int e = threadIdx.x; e < 64 * mj; e += 256) {
+        const int fl = e / mj, i = e - fl * mj;
+        lds[i * ld + fl] = in[mode_addr(j, d0, d1, d2, i, f0 + fl)];
+      }
+    } else {
+      for (int e = threadIdx.x; e < 64 * mj; e += 256) {
+        const int i = e >> 6, fl = e & 63;
+        lds[i * ld + fl] = in[mode_addr(j, d0, d1, d2, i, f0 + fl)];
+      }
+    }
+    __syncthreads();
+    const T* Ap = A + l16;
+    for (int k0 = 0; k0 < mj; k0 += 4) {
+      const T bop = lds[(k0 + l4) * ld + 16 * wave + l16] * coef;
+      const T* Ak = Ap + (int64_t)(k0 + l4) * mj;
+#pragma unroll
+      for (int q = 0; q < NI; q++) acc[q] = mfma16(Ak[16 * q], bop, acc[q]);
+    }
+  }
+  T* out = (T*)t.out;
+  const int64_t f = f0 + 16 * wave + l16;
+#pragma unroll
+  for (int q = 0; q < NI; q++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int64_t ad = mode_addr(j, d0, d1, d2, 16 * q + drow<T>(l4, i), f);
+      if (t.accumulate) out[ad] += acc[q][i];
+      else out[ad] = acc[q][i];
+    }
+}
+
+// Generic mode product: one thread per output element.  wu = (task, first element).
+template <typename T>
+__global__ __launch_bounds__(256) void k_mode_gen(const MPTask* __restrict__ tasks,
+                                                  const MPJob* __restrict__ jobs,
+                                                  const int2* __restrict__ wus,
+                                                  const T* __restrict__ xbase) {
+  const int2 wu = wus[blockIdx.x];
+  const MPTask& t = tasks[wu.x];
+  const int64_t e = (int64_t)wu.y + threadIdx.x;
+  const int j = t.j, d0 = t.d0, d1 = t.d1, d2 = t.d2;
+  const int mj = j == 0 ? d0 : (j == 1 ? d1 : d2);
+  const int64_t total = (int64_t)d0 * d1 * d2;
+  if (e >= total) return;
+  const int64_t F = total / mj;
+  const int i = (int)(e / F);
+  const int64_t f = e - (int64_t)i * F;
+  T acc = 0;
+  for (int jb = t.job0; jb < t.job0 + t.njob; jb++) {
+    const T* in = jobs[jb].in ? (const T*)jobs[jb].in : xbase;
+    const T* A = (const T*)jobs[jb].A;
+    T sum = 0;
+    for (int k = 0; k < mj; k++) sum += A[(int64_t)k * mj + i] * in[mode_addr(j, d0, d1, d2, k, f)];
+    acc += (T)jobs[jb].coef * sum;
+  }
+  T* out = (T*)t.out;
+  const int64_t ad = mode_addr(j, d0, d1, d2, i, f);
+  if (t.accumulate) out[ad] += acc;
+  else out[ad] = acc;
+}
+
+// ============================================================================ gram
+// partial[j][j'] (column-major) = sum_{f in [f0, f1)} X[f][j] Z[f][j'].
+template <int NI>
+__global__ __launch_bounds__(256) void k_gram(const GRTask* __restrict__ tasks) {
+  constexpr int mj = 16 * NI;
+  constexpr int ld = mj + 2;
+  constexpr int NT = NI * NI;
+  constexpr int MAXT = (NT + 3) / 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lx = reinterpret_cast<double*>(smem_raw);
+  double* lz = lx + 64 * ld;
+  const GRTask& t = tasks[blockIdx.x];
+  const int j = t.j, d0 = t.d0, d1 = t.d1, d2 = t.d2;
+  const double* X = (const double*)t.X;
+  const double* Z = (const double*)t.Z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  d4 acc[MAXT];
+#pragma unroll
+  for (int q = 0; q < MAXT; q++) acc[q] = d4{0, 0, 0, 0};
+  for (int64_t fb = t.f0; fb < t.f1; fb += 64) {
+    __syncthreads();
+    if (j == 2) {
+      for (int e = threadIdx.x; e < 64 * mj; e += 256) {
+        const int fl = e / mj, i = e - fl * mj;
+        const int64_t ad = mode_addr(j, d0, d1, d2, i, fb + fl);
+        lx[fl * ld + i] = X[ad];
+        lz[fl * ld + i] = Z[ad];
+      }
+    } else {
+      for (int e = threadIdx.x; e < 64 * mj; e += 256) {
+        const int i = e >> 6, fl = e & 63;
+        const int64_t ad = mode_addr(j, d0, d1, d2, i, fb + fl);
+        lx[fl * ld + i] = X[ad];
+        lz[fl * ld + i] = Z[ad];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXT; q++) {
+      const int tt = wave + 4 * q;
+      if (tt < NT) {
+        const int tj = tt / NI, tk = tt - tj * NI;
+        for (int k0 = 0; k0 < 64; k0 += 4) {
+          const double a = lx[(k0 + l4) * ld + 16 * tj + l16];
+          const double b = lz[(k0 + l4) * ld + 16 * tk + l16];
+          acc[q] = mfma16(a, b, acc[q]);
+        }
+      }
+    }
+  }
+  double* P = (double*)t.partial;
+#pragma unroll
+  for (int q = 0; q < MAXT; q++) {
+    const int tt = wave + 4 * q;
+    if (tt < NT) {
+      const int tj = tt / NI, tk = tt - tj * NI;
+#pragma unroll
+      for (int i = 0; i < 4; i++) P[(int64_t)(16 * tk + l16) * mj + 16 * tj + drow<double>(l4, i)] = acc[q][i];
+    }
+  }
+}
+
+// Generic gram: one thread per output element (j, j'), loop over the f range.
+__global__ __launch_bounds__(256) void k_gram_gen(const GRTask* __restrict__ tasks, int maxm) {
+  const GRTask& t = tasks[blockIdx.y];
+  const int j = t.j, d0 = t.d0, d1 = t.d1, d2 = t.d2;
+  const int mj = j == 0 ? d0 : (j == 1 ? d1 : d2);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= mj * mj) return;
+  const int a = e % mj, b = e / mj;   // element (a, b) stored at b * mj + a
+  const double* X = (const double*)t.X;
+  const double* Z = (const double*)t.Z;
+  double acc = 0;
+  for (int64_t f = t.f0; f < t.f1; f++)
+    acc += X[mode_addr(j, d0, d1, d2, a, f)] * Z[mode_addr(j, d0, d1, d2, b, f)];
+  ((double*)t.partial)[e] = acc;
+  (void)maxm;
+}
+
+__global__ __launch_bounds__(256) void k_gram_reduce(const GRReduce* __restrict__ rs) {
+  const GRReduce& r = rs[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t mm = (int64_t)r.m * r.m;
+  if (e >= mm) return;
+  const double* P = (const double*)r.partial;
+  double acc = 0;
+  for (int c = 0; c < r.npart; c++) acc += P[c * mm + e];
+  double* out = (double*)r.out;
+  acc *= r.coef;
+  if (r.accumulate) out[e] += acc;
+  else out[e] = acc;
+}
+
+// ============================================================================ small elementwise kernels
+__global__ __launch_bounds__(256) void k_combine(const CBTask* __restrict__ tasks,
+                                                 const CBTerm* __restrict__ terms) {
+  const CBTask& t = tasks[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= t.n) return;
+  double acc = 0;
+  for (int k = t.term0; k < t.term0 + t.nterm; k++)
+    acc += terms[k].coef * ((const double*)terms[k].in)[e];
+  ((double*)t.out)[e] = acc;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_reduce_out(const RDSrc* __restrict__ srcs, int nsrc,
+                                                    TO* __restrict__ y, int ml, int mr, int mp) {
+  const int64_t M = (int64_t)ml * mr * mp;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M) return;
+  const int64_t l = e / ((int64_t)mr * mp);
+  const int64_t rem = e - l * mr * mp;
+  const int64_t r = rem / mp, p = rem - r * mp;
+  const int64_t et = p * ml * mr + l * mr + r;
+  double acc = 0;
+  for (int k = 0; k < nsrc; k++) {
+    const TI* src = (const TI*)srcs[k].p;
+    acc += (double)(srcs[k].layout ? src[et] : src[e]);
+  }
+  y[e] = (TO)acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_plr(const T* __restrict__ x, T* __restrict__ xt,
+                                                       int ml, int mr, int mp) {
+  const int64_t M = (int64_t)ml * mr * mp;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= M) return;
+  const int64_t l = e / ((int64_t)mr * mp);
+  const int64_t rem = e - l * mr * mp;
+  const int64_t r = rem / mp, p = rem - r * mp;
+  xt[p * ml * mr + l * mr + r] = x[e];
+}
+
+__global__ __launch_bounds__(256) void k_convert_f32(const CVTask* __restrict__ tasks) {
+  const CVTask& t = tasks[blockIdx.y];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < t.n; e += (int64_t)gridDim.x * 256)
+    ((float*)t.dst)[e] = (float)t.src[e];
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void k_cast(const TS* __restrict__ s, TD* __restrict__ d, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    d[e] = (TD)s[e];
+}
+
+// ============================================================================ Krylov (FP64)
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // deterministic: wave shuffle tree, then fixed-order sum of the 4 waves
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  return red[0] + red[1] + red[2] + red[3];
+}
+
+// partial[i][b] = sum over block b's elements of V_i . w   (i < nv; V == nullptr -> w . w)
+__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, int nv,
+                                                  const double* __restrict__ w, int64_t n,
+                                                  double* __restrict__ partial,
+                                                  const KrylovState* __restrict__ st) {
+  __shared__ double red[4];
+  if (st && st->stop) return;
+  const int b = blockIdx.x;
+  for (int i = 0; i < nv; i++) {
+    const double* v = V ? V + (int64_t)i * n : w;
+    double acc = 0;
+    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
+      acc += v[e] * w[e];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
+  }
+}
+
+// mode 0: out[i] = sum_b partial[i][b]; 1: alpha[j] = ...; 2: h[i] = ...;
+// 3: beta[j] = sqrt(...) with breakdown test and keff update; 4: scal[1] = sqrt(...)
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ partial, int nv,
+                                                   double* __restrict__ out, int mode,
+                                                   KrylovState* __restrict__ st, int j) {
+  __shared__ double red[4];
+  if (st && st->stop && mode != 4 && mode != 0) return;
+  for (int i = 0; i < nv; i++) {
+    const double v = partial[i * kRedBlocks + threadIdx.x];   // kRedBlocks == 256
+    const double s = block_sum(v, red);
+    if (threadIdx.x == 0) {
+      if (!isfinite(s) && st) st->status = 1;
+      if (mode == 0) out[i] = s;
+      else if (mode == 1) st->alpha[j] = s;
+      else if (mode == 2) st->h[i] = s;
+      else if (mode == 3) {
+        const double b = sqrt(s);
+        double amax = 0;
+        for (int k = 0; k <= j; k++) amax = fmax(amax, fabs(st->alpha[k]));
+        if (b <= 1e-14 * amax) {
+          st->stop = 1;
+        } else {
+          st->beta[j] = b;
+          st->keff = j + 2;
+        }
+      } else if (mode == 4) st->scal[1] = sqrt(s);
+    }
+  }
+}
+
+// w -= alpha_j v_j + beta_{j-1} v_{j-1}, then partial dots of the new w with V[0..j]
+__global__ __launch_bounds__(256) void k_lanczos_update(double* __restrict__ w,
+                                                        const double* __restrict__ V, int64_t n,
+                                                        const KrylovState* __restrict__ st, int j,
+                                                        double* __restrict__ partial) {
+  __shared__ double red[4];
+  if (st->stop) return;
+  const int b = blockIdx.x;
+  const double a = st->alpha[j];
+  const double bb = j > 0 ? st->beta[j - 1] : 0.0;
+  const double* vj = V + (int64_t)j * n;
+  const double* vm = j > 0 ? V + (int64_t)(j - 1) * n : V;
+  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
+    double x = w[e] - a * vj[e];
+    if (j > 0) x -= bb * vm[e];
+    w[e] = x;
+  }
+  // the same thread touches the same elements below: no barrier needed for w
+  for (int i = 0; i <= j; i++) {
+    const double* v = V + (int64_t)i * n;
+    double acc = 0;
+    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
+      acc += v[e] * w[e];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
+  }
+}
+
+// w -= sum_{i < nv} h_i V_i; then partial dots with V[0..nv) (or w . w if norm_only)
+__global__ __launch_bounds__(256) void k_axpy_dots(double* __restrict__ w,
+                                                   const double* __restrict__ V, int nv, int64_t n,
+                                                   const KrylovState* __restrict__ st,
+                                                   double* __restrict__ partial, int norm_only) {
+  __shared__ double red[4];
+  __shared__ double hs[128];
+  if (st->stop) return;
+  if (threadIdx.x < nv) hs[threadIdx.x] = st->h[threadIdx.x];
+  __syncthreads();
+  const int b = blockIdx.x;
+  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
+    double x = w[e];
+    for (int i = 0; i < nv; i++) x -= hs[i] * V[(int64_t)i * n + e];
+    w[e] = x;
+  }
+  if (norm_only) {
+    double acc = 0;
+    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
+      acc += w[e] * w[e];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[b] = s;
+    return;
+  }
+  for (int i = 0; i < nv; i++) {
+    const double* v = V + (int64_t)i * n;
+    double acc = 0;
+    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
+      acc += v[e] * w[e];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
+  }
+}
+
+// out = w / scale; which 0: scale = beta[j] (skipped after breakdown), 1: scal[1]
+__global__ __launch_bounds__(256) void k_scale_into(const double* __restrict__ w,
+                                                    double* __restrict__ out, int64_t n,
+                                                    const KrylovState* __restrict__ st, int which,
+                                                    int j) {
+  if (which == 0 && st->stop) return;
+  const double sc = which == 0 ? st->beta[j] : st->scal[1];
+  const double inv = 1.0 / sc;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    out[e] = w[e] * inv;
+}
+
+// Lowest eigenpair of the keff x keff tridiagonal matrix (alpha, beta) by cyclic
+// Jacobi rotations on the dense symmetric matrix, one wavefront.  The
+// eigenvector is normalised with its first non-zero component positive.
+__global__ __launch_bounds__(64) void k_tridiag(KrylovState* __restrict__ st) {
+  __shared__ double A[64][65];
+  __shared__ double Vm[64][65];
+  __shared__ double cs_sn[2];
+  const int k = st->keff;
+  const int t = threadIdx.x;
+  for (int i = 0; i < k; i++) {
+    if (t < k) {
+      double v = 0;
+      if (i == t) v = st->alpha[i];
+      else if (t == i + 1) v = st->beta[i];
+      else if (i == t + 1) v = st->beta[t];
+      A[i][t] = v;
+      Vm[i][t] = (i == t) ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 60; sweep++) {
+    double off = 0, dia = 0;
+    for (int i = 0; i < k; i++)
+      for (int j2 = 0; j2 < k; j2++) {
+        if (i == j2) dia += A[i][i] * A[i][i];
+        else off += A[i][j2] * A[i][j2];
+      }
+    if (off <= 1e-32 * dia || off == 0.0) break;
+    for (int p = 0; p < k - 1; p++)
+      for (int q = p + 1; q < k; q++) {
+        if (t == 0) {
+          const double apq = A[p][q];
+          double c = 1.0, s = 0.0;
+          if (apq != 0.0) {
+            const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+            const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+          cs_sn[0] = c;
+          cs_sn[1] = s;
+        }
+        __syncthreads();
+        const double c = cs_sn[0], s = cs_sn[1];
+        if (s != 0.0) {
+          // columns p, q
+          if (t < k) {
+            const double x = A[t][p], y = A[t][q];
+            A[t][p] = c * x - s * y;
+            A[t][q] = s * x + c * y;
+          }
+          __syncthreads();
+          if (t < k) {
+            const double x = A[p][t], y = A[q][t];
+            A[p][t] = c * x - s * y;
+            A[q][t] = s * x + c * y;
+            const double vx = Vm[t][p], vy = Vm[t][q];
+            Vm[t][p] = c * vx - s * vy;
+            Vm[t][q] = s * vx + c * vy;
+          }
+        }
+        __syncthreads();
+      }
+  }
+  if (t == 0) {
+    int best = 0;
+    for (int i = 1; i < k; i++)
+      if (A[i][i] < A[best][best]) best = i;
+    double nrm = 0;
+    for (int i = 0; i < k; i++) nrm += Vm[i][best] * Vm[i][best];
+    nrm = sqrt(nrm);
+    int first = 0;
+    while (first < k - 1 && Vm[first][best] == 0.0) first++;
+    const double sg = Vm[first][best] < 0 ? -1.0 : 1.0;
+    for (int i = 0; i < k; i++) st->y[i] = sg * Vm[i][best] / nrm;
+    st->scal[0] = A[best][best];
+    if (!isfinite(A[best][best])) st->status = 1;
+  }
+}
+
+// out = sum_i y_i V_i with partial ||out||^2
+__global__ __launch_bounds__(256) void k_ritz(const double* __restrict__ V, int64_t n,
+                                              double* __restrict__ out,
+                                              const KrylovState* __restrict__ st,
+                                              double* __restrict__ partial) {
+  __shared__ double red[4];
+  __shared__ double ys[128];
+  const int k = st->keff;
+  if (threadIdx.x < k) ys[threadIdx.x] = st->y[threadIdx.x];
+  __syncthreads();
+  const int b = blockIdx.x;
+  double acc2 = 0;
+  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
+    double x = 0;
+    for (int i = 0; i < k; i++) x += ys[i] * V[(int64_t)i * n + e];
+    out[e] = x;
+    acc2 += x * x;
+  }
+  const double s = block_sum(acc2, red);
+  if (threadIdx.x == 0) partial[b] = s;
+}
+
+// ============================================================================ QR helpers
+// Cholesky of G + shift*I = R^T R (R upper, positive diagonal) and the row-major
+// inverse of R, one workgroup.  G column-major n x n (symmetric).
+// shift_mode 1: shift = 11 (rows n + n (n + 1)) u trace(G) (shifted CholeskyQR).
+__global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, int n,
+                                                  double* __restrict__ R,
+                                                  double* __restrict__ RinvRow, int shift_mode,
+                                                  int64_t rows, KrylovState* __restrict__ st) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* L = reinterpret_cast<double*>(smem_raw);   // n x n, L[i * n + j] lower
+  __shared__ double shift;
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    bad = 0;
+    double tr = 0;
+    for (int i = 0; i < n; i++) tr += G[(int64_t)i * n + i];
+    shift = shift_mode ? 11.0 * ((double)rows * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * tr : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < n * n; e += 256) {
+    const int i = e / n, j = e - i * n;
+    L[e] = G[(int64_t)j * n + i] + (i == j ? shift : 0.0);
+  }
+  __syncthreads();
+  for (int k = 0; k < n; k++) {
+    if (t == 0) {
+      const double dkk = L[k * n + k];
+      if (!(dkk > 0.0) || !isfinite(dkk)) bad = 1;
+      L[k * n + k] = sqrt(fmax(dkk, 1e-300));
+    }
+    __syncthreads();
+    const double piv = L[k * n + k];
+    for (int i = k + 1 + t; i < n; i += 256) L[i * n + k] /= piv;
+    __syncthreads();
+    for (int e = t; e < (n - k - 1) * (n - k - 1); e += 256) {
+      const int i = k + 1 + e / (n - k - 1), j = k + 1 + e % (n - k - 1);
+      if (j <= i) L[i * n + j] -= L[i * n + k] * L[j * n + k];
+    }
+    __syncthreads();
+  }
+  // R = L^T (column-major R[i][j] at j * n + i), zero below the diagonal
+  for (int e = t; e < n * n; e += 256) {
+    const int j = e / n, i = e - j * n;
+    R[e] = (i <= j) ? L[j * n + i] : 0.0;
+  }
+  // inverse of R (upper): column c of Rinv solves R x = e_c; thread per column
+  for (int c = t; c < n; c += 256) {
+    for (int i = n - 1; i >= 0; i--) {
+      double x = (i == c) ? 1.0 : 0.0;
+      if (i > c) x = 0.0;
+      else {
+        for (int j = i + 1; j <= c; j++) x -= L[j * n + i] * RinvRow[(int64_t)j * n + c];
+        x /= L[i * n + i];
+      }
+      RinvRow[(int64_t)i * n + c] = x;   // row-major Rinv
+    }
+  }
+  __syncthreads();
+  if (t == 0 && bad && st) st->status = 2;
+}
+
+// C = A B for n x n column-major matrices (one workgroup)
+__global__ __launch_bounds__(256) void k_small_matmul(const double* __restrict__ A,
+                                                      const double* __restrict__ B,
+                                                      double* __restrict__ C, int n) {
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int j = e / n, i = e - j * n;
+    double acc = 0;
+    for (int k = 0; k < n; k++) acc += A[(int64_t)k * n + i] * B[(int64_t)j * n + k];
+    C[e] = acc;
+  }
+}
+
+// ============================================================================ launchers
+static inline unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T, int NB>
+static hipError_t sand_launch(const SWTask* tasks, const SWItem* items, const int4* wus, int nwu,
+                              int ma, const void* xbase, hipStream_t s) {
+  const size_t lds = (size_t)ma * (16 * NB + 2) * sizeof(T);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_sandwich<T, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_sandwich<T, NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus,
+                     (const T*)xbase);
+  return hipGetLastError();
+}
+
+hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const SWItem* items,
+                           const int4* wus, int nwu, const void* xbase, hipStream_t s) {
+  if (nwu == 0) return hipSuccess;
+  const bool mf = (ma % 16 == 0) && (mb % 16 == 0) && ma <= 128 && mb <= 128;
+  if (dtype == 0) {
+    if (!mf) {
+      hipLaunchKernelGGL(k_sandwich_gen<double>, dim3(nwu), dim3(256), 0, s, tasks, items, wus,
+                         (const double*)xbase);
+      return hipGetLastError();
+    }
+    switch (mb / 16) {
+      case 1: return sand_launch<double, 1>(tasks, items, wus, nwu, ma, xbase, s);
+      case 2: return sand_launch<double, 2>(tasks, items, wus, nwu, ma, xbase, s);
+      case 3: return sand_launch<double, 3>(tasks, items, wus, nwu, ma, xbase, s);
+      case 4: return sand_launch<double, 4>(tasks, items, wus, nwu, ma, xbase, s);
+      case 5: return sand_launch<double, 5>(tasks, items, wus, nwu, ma, xbase, s);
+      case 6: return sand_launch<double, 6>(tasks, items, wus, nwu, ma, xbase, s);
+      case 7: return sand_launch<double, 7>(tasks, items, wus, nwu, ma, xbase, s);
+      case 8: return sand_launch<double, 8>(tasks, items, wus, nwu, ma, xbase, s);
+    }
+  } else {
+    if (!mf) {
+      hipLaunchKernelGGL(k_sandwich_gen<float>, dim3(nwu), dim3(256), 0, s, tasks, items, wus,
+                         (const float*)xbase);
+      return hipGetLastError();
+    }
+    switch (mb / 16) {
+      case 1: return sand_launch<float, 1>(tasks, items, wus, nwu, ma, xbase, s);
+      case 2: return sand_launch<float, 2>(tasks, items, wus, nwu, ma, xbase, s);
+      case 3: return sand_launch<float, 3>(tasks, items, wus, nwu, ma, xbase, s);
+      case 4: return sand_launch<float, 4>(tasks, items, wus, nwu, ma, xbase, s);
+      case 5: return sand_launch<float, 5>(tasks, items, wus, nwu, ma, xbase, s);
+      case 6: return sand_launch<float, 6>(tasks, items, wus, nwu, ma, xbase, s);
+      case 7: return sand_launch<float, 7>(tasks, items, wus, nwu, ma, xbase, s);
+      case 8: return sand_launch<float, 8>(tasks, items, wus, nwu, ma, xbase, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int NI>
+static hipError_t mode_launch(const MPTask* tasks, const MPJob* jobs, const int2* wus, int nwu,
+                              const void* xbase, hipStream_t s) {
+  const size_t lds = (size_t)16 * NI * 66 * sizeof(T);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_mode<T, NI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_mode<T, NI>), dim3(nwu), dim3(256), lds, s, tasks, jobs, wus,
+                     (const T*)xbase);
+  return hipGetLastError();
+}
+
+hipError_t launch_mode(int dtype, int mj, bool mfma, const MPTask* tasks, const MPJob* jobs,
+                       const int2* wus, int nwu, const void* xbase, hipStream_t s) {
+  if (nwu == 0) return hipSuccess;
+  if (!mfma) {
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_mode_gen<double>, dim3(nwu), dim3(256), 0, s, tasks, jobs, wus,
+                         (const double*)xbase);
+    else
+      hipLaunchKernelGGL(k_mode_gen<float>, dim3(nwu), dim3(256), 0, s, tasks, jobs, wus,
+                         (const float*)xbase);
+    return hipGetLastError();
+  }
+#define MODE_CASES(T)                                                        \
+  switch (mj / 16) {                                                         \
+    case 1: return mode_launch<T, 1>(tasks, jobs, wus, nwu, xbase, s);       \
+    case 2: return mode_launch<T, 2>(tasks, jobs, wus, nwu, xbase, s);       \
+    case 3: return mode_launch<T, 3>(tasks, jobs, wus, nwu, xbase, s);       \
+    case 4: return mode_launch<T, 4>(tasks, jobs, wus, nwu, xbase, s);       \
+    case 5: return mode_launch<T, 5>(tasks, jobs, wus, nwu, xbase, s);       \
+    case 6: return mode_launch<T, 6>(tasks, jobs, wus, nwu, xbase, s);       \
+    case 7: return mode_launch<T, 7>(tasks, jobs, wus, nwu, xbase, s);       \
+    case 8: return mode_launch<T, 8>(tasks, jobs, wus, nwu, xbase, s);       \
+  }
+  if (dtype == 0) { MODE_CASES(double) }
+  else { MODE_CASES(float) }
+#undef MODE_CASES
+  return hipErrorInvalidValue;
+}
+
+template <int NI>
+static hipError_t gram_launch(const GRTask* tasks, int ntask, hipStream_t s) {
+  const size_t lds = (size_t)2 * 64 * (16 * NI + 2) * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_gram<NI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_gram<NI>, dim3(ntask), dim3(256), lds, s, tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram(int mj, bool mfma, const GRTask* tasks, int ntask, hipStream_t s) {
+  if (ntask == 0) return hipSuccess;
+  if (!mfma) {
+    hipLaunchKernelGGL(k_gram_gen, dim3(grid1((int64_t)mj * mj), ntask), dim3(256), 0, s, tasks, mj);
+    return hipGetLastError();
+  }
+  switch (mj / 16) {
+    case 1: return gram_launch<1>(tasks, ntask, s);
+    case 2: return gram_launch<2>(tasks, ntask, s);
+    case 3: return gram_launch<3>(tasks, ntask, s);
+    case 4: return gram_launch<4>(tasks, ntask, s);
+    case 5: return gram_launch<5>(tasks, ntask, s);
+    case 6: return gram_launch<6>(tasks, ntask, s);
+    case 7: return gram_launch<7>(tasks, ntask, s);
+    case 8: return gram_launch<8>(tasks, ntask, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gram_reduce(const GRReduce* r, int nr, int maxm, hipStream_t s) {
+  if (nr == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram_reduce, dim3(grid1((int64_t)maxm * maxm), nr), dim3(256), 0, s, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const CBTask* tasks, const CBTerm* terms, int ntask, int maxn,
+                          hipStream_t s) {
+  if (ntask == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine, dim3(grid1(maxn), ntask), dim3(256), 0, s, tasks, terms);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_out(int dtype_in, const RDSrc* srcs, int nsrc, void* y, int dtype_out,
+                             int ml, int mr, int mp, hipStream_t s) {
+  const int64_t M = (int64_t)ml * mr * mp;
+  if (dtype_in == 0 && dtype_out == 0)
+    hipLaunchKernelGGL((k_reduce_out<double, double>), dim3(grid1(M)), dim3(256), 0, s, srcs, nsrc,
+                       (double*)y, ml, mr, mp);
+  else if (dtype_in == 1 && dtype_out == 0)
+    hipLaunchKernelGGL((k_reduce_out<float, double>), dim3(grid1(M)), dim3(256), 0, s, srcs, nsrc,
+                       (double*)y, ml, mr, mp);
+  else if (dtype_in == 1 && dtype_out == 1)
+    hipLaunchKernelGGL((k_reduce_out<float, float>), dim3(grid1(M)), dim3(256), 0, s, srcs, nsrc,
+                       (float*)y, ml, mr, mp);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_plr(int dtype, const void* x, void* xt, int ml, int mr, int mp,
+                                hipStream_t s) {
+  const int64_t M = (int64_t)ml * mr * mp;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_transpose_plr<double>, dim3(grid1(M)), dim3(256), 0, s, (const double*)x,
+                       (double*)xt, ml, mr, mp);
+  else
+    hipLaunchKernelGGL(k_transpose_plr<float>, dim3(grid1(M)), dim3(256), 0, s, (const float*)x,
+                       (float*)xt, ml, mr, mp);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(int dtype, const CVTask* tasks, int ntask, int64_t maxn, hipStream_t s) {
+  if (ntask == 0) return hipSuccess;
+  int64_t g = grid1(maxn);
+  if (g > 1024) g = 1024;
+  if (dtype == 1) hipLaunchKernelGGL(k_convert_f32, dim3((unsigned)g, ntask), dim3(256), 0, s, tasks);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t n,
+                       hipStream_t s) {
+  int64_t g = grid1(n);
+  if (g > 2048) g = 2048;
+  if (g == 0) return hipSuccess;
+  if (src_dtype == 0 && dst_dtype == 1)
+    hipLaunchKernelGGL((k_cast<double, float>), dim3((unsigned)g), dim3(256), 0, s,
+                       (const double*)src, (float*)dst, n);
+  else if (src_dtype == 1 && dst_dtype == 0)
+    hipLaunchKernelGGL((k_cast<float, double>), dim3((unsigned)g), dim3(256), 0, s,
+                       (const float*)src, (double*)dst, n);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_multidot(const double* V, int nv, const double* w, int64_t n, double* partial,
+                           const KrylovState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(256), 0, s, V, nv, w, n, partial, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_final(const double* partial, int nv, double* out, int mode,
+                            KrylovState* st, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, partial, nv, out, mode, st, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_update(double* w, const double* V, int64_t n, KrylovState* st, int j,
+                                 double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_update, dim3(kRedBlocks), dim3(256), 0, s, w, V, n, st, j, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dots(double* w, const double* V, int nv, int64_t n, KrylovState* st,
+                            double* partial, int norm_only, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dots, dim3(kRedBlocks), dim3(256), 0, s, w, V, nv, n, st, partial,
+                     norm_only);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_into(const double* w, double* out, int64_t n, KrylovState* st, int which,
+                             int j, hipStream_t s) {
+  int64_t g = grid1(n);
+  if (g > 2048) g = 2048;
+  hipLaunchKernelGGL(k_scale_into, dim3((unsigned)g), dim3(256), 0, s, w, out, n, st, which, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_tridiag(KrylovState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_ritz(const double* V, int64_t n, double* out, KrylovState* st, double* partial,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_ritz, dim3(kRedBlocks), dim3(256), 0, s, V, n, out, st, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(const double* x, int64_t n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(256), 0, s, (const double*)nullptr, 1, x,
+                     n, partial, (const KrylovState*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(double* x, int64_t n, double* partial, KrylovState* st, hipStream_t s) {
+  hipError_t e = launch_norm2(x, n, partial, s);
+  if (e != hipSuccess) return e;
+  e = launch_dot_final(partial, 1, nullptr, 4, st, 0, s);
+  if (e != hipSuccess) return e;
+  return launch_scale_into(x, x, n, st, 1, 0, s);
+}
+
+hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, int shift_mode,
+                           int64_t rows, KrylovState* st, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        150 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), (size_t)n * n * sizeof(double), s, G, n, R,
+                     RinvRow, shift_mode, rows, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_small_matmul(const double* A, const double* B, double* C, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_matmul, dim3(1), dim3(256), 0, s, A, B, C, n);
+  return hipGetLastError();
+}
+
+}  // namespace attn

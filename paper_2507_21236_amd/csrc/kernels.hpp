@@ -1,0 +1,98 @@
+// Work descriptors shared by the host runtime and the gfx950 kernels.
+//
+// Every kernel is driven by a device-resident list of work units so that one
+// launch can cover many terms, output blocks or problem instances of uneven
+// size.  All operator blocks are m x m, stored column-major: element O[i][i']
+// (acting as (O x_j v)[.., i, ..] = sum_i' O[i][i'] v[.., i', ..]) lives at
+// O + i' * m + i.  Tensors are row-major [d0][d1][d2].
+#pragma once
+#include <stdint.h>
+
+namespace attn {
+
+// ---------------------------------------------------------------- sandwich
+// Y_s (+)= sum_items coef * A X_s B^T over slices s of a spectator leg:
+// X_s[a][b] at x + s*xs_slice + a*xs_row + b (same for y).  A acts on the
+// a leg (ma x ma), B on the b leg (mb x mb).
+struct SWItem {
+  const void* A;
+  const void* B;
+  double coef;
+};
+
+struct SWTask {
+  const void* x;
+  void* y;
+  int64_t xs_slice, xs_row;
+  int64_t ys_slice, ys_row;
+  int32_t ma, mb;
+  int32_t item0, nitem;
+  int32_t accumulate;
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------- mode product
+// out (+)= sum_jobs coef * A x_j in, all tensors of dims (d0, d1, d2).
+struct MPJob {
+  const void* A;
+  const void* in;
+  double coef;
+};
+
+struct MPTask {
+  void* out;
+  int32_t d0, d1, d2, j;
+  int32_t job0, njob;
+  int32_t accumulate;
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------- gram
+// partial[o][c] = sum_{f in chunk c} X[f][j] Z_o[f][j'] with f the two legs
+// other than j of a (d0, d1, d2) tensor; reduced afterwards over c.
+struct GRTask {
+  const void* X;
+  const void* Z;
+  void* partial;      // m_j x m_j, column-major
+  int32_t d0, d1, d2, j;
+  int32_t f0, f1;     // free-index range of this unit
+};
+
+// Final block = coef * sum over npart partials (fixed order) (+ existing if accumulate)
+struct GRReduce {
+  const void* partial;   // npart consecutive m*m partials
+  void* out;
+  int32_t m, npart;
+  double coef;
+  int32_t accumulate;
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------- block combine
+// out = sum_k coef_k * in_k (blocks of n elements)
+struct CBTerm {
+  const void* in;
+  double coef;
+};
+struct CBTask {
+  void* out;
+  int32_t n, term0, nterm;
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------- reduction of partial outputs
+// y[l][r][p] = sum_k src_k, src_k in layout 0 ([l][r][p]) or 1 ([p][l][r])
+struct RDSrc {
+  const void* p;
+  int32_t layout;
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------- conversion
+struct CVTask {
+  const double* src;
+  void* dst;       // float (FP32) or two bf16 planes (hi then lo)
+  int64_t n;
+};
+
+}  // namespace attn

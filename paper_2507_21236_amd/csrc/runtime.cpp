@@ -1,0 +1,1349 @@
+// Runtime of the aTTN hot path: device memory, per-node device plans and the
+// C interface declared in attn.h.  All arithmetic of the path runs in the
+// kernels of kernels.hip; this file only allocates, uploads work lists and
+// enqueues launches.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <functional>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "attn.h"
+#include "kernels.hpp"
+#include "launch.hpp"
+#include "model.hpp"
+
+using namespace attn;
+
+namespace {
+
+thread_local std::string g_build_error;
+
+struct HipFail {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(x)                                 \
+  do {                                            \
+    hipError_t _e = (x);                          \
+    if (_e != hipSuccess) throw HipFail{_e, #x};  \
+  } while (0)
+
+struct StatusFail {
+  attn_status st;
+  std::string msg;
+};
+
+// A sandwich launch group: tasks with the same (ma, mb).
+struct SWGroup {
+  int ma = 0, mb = 0;
+  std::vector<SWTask> tasks;
+  std::vector<SWItem> items;
+  std::vector<int4> wus;
+  SWTask* d_tasks = nullptr;
+  SWItem* d_items = nullptr;
+  int4* d_wus = nullptr;
+};
+
+struct MPGroup {
+  int mj = 0;
+  bool mfma = false;
+  std::vector<MPTask> tasks;
+  std::vector<MPJob> jobs;
+  std::vector<int2> wus;
+  MPTask* d_tasks = nullptr;
+  MPJob* d_jobs = nullptr;
+  int2* d_wus = nullptr;
+};
+
+struct CBPlan {
+  std::vector<CBTask> tasks;
+  std::vector<CBTerm> terms;
+  CBTask* d_tasks = nullptr;
+  CBTerm* d_terms = nullptr;
+  int maxn = 0;
+};
+
+struct GRPlan {
+  int mj = 0;
+  bool mfma = false;
+  std::vector<GRTask> tasks;
+  std::vector<GRReduce> reds;
+  GRTask* d_tasks = nullptr;
+  GRReduce* d_reds = nullptr;
+};
+
+struct MVDev {
+  CBPlan comb;
+  std::vector<SWGroup> sw;
+  std::vector<MPGroup> chainA, chainB, chainC;   // one group per mj
+  std::vector<RDSrc> srcs;
+  RDSrc* d_srcs = nullptr;
+  bool need_xt = false;
+  int dims[3] = {0, 0, 0};
+};
+
+struct EnvChunk {
+  std::vector<SWGroup> sw;
+  GRPlan gr;
+  std::vector<std::pair<double*, int64_t>> zero_blocks;
+};
+
+struct EnvDev {
+  bool present = false;
+  bool transpose = false;
+  int dims[3] = {0, 0, 0};
+  CBPlan comb;
+  std::vector<EnvChunk> chunks;
+  int node = -1, leg = -1, out_edge = -1, out_dir = 0;
+};
+
+// QR of a node tensor with one leg as the column index (three CholeskyQR passes)
+struct QRDev {
+  bool present = false;
+  int mj = 0, nfc = 0, nwus = 0;
+  bool gmf = false, mmf = false;
+  int64_t rows = 0, Msz = 0;
+  GRTask* d_gt[3] = {nullptr, nullptr, nullptr};
+  GRReduce* d_gr = nullptr;
+  MPTask* d_mt[3] = {nullptr, nullptr, nullptr};
+  MPJob* d_mj[3] = {nullptr, nullptr, nullptr};
+  int2* d_wus = nullptr;
+  std::vector<GRTask> h_gt[3];
+  std::vector<GRReduce> h_gr;
+  MPGroup h_mp[3];   // host copies for validation
+};
+
+// T <- R x_leg T through a temporary
+struct ABDev {
+  bool present = false;
+  int mj = 0, nwus = 0;
+  bool mmf = false;
+  int64_t Msz = 0;
+  MPTask* d_mt = nullptr;
+  MPJob* d_mj = nullptr;
+  int2* d_wus = nullptr;
+  MPGroup h_mp;   // host copy for validation
+};
+
+bool mode_mfma_ok(int mj, int64_t M) { return mj % 16 == 0 && mj <= 128 && (M / mj) % 64 == 0; }
+bool gram_mfma_ok(int mj, int64_t M) { return mj % 16 == 0 && mj <= 128 && (M / mj) % 64 == 0; }
+
+}  // namespace
+
+struct attn_handle {
+  Model M;
+  std::string err;
+  bool host_only = false;
+  bool dryrun = false;
+  bool dead = false;
+  uintptr_t fake_next = (uintptr_t)1 << 40;
+  std::vector<std::pair<uintptr_t, size_t>> allocs;
+  int device = 0;
+  std::vector<void*> owned;
+  // tensors
+  double* d_T = nullptr;
+  std::vector<int64_t> T_off;
+  std::vector<int64_t> T_len;
+  // effective-operator stores per edge and direction
+  std::vector<double*> store[2];
+  std::vector<char> valid[2];
+  std::vector<int> iso;       // per node: leg it is isometric toward, -1 = centre
+  int center = -1;
+  bool state_ready = false;
+  // scratch
+  int64_t Mmax = 0;
+  int kcap = 65;   // at most 64 Krylov vectors (+1)
+  double* d_V = nullptr;      // (kcap) x Mmax
+  double* d_w = nullptr;
+  double* d_xt = nullptr;
+  double* d_tmp = nullptr;
+  double* d_tmp2 = nullptr;
+  float* d_x32 = nullptr;
+  float* d_y32 = nullptr;
+  double* d_part = nullptr;   // mv partial outputs
+  int64_t part_cap = 0;
+  double* d_chain = nullptr;
+  int64_t chain_cap = 0;
+  double* d_mvcomb = nullptr;
+  double* d_envcomb = nullptr;
+  double* d_Z = nullptr;
+  double* d_grpart = nullptr;
+  double* d_red = nullptr;    // 128 x kRedBlocks
+  double* d_qrmat = nullptr;  // G, R0, R1, R2, Rinv, Rt (mmax^2 each)
+  double* d_qrR = nullptr;    // R of the last QR (absorbed into the neighbour)
+  int mmax = 1;
+  KrylovState* d_st = nullptr;
+  // plans
+  std::vector<MVDev> mv;
+  std::vector<EnvDev> env_up, env_down[2];
+  std::vector<QRDev> qr[3];   // per leg, per node
+  std::vector<ABDev> ab[3];   // absorb into node along leg
+  // counters
+  int64_t n_matvec = 0, n_env = 0, n_qr = 0;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ device memory
+// Every device buffer goes through dev_alloc so that a dry-run build can lay
+// out all work lists in a fake address space and check them on the host.
+void* dev_alloc(attn_handle* h, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 8);
+  void* p = nullptr;
+  if (h->dryrun) {
+    p = (void*)h->fake_next;
+    h->fake_next += (bytes + (1u << 20) - 1) / (1u << 20) * (1u << 20) + (1u << 20);
+  } else {
+    HIPCHK(hipMalloc(&p, bytes));
+    h->owned.push_back(p);
+  }
+  h->allocs.push_back({(uintptr_t)p, bytes});
+  return p;
+}
+
+template <typename T>
+T* upload(attn_handle* h, const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  void* p = dev_alloc(h, v.size() * sizeof(T));
+  if (!h->dryrun) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return (T*)p;
+}
+
+// ------------------------------------------------------------------ pointers
+double* block_ptr(attn_handle* h, const BRef& b, double* comb_base, const std::vector<int64_t>& comb_off) {
+  if (b.kind == 0) {
+    int dim = h->M.tree.edge_dim(b.edge);
+    return h->store[b.dir][b.edge] + (int64_t)(b.slot + 1) * dim * dim;
+  }
+  if (b.kind == 1) return comb_base + comb_off[b.slot];
+  return nullptr;
+}
+
+void build_comb(attn_handle* h, const std::vector<Combine>& cs, double* base, CBPlan& P,
+                std::vector<int64_t>& off, int64_t& total) {
+  off.clear();
+  total = 0;
+  for (const Combine& c : cs) {
+    off.push_back(total);
+    total += (int64_t)c.dim * c.dim;
+  }
+  for (size_t i = 0; i < cs.size(); i++) {
+    CBTask t;
+    t.out = base ? base + off[i] : nullptr;
+    t.n = cs[i].dim * cs[i].dim;
+    t.term0 = (int)P.terms.size();
+    t.nterm = (int)cs[i].in.size();
+    t.pad = 0;
+    for (auto& pr : cs[i].in) {
+      CBTerm ct;
+      ct.in = block_ptr(h, pr.first, nullptr, off);
+      ct.coef = pr.second;
+      P.terms.push_back(ct);
+    }
+    P.maxn = std::max(P.maxn, t.n);
+    P.tasks.push_back(t);
+  }
+}
+
+void upload_comb(attn_handle* h, CBPlan& P) {
+  P.d_tasks = upload(h, P.tasks);
+  P.d_terms = upload(h, P.terms);
+}
+
+// slice geometry of a spectator leg for a (d0, d1, d2) tensor in layout [l][r][p]
+// (or [p][l][r] for spectator p when transposed)
+void slice_geom(int spect, const int* dm, int& ma, int& mb, int& ns, int64_t& sl, int64_t& row) {
+  if (spect == 0) { ma = dm[1]; mb = dm[2]; ns = dm[0]; sl = (int64_t)dm[1] * dm[2]; row = dm[2]; }
+  else if (spect == 1) { ma = dm[0]; mb = dm[2]; ns = dm[1]; sl = dm[2]; row = (int64_t)dm[1] * dm[2]; }
+  else { ma = dm[0]; mb = dm[1]; ns = dm[2]; sl = (int64_t)dm[0] * dm[1]; row = dm[1]; }
+}
+
+bool sw_mfma(int ma, int mb) { return ma % 16 == 0 && mb % 16 == 0 && ma <= 128 && mb <= 128; }
+
+void add_sw_task(SWGroup& g, SWTask t, int ns) {
+  g.ma = t.ma;
+  g.mb = t.mb;
+  const int ti = (int)g.tasks.size();
+  g.tasks.push_back(t);
+  if (sw_mfma(t.ma, t.mb)) {
+    for (int s = 0; s < ns; s++)
+      for (int st = 0; st < t.ma / 16; st += 4) g.wus.push_back(make_int4(ti, s, st, 0));
+  } else {
+    for (int s = 0; s < ns; s++)
+      for (int e = 0; e < t.ma * t.mb; e += 256) g.wus.push_back(make_int4(ti, s, e, 0));
+  }
+}
+
+SWGroup& group_for(std::vector<SWGroup>& gs, int ma, int mb) {
+  for (auto& g : gs)
+    if (g.ma == ma && g.mb == mb) return g;
+  gs.emplace_back();
+  gs.back().ma = ma;
+  gs.back().mb = mb;
+  return gs.back();
+}
+
+MPGroup& mgroup_for(std::vector<MPGroup>& gs, int mj, bool mf) {
+  for (auto& g : gs)
+    if (g.mj == mj && g.mfma == mf) return g;
+  gs.emplace_back();
+  gs.back().mj = mj;
+  gs.back().mfma = mf;
+  return gs.back();
+}
+
+void add_mp_task(MPGroup& g, MPTask t) {
+  const int ti = (int)g.tasks.size();
+  g.tasks.push_back(t);
+  const int mj = t.j == 0 ? t.d0 : (t.j == 1 ? t.d1 : t.d2);
+  const int64_t M = (int64_t)t.d0 * t.d1 * t.d2;
+  if (g.mfma) {
+    for (int64_t f = 0; f < M / mj / 64; f++) g.wus.push_back(make_int2(ti, (int)f));
+  } else {
+    for (int64_t e = 0; e < M; e += 256) g.wus.push_back(make_int2(ti, (int)e));
+  }
+}
+
+void upload_sw(attn_handle* h, std::vector<SWGroup>& gs) {
+  for (auto& g : gs) {
+    g.d_tasks = upload(h, g.tasks);
+    g.d_items = upload(h, g.items);
+    g.d_wus = upload(h, g.wus);
+  }
+}
+
+void upload_mp(attn_handle* h, std::vector<MPGroup>& gs) {
+  for (auto& g : gs) {
+    g.d_tasks = upload(h, g.tasks);
+    g.d_jobs = upload(h, g.jobs);
+    g.d_wus = upload(h, g.wus);
+  }
+}
+
+int chunks_for(size_t nitems, int64_t units_per_chunk) {
+  // aim at roughly 1024 workgroups for the whole launch
+  int64_t c = (int64_t)1024 / std::max<int64_t>(1, units_per_chunk);
+  c = std::max<int64_t>(1, std::min<int64_t>(c, (int64_t)nitems));
+  c = std::min<int64_t>(c, 32);
+  return (int)c;
+}
+
+// ------------------------------------------------------------------ plan construction
+void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
+  const Model& M = h->M;
+  const MatvecPlan& P = M.mv[n];
+  MVDev& D = h->mv[n];
+  const Node& nd = M.tree.nodes[n];
+  const int dm[3] = {nd.dims[0], nd.dims[1], nd.dims[2]};
+  std::copy(dm, dm + 3, D.dims);
+  const int64_t Msz = (int64_t)dm[0] * dm[1] * dm[2];
+  std::vector<int64_t> off;
+  int64_t total = 0;
+  build_comb(h, P.combines, h->d_mvcomb, D.comb, off, total);
+  comb_off_out = off;
+  int64_t part_used = 0;
+  // two-leg items and local operators, grouped by spectator
+  for (int sp = 0; sp < 3; sp++) {
+    std::vector<const Item2*> its;
+    for (const Item2& it : P.items)
+      if (it.spect == sp) its.push_back(&it);
+    if (its.empty()) continue;
+    int ma, mb, ns;
+    int64_t sl, row;
+    slice_geom(sp, dm, ma, mb, ns, sl, row);
+    const int64_t units = sw_mfma(ma, mb) ? (int64_t)ns * ((ma / 16 + 3) / 4)
+                                          : (int64_t)ns * ((ma * mb + 255) / 256);
+    const int nch = chunks_for(its.size(), units);
+    SWGroup& g = group_for(D.sw, ma, mb);
+    for (int c = 0; c < nch; c++) {
+      const size_t i0 = its.size() * c / nch, i1 = its.size() * (c + 1) / nch;
+      if (i1 == i0) continue;
+      SWTask t;
+      std::memset(&t, 0, sizeof(t));
+      t.x = sp == 2 ? (const void*)h->d_xt : nullptr;
+      t.y = h->d_part + part_used;
+      t.xs_slice = sl; t.xs_row = row; t.ys_slice = sl; t.ys_row = row;
+      t.ma = ma; t.mb = mb;
+      t.item0 = (int)g.items.size();
+      for (size_t i = i0; i < i1; i++) {
+        SWItem si;
+        si.A = block_ptr(h, its[i]->A, h->d_mvcomb, off);
+        si.B = block_ptr(h, its[i]->B, h->d_mvcomb, off);
+        si.coef = its[i]->coef;
+        g.items.push_back(si);
+      }
+      t.nitem = (int)(i1 - i0);
+      t.accumulate = 0;
+      add_sw_task(g, t, ns);
+      D.srcs.push_back({h->d_part + part_used, sp == 2 ? 1 : 0, 0});
+      part_used += Msz;
+      if (sp == 2) D.need_xt = true;
+    }
+  }
+  // three-leg chains
+  int64_t chain_used = 0;
+  std::vector<std::vector<std::pair<const double*, const double*>>> stageC(3);   // per o1 leg: (op, V)
+  for (const Chain& ch : P.chains) {
+    const int t2 = (int)ch.O2.size(), t1 = (int)ch.O1.size();
+    std::vector<double*> W(t2), Vv(t1);
+    for (int c = 0; c < t2; c++) {
+      W[c] = h->d_chain + chain_used;
+      chain_used += Msz;
+      MPGroup& g = mgroup_for(D.chainA, dm[ch.o2], mode_mfma_ok(dm[ch.o2], Msz));
+      MPTask t{W[c], dm[0], dm[1], dm[2], ch.o2, (int)g.jobs.size(), 1, 0, 0};
+      g.jobs.push_back({block_ptr(h, ch.O2[c], h->d_mvcomb, off), nullptr, 1.0});
+      add_mp_task(g, t);
+    }
+    for (int a = 0; a < t1; a++) {
+      MPGroup& g = mgroup_for(D.chainB, dm[ch.mid], mode_mfma_ok(dm[ch.mid], Msz));
+      int j0 = (int)g.jobs.size();
+      for (int c = 0; c < t2; c++) {
+        const BRef& b = ch.Mid[(size_t)a * t2 + c];
+        if (b.is_zero()) continue;
+        g.jobs.push_back({block_ptr(h, b, h->d_mvcomb, off), W[c], 1.0});
+      }
+      if ((int)g.jobs.size() == j0) { Vv[a] = nullptr; continue; }
+      Vv[a] = h->d_chain + chain_used;
+      chain_used += Msz;
+      MPTask t{Vv[a], dm[0], dm[1], dm[2], ch.mid, j0, (int)g.jobs.size() - j0, 0, 0};
+      add_mp_task(g, t);
+    }
+    for (int a = 0; a < t1; a++)
+      if (Vv[a]) stageC[ch.o1].push_back({block_ptr(h, ch.O1[a], h->d_mvcomb, off), Vv[a]});
+  }
+  for (int leg = 0; leg < 3; leg++) {
+    if (stageC[leg].empty()) continue;
+    double* out = h->d_chain + chain_used;
+    chain_used += Msz;
+    MPGroup& g = mgroup_for(D.chainC, dm[leg], mode_mfma_ok(dm[leg], Msz));
+    MPTask t{out, dm[0], dm[1], dm[2], leg, (int)g.jobs.size(), (int)stageC[leg].size(), 0, 0};
+    for (auto& pr : stageC[leg]) g.jobs.push_back({pr.first, pr.second, 1.0});
+    add_mp_task(g, t);
+    D.srcs.push_back({out, 0, 0});
+  }
+  if (part_used > h->part_cap || chain_used > h->chain_cap)
+    throw StatusFail{ATTN_ERR_STATE, "internal: scratch sizing"};
+  upload_comb(h, D.comb);
+  upload_sw(h, D.sw);
+  upload_mp(h, D.chainA);
+  upload_mp(h, D.chainB);
+  upload_mp(h, D.chainC);
+  D.d_srcs = upload(h, D.srcs);
+}
+
+int64_t env_chunk_outputs(attn_handle* h, int64_t Msz) {
+  const int64_t budget = (int64_t)2 << 30;   // bytes of Z scratch
+  return std::max<int64_t>(1, std::min<int64_t>(4096, budget / (Msz * 8)));
+}
+
+void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
+  if (P.node < 0) return;
+  const Model& M = h->M;
+  const Node& nd = M.tree.nodes[P.node];
+  // toward the parent the tensor is first transposed to [p][l][r] so that the
+  // (l, r) slices are contiguous; the contracted leg is then the first one
+  const bool tr_in = P.leg == 2;
+  const int dm[3] = {tr_in ? nd.dims[2] : nd.dims[0], tr_in ? nd.dims[0] : nd.dims[1],
+                     tr_in ? nd.dims[1] : nd.dims[2]};
+  const int64_t Msz = (int64_t)dm[0] * dm[1] * dm[2];
+  const int j = tr_in ? 0 : P.leg;
+  const int mj = dm[j];
+  D.transpose = tr_in;
+  std::copy(nd.dims, nd.dims + 3, D.dims);
+  D.present = true;
+  D.node = P.node; D.leg = P.leg; D.out_edge = P.out_edge; D.out_dir = P.out_dir;
+  std::vector<int64_t> off;
+  int64_t total = 0;
+  build_comb(h, P.combines, h->d_envcomb, D.comb, off, total);
+  upload_comb(h, D.comb);
+  double* T = tr_in ? h->d_xt : h->d_T + h->T_off[P.node];
+  double* base = h->store[P.out_dir][P.out_edge];
+  const int64_t per = env_chunk_outputs(h, Msz);
+  const int64_t F = Msz / mj;
+  const bool gmf = gram_mfma_ok(mj, Msz);
+  int64_t fchunk = F;
+  if (gmf) {
+    // enough gram workgroups: ~8 chunks of the free index per output at most
+    fchunk = std::max<int64_t>(64, ((F / 8) + 63) / 64 * 64);
+    while (F % fchunk) fchunk += 64;
+  }
+  const int nfc = (int)(F / fchunk);
+  int ma, mb, ns;
+  int64_t sl, row;
+  slice_geom(j, dm, ma, mb, ns, sl, row);
+  for (size_t o0 = 0; o0 < P.outs.size(); o0 += per) {
+    const size_t o1 = std::min(P.outs.size(), o0 + (size_t)per);
+    EnvChunk ch;
+    ch.gr.mj = mj;
+    ch.gr.mfma = gmf;
+    for (size_t o = o0; o < o1; o++) {
+      const EnvOut& out = P.outs[o];
+      double* blk = base + (int64_t)(out.slot + 1) * mj * mj;
+      if (out.items.empty()) {
+        ch.zero_blocks.push_back({blk, (int64_t)mj * mj});
+        continue;
+      }
+      double* Z = h->d_Z + (int64_t)(o - o0) * Msz;
+      SWGroup& g = group_for(ch.sw, ma, mb);
+      SWTask t;
+      std::memset(&t, 0, sizeof(t));
+      t.x = T; t.y = Z;
+      t.xs_slice = sl; t.xs_row = row; t.ys_slice = sl; t.ys_row = row;
+      t.ma = ma; t.mb = mb;
+      t.item0 = (int)g.items.size();
+      for (const Item2& it : out.items) {
+        SWItem si;
+        si.A = block_ptr(h, it.A, h->d_envcomb, off);
+        si.B = block_ptr(h, it.B, h->d_envcomb, off);
+        si.coef = it.coef;
+        g.items.push_back(si);
+      }
+      t.nitem = (int)out.items.size();
+      add_sw_task(g, t, ns);
+      double* part = h->d_grpart + (int64_t)(o - o0) * nfc * mj * mj;
+      for (int c = 0; c < nfc; c++) {
+        GRTask gt;
+        gt.X = T; gt.Z = Z; gt.partial = part + (int64_t)c * mj * mj;
+        gt.d0 = dm[0]; gt.d1 = dm[1]; gt.d2 = dm[2]; gt.j = j;
+        gt.f0 = (int)(c * fchunk); gt.f1 = (int)((c + 1) * fchunk);
+        ch.gr.tasks.push_back(gt);
+      }
+      GRReduce r;
+      r.partial = part; r.out = blk; r.m = mj; r.npart = nfc; r.coef = 1.0; r.accumulate = 0; r.pad = 0;
+      ch.gr.reds.push_back(r);
+    }
+    upload_sw(h, ch.sw);
+    ch.gr.d_tasks = upload(h, ch.gr.tasks);
+    ch.gr.d_reds = upload(h, ch.gr.reds);
+    D.chunks.push_back(std::move(ch));
+  }
+}
+
+// ------------------------------------------------------------------ execution helpers
+void run_comb(CBPlan& P, hipStream_t s) {
+  if (!P.tasks.empty()) HIPCHK(launch_combine(P.d_tasks, P.d_terms, (int)P.tasks.size(), P.maxn, s));
+}
+
+void run_sw(std::vector<SWGroup>& gs, int dtype, const void* xbase, hipStream_t s) {
+  for (auto& g : gs)
+    HIPCHK(launch_sandwich(dtype, g.ma, g.mb, g.d_tasks, g.d_items, g.d_wus, (int)g.wus.size(), xbase, s));
+}
+
+void run_mp(std::vector<MPGroup>& gs, int dtype, const void* xbase, hipStream_t s) {
+  for (auto& g : gs)
+    HIPCHK(launch_mode(dtype, g.mj, g.mfma, g.d_tasks, g.d_jobs, g.d_wus, (int)g.wus.size(), xbase, s));
+}
+
+// y <- H_eff(n) x (FP64), combines must be current
+void matvec_f64(attn_handle* h, int n, const double* x, double* y, hipStream_t s) {
+  MVDev& D = h->mv[n];
+  if (D.need_xt) HIPCHK(launch_transpose_plr(0, x, h->d_xt, D.dims[0], D.dims[1], D.dims[2], s));
+  run_mp(D.chainA, 0, x, s);
+  run_mp(D.chainB, 0, x, s);
+  run_mp(D.chainC, 0, x, s);
+  run_sw(D.sw, 0, x, s);
+  if (D.srcs.empty()) {
+    HIPCHK(hipMemsetAsync(y, 0, (size_t)D.dims[0] * D.dims[1] * D.dims[2] * sizeof(double), s));
+  } else {
+    HIPCHK(launch_reduce_out(0, D.d_srcs, (int)D.srcs.size(), y, 0, D.dims[0], D.dims[1], D.dims[2], s));
+  }
+  h->n_matvec++;
+}
+
+int leg_toward(const Tree& tr, int a, int b) {
+  if (tr.nodes[a].parent == b) return 2;
+  if (tr.nodes[a].child[0] == b) return 0;
+  if (tr.nodes[a].child[1] == b) return 1;
+  return -1;
+}
+
+// Mark stale every store whose source side contains node n.
+void invalidate_from(attn_handle* h, int n) {
+  const Tree& tr = h->M.tree;
+  const Node& nd = tr.nodes[n];
+  for (int c = 0; c < (int)tr.nodes.size(); c++) {
+    if (c == tr.root) continue;
+    const Node& cn = tr.nodes[c];
+    const int e = tr.edge_of_node(c);
+    const bool below = nd.lo >= cn.lo && nd.hi <= cn.hi;   // n inside subtree(c)
+    if (below) h->valid[0][e] = 0;
+    else h->valid[1][e] = 0;
+  }
+}
+
+bool incoming_valid(attn_handle* h, int n) {
+  const Tree& tr = h->M.tree;
+  for (int sd = 0; sd < 2; sd++) {
+    const int e = tr.edge_of_child(n, sd);
+    if (!tr.edge_is_site(e) && !h->valid[0][e]) return false;
+  }
+  if (n != tr.root && !h->valid[1][tr.edge_of_node(n)]) return false;
+  return true;
+}
+
+void run_env(attn_handle* h, EnvDev& D, hipStream_t s) {
+  run_comb(D.comb, s);
+  if (D.transpose)
+    HIPCHK(launch_transpose_plr(0, h->d_T + h->T_off[D.node], h->d_xt, D.dims[0], D.dims[1], D.dims[2], s));
+  for (auto& ch : D.chunks) {
+    for (auto& zb : ch.zero_blocks) HIPCHK(hipMemsetAsync(zb.first, 0, zb.second * sizeof(double), s));
+    run_sw(ch.sw, 0, nullptr, s);
+    HIPCHK(launch_gram(ch.gr.mj, ch.gr.mfma, ch.gr.d_tasks, (int)ch.gr.tasks.size(), s));
+    HIPCHK(launch_gram_reduce(ch.gr.d_reds, (int)ch.gr.reds.size(), ch.gr.mj, s));
+  }
+  h->n_env++;
+}
+
+void build_qr_dev(attn_handle* h, int n, int leg, QRDev& Q) {
+  const Node& nd = h->M.tree.nodes[n];
+  const int dm[3] = {nd.dims[0], nd.dims[1], nd.dims[2]};
+  const int mj = dm[leg];
+  const int64_t Msz = (int64_t)dm[0] * dm[1] * dm[2];
+  const int64_t rows = Msz / mj;
+  const int64_t nn = (int64_t)h->mmax * h->mmax;
+  double* T = h->d_T + h->T_off[n];
+  double* G = h->d_qrmat;
+  double* Rinv = G + 4 * nn;
+  Q.present = true;
+  Q.mj = mj; Q.rows = rows; Q.Msz = Msz;
+  Q.gmf = gram_mfma_ok(mj, Msz);
+  int64_t fchunk = rows;
+  if (Q.gmf) {
+    fchunk = std::max<int64_t>(64, ((rows / 32) + 63) / 64 * 64);
+    while (rows % fchunk) fchunk += 64;
+  }
+  Q.nfc = (int)(rows / fchunk);
+  GRReduce gr;
+  gr.partial = h->d_grpart; gr.out = G; gr.m = mj; gr.npart = Q.nfc; gr.coef = 1.0; gr.accumulate = 0; gr.pad = 0;
+  Q.d_gr = upload(h, std::vector<GRReduce>{gr});
+  Q.h_gr = {gr};
+  Q.mmf = mode_mfma_ok(mj, Msz);
+  std::vector<int2> wus;
+  if (Q.mmf) for (int64_t f = 0; f < rows / 64; f++) wus.push_back(make_int2(0, (int)f));
+  else for (int64_t e = 0; e < Msz; e += 256) wus.push_back(make_int2(0, (int)e));
+  Q.nwus = (int)wus.size();
+  Q.d_wus = upload(h, wus);
+  for (int pass = 0; pass < 3; pass++) {
+    double* src = (pass % 2 == 0) ? T : h->d_tmp;
+    double* dst = (pass % 2 == 0) ? h->d_tmp : T;
+    std::vector<GRTask> gt(Q.nfc);
+    for (int c = 0; c < Q.nfc; c++) {
+      gt[c].X = src; gt[c].Z = src; gt[c].partial = h->d_grpart + (int64_t)c * mj * mj;
+      gt[c].d0 = dm[0]; gt[c].d1 = dm[1]; gt[c].d2 = dm[2]; gt[c].j = leg;
+      gt[c].f0 = (int)(c * fchunk); gt[c].f1 = (int)((c + 1) * fchunk);
+    }
+    Q.d_gt[pass] = upload(h, gt);
+    Q.h_gt[pass] = gt;
+    MPTask mt{dst, dm[0], dm[1], dm[2], leg, 0, 1, 0, 0};
+    Q.d_mt[pass] = upload(h, std::vector<MPTask>{mt});
+    MPJob mjb{Rinv, src, 1.0};
+    Q.d_mj[pass] = upload(h, std::vector<MPJob>{mjb});
+    Q.h_mp[pass].mj = mj;
+    Q.h_mp[pass].mfma = Q.mmf;
+    Q.h_mp[pass].tasks = {mt};
+    Q.h_mp[pass].jobs = {mjb};
+    Q.h_mp[pass].wus = wus;
+  }
+}
+
+void build_ab_dev(attn_handle* h, int q, int leg, ABDev& A) {
+  const Node& nd = h->M.tree.nodes[q];
+  const int dm[3] = {nd.dims[0], nd.dims[1], nd.dims[2]};
+  const int mj = dm[leg];
+  const int64_t Msz = (int64_t)dm[0] * dm[1] * dm[2];
+  double* T = h->d_T + h->T_off[q];
+  A.present = true;
+  A.mj = mj; A.Msz = Msz;
+  A.mmf = mode_mfma_ok(mj, Msz);
+  std::vector<int2> wus;
+  if (A.mmf) for (int64_t f = 0; f < Msz / mj / 64; f++) wus.push_back(make_int2(0, (int)f));
+  else for (int64_t e = 0; e < Msz; e += 256) wus.push_back(make_int2(0, (int)e));
+  A.nwus = (int)wus.size();
+  A.d_wus = upload(h, wus);
+  MPTask mt{h->d_tmp2, dm[0], dm[1], dm[2], leg, 0, 1, 0, 0};
+  A.d_mt = upload(h, std::vector<MPTask>{mt});
+  MPJob mjb{h->d_qrR, T, 1.0};
+  A.d_mj = upload(h, std::vector<MPJob>{mjb});
+  A.h_mp.mj = mj;
+  A.h_mp.mfma = A.mmf;
+  A.h_mp.tasks = {mt};
+  A.h_mp.jobs = {mjb};
+  A.h_mp.wus = wus;
+}
+
+// QR of T_n with leg `leg` as the column index (shifted CholeskyQR followed by
+// two CholeskyQR passes): T_n <- Q in place, R (column-major) into d_qrR.
+void qr_node(attn_handle* h, int n, int leg, hipStream_t s) {
+  QRDev& Q = h->qr[leg][n];
+  if (!Q.present) throw StatusFail{ATTN_ERR_STATE, "internal: no QR plan for this leg"};
+  const int mj = Q.mj;
+  const int64_t nn = (int64_t)h->mmax * h->mmax;
+  double* G = h->d_qrmat;
+  double* R[3] = {G + nn, G + 2 * nn, G + 3 * nn};
+  double* Rinv = G + 4 * nn;
+  double* Rt = G + 5 * nn;
+  double* T = h->d_T + h->T_off[n];
+  for (int pass = 0; pass < 3; pass++) {
+    HIPCHK(launch_gram(mj, Q.gmf, Q.d_gt[pass], Q.nfc, s));
+    HIPCHK(launch_gram_reduce(Q.d_gr, 1, mj, s));
+    HIPCHK(launch_chol_inv(G, mj, R[pass], Rinv, pass == 0 ? 1 : 0, Q.rows, h->d_st, s));
+    HIPCHK(launch_mode(0, mj, Q.mmf, Q.d_mt[pass], Q.d_mj[pass], Q.d_wus, Q.nwus, nullptr, s));
+  }
+  // passes write tmp, T, tmp: the result is in tmp
+  HIPCHK(hipMemcpyAsync(T, h->d_tmp, Q.Msz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_small_matmul(R[1], R[0], Rt, mj, s));
+  HIPCHK(launch_small_matmul(R[2], Rt, h->d_qrR, mj, s));
+  h->n_qr++;
+}
+
+// T_q <- R x_leg T_q with R in d_qrR
+void absorb(attn_handle* h, int q, int leg, hipStream_t s) {
+  ABDev& A = h->ab[leg][q];
+  if (!A.present) throw StatusFail{ATTN_ERR_STATE, "internal: no absorb plan for this leg"};
+  HIPCHK(launch_mode(0, A.mj, A.mmf, A.d_mt, A.d_mj, A.d_wus, A.nwus, nullptr, s));
+  HIPCHK(hipMemcpyAsync(h->d_T + h->T_off[q], h->d_tmp2, A.Msz * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+attn_status guard(attn_handle* h, const std::function<attn_status()>& f) {
+  if (!h) return ATTN_ERR_ARG;
+  if (h->dead) { h->err = "handle unusable after an earlier HIP or numeric error"; return ATTN_ERR_STATE; }
+  try {
+    h->err.clear();
+    return f();
+  } catch (const HipFail& e) {
+    h->err = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+    h->dead = true;
+    return ATTN_ERR_HIP;
+  } catch (const StatusFail& e) {
+    h->err = e.msg;
+    if (e.st == ATTN_ERR_NUMERIC) h->dead = true;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return ATTN_ERR_OOM;
+  }
+}
+
+void check_state(attn_handle* h, hipStream_t s, const char* where) {
+  KrylovState st;
+  HIPCHK(hipMemcpyAsync(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st.status != 0)
+    throw StatusFail{ATTN_ERR_NUMERIC, std::string(where) + (st.status == 2 ? ": QR factorisation broke down" : ": non-finite value")};
+}
+
+void reset_state(attn_handle* h, int kmax, hipStream_t s) {
+  KrylovState st;
+  std::memset(&st, 0, sizeof(st));
+  st.kmax = kmax;
+  st.keff = 1;
+  HIPCHK(hipMemcpyAsync(h->d_st, &st, sizeof(st), hipMemcpyHostToDevice, s));
+}
+
+attn_status need_device(attn_handle* h) {
+  if (h->host_only) { h->err = "handle was built with ATTN_HOST_ONLY"; return ATTN_ERR_STATE; }
+  if (h->dryrun) { h->err = "handle was built with ATTN_DRYRUN"; return ATTN_ERR_STATE; }
+  return ATTN_OK;
+}
+
+// ------------------------------------------------------------------ eigensolver
+double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStream_t s) {
+  MVDev& D = h->mv[n];
+  const int64_t Msz = (int64_t)D.dims[0] * D.dims[1] * D.dims[2];
+  const int k = (int)std::min<int64_t>(std::min(kreq, h->kcap - 1), Msz);
+  double* T = h->d_T + h->T_off[n];
+  double* V = h->d_V;
+  double* w = h->d_w;
+  reset_state(h, k, s);
+  run_comb(D.comb, s);
+  HIPCHK(launch_norm2(T, Msz, h->d_red, s));
+  HIPCHK(launch_dot_final(h->d_red, 1, nullptr, 4, h->d_st, 0, s));
+  HIPCHK(launch_scale_into(T, V, Msz, h->d_st, 1, 0, s));
+  for (int j = 0; j < k; j++) {
+    double* vj = V + (int64_t)j * Msz;
+    if (precision == ATTN_F64) {
+      matvec_f64(h, n, vj, w, s);
+    } else {
+      throw StatusFail{ATTN_ERR_UNSUPPORTED, "precision form not available for this eigensolve"};
+    }
+    HIPCHK(launch_multidot(vj, 1, w, Msz, h->d_red, h->d_st, s));
+    HIPCHK(launch_dot_final(h->d_red, 1, nullptr, 1, h->d_st, j, s));
+    if (j == k - 1) break;
+    HIPCHK(launch_lanczos_update(w, V, Msz, h->d_st, j, h->d_red, s));
+    HIPCHK(launch_dot_final(h->d_red, j + 1, nullptr, 2, h->d_st, j, s));
+    HIPCHK(launch_axpy_dots(w, V, j + 1, Msz, h->d_st, h->d_red, 0, s));
+    HIPCHK(launch_dot_final(h->d_red, j + 1, nullptr, 2, h->d_st, j, s));
+    HIPCHK(launch_axpy_dots(w, V, j + 1, Msz, h->d_st, h->d_red, 1, s));
+    HIPCHK(launch_dot_final(h->d_red, 1, nullptr, 3, h->d_st, j, s));
+    HIPCHK(launch_scale_into(w, V + (int64_t)(j + 1) * Msz, Msz, h->d_st, 0, j, s));
+  }
+  HIPCHK(launch_tridiag(h->d_st, s));
+  HIPCHK(launch_ritz(V, Msz, T, h->d_st, h->d_red, s));
+  HIPCHK(launch_dot_final(h->d_red, 1, nullptr, 4, h->d_st, 0, s));
+  HIPCHK(launch_scale_into(T, T, Msz, h->d_st, 1, 0, s));
+  KrylovState st;
+  HIPCHK(hipMemcpyAsync(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st.status != 0 || !std::isfinite(st.scal[0])) throw StatusFail{ATTN_ERR_NUMERIC, "non-finite value in the eigensolver"};
+  if (nmv) *nmv = k;
+  return st.scal[0];
+}
+
+}  // namespace
+
+// ====================================================================== C interface
+extern "C" {
+
+attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
+  if (!out) { g_build_error = "out is NULL"; return ATTN_ERR_ARG; }
+  *out = nullptr;
+  attn_handle* h = new (std::nothrow) attn_handle();
+  if (!h) { g_build_error = "host allocation failed"; return ATTN_ERR_OOM; }
+  std::string err;
+  attn_status st;
+  try {
+    st = build_model(p, h->M, err);
+  } catch (const std::bad_alloc&) {
+    st = ATTN_ERR_OOM;
+    err = "host allocation failed";
+  }
+  if (st != ATTN_OK) {
+    g_build_error = err;
+    delete h;
+    return st;
+  }
+  h->host_only = (p->flags & ATTN_HOST_ONLY) != 0;
+  h->dryrun = (p->flags & ATTN_DRYRUN) != 0;
+  h->device = p->device;
+  const Tree& tr = h->M.tree;
+  const int nn = (int)tr.nodes.size();
+  h->iso.assign(nn, 2);
+  h->iso[tr.root] = -1;
+  h->center = tr.root;
+  h->valid[0].assign(tr.n_edges(), 0);
+  h->valid[1].assign(tr.n_edges(), 0);
+  for (int s = 0; s < tr.N; s++) h->valid[0][s] = 1;
+  if (h->host_only) {
+    *out = h;
+    return ATTN_OK;
+  }
+  try {
+    if (!h->dryrun) HIPCHK(hipSetDevice(h->device));
+    // tensors
+    int64_t tot = 0;
+    for (int n = 0; n < nn; n++) {
+      const Node& nd = tr.nodes[n];
+      const int64_t Msz = (int64_t)nd.dims[0] * nd.dims[1] * nd.dims[2];
+      h->T_off.push_back(tot);
+      h->T_len.push_back(Msz);
+      tot += Msz;
+      h->Mmax = std::max(h->Mmax, Msz);
+    }
+    h->d_T = (double*)dev_alloc(h, tot * sizeof(double));
+    // effective-operator stores
+    h->store[0].assign(tr.n_edges(), nullptr);
+    h->store[1].assign(tr.n_edges(), nullptr);
+    for (int e = 0; e < tr.n_edges(); e++) {
+      const int dim = tr.edge_dim(e);
+      const int64_t sz = (int64_t)(1 + h->M.n_slots[e]) * dim * dim;
+      if (tr.edge_is_site(e)) {
+        h->store[0][e] = upload(h, h->M.site_blocks[e]);
+        continue;
+      }
+      for (int dir = 0; dir < 2; dir++) {
+        void* q = dev_alloc(h, sz * sizeof(double));
+        if (!h->dryrun) HIPCHK(hipMemset(q, 0, sz * sizeof(double)));
+        h->store[dir][e] = (double*)q;
+      }
+    }
+    // scratch sizing
+    int64_t part_need = 0, chain_need = 0, mvcomb_need = 0, envcomb_need = 0, z_need = 0, grp_need = 0;
+    for (int n = 0; n < nn; n++) {
+      const Node& nd = tr.nodes[n];
+      const int dm[3] = {nd.dims[0], nd.dims[1], nd.dims[2]};
+      const int64_t Msz = (int64_t)dm[0] * dm[1] * dm[2];
+      const MatvecPlan& P = h->M.mv[n];
+      int nparts = 0;
+      for (int sp = 0; sp < 3; sp++) {
+        size_t cnt = 0;
+        for (auto& it : P.items) cnt += it.spect == sp;
+        if (!cnt) continue;
+        int ma, mb, ns;
+        int64_t sl, row;
+        slice_geom(sp, dm, ma, mb, ns, sl, row);
+        const int64_t units = sw_mfma(ma, mb) ? (int64_t)ns * ((ma / 16 + 3) / 4) : (int64_t)ns * ((ma * mb + 255) / 256);
+        nparts += chunks_for(cnt, units);
+      }
+      part_need = std::max(part_need, nparts * Msz);
+      int64_t cn = 0;
+      for (auto& ch : P.chains) cn += (int64_t)(ch.O1.size() + ch.O2.size());
+      cn += 3;
+      chain_need = std::max(chain_need, cn * Msz);
+      int64_t cb = 0;
+      for (auto& c : P.combines) cb += (int64_t)c.dim * c.dim;
+      mvcomb_need = std::max(mvcomb_need, cb);
+      const EnvPlan* eps[3] = {&h->M.env_up[n], &h->M.env_down[0][n], &h->M.env_down[1][n]};
+      for (const EnvPlan* ep : eps) {
+        if (ep->node < 0) continue;
+        int64_t c2 = 0;
+        for (auto& c : ep->combines) c2 += (int64_t)c.dim * c.dim;
+        envcomb_need = std::max(envcomb_need, c2);
+        const int64_t per = env_chunk_outputs(h, Msz);
+        const int64_t nout = std::min<int64_t>(per, (int64_t)ep->outs.size());
+        z_need = std::max(z_need, nout * Msz);
+        const int mj = dm[ep->leg];
+        grp_need = std::max(grp_need, nout * 8 * (int64_t)mj * mj + (int64_t)mj * mj);
+      }
+      for (int leg = 0; leg < 3; leg++) grp_need = std::max(grp_need, (int64_t)64 * dm[leg] * dm[leg]);
+    }
+    auto alloc = [&](int64_t n_doubles) -> double* {
+      return (double*)dev_alloc(h, std::max<int64_t>(n_doubles, 1) * sizeof(double));
+    };
+    h->d_V = alloc((int64_t)h->kcap * h->Mmax);
+    h->d_w = alloc(h->Mmax);
+    h->d_xt = alloc(h->Mmax);
+    h->d_tmp = alloc(h->Mmax);
+    h->d_tmp2 = alloc(h->Mmax);
+    h->d_x32 = (float*)alloc(h->Mmax);
+    h->d_y32 = (float*)alloc(h->Mmax);
+    h->part_cap = std::max<int64_t>(part_need, 1);
+    h->d_part = alloc(h->part_cap);
+    h->chain_cap = std::max<int64_t>(chain_need, 1);
+    h->d_chain = alloc(h->chain_cap);
+    h->d_mvcomb = alloc(mvcomb_need);
+    h->d_envcomb = alloc(envcomb_need);
+    h->d_Z = alloc(z_need);
+    h->d_grpart = alloc(grp_need);
+    h->d_red = alloc((int64_t)128 * kRedBlocks);
+    for (int n = 0; n < nn; n++)
+      for (int l = 0; l < 3; l++) h->mmax = std::max(h->mmax, tr.nodes[n].dims[l]);
+    h->d_qrmat = alloc(6 * (int64_t)h->mmax * h->mmax);
+    h->d_qrR = alloc((int64_t)h->mmax * h->mmax);
+    h->d_st = (KrylovState*)dev_alloc(h, sizeof(KrylovState));
+    // device plans
+    h->mv.assign(nn, MVDev());
+    h->env_up.assign(nn, EnvDev());
+    h->env_down[0].assign(nn, EnvDev());
+    h->env_down[1].assign(nn, EnvDev());
+    for (int l = 0; l < 3; l++) {
+      h->qr[l].assign(nn, QRDev());
+      h->ab[l].assign(nn, ABDev());
+    }
+    for (int n = 0; n < nn; n++) {
+      std::vector<int64_t> off;
+      build_mv_dev(h, n, off);
+      const Node& nd = tr.nodes[n];
+      if (n != tr.root) {
+        build_qr_dev(h, n, 2, h->qr[2][n]);
+        build_ab_dev(h, n, 2, h->ab[2][n]);   // R from a parent moving down
+      }
+      for (int sd = 0; sd < 2; sd++)
+        if (nd.child[sd] >= 0) {
+          build_qr_dev(h, n, sd, h->qr[sd][n]);
+          build_ab_dev(h, n, sd, h->ab[sd][n]);   // R from a child moving up
+        }
+      if (n != tr.root) build_env_dev(h, h->M.env_up[n], h->env_up[n]);
+      for (int sd = 0; sd < 2; sd++) build_env_dev(h, h->M.env_down[sd][n], h->env_down[sd][n]);
+    }
+    if (!h->dryrun) HIPCHK(hipDeviceSynchronize());
+  } catch (const HipFail& e) {
+    g_build_error = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
+    attn_destroy(h);
+    return e.e == hipErrorOutOfMemory ? ATTN_ERR_OOM : ATTN_ERR_HIP;
+  } catch (const StatusFail& e) {
+    g_build_error = e.msg;
+    attn_destroy(h);
+    return e.st;
+  }
+  *out = h;
+  return ATTN_OK;
+}
+
+attn_status attn_destroy(attn_handle* h) {
+  if (!h) return ATTN_OK;
+  if (!h->host_only && !h->dryrun) {
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    for (void* p : h->owned) (void)hipFree(p);
+  }
+  delete h;
+  return ATTN_OK;
+}
+
+const char* attn_last_error(const attn_handle* h) {
+  if (!h) return g_build_error.c_str();
+  return h->err.c_str();
+}
+
+attn_status attn_node_info(const attn_handle* h, int32_t node, int32_t dims[3], int32_t* n_cross,
+                           double* flops) {
+  if (!h) return ATTN_ERR_ARG;
+  const Tree& tr = h->M.tree;
+  if (node < 0 || node >= (int)tr.nodes.size()) return ATTN_ERR_ARG;
+  if (dims) for (int i = 0; i < 3; i++) dims[i] = tr.nodes[node].dims[i];
+  if (n_cross) *n_cross = h->M.mv[node].n_cross;
+  if (flops) *flops = (double)h->M.mv[node].flops;
+  return ATTN_OK;
+}
+
+attn_status attn_tree_info(const attn_handle* h, int32_t* n_nodes, int32_t* root, int64_t* env_bytes) {
+  if (!h) return ATTN_ERR_ARG;
+  const Tree& tr = h->M.tree;
+  if (n_nodes) *n_nodes = (int)tr.nodes.size();
+  if (root) *root = tr.root;
+  if (env_bytes) {
+    int64_t b = 0;
+    for (int e = 0; e < tr.n_edges(); e++) {
+      const int dim = tr.edge_dim(e);
+      b += (int64_t)(1 + h->M.n_slots[e]) * dim * dim * 8 * (tr.edge_is_site(e) ? 1 : 2);
+    }
+    *env_bytes = b;
+  }
+  return ATTN_OK;
+}
+
+attn_status attn_get_center(const attn_handle* h, int32_t* node) {
+  if (!h || !node) return ATTN_ERR_ARG;
+  *node = h->center;
+  return ATTN_OK;
+}
+
+attn_status attn_counters(const attn_handle* h, int64_t* n_matvec, int64_t* n_env, int64_t* n_qr) {
+  if (!h) return ATTN_ERR_ARG;
+  if (n_matvec) *n_matvec = h->n_matvec;
+  if (n_env) *n_env = h->n_env;
+  if (n_qr) *n_qr = h->n_qr;
+  return ATTN_OK;
+}
+
+attn_status attn_set_tensor(attn_handle* h, int32_t node, const double* host, int64_t len) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (node < 0 || node >= (int)h->M.tree.nodes.size() || !host) { h->err = "bad node or NULL"; return ATTN_ERR_ARG; }
+    if (len != h->T_len[node]) { h->err = "length does not match the tensor size"; return ATTN_ERR_SHAPE; }
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipMemcpy(h->d_T + h->T_off[node], host, len * sizeof(double), hipMemcpyHostToDevice));
+    invalidate_from(h, node);
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_get_tensor(attn_handle* h, int32_t node, double* host, int64_t len) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (node < 0 || node >= (int)h->M.tree.nodes.size() || !host) { h->err = "bad node or NULL"; return ATTN_ERR_ARG; }
+    if (len != h->T_len[node]) { h->err = "length does not match the tensor size"; return ATTN_ERR_SHAPE; }
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(host, h->d_T + h->T_off[node], len * sizeof(double), hipMemcpyDeviceToHost));
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_update_env(attn_handle* h, int32_t node, int32_t leg, void* stream) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    const Tree& tr = h->M.tree;
+    if (node < 0 || node >= (int)tr.nodes.size() || leg < 0 || leg > 2) { h->err = "bad node or leg"; return ATTN_ERR_ARG; }
+    if (leg == 2 && node == tr.root) { h->err = "the root has no parent link"; return ATTN_ERR_ARG; }
+    if (leg < 2 && tr.nodes[node].child[leg] < 0) { h->err = "leg leads to a site"; return ATTN_ERR_ARG; }
+    if (h->iso[node] != leg) { h->err = "node is not isometric toward the leg"; return ATTN_ERR_STATE; }
+    // inputs: the two other incoming stores
+    for (int l2 = 0; l2 < 3; l2++) {
+      if (l2 == leg) continue;
+      if (l2 == 2) {
+        if (node != tr.root && !h->valid[1][tr.edge_of_node(node)]) { h->err = "stale effective operator (parent link)"; return ATTN_ERR_STATE; }
+      } else {
+        const int e = tr.edge_of_child(node, l2);
+        if (!tr.edge_is_site(e) && !h->valid[0][e]) { h->err = "stale effective operator (child link)"; return ATTN_ERR_STATE; }
+      }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->device));
+    EnvDev& D = leg == 2 ? h->env_up[node] : h->env_down[leg][node];
+    run_env(h, D, s);
+    const int e = leg == 2 ? tr.edge_of_node(node) : tr.edge_of_child(node, leg);
+    h->valid[leg == 2 ? 0 : 1][e] = 1;
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_heff_apply(attn_handle* h, int32_t node, int32_t dtype, const void* x, void* y,
+                            void* stream) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (node < 0 || node >= (int)h->M.tree.nodes.size() || !x || !y) { h->err = "bad node or NULL pointer"; return ATTN_ERR_ARG; }
+    if (node != h->center) { h->err = "node is not the isometry centre"; return ATTN_ERR_STATE; }
+    if (!incoming_valid(h, node)) { h->err = "stale effective operators at the node"; return ATTN_ERR_STATE; }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->device));
+    MVDev& D = h->mv[node];
+    if (dtype == ATTN_F64) {
+      run_comb(D.comb, s);
+      matvec_f64(h, node, (const double*)x, (double*)y, s);
+      return ATTN_OK;
+    }
+    h->err = "dtype not available";
+    return ATTN_ERR_UNSUPPORTED;
+  });
+}
+
+attn_status attn_isometrize(attn_handle* h, int32_t from, int32_t to, void* stream) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    const Tree& tr = h->M.tree;
+    if (from < 0 || to < 0 || from >= (int)tr.nodes.size() || to >= (int)tr.nodes.size()) { h->err = "bad node"; return ATTN_ERR_ARG; }
+    const int leg = leg_toward(tr, from, to);
+    if (leg < 0) { h->err = "nodes are not adjacent"; return ATTN_ERR_ARG; }
+    if (from != h->center) { h->err = "from is not the isometry centre"; return ATTN_ERR_STATE; }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->device));
+    qr_node(h, from, leg, s);
+    absorb(h, to, leg_toward(tr, to, from), s);
+    h->iso[from] = leg;
+    h->iso[to] = -1;
+    h->center = to;
+    invalidate_from(h, from);
+    invalidate_from(h, to);
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_eigsolve_node(attn_handle* h, int32_t node, const attn_solver_opts* opts,
+                               double* theta, int32_t* n_matvec, void* stream) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (node < 0 || node >= (int)h->M.tree.nodes.size()) { h->err = "bad node"; return ATTN_ERR_ARG; }
+    if (node != h->center) { h->err = "node is not the isometry centre"; return ATTN_ERR_STATE; }
+    if (!incoming_valid(h, node)) { h->err = "stale effective operators at the node"; return ATTN_ERR_STATE; }
+    attn_solver_opts o;
+    if (opts) o = *opts;
+    else { std::memset(&o, 0, sizeof(o)); o.krylov_k = 20; }
+    if (o.krylov_k < 1) { h->err = "krylov_k must be >= 1"; return ATTN_ERR_ARG; }
+    if (o.solver != ATTN_SOLVER_LANCZOS) { h->err = "solver not available"; return ATTN_ERR_UNSUPPORTED; }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->device));
+    int nmv = 0;
+    const double th = lanczos(h, node, o.krylov_k, o.precision, &nmv, s);
+    invalidate_from(h, node);
+    if (theta) *theta = th;
+    if (n_matvec) *n_matvec = nmv;
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_init_state(attn_handle* h, const double* raw, int64_t len, void* stream) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    const Tree& tr = h->M.tree;
+    int64_t tot = 0;
+    for (int64_t l : h->T_len) tot += l;
+    if (!raw) { h->err = "raw is NULL"; return ATTN_ERR_ARG; }
+    if (len != tot) { h->err = "raw length does not match the tree"; return ATTN_ERR_SHAPE; }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipMemcpyAsync(h->d_T, raw, tot * sizeof(double), hipMemcpyHostToDevice, s));
+    reset_state(h, 0, s);
+    const int nn = (int)tr.nodes.size();
+    for (int n = 0; n < nn; n++) {
+      if (n == tr.root) continue;
+      qr_node(h, n, 2, s);   // Q replaces the block, R is discarded
+    }
+    double* T = h->d_T + h->T_off[tr.root];
+    HIPCHK(launch_normalize(T, h->T_len[tr.root], h->d_red, h->d_st, s));
+    for (int n = 0; n < nn; n++) h->iso[n] = 2;
+    h->iso[tr.root] = -1;
+    h->center = tr.root;
+    for (int e = tr.N; e < tr.n_edges(); e++) { h->valid[0][e] = 0; h->valid[1][e] = 0; }
+    for (int n = 0; n < nn; n++) {
+      if (n == tr.root) continue;
+      run_env(h, h->env_up[n], s);
+      h->valid[0][tr.edge_of_node(n)] = 1;
+    }
+    check_state(h, s, "attn_init_state");
+    h->state_ready = true;
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* opts,
+                       double* energies, double* seconds) {
+  if (!h) return ATTN_ERR_ARG;
+  if (n_sweeps < 0) { h->err = "n_sweeps < 0"; return ATTN_ERR_ARG; }
+  const Tree& tr = h->M.tree;
+  attn_solver_opts so;
+  if (opts) so = opts->solver;
+  else { std::memset(&so, 0, sizeof(so)); so.krylov_k = 20; }
+  for (int sw = 0; sw < n_sweeps; sw++) {
+    auto t0 = std::chrono::steady_clock::now();
+    double th = 0;
+    for (int n = 0; n < (int)tr.nodes.size(); n++) {
+      // centre path: up to the lowest common ancestor, then down
+      std::vector<int> up, down;
+      int a = h->center, b = n;
+      auto depth = [&](int x) { int dd = 0; while (tr.nodes[x].parent >= 0) { x = tr.nodes[x].parent; dd++; } return dd; };
+      int da = depth(a), db = depth(b);
+      std::vector<int> pa{a}, pb{b};
+      while (da > db) { a = tr.nodes[a].parent; pa.push_back(a); da--; }
+      while (db > da) { b = tr.nodes[b].parent; pb.push_back(b); db--; }
+      while (a != b) { a = tr.nodes[a].parent; pa.push_back(a); b = tr.nodes[b].parent; pb.push_back(b); }
+      pb.pop_back();
+      std::vector<int> path = pa;
+      for (int i = (int)pb.size() - 1; i >= 0; i--) path.push_back(pb[i]);
+      for (size_t i = 0; i + 1 < path.size(); i++) {
+        attn_status st = attn_isometrize(h, path[i], path[i + 1], nullptr);
+        if (st) return st;
+        st = attn_update_env(h, path[i], leg_toward(tr, path[i], path[i + 1]), nullptr);
+        if (st) return st;
+      }
+      attn_status st = attn_eigsolve_node(h, n, &so, &th, nullptr, nullptr);
+      if (st) return st;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) { h->err = "device synchronisation failed"; return ATTN_ERR_HIP; }
+    auto t1 = std::chrono::steady_clock::now();
+    if (energies) energies[sw] = th;
+    if (seconds) seconds[sw] = std::chrono::duration<double>(t1 - t0).count();
+  }
+  return ATTN_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ work-list validation
+// Checks, on the host, that every work unit of every device plan reads and
+// writes only inside the buffers it was built for.
+namespace {
+struct Checker {
+  const attn_handle* h;
+  std::string err;
+  bool ok = true;
+  void fail(const std::string& m) { if (ok) err = m; ok = false; }
+  // [p, p + bytes) inside one allocation
+  void span(const void* p, int64_t bytes, const char* what) {
+    if (!ok) return;
+    if (!p) { fail(std::string(what) + ": null pointer"); return; }
+    uintptr_t a = (uintptr_t)p;
+    for (auto& al : h->allocs)
+      if (a >= al.first && a + (uint64_t)bytes <= al.first + al.second) return;
+    fail(std::string(what) + ": out of bounds");
+  }
+  void sw(const SWGroup& g, int64_t xbase_len, int esz) {
+    for (const int4& wu : g.wus) {
+      if (wu.x < 0 || wu.x >= (int)g.tasks.size()) { fail("sandwich: task index"); return; }
+      const SWTask& t = g.tasks[wu.x];
+      if (t.ma != g.ma || t.mb != g.mb) { fail("sandwich: group dims"); return; }
+      const bool mf = sw_mfma(t.ma, t.mb);
+      int64_t rows_hi;
+      if (mf) {
+        if (wu.z % 4 || wu.z * 16 >= t.ma) { fail("sandwich: strip"); return; }
+        rows_hi = t.ma;   // the WG stages all rows of the slice
+      } else {
+        if (wu.z < 0 || wu.z >= t.ma * t.mb) { fail("sandwich: element"); return; }
+        rows_hi = t.ma;
+      }
+      const int64_t xext = wu.y * t.xs_slice + (rows_hi - 1) * t.xs_row + t.mb;
+      if (t.x) span(t.x, xext * esz, "sandwich x");
+      else if (xext > xbase_len) fail("sandwich: x beyond the input vector");
+      span(t.y, (wu.y * t.ys_slice + (t.ma - 1) * t.ys_row + t.mb) * esz, "sandwich y");
+      if (t.item0 < 0 || t.item0 + t.nitem > (int)g.items.size()) { fail("sandwich: item range"); return; }
+      for (int i = t.item0; i < t.item0 + t.nitem; i++) {
+        if (g.items[i].A) span(g.items[i].A, (int64_t)t.ma * t.ma * esz, "sandwich A");
+        if (g.items[i].B) span(g.items[i].B, (int64_t)t.mb * t.mb * esz, "sandwich B");
+      }
+      if (!ok) return;
+    }
+  }
+  void mp(const MPGroup& g, int64_t xbase_len, int esz) {
+    for (const int2& wu : g.wus) {
+      if (wu.x < 0 || wu.x >= (int)g.tasks.size()) { fail("mode: task index"); return; }
+      const MPTask& t = g.tasks[wu.x];
+      const int mj = t.j == 0 ? t.d0 : (t.j == 1 ? t.d1 : t.d2);
+      if (mj != g.mj) { fail("mode: group dims"); return; }
+      const int64_t M = (int64_t)t.d0 * t.d1 * t.d2;
+      if (g.mfma) { if ((int64_t)(wu.y + 1) * 64 * mj > M) { fail("mode: tile"); return; } }
+      else if (wu.y < 0 || wu.y >= M) { fail("mode: element"); return; }
+      span(t.out, M * esz, "mode out");
+      if (t.job0 < 0 || t.job0 + t.njob > (int)g.jobs.size()) { fail("mode: job range"); return; }
+      for (int k = t.job0; k < t.job0 + t.njob; k++) {
+        span(g.jobs[k].A, (int64_t)mj * mj * esz, "mode A");
+        if (g.jobs[k].in) span(g.jobs[k].in, M * esz, "mode in");
+        else if (M > xbase_len) fail("mode: in beyond the input vector");
+      }
+      if (!ok) return;
+    }
+  }
+  void gr(const std::vector<GRTask>& ts, bool mfma) {
+    for (const GRTask& t : ts) {
+      const int mj = t.j == 0 ? t.d0 : (t.j == 1 ? t.d1 : t.d2);
+      const int64_t M = (int64_t)t.d0 * t.d1 * t.d2;
+      if (t.f0 < 0 || t.f1 > M / mj || t.f0 >= t.f1) { fail("gram: f range"); return; }
+      if (mfma && ((t.f1 - t.f0) % 64 || t.f0 % 64)) { fail("gram: f range not tiled"); return; }
+      span(t.X, M * 8, "gram X");
+      span(t.Z, M * 8, "gram Z");
+      span(t.partial, (int64_t)mj * mj * 8, "gram partial");
+    }
+  }
+  void red(const std::vector<GRReduce>& rs) {
+    for (const GRReduce& r : rs) {
+      span(r.partial, (int64_t)r.npart * r.m * r.m * 8, "reduce partial");
+      span(r.out, (int64_t)r.m * r.m * 8, "reduce out");
+    }
+  }
+  void cb(const CBPlan& P) {
+    for (const CBTask& t : P.tasks) {
+      span(t.out, (int64_t)t.n * 8, "combine out");
+      for (int k = t.term0; k < t.term0 + t.nterm; k++) span(P.terms[k].in, (int64_t)t.n * 8, "combine in");
+    }
+  }
+};
+}  // namespace
+
+extern "C" attn_status attn_validate(const attn_handle* h) {
+  if (!h) return ATTN_ERR_ARG;
+  if (h->host_only) return ATTN_ERR_STATE;
+  Checker c{h, "", true};
+  const Tree& tr = h->M.tree;
+  for (int n = 0; n < (int)tr.nodes.size() && c.ok; n++) {
+    const MVDev& D = h->mv[n];
+    const int64_t M = (int64_t)D.dims[0] * D.dims[1] * D.dims[2];
+    c.cb(D.comb);
+    for (auto& g : D.sw) c.sw(g, M, 8);
+    for (auto& g : D.chainA) c.mp(g, M, 8);
+    for (auto& g : D.chainB) c.mp(g, M, 8);
+    for (auto& g : D.chainC) c.mp(g, M, 8);
+    for (auto& sr : D.srcs) c.span(sr.p, M * 8, "reduce source");
+    if (D.need_xt) c.span(h->d_xt, M * 8, "transposed input");
+    const EnvDev* eds[3] = {&h->env_up[n], &h->env_down[0][n], &h->env_down[1][n]};
+    for (const EnvDev* E : eds) {
+      if (!E->present) continue;
+      c.cb(E->comb);
+      for (auto& ch : E->chunks) {
+        for (auto& g : ch.sw) c.sw(g, 0, 8);
+        c.gr(ch.gr.tasks, ch.gr.mfma);
+        c.red(ch.gr.reds);
+        for (auto& zb : ch.zero_blocks) c.span(zb.first, zb.second * 8, "zero block");
+      }
+    }
+    for (int l = 0; l < 3; l++) {
+      const QRDev& Q = h->qr[l][n];
+      if (Q.present) {
+        for (int pass = 0; pass < 3; pass++) {
+          c.gr(Q.h_gt[pass], Q.gmf);
+          c.mp(Q.h_mp[pass], 0, 8);
+        }
+        c.red(Q.h_gr);
+        c.span(h->d_qrmat, 6 * (int64_t)h->mmax * h->mmax * 8, "qr matrices");
+      }
+      const ABDev& A = h->ab[l][n];
+      if (A.present) c.mp(A.h_mp, 0, 8);
+    }
+  }
+  if (!c.ok) { const_cast<attn_handle*>(h)->err = c.err; return ATTN_ERR_STATE; }
+  return ATTN_OK;
+}

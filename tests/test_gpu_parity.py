@@ -1,0 +1,116 @@
+"""GPU parity of the HIP path (through the C interface) against the FP64 CPU
+oracle on the same seeded inputs.  Tolerances: 1e-12 relative for FP64
+matvecs, tensors compared up to rounding (1e-11 absolute on unit-norm data),
+energies per site to 1e-10."""
+import numpy as np
+import pytest
+
+from problems import config_problem, make_chain_problem, batch_instances
+from tests.gpu_util import make_pair, move_both, gpu_matvec, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _tensors_close(a, o, tol=1e-11):
+    for n in range(o.tree.n_nodes):
+        d = np.abs(a.get_tensor(n) - o.T[n]).max()
+        assert d < tol, (n, d)
+
+
+def test_init_state_matches_oracle_4x4():
+    p = config_problem("ising4_m8")
+    a, o = make_pair(p)
+    _tensors_close(a, o)
+
+
+def test_matvec_root_4x4():
+    p = config_problem("ising4_m8")
+    a, o = make_pair(p)
+    n = o.tree.root
+    x = np.random.default_rng(0).standard_normal(o.T[n].shape)
+    assert rel(gpu_matvec(a, n, x), o.matvec(n, x)) < 1e-12
+
+
+@pytest.mark.parametrize("key", ["ising4_m8", "ising8_m16"])
+def test_matvec_every_node_after_moves(key):
+    p = config_problem(key)
+    a, o = make_pair(p)
+    rng = np.random.default_rng(1)
+    for n in range(o.tree.n_nodes):
+        move_both(a, o, n)
+        x = rng.standard_normal(o.T[n].shape)
+        r = rel(gpu_matvec(a, n, x), o.matvec(n, x))
+        assert r < 1e-12, (n, o.T[n].shape, r)
+    _tensors_close(a, o)
+
+
+def test_matvec_full_nodes_8x8_m32():
+    p = config_problem("ising8_m32")
+    a, o = make_pair(p)
+    rng = np.random.default_rng(2)
+    full = [n for n in range(o.tree.n_nodes) if o.tree.dims[n] == (32, 32, 32)]
+    for n in full[:3] + [o.tree.root]:
+        move_both(a, o, n)
+        x = rng.standard_normal(o.T[n].shape)
+        assert rel(gpu_matvec(a, n, x), o.matvec(n, x)) < 1e-12, n
+
+
+def test_matvec_four_body_terms_chain():
+    # gates on non-adjacent sites, terms touching two gates (bond 16), uneven tree
+    p = make_chain_problem("c", 12, 1.7, 8, 9, de_pairs=[(1, 3), (4, 6), (8, 10)])
+    a, o = make_pair(p)
+    rng = np.random.default_rng(3)
+    for n in range(o.tree.n_nodes):
+        move_both(a, o, n)
+        x = rng.standard_normal(o.T[n].shape)
+        assert rel(gpu_matvec(a, n, x), o.matvec(n, x)) < 1e-12, n
+
+
+def test_eigsolve_matches_oracle():
+    p = config_problem("ising4_m8")
+    a, o = make_pair(p)
+    for n in (o.tree.root, 0, 6):
+        move_both(a, o, n)
+        th_o = o.eigsolve(n)
+        th_a, nmv = a.eigsolve(n)
+        assert abs(th_a - th_o) < 1e-10 * max(1, abs(th_o)), (n, th_a, th_o)
+        assert np.abs(a.get_tensor(n) - o.T[n]).max() < 1e-9
+
+
+def test_sweeps_4x4_energy_parity():
+    p = config_problem("ising4_m8")
+    a, o = make_pair(p)
+    e_a, secs = a.sweep(5)
+    for s in range(5):
+        e_o = o.sweep()
+        assert abs(e_a[s] - e_o) / p.n_sites < 1e-10, (s, e_a[s], e_o)
+
+
+def test_sweep_chain_four_body_parity():
+    p = make_chain_problem("c", 12, 1.7, 8, 9, de_pairs=[(1, 3), (4, 6), (8, 10)])
+    a, o = make_pair(p)
+    e_a, _ = a.sweep(2)
+    for s in range(2):
+        e_o = o.sweep()
+        assert abs(e_a[s] - e_o) / p.n_sites < 1e-10, (s, e_a[s], e_o)
+
+
+def test_uneven_instance_matvec():
+    # an L = 12 instance: node shapes such as (32, 16, 48) and (8, 4, 32)
+    inst = [p for p in batch_instances(8) if p.meta["L"] == 12][:1]
+    for p in inst:
+        a, o = make_pair(p)
+        rng = np.random.default_rng(4)
+        nodes = sorted(range(o.tree.n_nodes), key=lambda n: -np.prod(o.tree.dims[n]))[:3]
+        nodes += [n for n in range(o.tree.n_nodes) if len(set(o.tree.dims[n])) == 3][:3]
+        for n in nodes:
+            move_both(a, o, n)
+            x = rng.standard_normal(o.T[n].shape)
+            assert rel(gpu_matvec(a, n, x), o.matvec(n, x)) < 1e-12, (n, o.tree.dims[n])
