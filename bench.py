@@ -1,0 +1,179 @@
+"""Benchmark of the aTTN hot path on one MI355X.
+
+A step is one full sweep of the ground-state search (every node: QR moves,
+effective-operator updates, Lanczos eigensolve with 20 H_eff matvecs) over the
+16 x 16 open-boundary Ising model (h = 3, m = 64, 64 disentanglers; seeded
+synthetic instance).  The reported value is the whole-job H_eff matvec
+throughput: algorithmic matvec flops of the timed sweeps / timed wall time.
+
+Also reported: the sweep energies, the time to reach Delta E / N <= 1e-7 with
+respect to the reference energy, the live-timed roofline of the dominant kernel
+(the FP64 two-leg contraction kernel at the full (64, 64) legs) and the FP64
+CPU oracle timed on this host on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64]
+                       [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("H_eff matvec TFLOP/s + sweep time to ΔE/N≤1e-7 (16x16 Ising, m=64) "
+          "vs FP64 GPU")
+PEAK_FP64 = 78.6   # TFLOP/s, MI355X dense FP64 (vector and matrix)
+REF_FILE = os.path.join(ROOT, "tests", "golden", "ising16_m64_reference.json")
+
+
+def reference_energy():
+    """Converged reference energy of the workload if a committed file has it."""
+    if os.path.exists(REF_FILE):
+        with open(REF_FILE) as f:
+            d = json.load(f)
+        return d.get("E_ref"), d.get("source")
+    return None, None
+
+
+def cpu_baseline(problem, sample_matvecs=3):
+    """FP64 oracle on this host: build its effective operators for the initial
+    state, move the centre to the heaviest full node, time `sample_matvecs`
+    matvecs there.  Returns the dict for the JSON line."""
+    import numpy as np
+    from oracle.ttn import OracleTTN
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    t0 = time.time()
+    o = OracleTTN(problem.n_sites, problem.d, problem.m, problem.leaf_order, problem.terms,
+                  problem.de_sites, problem.de_u, problem.raw_tensors)
+    full = [n for n in range(o.tree.n_nodes) if o.tree.dims[n] == (64, 64, 64)]
+    node = max(full, key=o.flops)
+    o.move_center(node)
+    prep = o.prepare(node)
+    setup = time.time() - t0
+    x = np.random.default_rng(0).standard_normal(o.T[node].shape)
+    t1 = time.time()
+    for _ in range(sample_matvecs):
+        o.matvec(node, x, prep)
+    dt = time.time() - t1
+    F = o.flops(node) * sample_matvecs
+    return {"value": F / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": (f"{sample_matvecs} FP64 oracle matvecs at the heaviest (64,64,64) node "
+                       f"({o.flops(node) / 1e9:.1f} GFLOP each) of the same instance; "
+                       f"oracle set-up (effective operators of the initial state) {setup:.1f} s "
+                       f"not timed")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=12)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="f64", choices=["f64"])
+    ap.add_argument("--config", default="ising16_m64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is a "
+              "single-GPU build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from problems import config_problem
+    from paper_2507_21236_amd import AttnHandle, solver_opts, ATTN_F64
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.init()
+    p = config_problem(args.config)
+    N = p.n_sites
+    print(f"[bench] workload {args.config}: N={N} m={p.m} terms={len(p.terms)} "
+          f"disentanglers={len(p.de_sites)}", file=sys.stderr, flush=True)
+    t0 = time.time()
+    a = AttnHandle(p)
+    print(f"[bench] build {time.time() - t0:.2f} s, effective-operator storage "
+          f"{a.env_bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
+    opts = solver_opts(krylov_k=20, precision=ATTN_F64)
+    a.init_state()
+    for w in range(args.warmup):
+        e, s = a.sweep(1, opts)
+        print(f"[bench] warmup sweep {w}: E={e[0]:.12f} {s[0]:.3f} s", file=sys.stderr, flush=True)
+    # timed region: K sweeps from the initial state
+    a.init_state()
+    torch.cuda.synchronize()
+    _, _, _, f0 = a.counters()
+    a.profile_start()
+    energies, secs = [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        e, s = a.sweep(1, opts)
+        energies.append(float(e[0]))
+        secs.append(float(s[0]))
+        print(f"[bench] sweep {k}: E={e[0]:.12f} E/N={e[0] / N:.12f} {s[0]:.3f} s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_sw, fl_sw, n_sw = a.profile_stop(min_dim=64)
+    _, _, _, f1 = a.counters()
+    mv_flops = f1 - f0
+    value = mv_flops / t_total / 1e12
+
+    E_ref, ref_src = reference_energy()
+    if E_ref is None:
+        E_ref, ref_src = energies[-1], "last timed sweep of this run (FP64 GPU)"
+    t_target = None
+    cum = 0.0
+    for e, s in zip(energies, secs):
+        cum += s
+        if abs(e - E_ref) / N <= 1e-7:
+            t_target = cum
+            break
+
+    achieved = fl_sw / (ms_sw / 1e3) / 1e12 if ms_sw > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_total / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ising16x16_h3_m64_de64_seed16", "lattice": "16x16 OBC square",
+                   "m": p.m, "disentanglers": len(p.de_sites), "krylov_k": 20,
+                   "precision": args.precision},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4),
+                     "traffic": None,
+                     "kernel": "k_sandwich<double,4> (two-leg terms and local operators, "
+                               "legs of dimension 64)",
+                     "launches": n_sw, "kernel_ms": round(ms_sw, 3)},
+        "sweep_energies": energies,
+        "sweep_seconds": [round(s, 4) for s in secs],
+        "E_ref": E_ref,
+        "E_ref_source": ref_src,
+        "time_to_dE_per_site_1e-7_s": None if t_target is None else round(t_target, 3),
+        "matvec_gflop_timed": round(mv_flops / 1e9, 1),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p)
+    a.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

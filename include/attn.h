@@ -247,9 +247,20 @@ attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* 
  * violation), ARG. */
 attn_status attn_validate(const attn_handle* h);
 
-/* Counters since the handle was built: matvecs, env updates, QR moves. */
+/* Counters since the handle was built: matvecs, env updates, QR moves and the
+ * algorithmic flops of all matvecs (attn_node_info's count per matvec).  Any
+ * pointer may be NULL. */
 attn_status attn_counters(const attn_handle* h, int64_t* n_matvec, int64_t* n_env,
-                          int64_t* n_qr);
+                          int64_t* n_qr, double* matvec_flops);
+
+/* Live timing of the matvec's two-leg contraction kernel.  enable = 1 starts
+ * recording: every launch of that kernel is bracketed by HIP events on its own
+ * stream.  enable = 0 synchronises the device, stops recording and returns the
+ * summed event time (*ms), algorithmic flops (*flops) and number of launches
+ * (*launches) of the launches whose two contracted legs are both >= min_dim.
+ * Errors: STATE (host-only / dry-run handle), HIP. */
+attn_status attn_profile(attn_handle* h, int32_t enable, int32_t min_dim, double* ms,
+                         double* flops, int64_t* launches);
 
 #ifdef __cplusplus
 }

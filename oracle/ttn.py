@@ -366,8 +366,10 @@ class OracleTTN:
         k = min(krylov_k, M) matvecs, three-term recurrence followed by two
         passes of classical Gram-Schmidt against all previous vectors, stop when
         beta_j <= 1e-14 max|alpha|; lowest eigenpair of the tridiagonal matrix;
-        Ritz vector normalised, sign chosen so that its overlap with the start
-        vector is >= 0.  The Ritz vector replaces T_n."""
+        Ritz vector normalised; its sign (a gauge) is fixed by making the first
+        component of the tridiagonal eigenvector with magnitude >= 1e-8 of the
+        largest one positive (the overlap with the start vector when that is
+        not negligible).  The Ritz vector replaces T_n."""
         shape = self.T[n].shape
         M = int(np.prod(shape))
         k = min(self.krylov_k, M)
@@ -398,7 +400,7 @@ class OracleTTN:
         evals, evecs = np.linalg.eigh(Tm)
         theta = float(evals[0])
         y = evecs[:, 0]
-        nz = np.flatnonzero(np.abs(y) > 0)
+        nz = np.flatnonzero(np.abs(y) >= 1e-8 * np.abs(y).max())
         if y[nz[0]] < 0:
             y = -y
         x = np.array(V[:ke]).T @ y

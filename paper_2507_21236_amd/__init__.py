@@ -78,7 +78,10 @@ class AttnHandle:
     def counters(self):
         return _lib.attn_counters(self.h)
 
-    # tree helpers (structure only)
-    def path_moves(self, target):
-        """Sequence of (from, to, leg) moves that bring the centre to target."""
-        return None
+    def profile_start(self):
+        _lib.attn_profile(self.h, 1)
+
+    def profile_stop(self, min_dim=0):
+        """(ms, flops, launches) of the matvec contraction launches since start."""
+        return _lib.attn_profile(self.h, 0, min_dim)
+

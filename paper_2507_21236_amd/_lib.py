@@ -81,7 +81,9 @@ _proto = {
     "attn_validate": (ctypes.c_int32, [_H]),
     "attn_counters": (ctypes.c_int32, [_H, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int64),
-                                       ctypes.POINTER(ctypes.c_int64)]),
+                                       ctypes.POINTER(ctypes.c_int64), _f64p]),
+    "attn_profile": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_int32, _f64p, _f64p,
+                                      ctypes.POINTER(ctypes.c_int64)]),
 }
 for _name, (_res, _args) in _proto.items():
     _f = getattr(_lib, _name)
@@ -210,5 +212,14 @@ def attn_validate(h):
 
 def attn_counters(h):
     a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(_lib.attn_counters(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), h)
-    return a.value, b.value, c.value
+    f = ctypes.c_double()
+    _check(_lib.attn_counters(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                              ctypes.byref(f)), h)
+    return a.value, b.value, c.value, f.value
+
+
+def attn_profile(h, enable, min_dim=0):
+    ms, fl, nl = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    _check(_lib.attn_profile(h, enable, min_dim, ctypes.byref(ms), ctypes.byref(fl),
+                             ctypes.byref(nl)), h)
+    return ms.value, fl.value, nl.value

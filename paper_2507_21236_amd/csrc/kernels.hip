@@ -29,6 +29,12 @@ template <typename T> struct V4;
 template <> struct V4<double> { typedef d4 type; };
 template <> struct V4<float> { typedef f4 type; };
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // accumulator row of item i in lane group g = lane / 16
 template <typename T> __device__ __forceinline__ int drow(int g, int i);
 template <> __device__ __forceinline__ int drow<double>(int g, int i) { return g + 4 * i; }
@@ -121,15 +127,9 @@ __global__ __launch_bounds__(256) void k_sandwich(const SWTask* __restrict__ tas
 // Generic sandwich for dimensions that are not multiples of 16: one thread per
 // output element of one slice.  wu = (task, slice, first element).
 template <typename T>
-__global__ __launch_bounds__(256) void k_sandwich_gen(const SWTask* __restrict__ tasks,
-                                                      const SWItem* __restrict__ items,
-                                                      const int4* __restrict__ wus,
-                                                      const T* __restrict__ xbase) {
-  const int4 wu = wus[blockIdx.x];
-  const SWTask& t = tasks[wu.x];
-  const int s = wu.y;
+__device__ __forceinline__ void sandwich_gen_elem(const SWTask& t, const SWItem* __restrict__ items,
+                                                  int s, int e, const T* __restrict__ xbase) {
   const int ma = t.ma, mb = t.mb;
-  const int e = wu.z + threadIdx.x;
   if (e >= ma * mb) return;
   const int ap = e / mb, bp = e - ap * mb;
   const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)s * t.xs_slice;
@@ -154,6 +154,15 @@ __global__ __launch_bounds__(256) void k_sandwich_gen(const SWTask* __restrict__
   T* Y = (T*)t.y + (int64_t)s * t.ys_slice + (int64_t)ap * t.ys_row + bp;
   if (t.accumulate) *Y += acc;
   else *Y = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sandwich_gen(const SWTask* __restrict__ tasks,
+                                                      const SWItem* __restrict__ items,
+                                                      const int4* __restrict__ wus,
+                                                      const T* __restrict__ xbase) {
+  const int4 wu = wus[blockIdx.x];
+  sandwich_gen_elem<T>(tasks[wu.x], items, wu.y, wu.z + threadIdx.x, xbase);
 }
 
 // ============================================================================ mode product
@@ -228,13 +237,8 @@ __global__ __launch_bounds__(256) void k_mode(const MPTask* __restrict__ tasks,
 
 // Generic mode product: one thread per output element.  wu = (task, first element).
 template <typename T>
-__global__ __launch_bounds__(256) void k_mode_gen(const MPTask* __restrict__ tasks,
-                                                  const MPJob* __restrict__ jobs,
-                                                  const int2* __restrict__ wus,
-                                                  const T* __restrict__ xbase) {
-  const int2 wu = wus[blockIdx.x];
-  const MPTask& t = tasks[wu.x];
-  const int64_t e = (int64_t)wu.y + threadIdx.x;
+__device__ __forceinline__ void mode_gen_elem(const MPTask& t, const MPJob* __restrict__ jobs,
+                                              int64_t e, const T* __restrict__ xbase) {
   const int j = t.j, d0 = t.d0, d1 = t.d1, d2 = t.d2;
   const int mj = j == 0 ? d0 : (j == 1 ? d1 : d2);
   const int64_t total = (int64_t)d0 * d1 * d2;
@@ -254,6 +258,15 @@ __global__ __launch_bounds__(256) void k_mode_gen(const MPTask* __restrict__ tas
   const int64_t ad = mode_addr(j, d0, d1, d2, i, f);
   if (t.accumulate) out[ad] += acc;
   else out[ad] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mode_gen(const MPTask* __restrict__ tasks,
+                                                  const MPJob* __restrict__ jobs,
+                                                  const int2* __restrict__ wus,
+                                                  const T* __restrict__ xbase) {
+  const int2 wu = wus[blockIdx.x];
+  mode_gen_elem<T>(tasks[wu.x], jobs, (int64_t)wu.y + threadIdx.x, xbase);
 }
 
 // ============================================================================ gram
@@ -538,84 +551,381 @@ __global__ __launch_bounds__(256) void k_scale_into(const double* __restrict__ w
     out[e] = w[e] * inv;
 }
 
-// Lowest eigenpair of the keff x keff tridiagonal matrix (alpha, beta) by cyclic
-// Jacobi rotations on the dense symmetric matrix, one wavefront.  The
-// eigenvector is normalised with its first non-zero component positive.
-__global__ __launch_bounds__(64) void k_tridiag(KrylovState* __restrict__ st) {
-  __shared__ double A[64][65];
-  __shared__ double Vm[64][65];
-  __shared__ double cs_sn[2];
-  const int k = st->keff;
+// ---- fused Lanczos steps: every workgroup first reduces the partial sums of
+// the previous kernel itself (fixed order, identical in every workgroup), so
+// no separate reduction launch is needed between the steps.
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, double* red) {
+  return block_sum(p[threadIdx.x], red);   // kRedBlocks == blockDim.x == 256
+}
+
+__global__ __launch_bounds__(256) void k_state_init(KrylovState* __restrict__ st, int kmax) {
   const int t = threadIdx.x;
-  for (int i = 0; i < k; i++) {
-    if (t < k) {
-      double v = 0;
-      if (i == t) v = st->alpha[i];
-      else if (t == i + 1) v = st->beta[i];
-      else if (i == t + 1) v = st->beta[t];
-      A[i][t] = v;
-      Vm[i][t] = (i == t) ? 1.0 : 0.0;
-    }
+  if (t < 128) { st->alpha[t] = 0; st->beta[t] = 0; st->h[t] = 0; st->y[t] = 0; }
+  if (t < 8) st->scal[t] = 0;
+  if (t == 0) { st->kmax = kmax; st->keff = 1; st->stop = 0; st->status = 0; }
+}
+
+// alpha_j = sum(partial_a); w -= alpha_j v_j + beta_{j-1} v_{j-1}; partial dots V[0..j].w
+__global__ __launch_bounds__(256) void k_lanczos_update2(double* __restrict__ w,
+                                                         const double* __restrict__ V, int64_t n,
+                                                         KrylovState* __restrict__ st, int j,
+                                                         const double* __restrict__ partial_a,
+                                                         double* __restrict__ partial) {
+  __shared__ double red[4];
+  if (st->stop) return;
+  const double a = sum_partials(partial_a, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->alpha[j] = a;
+    if (!isfinite(a)) st->status = 1;
+  }
+  const int b = blockIdx.x;
+  const double bb = j > 0 ? st->beta[j - 1] : 0.0;
+  const double* vj = V + (int64_t)j * n;
+  const double* vm = j > 0 ? V + (int64_t)(j - 1) * n : V;
+  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
+    double x = w[e] - a * vj[e];
+    if (j > 0) x -= bb * vm[e];
+    w[e] = x;
+  }
+  for (int i = 0; i <= j; i++) {
+    const double* v = V + (int64_t)i * n;
+    double acc = 0;
+    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
+      acc += v[e] * w[e];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
+  }
+}
+
+// h = sums of partial_in (nv vectors); w -= sum h_i V_i; partial dots (or norm)
+__global__ __launch_bounds__(256) void k_axpy_dots2(double* __restrict__ w,
+                                                    const double* __restrict__ V, int nv, int64_t n,
+                                                    const KrylovState* __restrict__ st,
+                                                    const double* __restrict__ partial_in,
+                                                    double* __restrict__ partial, int norm_only) {
+  __shared__ double red[4];
+  __shared__ double hs[128];
+  if (st->stop) return;
+  for (int i = 0; i < nv; i++) {
+    const double hv = sum_partials(partial_in + i * kRedBlocks, red);
+    if (threadIdx.x == 0) hs[i] = hv;
   }
   __syncthreads();
-  for (int sweep = 0; sweep < 60; sweep++) {
-    double off = 0, dia = 0;
-    for (int i = 0; i < k; i++)
-      for (int j2 = 0; j2 < k; j2++) {
-        if (i == j2) dia += A[i][i] * A[i][i];
-        else off += A[i][j2] * A[i][j2];
-      }
-    if (off <= 1e-32 * dia || off == 0.0) break;
-    for (int p = 0; p < k - 1; p++)
-      for (int q = p + 1; q < k; q++) {
-        if (t == 0) {
-          const double apq = A[p][q];
-          double c = 1.0, s = 0.0;
-          if (apq != 0.0) {
-            const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-            const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
-          }
-          cs_sn[0] = c;
-          cs_sn[1] = s;
-        }
-        __syncthreads();
-        const double c = cs_sn[0], s = cs_sn[1];
-        if (s != 0.0) {
-          // columns p, q
-          if (t < k) {
-            const double x = A[t][p], y = A[t][q];
-            A[t][p] = c * x - s * y;
-            A[t][q] = s * x + c * y;
-          }
-          __syncthreads();
-          if (t < k) {
-            const double x = A[p][t], y = A[q][t];
-            A[p][t] = c * x - s * y;
-            A[q][t] = s * x + c * y;
-            const double vx = Vm[t][p], vy = Vm[t][q];
-            Vm[t][p] = c * vx - s * vy;
-            Vm[t][q] = s * vx + c * vy;
-          }
-        }
-        __syncthreads();
-      }
+  const int b = blockIdx.x;
+  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
+    double x = w[e];
+    for (int i = 0; i < nv; i++) x -= hs[i] * V[(int64_t)i * n + e];
+    w[e] = x;
   }
-  if (t == 0) {
-    int best = 0;
-    for (int i = 1; i < k; i++)
-      if (A[i][i] < A[best][best]) best = i;
-    double nrm = 0;
-    for (int i = 0; i < k; i++) nrm += Vm[i][best] * Vm[i][best];
-    nrm = sqrt(nrm);
+  if (norm_only) {
+    double acc = 0;
+    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
+      acc += w[e] * w[e];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[b] = s;
+    return;
+  }
+  for (int i = 0; i < nv; i++) {
+    const double* v = V + (int64_t)i * n;
+    double acc = 0;
+    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
+      acc += v[e] * w[e];
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
+  }
+}
+
+// beta_j = sqrt(sum partial); breakdown test; V_{j+1} = w / beta_j
+__global__ __launch_bounds__(256) void k_scale_beta(const double* __restrict__ w,
+                                                    double* __restrict__ out, int64_t n,
+                                                    KrylovState* __restrict__ st, int j,
+                                                    const double* __restrict__ partial) {
+  __shared__ double red[4];
+  if (st->stop) return;
+  const double b = sqrt(sum_partials(partial, red));
+  double amax = 0;
+  for (int k = 0; k <= j; k++) amax = fmax(amax, fabs(st->alpha[k]));
+  const bool brk = !(b > 1e-14 * amax);
+  __syncthreads();   // every block has read the state before block 0 updates it
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (!isfinite(b)) st->status = 1;
+    if (brk) st->stop = 1;
+    else { st->beta[j] = b; st->keff = j + 2; }
+  }
+  if (brk) return;
+  const double inv = 1.0 / b;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    out[e] = w[e] * inv;
+}
+
+// out = x / sqrt(sum partial)
+__global__ __launch_bounds__(256) void k_scale_norm(const double* __restrict__ x,
+                                                    double* __restrict__ out, int64_t n,
+                                                    const double* __restrict__ partial,
+                                                    KrylovState* __restrict__ st) {
+  __shared__ double red[4];
+  const double nr = sqrt(sum_partials(partial, red));
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !(nr > 0 && isfinite(nr))) st->status = 1;
+  const double inv = 1.0 / nr;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    out[e] = x[e] * inv;
+}
+
+// Lowest eigenpair of the keff x keff symmetric tridiagonal matrix
+// T = tridiag(beta, alpha, beta), one thread:
+//  * eigenvalue by bisection on Sturm counts (number of negative pivots of the
+//    LDL^T factorisation of T - x I) inside the Gershgorin interval, down to
+//    adjacent floating-point numbers;
+//  * eigenvector by inverse iteration with T - theta I (Gaussian elimination
+//    with partial pivoting on the tridiagonal system, three iterations);
+//  * normalised, sign fixed as described at the end of the kernel.
+__device__ int sturm_count(const double* a, const double* b, int k, double x) {
+  int cnt = 0;
+  double q = a[0] - x;
+  if (q < 0) cnt++;
+  for (int i = 1; i < k; i++) {
+    if (q == 0.0) q = 1e-300;
+    q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
+    if (q < 0) cnt++;
+  }
+  return cnt;
+}
+
+// Run by one full wavefront (64 lanes); lds must hold 8 * 64 doubles.
+__device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restrict__ lds) {
+  const int lane = threadIdx.x & 63;
+  const int k = st->keff;
+  double* a = lds;
+  double* b = lds + 64;
+  double* y = lds + 128;
+  double* d = lds + 192;
+  double* du = lds + 256;
+  double* du2 = lds + 320;
+  double* dl = lds + 384;
+  double* rhs = lds + 448;
+  if (lane < k) a[lane] = st->alpha[lane];
+  if (lane + 1 < k) b[lane] = st->beta[lane];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  double lo = a[0], hi = a[0], nrm = 0;
+  for (int i = 0; i < k; i++) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < k ? fabs(b[i]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
+    nrm = fmax(nrm, fabs(a[i]) + r);
+  }
+  // multisection: 64 Sturm counts per step, bracket [lo, hi] keeps lambda_min
+  for (int it = 0; it < 40; it++) {
+    const double w = hi - lo;
+    const double x = lo + w * (double)(lane + 1) / 65.0;
+    const bool has = (x > lo && x < hi) ? sturm_count(a, b, k, x) >= 1 : (x >= hi);
+    const unsigned long long m = __ballot(has);
+    const int first = m ? __ffsll((long long)m) - 1 : 64;
+    const double nhi = first < 64 ? lo + w * (double)(first + 1) / 65.0 : hi;
+    const double nlo = first > 0 ? lo + w * (double)first / 65.0 : lo;
+    if (!(nhi < hi || nlo > lo)) break;
+    hi = fmin(hi, nhi);
+    lo = fmax(lo, nlo);
+    if (hi - lo <= 2.2e-16 * fmax(fabs(lo), fabs(hi))) break;
+  }
+  // bisection to the last bits
+  for (int it = 0; it < 64; it++) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(a, b, k, mid) >= 1) hi = mid;
+    else lo = mid;
+  }
+  const double theta = hi;
+  if (lane == 0) {
+    const double tiny = 1e-300 + 2.2e-16 * nrm * 1e-3;
+    for (int i = 0; i < k; i++) y[i] = 1.0;
+    for (int rep = 0; rep < 3; rep++) {
+      for (int i = 0; i < k; i++) {
+        d[i] = a[i] - theta;
+        rhs[i] = y[i];
+        du[i] = (i + 1 < k) ? b[i] : 0.0;
+        dl[i] = (i + 1 < k) ? b[i] : 0.0;
+        du2[i] = 0.0;
+      }
+      for (int i = 0; i + 1 < k; i++) {
+        if (fabs(d[i]) >= fabs(dl[i])) {
+          if (d[i] == 0.0) d[i] = tiny;
+          const double f = dl[i] / d[i];
+          d[i + 1] -= f * du[i];
+          rhs[i + 1] -= f * rhs[i];
+          dl[i] = 0.0;
+        } else {
+          const double f = d[i] / dl[i];
+          d[i] = dl[i];
+          const double t1 = d[i + 1];
+          d[i + 1] = du[i] - f * t1;
+          du[i] = t1;
+          if (i + 2 < k) {
+            du2[i] = du[i + 1];
+            du[i + 1] = -f * du2[i];
+          }
+          const double tr = rhs[i];
+          rhs[i] = rhs[i + 1];
+          rhs[i + 1] = tr - f * rhs[i + 1];
+        }
+      }
+      if (d[k - 1] == 0.0) d[k - 1] = tiny;
+      for (int i = k - 1; i >= 0; i--) {
+        double v = rhs[i];
+        if (i + 1 < k) v -= du[i] * y[i + 1];
+        if (i + 2 < k) v -= du2[i] * y[i + 2];
+        y[i] = v / (d[i] == 0.0 ? tiny : d[i]);
+      }
+      double n2 = 0;
+      for (int i = 0; i < k; i++) n2 += y[i] * y[i];
+      const double inv = 1.0 / sqrt(n2);
+      for (int i = 0; i < k; i++) y[i] *= inv;
+    }
+    // sign (a gauge): first component with magnitude >= 1e-8 of the largest one positive
+    double ymax = 0;
+    for (int i = 0; i < k; i++) ymax = fmax(ymax, fabs(y[i]));
     int first = 0;
-    while (first < k - 1 && Vm[first][best] == 0.0) first++;
-    const double sg = Vm[first][best] < 0 ? -1.0 : 1.0;
-    for (int i = 0; i < k; i++) st->y[i] = sg * Vm[i][best] / nrm;
-    st->scal[0] = A[best][best];
-    if (!isfinite(A[best][best])) st->status = 1;
+    while (first < k - 1 && fabs(y[first]) < 1e-8 * ymax) first++;
+    const double sg = y[first] < 0 ? -1.0 : 1.0;
+    for (int i = 0; i < k; i++) st->y[i] = sg * y[i];
+    st->scal[0] = theta;
+    if (!isfinite(theta)) st->status = 1;
   }
+}
+
+__global__ __launch_bounds__(64) void k_tridiag(KrylovState* __restrict__ st) {
+  __shared__ double lds[512];
+  tridiag_solve_wave(st, lds);
+}
+
+// ---- tiny nodes: the whole Lanczos eigensolve in one workgroup.  The matvec
+// interprets the node's work lists (generic kernels only) phase by phase with
+// barriers in between; the vector steps are the same as in the multi-kernel
+// path, with workgroup reductions.
+// ---- tiny nodes (M <= 1024): H_eff is assembled densely once per eigensolve
+// (the same operator as the factorised matvec: every item's Kronecker product
+// written out entry by entry), then the Lanczos steps run in one workgroup
+// with a dense matvec.
+__device__ __forceinline__ double blk(const double* O, int m, int i, int ip) {
+  return O ? O[(int64_t)ip * m + i] : (i == ip ? 1.0 : 0.0);
+}
+
+// H^T[j][i] = H[i][j] (H is symmetric), one thread per entry
+__global__ __launch_bounds__(256) void k_tiny_assemble(const TinyPlan* __restrict__ plan,
+                                                       double* __restrict__ H) {
+  const TinyPlan P = *plan;
+  const int d0 = P.d0, d1 = P.d1, d2 = P.d2;
+  const int M = d0 * d1 * d2;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)M * M) return;
+  const int col = (int)(e / M), row = (int)(e - (int64_t)col * M);
+  const int l1 = row / (d1 * d2), r1 = (row / d2) % d1, p1 = row % d2;
+  const int l2 = col / (d1 * d2), r2 = (col / d2) % d1, p2 = col % d2;
+  double acc = 0;
+  if (l1 == l2)
+    for (int it = P.item0[0]; it < P.item0[0] + P.nitem[0]; it++)
+      acc += P.items[it].coef * blk((const double*)P.items[it].A, d1, r1, r2) *
+             blk((const double*)P.items[it].B, d2, p1, p2);
+  if (r1 == r2)
+    for (int it = P.item0[1]; it < P.item0[1] + P.nitem[1]; it++)
+      acc += P.items[it].coef * blk((const double*)P.items[it].A, d0, l1, l2) *
+             blk((const double*)P.items[it].B, d2, p1, p2);
+  if (p1 == p2)
+    for (int it = P.item0[2]; it < P.item0[2] + P.nitem[2]; it++)
+      acc += P.items[it].coef * blk((const double*)P.items[it].A, d0, l1, l2) *
+             blk((const double*)P.items[it].B, d1, r1, r2);
+  for (int it = 0; it < P.n3; it++) {
+    const Item3& q = P.items3[it];
+    acc += q.coef * blk((const double*)q.op[0], d0, l1, l2) * blk((const double*)q.op[1], d1, r1, r2) *
+           blk((const double*)q.op[2], d2, p1, p2);
+  }
+  H[e] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_tiny_lanczos(const double* __restrict__ H, int M,
+                                                      double* __restrict__ T,
+                                                      double* __restrict__ V,
+                                                      double* __restrict__ w,
+                                                      KrylovState* __restrict__ st, int k) {
+  __shared__ double red[4];
+  __shared__ double hs[64];
+  __shared__ double xs[1024];
+  __shared__ double tri_lds[512];
+  const int t = threadIdx.x;
+  if (t == 0) { st->kmax = k; st->keff = 1; st->stop = 0; st->status = 0; }
+  double s2 = 0;
+  for (int e = t; e < M; e += 256) s2 += T[e] * T[e];
+  const double nrm = sqrt(block_sum(s2, red));
+  for (int e = t; e < M; e += 256) V[e] = T[e] / nrm;
+  __syncthreads();
+  double beta_prev = 0, amax = 0;
+  int keff = 1;
+  for (int j = 0; j < k; j++) {
+    const double* vj = V + (int64_t)j * M;
+    for (int e = t; e < M; e += 256) xs[e] = vj[e];
+    __syncthreads();
+    for (int i = t; i < M; i += 256) {   // w = H v_j
+      double acc = 0;
+      for (int c = 0; c < M; c++) acc += H[(int64_t)c * M + i] * xs[c];
+      w[i] = acc;
+    }
+    __syncthreads();
+    double a = 0;
+    for (int e = t; e < M; e += 256) a += xs[e] * w[e];
+    a = block_sum(a, red);
+    if (t == 0) st->alpha[j] = a;
+    amax = fmax(amax, fabs(a));
+    if (j == k - 1) break;
+    const double* vm = j > 0 ? V + (int64_t)(j - 1) * M : V;
+    for (int e = t; e < M; e += 256) {
+      double xv = w[e] - a * xs[e];
+      if (j > 0) xv -= beta_prev * vm[e];
+      w[e] = xv;
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 2; pass++) {
+      for (int i = 0; i <= j; i++) {
+        double d = 0;
+        for (int e = t; e < M; e += 256) d += V[(int64_t)i * M + e] * w[e];
+        d = block_sum(d, red);
+        if (t == 0) hs[i] = d;
+      }
+      __syncthreads();
+      for (int e = t; e < M; e += 256) {
+        double xv = w[e];
+        for (int i = 0; i <= j; i++) xv -= hs[i] * V[(int64_t)i * M + e];
+        w[e] = xv;
+      }
+      __syncthreads();
+    }
+    double b2 = 0;
+    for (int e = t; e < M; e += 256) b2 += w[e] * w[e];
+    const double b = sqrt(block_sum(b2, red));
+    if (!(b > 1e-14 * amax)) break;
+    if (t == 0) st->beta[j] = b;
+    beta_prev = b;
+    keff = j + 2;
+    for (int e = t; e < M; e += 256) V[(int64_t)(j + 1) * M + e] = w[e] / b;
+    __syncthreads();
+  }
+  if (t == 0) st->keff = keff;
+  __syncthreads();
+  if (t < 64) tridiag_solve_wave(st, tri_lds);
+  __syncthreads();
+  const int kk = keff;
+  if (t < kk) hs[t] = st->y[t];
+  __syncthreads();
+  double n2 = 0;
+  for (int e = t; e < M; e += 256) {
+    double xv = 0;
+    for (int i = 0; i < kk; i++) xv += hs[i] * V[(int64_t)i * M + e];
+    w[e] = xv;
+    n2 += xv * xv;
+  }
+  const double nr = sqrt(block_sum(n2, red));
+  for (int e = t; e < M; e += 256) T[e] = w[e] / nr;
+  if (t == 0 && !(nr > 0 && isfinite(nr))) st->status = 1;
 }
 
 // out = sum_i y_i V_i with partial ||out||^2
@@ -641,18 +951,87 @@ __global__ __launch_bounds__(256) void k_ritz(const double* __restrict__ V, int6
 }
 
 // ============================================================================ QR helpers
-// Cholesky of G + shift*I = R^T R (R upper, positive diagonal) and the row-major
-// inverse of R, one workgroup.  G column-major n x n (symmetric).
-// shift_mode 1: shift = 11 (rows n + n (n + 1)) u trace(G) (shifted CholeskyQR).
+// Cholesky of G + shift*I = L L^T (R = L^T upper with positive diagonal) and
+// the inverse of R, one workgroup.  L and X = L^{-1} are kept in LDS as packed
+// lower triangles (n (n + 1) doubles in total, n <= 128).  G is column-major.
+// Outputs: R column-major, RinvRow = R^{-1} row-major (= X^T column-major).
+// shift_mode 1: shift = 11 (rows n + n (n + 1)) u trace(G) (shifted CholeskyQR
+// of Fukaya et al.), making the factorisation safe for ill-conditioned input.
+__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// (a) n = 16, 32, 48 or 64: one wavefront, lane j keeps column j of L (and
+//     later column j of L^{-1}) in registers; column k is published in LDS at
+//     step k and every lane updates its own column from broadcast reads.
+template <int N>
+__global__ __launch_bounds__(64) void k_chol_inv_reg(const double* __restrict__ G,
+                                                     double* __restrict__ R,
+                                                     double* __restrict__ RinvRow, int shift_mode,
+                                                     int64_t rows, KrylovState* __restrict__ st) {
+  __shared__ double Ls[N * N];
+  const int lane = threadIdx.x;
+  double tr = (lane < N) ? G[(int64_t)lane * N + lane] : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
+  const double shift =
+      shift_mode ? 11.0 * ((double)rows * N + (double)N * (N + 1)) * 1.1102230246251565e-16 * tr : 0.0;
+  double c[N];
+#pragma unroll
+  for (int i = 0; i < N; i++)
+    c[i] = (lane < N && i >= lane) ? G[(int64_t)lane * N + i] + (i == lane ? shift : 0.0) : 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int k = 0; k < N; k++) {
+    if (lane == k) {
+      if (!(c[k] > 0.0) || !isfinite(c[k])) bad = 1;
+      const double piv = sqrt(fmax(c[k], 1e-300));
+      const double inv = 1.0 / piv;
+      c[k] = piv;
+#pragma unroll
+      for (int i = k + 1; i < N; i++) c[i] *= inv;
+#pragma unroll
+      for (int i = k; i < N; i++) Ls[i * N + k] = c[i];
+    }
+    wave_sync();
+    if (lane > k && lane < N) {
+      const double ljk = Ls[lane * N + k];
+#pragma unroll
+      for (int i = k + 1; i < N; i++)
+        if (i >= lane) c[i] -= Ls[i * N + k] * ljk;
+    }
+  }
+  wave_sync();
+  // column lane of X = L^{-1} by forward substitution
+  double x[N];
+#pragma unroll
+  for (int i = 0; i < N; i++) {
+    double v = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < i; j++)
+      if (j >= lane) v -= Ls[i * N + j] * x[j];
+    x[i] = (i >= lane) ? v / Ls[i * N + i] : 0.0;
+  }
+  if (lane < N) {
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+      R[(int64_t)lane * N + i] = (i <= lane) ? Ls[lane * N + i] : 0.0;   // R = L^T, column lane
+      RinvRow[(int64_t)lane * N + i] = x[i];                              // row lane of R^{-1}
+    }
+  }
+  if (bad && st) st->status = 2;
+}
+
+// (b) other n (<= 128): LDS-resident packed triangles, rank-1 updates over a
+//     16 x 16 thread grid.
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, int n,
                                                   double* __restrict__ R,
                                                   double* __restrict__ RinvRow, int shift_mode,
                                                   int64_t rows, KrylovState* __restrict__ st) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* L = reinterpret_cast<double*>(smem_raw);   // n x n, L[i * n + j] lower
+  double* L = reinterpret_cast<double*>(smem_raw);
+  double* X = L + n * (n + 1) / 2;
   __shared__ double shift;
   __shared__ int bad;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
   if (t == 0) {
     bad = 0;
     double tr = 0;
@@ -660,58 +1039,150 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, 
     shift = shift_mode ? 11.0 * ((double)rows * n + (double)n * (n + 1)) * 1.1102230246251565e-16 * tr : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < n * n; e += 256) {
-    const int i = e / n, j = e - i * n;
-    L[e] = G[(int64_t)j * n + i] + (i == j ? shift : 0.0);
-  }
+  for (int i = ty; i < n; i += 16)
+    for (int j = tx; j <= i; j += 16) {
+      L[tri(i, j)] = G[(int64_t)j * n + i] + (i == j ? shift : 0.0);
+      X[tri(i, j)] = (i == j) ? 1.0 : 0.0;
+    }
   __syncthreads();
   for (int k = 0; k < n; k++) {
+    const double dkk = L[tri(k, k)];
+    const double piv = sqrt(fmax(dkk, 1e-300));
+    const double inv = 1.0 / piv;
+    __syncthreads();
     if (t == 0) {
-      const double dkk = L[k * n + k];
       if (!(dkk > 0.0) || !isfinite(dkk)) bad = 1;
-      L[k * n + k] = sqrt(fmax(dkk, 1e-300));
+      L[tri(k, k)] = piv;
     }
+    for (int i = k + 1 + t; i < n; i += 256) L[tri(i, k)] *= inv;
     __syncthreads();
-    const double piv = L[k * n + k];
-    for (int i = k + 1 + t; i < n; i += 256) L[i * n + k] /= piv;
-    __syncthreads();
-    for (int e = t; e < (n - k - 1) * (n - k - 1); e += 256) {
-      const int i = k + 1 + e / (n - k - 1), j = k + 1 + e % (n - k - 1);
-      if (j <= i) L[i * n + j] -= L[i * n + k] * L[j * n + k];
+    for (int i = k + 1 + ty; i < n; i += 16) {
+      const double lik = L[tri(i, k)];
+      for (int j = k + 1 + tx; j <= i; j += 16) L[tri(i, j)] -= lik * L[tri(j, k)];
     }
     __syncthreads();
   }
-  // R = L^T (column-major R[i][j] at j * n + i), zero below the diagonal
-  for (int e = t; e < n * n; e += 256) {
-    const int j = e / n, i = e - j * n;
-    R[e] = (i <= j) ? L[j * n + i] : 0.0;
-  }
-  // inverse of R (upper): column c of Rinv solves R x = e_c; thread per column
-  for (int c = t; c < n; c += 256) {
-    for (int i = n - 1; i >= 0; i--) {
-      double x = (i == c) ? 1.0 : 0.0;
-      if (i > c) x = 0.0;
-      else {
-        for (int j = i + 1; j <= c; j++) x -= L[j * n + i] * RinvRow[(int64_t)j * n + c];
-        x /= L[i * n + i];
-      }
-      RinvRow[(int64_t)i * n + c] = x;   // row-major Rinv
+  for (int k = 0; k < n; k++) {
+    const double inv = 1.0 / L[tri(k, k)];
+    for (int c = t; c <= k; c += 256) X[tri(k, c)] *= inv;
+    __syncthreads();
+    for (int i = k + 1 + ty; i < n; i += 16) {
+      const double lik = L[tri(i, k)];
+      for (int c = tx; c <= k; c += 16) X[tri(i, c)] -= lik * X[tri(k, c)];
     }
+    __syncthreads();
   }
-  __syncthreads();
+  for (int j = ty; j < n; j += 16)
+    for (int i = tx; i < n; i += 16) {
+      R[(int64_t)j * n + i] = (i <= j) ? L[tri(j, i)] : 0.0;
+      RinvRow[(int64_t)i * n + j] = (i <= j) ? X[tri(j, i)] : 0.0;
+    }
   if (t == 0 && bad && st) st->status = 2;
 }
 
-// C = A B for n x n column-major matrices (one workgroup)
-__global__ __launch_bounds__(256) void k_small_matmul(const double* __restrict__ A,
-                                                      const double* __restrict__ B,
-                                                      double* __restrict__ C, int n) {
-  for (int e = threadIdx.x; e < n * n; e += 256) {
-    const int j = e / n, i = e - j * n;
-    double acc = 0;
-    for (int k = 0; k < n; k++) acc += A[(int64_t)k * n + i] * B[(int64_t)j * n + k];
-    C[e] = acc;
+// Householder QR of a small matricisation in one workgroup (rows * n <= 16384,
+// n <= 64): A[f][j] = T[.. j ..] with j the column leg.  The matrix lives in
+// LDS (column-major); reflectors as in LAPACK's geqr2, Q formed in place as in
+// org2r, then the signs are fixed so that diag(R) >= 0.  Q overwrites T, R
+// (column-major n x n) goes to Rout.
+__global__ __launch_bounds__(256) void k_qr_small(double* __restrict__ T, int d0, int d1, int d2,
+                                                  int j, double* __restrict__ Rout,
+                                                  KrylovState* __restrict__ st) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* A = reinterpret_cast<double*>(smem_raw);
+  __shared__ double tau[64];
+  __shared__ double red[4];
+  __shared__ double sgn[64];
+  const int n = j == 0 ? d0 : (j == 1 ? d1 : d2);
+  const int64_t rows = (int64_t)d0 * d1 * d2 / n;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  for (int64_t e = t; e < rows * n; e += 256) {
+    const int c = (int)(e / rows);
+    const int64_t f = e - (int64_t)c * rows;
+    A[e] = T[mode_addr(j, d0, d1, d2, c, f)];
   }
+  __syncthreads();
+  const int kmax = (int)(rows < n ? rows : n);
+  for (int k = 0; k < kmax; k++) {
+    double* col = A + (int64_t)k * rows;
+    double s2 = 0;
+    for (int64_t i = k + 1 + t; i < rows; i += 256) s2 += col[i] * col[i];
+    s2 = block_sum(s2, red);
+    const double alpha = col[k];
+    double tk = 0, beta = alpha, scale = 0;
+    if (s2 > 0) {
+      beta = -copysign(sqrt(alpha * alpha + s2), alpha);
+      tk = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    if (s2 > 0) for (int64_t i = k + 1 + t; i < rows; i += 256) col[i] *= scale;
+    if (t == 0) { col[k] = beta; tau[k] = tk; }
+    __syncthreads();
+    if (tk != 0.0) {
+      // apply H_k = I - tau v v^T (v_k = 1) to columns c > k; one wave per column
+      for (int c = k + 1 + wave; c < n; c += 4) {
+        double* cc = A + (int64_t)c * rows;
+        double w = 0;
+        for (int64_t i = k + lane; i < rows; i += 64) w += (i == k ? 1.0 : col[i]) * cc[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+        w *= tk;
+        for (int64_t i = k + lane; i < rows; i += 64) cc[i] -= w * (i == k ? 1.0 : col[i]);
+      }
+    }
+    __syncthreads();
+  }
+  // R and its sign fix
+  for (int e = t; e < n * n; e += 256) {
+    const int c = e / n, r = e - c * n;
+    Rout[e] = (r <= c && r < kmax) ? A[(int64_t)c * rows + r] : 0.0;
+  }
+  if (t < n) sgn[t] = (t < kmax && A[(int64_t)t * rows + t] < 0) ? -1.0 : 1.0;
+  __syncthreads();
+  for (int e = t; e < n * n; e += 256) {
+    const int r = e % n;
+    Rout[e] *= sgn[r];
+  }
+  // form Q in place (org2r), columns from last to first
+  for (int k = kmax - 1; k >= 0; k--) {
+    double* col = A + (int64_t)k * rows;
+    const double tk = tau[k];
+    if (k < n - 1) {
+      for (int c = k + 1 + wave; c < n; c += 4) {
+        double* cc = A + (int64_t)c * rows;
+        double w = 0;
+        for (int64_t i = k + lane; i < rows; i += 64) w += (i == k ? 1.0 : col[i]) * cc[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off, 64);
+        w *= tk;
+        for (int64_t i = k + lane; i < rows; i += 64) cc[i] -= w * (i == k ? 1.0 : col[i]);
+      }
+    }
+    __syncthreads();
+    for (int64_t i = k + 1 + t; i < rows; i += 256) col[i] *= -tk;
+    if (t == 0) col[k] = 1.0 - tk;
+    for (int i = t; i < k; i += 256) col[i] = 0.0;
+    __syncthreads();
+  }
+  for (int64_t e = t; e < rows * n; e += 256) {
+    const int c = (int)(e / rows);
+    const int64_t f = e - (int64_t)c * rows;
+    T[mode_addr(j, d0, d1, d2, c, f)] = A[e] * sgn[c];
+  }
+  if (t == 0 && st && !isfinite(tau[0])) st->status = 2;
+}
+
+// C = A B for n x n column-major matrices, one thread per output element
+__global__ __launch_bounds__(64) void k_small_matmul(const double* __restrict__ A,
+                                                     const double* __restrict__ B,
+                                                     double* __restrict__ C, int n) {
+  const int e = blockIdx.x * 64 + threadIdx.x;
+  if (e >= n * n) return;
+  const int j = e / n, i = e - j * n;
+  double acc = 0;
+  for (int k = 0; k < n; k++) acc += A[(int64_t)k * n + i] * B[(int64_t)j * n + k];
+  C[e] = acc;
 }
 
 // ============================================================================ launchers
@@ -948,6 +1419,50 @@ hipError_t launch_scale_into(const double* w, double* out, int64_t n, KrylovStat
   return hipGetLastError();
 }
 
+hipError_t launch_state_init(KrylovState* st, int kmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(256), 0, s, st, kmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos_update2(double* w, const double* V, int64_t n, KrylovState* st, int j,
+                                  const double* partial_a, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_lanczos_update2, dim3(kRedBlocks), dim3(256), 0, s, w, V, n, st, j,
+                     partial_a, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_dots2(double* w, const double* V, int nv, int64_t n, KrylovState* st,
+                             const double* partial_in, double* partial, int norm_only,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dots2, dim3(kRedBlocks), dim3(256), 0, s, w, V, nv, n, st,
+                     partial_in, partial, norm_only);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_beta(const double* w, double* out, int64_t n, KrylovState* st, int j,
+                             const double* partial, hipStream_t s) {
+  int64_t g = grid1(n);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_scale_beta, dim3((unsigned)g), dim3(256), 0, s, w, out, n, st, j, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_norm(const double* x, double* out, int64_t n, const double* partial,
+                             KrylovState* st, hipStream_t s) {
+  int64_t g = grid1(n);
+  if (g > 1024) g = 1024;
+  hipLaunchKernelGGL(k_scale_norm, dim3((unsigned)g), dim3(256), 0, s, x, out, n, partial, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_tiny_lanczos(const TinyPlan* plan, int M, double* H, double* T, double* V,
+                               double* w, KrylovState* st, int k, hipStream_t s) {
+  hipLaunchKernelGGL(k_tiny_assemble, dim3((unsigned)(((int64_t)M * M + 255) / 256)), dim3(256), 0, s,
+                     plan, H);
+  hipLaunchKernelGGL(k_tiny_lanczos, dim3(1), dim3(256), 0, s, H, M, T, V, w, st, k);
+  return hipGetLastError();
+}
+
 hipError_t launch_tridiag(KrylovState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
@@ -975,19 +1490,39 @@ hipError_t launch_normalize(double* x, int64_t n, double* partial, KrylovState* 
 
 hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, int shift_mode,
                            int64_t rows, KrylovState* st, hipStream_t s) {
+  switch (n) {
+    case 16: hipLaunchKernelGGL(k_chol_inv_reg<16>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
+    case 32: hipLaunchKernelGGL(k_chol_inv_reg<32>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
+    case 48: hipLaunchKernelGGL(k_chol_inv_reg<48>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
+    case 64: hipLaunchKernelGGL(k_chol_inv_reg<64>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
+    default: break;
+  }
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        150 * 1024);
+                              150 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), (size_t)n * n * sizeof(double), s, G, n, R,
-                     RinvRow, shift_mode, rows, st);
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), (size_t)n * (n + 1) * sizeof(double), s, G,
+                     n, R, RinvRow, shift_mode, rows, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_small(double* T, int d0, int d1, int d2, int j, double* Rout, KrylovState* st,
+                           hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_qr_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              150 * 1024);
+    attr_set = true;
+  }
+  const size_t lds = (size_t)d0 * d1 * d2 * sizeof(double);
+  hipLaunchKernelGGL(k_qr_small, dim3(1), dim3(256), lds, s, T, d0, d1, d2, j, Rout, st);
   return hipGetLastError();
 }
 
 hipError_t launch_small_matmul(const double* A, const double* B, double* C, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_small_matmul, dim3(1), dim3(256), 0, s, A, B, C, n);
+  hipLaunchKernelGGL(k_small_matmul, dim3((unsigned)((n * n + 63) / 64)), dim3(64), 0, s, A, B, C, n);
   return hipGetLastError();
 }
 

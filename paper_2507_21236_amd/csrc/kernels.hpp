@@ -95,4 +95,21 @@ struct CVTask {
   int64_t n;
 };
 
+// ---------------------------------------------------------------- tiny nodes
+// Whole matvec plan of a node whose contractions all use the generic kernels,
+// executed inside one workgroup (see k_tiny_lanczos).
+// Three-operator product item (one operator per leg) of a three-leg term.
+struct Item3 {
+  const void* op[3];
+  double coef;
+};
+
+struct TinyPlan {
+  const SWItem* items;  // two-leg terms and local operators, grouped by spectator
+  const Item3* items3;  // three-leg terms expanded into products
+  int32_t item0[3], nitem[3];
+  int32_t n3;
+  int32_t d0, d1, d2;
+};
+
 }  // namespace attn

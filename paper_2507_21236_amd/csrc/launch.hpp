@@ -51,14 +51,29 @@ hipError_t launch_axpy_dots(double* w, const double* V, int nv, int64_t n, Krylo
 hipError_t launch_scale_into(const double* w, double* out, int64_t n, KrylovState* st, int which,
                              int j, hipStream_t s);
 hipError_t launch_tridiag(KrylovState* st, hipStream_t s);
+hipError_t launch_tiny_lanczos(const TinyPlan* plan, int M, double* H, double* T, double* V,
+                               double* w, KrylovState* st, int k, hipStream_t s);
 hipError_t launch_ritz(const double* V, int64_t n, double* out, KrylovState* st, double* partial,
                        hipStream_t s);
 hipError_t launch_normalize(double* x, int64_t n, double* partial, KrylovState* st, hipStream_t s);
 hipError_t launch_norm2(const double* x, int64_t n, double* partial, hipStream_t s);
 
+hipError_t launch_state_init(KrylovState* st, int kmax, hipStream_t s);
+hipError_t launch_lanczos_update2(double* w, const double* V, int64_t n, KrylovState* st, int j,
+                                  const double* partial_a, double* partial, hipStream_t s);
+hipError_t launch_axpy_dots2(double* w, const double* V, int nv, int64_t n, KrylovState* st,
+                             const double* partial_in, double* partial, int norm_only,
+                             hipStream_t s);
+hipError_t launch_scale_beta(const double* w, double* out, int64_t n, KrylovState* st, int j,
+                             const double* partial, hipStream_t s);
+hipError_t launch_scale_norm(const double* x, double* out, int64_t n, const double* partial,
+                             KrylovState* st, hipStream_t s);
+
 // QR helpers
 hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, int shift_mode,
                            int64_t rows, KrylovState* st, hipStream_t s);
+hipError_t launch_qr_small(double* T, int d0, int d1, int d2, int j, double* Rout, KrylovState* st,
+                           hipStream_t s);
 hipError_t launch_small_matmul(const double* A, const double* B, double* C, int n, hipStream_t s);
 
 }  // namespace attn

@@ -792,6 +792,20 @@ attn_status build_model(const attn_problem* p, Model& M, std::string& err) {
       }
     }
   }
+  // ---- the root's parent leg has dimension 1: an item with no operator on it
+  //      is the same contraction with p as the (single-slice) spectator, which
+  //      keeps both contracted legs at full size
+  auto to_spect_p = [](Item2& it) {
+    if (it.spect == 2 || !it.B.is_none()) return;
+    if (it.spect == 0) { it.B = it.A; it.A = BRef::none(); }   // op on r
+    it.spect = 2;                                             // spect 1: op on l stays A
+  };
+  if (tr.nodes[tr.root].dims[2] == 1) {
+    for (Item2& it : M.mv[tr.root].items) to_spect_p(it);
+    for (int sd = 0; sd < 2; sd++)
+      for (EnvOut& o : M.env_down[sd][tr.root].outs)
+        for (Item2& it : o.items) to_spect_p(it);
+  }
   return ATTN_OK;
 }
 

@@ -42,6 +42,7 @@ struct StatusFail {
 // A sandwich launch group: tasks with the same (ma, mb).
 struct SWGroup {
   int ma = 0, mb = 0;
+  double flops = 0;   // algorithmic flops of one launch
   std::vector<SWTask> tasks;
   std::vector<SWItem> items;
   std::vector<int4> wus;
@@ -79,6 +80,10 @@ struct GRPlan {
 };
 
 struct MVDev {
+  TinyPlan* d_tiny = nullptr;   // set when the whole plan runs in one workgroup
+  std::vector<SWItem> tiny_items;
+  int tiny_item0[3] = {0, 0, 0}, tiny_nitem[3] = {0, 0, 0};
+  std::vector<Item3> tiny_items3;
   CBPlan comb;
   std::vector<SWGroup> sw;
   std::vector<MPGroup> chainA, chainB, chainC;   // one group per mj
@@ -186,6 +191,13 @@ struct attn_handle {
   std::vector<ABDev> ab[3];   // absorb into node along leg
   // counters
   int64_t n_matvec = 0, n_env = 0, n_qr = 0;
+  double mv_flops = 0;
+  // live timing of the matvec sandwich launches (HIP events on the launch stream)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct ProfRec { int a, b; double flops; int ma, mb; };
+  std::vector<ProfRec> prof_recs;
 };
 
 namespace {
@@ -271,6 +283,9 @@ void add_sw_task(SWGroup& g, SWTask t, int ns) {
   g.mb = t.mb;
   const int ti = (int)g.tasks.size();
   g.tasks.push_back(t);
+  const double M = (double)ns * t.ma * t.mb;
+  for (int i = t.item0; i < t.item0 + t.nitem; i++)
+    g.flops += 2.0 * M * ((g.items[i].A ? t.ma : 0) + (g.items[i].B ? t.mb : 0));
   if (sw_mfma(t.ma, t.mb)) {
     for (int s = 0; s < ns; s++)
       for (int st = 0; st < t.ma / 16; st += 4) g.wus.push_back(make_int4(ti, s, st, 0));
@@ -366,7 +381,8 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
       if (i1 == i0) continue;
       SWTask t;
       std::memset(&t, 0, sizeof(t));
-      t.x = sp == 2 ? (const void*)h->d_xt : nullptr;
+      const bool trans = sp == 2 && dm[2] > 1;   // [p][l][r] == [l][r][p] when m_p = 1
+      t.x = trans ? (const void*)h->d_xt : nullptr;
       t.y = h->d_part + part_used;
       t.xs_slice = sl; t.xs_row = row; t.ys_slice = sl; t.ys_row = row;
       t.ma = ma; t.mb = mb;
@@ -381,9 +397,9 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
       t.nitem = (int)(i1 - i0);
       t.accumulate = 0;
       add_sw_task(g, t, ns);
-      D.srcs.push_back({h->d_part + part_used, sp == 2 ? 1 : 0, 0});
+      D.srcs.push_back({h->d_part + part_used, trans ? 1 : 0, 0});
       part_used += Msz;
-      if (sp == 2) D.need_xt = true;
+      if (trans) D.need_xt = true;
     }
   }
   // three-leg chains
@@ -435,6 +451,42 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
   upload_mp(h, D.chainB);
   upload_mp(h, D.chainC);
   D.d_srcs = upload(h, D.srcs);
+  // tiny nodes: H_eff assembled densely (M <= 1024)
+  if (Msz <= 1024) {
+    TinyPlan tp;
+    std::memset(&tp, 0, sizeof(tp));
+    std::vector<SWItem> titems;
+    for (int sp = 0; sp < 3; sp++) {
+      tp.item0[sp] = (int)titems.size();
+      for (const Item2& it : P.items)
+        if (it.spect == sp)
+          titems.push_back({block_ptr(h, it.A, h->d_mvcomb, off), block_ptr(h, it.B, h->d_mvcomb, off), it.coef});
+      tp.nitem[sp] = (int)titems.size() - tp.item0[sp];
+    }
+    tp.items = upload(h, titems);
+    D.tiny_items = titems;
+    for (int sp = 0; sp < 3; sp++) { D.tiny_item0[sp] = tp.item0[sp]; D.tiny_nitem[sp] = tp.nitem[sp]; }
+    std::vector<Item3> it3;
+    for (const Chain& ch : P.chains) {
+      const int t2 = (int)ch.O2.size();
+      for (size_t a = 0; a < ch.O1.size(); a++)
+        for (int c = 0; c < t2; c++) {
+          const BRef& mid = ch.Mid[a * t2 + c];
+          if (mid.is_zero()) continue;
+          Item3 q;
+          q.op[ch.o1] = block_ptr(h, ch.O1[a], h->d_mvcomb, off);
+          q.op[ch.mid] = block_ptr(h, mid, h->d_mvcomb, off);
+          q.op[ch.o2] = block_ptr(h, ch.O2[c], h->d_mvcomb, off);
+          q.coef = 1.0;
+          it3.push_back(q);
+        }
+    }
+    tp.items3 = upload(h, it3);
+    D.tiny_items3 = it3;
+    tp.n3 = (int)it3.size();
+    tp.d0 = dm[0]; tp.d1 = dm[1]; tp.d2 = dm[2];
+    D.d_tiny = upload(h, std::vector<TinyPlan>{tp});
+  }
 }
 
 int64_t env_chunk_outputs(attn_handle* h, int64_t Msz) {
@@ -447,12 +499,17 @@ void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
   const Model& M = h->M;
   const Node& nd = M.tree.nodes[P.node];
   // toward the parent the tensor is first transposed to [p][l][r] so that the
-  // (l, r) slices are contiguous; the contracted leg is then the first one
+  // (l, r) slices are contiguous; the contracted leg is then the first one.
+  // At the root (m_p = 1) the items may use p as spectator: no transpose needed.
+  int spect = P.leg;
+  for (const EnvOut& o : P.outs)
+    if (!o.items.empty()) { spect = o.items[0].spect; break; }
   const bool tr_in = P.leg == 2;
   const int dm[3] = {tr_in ? nd.dims[2] : nd.dims[0], tr_in ? nd.dims[0] : nd.dims[1],
                      tr_in ? nd.dims[1] : nd.dims[2]};
   const int64_t Msz = (int64_t)dm[0] * dm[1] * dm[2];
   const int j = tr_in ? 0 : P.leg;
+  const int sw_spect = tr_in ? 0 : spect;
   const int mj = dm[j];
   D.transpose = tr_in;
   std::copy(nd.dims, nd.dims + 3, D.dims);
@@ -476,7 +533,7 @@ void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
   const int nfc = (int)(F / fchunk);
   int ma, mb, ns;
   int64_t sl, row;
-  slice_geom(j, dm, ma, mb, ns, sl, row);
+  slice_geom(sw_spect, dm, ma, mb, ns, sl, row);
   for (size_t o0 = 0; o0 < P.outs.size(); o0 += per) {
     const size_t o1 = std::min(P.outs.size(), o0 + (size_t)per);
     EnvChunk ch;
@@ -535,6 +592,32 @@ void run_sw(std::vector<SWGroup>& gs, int dtype, const void* xbase, hipStream_t 
     HIPCHK(launch_sandwich(dtype, g.ma, g.mb, g.d_tasks, g.d_items, g.d_wus, (int)g.wus.size(), xbase, s));
 }
 
+hipEvent_t next_event(attn_handle* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// matvec sandwich launches, bracketed by events when profiling
+void run_sw_mv(attn_handle* h, std::vector<SWGroup>& gs, int dtype, const void* xbase, hipStream_t s) {
+  for (auto& g : gs) {
+    int a = -1, b = -1;
+    if (h->prof && h->ev_used + 2 <= (size_t)1 << 20) {
+      a = (int)h->ev_used;
+      HIPCHK(hipEventRecord(next_event(h), s));
+    }
+    HIPCHK(launch_sandwich(dtype, g.ma, g.mb, g.d_tasks, g.d_items, g.d_wus, (int)g.wus.size(), xbase, s));
+    if (a >= 0) {
+      b = (int)h->ev_used;
+      HIPCHK(hipEventRecord(next_event(h), s));
+      h->prof_recs.push_back({a, b, g.flops, g.ma, g.mb});
+    }
+  }
+}
+
 void run_mp(std::vector<MPGroup>& gs, int dtype, const void* xbase, hipStream_t s) {
   for (auto& g : gs)
     HIPCHK(launch_mode(dtype, g.mj, g.mfma, g.d_tasks, g.d_jobs, g.d_wus, (int)g.wus.size(), xbase, s));
@@ -547,13 +630,14 @@ void matvec_f64(attn_handle* h, int n, const double* x, double* y, hipStream_t s
   run_mp(D.chainA, 0, x, s);
   run_mp(D.chainB, 0, x, s);
   run_mp(D.chainC, 0, x, s);
-  run_sw(D.sw, 0, x, s);
+  run_sw_mv(h, D.sw, 0, x, s);
   if (D.srcs.empty()) {
     HIPCHK(hipMemsetAsync(y, 0, (size_t)D.dims[0] * D.dims[1] * D.dims[2] * sizeof(double), s));
   } else {
     HIPCHK(launch_reduce_out(0, D.d_srcs, (int)D.srcs.size(), y, 0, D.dims[0], D.dims[1], D.dims[2], s));
   }
   h->n_matvec++;
+  h->mv_flops += (double)h->M.mv[n].flops;
 }
 
 int leg_toward(const Tree& tr, int a, int b) {
@@ -679,9 +763,21 @@ void build_ab_dev(attn_handle* h, int q, int leg, ABDev& A) {
 
 // QR of T_n with leg `leg` as the column index (shifted CholeskyQR followed by
 // two CholeskyQR passes): T_n <- Q in place, R (column-major) into d_qrR.
+bool qr_small_ok(const int* dm, int leg) {
+  const int64_t M = (int64_t)dm[0] * dm[1] * dm[2];
+  return dm[leg] <= 64 && M <= 4096;
+}
+
 void qr_node(attn_handle* h, int n, int leg, hipStream_t s) {
   QRDev& Q = h->qr[leg][n];
   if (!Q.present) throw StatusFail{ATTN_ERR_STATE, "internal: no QR plan for this leg"};
+  const Node& nd = h->M.tree.nodes[n];
+  if (qr_small_ok(nd.dims, leg)) {
+    HIPCHK(launch_qr_small(h->d_T + h->T_off[n], nd.dims[0], nd.dims[1], nd.dims[2], leg, h->d_qrR,
+                           h->d_st, s));
+    h->n_qr++;
+    return;
+  }
   const int mj = Q.mj;
   const int64_t nn = (int64_t)h->mmax * h->mmax;
   double* G = h->d_qrmat;
@@ -739,11 +835,7 @@ void check_state(attn_handle* h, hipStream_t s, const char* where) {
 }
 
 void reset_state(attn_handle* h, int kmax, hipStream_t s) {
-  KrylovState st;
-  std::memset(&st, 0, sizeof(st));
-  st.kmax = kmax;
-  st.keff = 1;
-  HIPCHK(hipMemcpyAsync(h->d_st, &st, sizeof(st), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_state_init(h->d_st, kmax, s));
 }
 
 attn_status need_device(attn_handle* h) {
@@ -760,11 +852,24 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
   double* T = h->d_T + h->T_off[n];
   double* V = h->d_V;
   double* w = h->d_w;
-  reset_state(h, k, s);
+  // four partial-sum areas (64 vectors x kRedBlocks each) used round robin
+  double* P[4];
+  for (int i = 0; i < 4; i++) P[i] = h->d_red + (int64_t)i * 64 * kRedBlocks;
   run_comb(D.comb, s);
-  HIPCHK(launch_norm2(T, Msz, h->d_red, s));
-  HIPCHK(launch_dot_final(h->d_red, 1, nullptr, 4, h->d_st, 0, s));
-  HIPCHK(launch_scale_into(T, V, Msz, h->d_st, 1, 0, s));
+  if (D.d_tiny && precision == ATTN_F64) {
+    HIPCHK(launch_tiny_lanczos(D.d_tiny, (int)Msz, h->d_tmp2, T, V, w, h->d_st, k, s));
+    h->n_matvec += k;
+    h->mv_flops += (double)k * h->M.mv[n].flops;
+    KrylovState st;
+    HIPCHK(hipMemcpyAsync(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st.status != 0 || !std::isfinite(st.scal[0])) throw StatusFail{ATTN_ERR_NUMERIC, "non-finite value in the eigensolver"};
+    if (nmv) *nmv = k;
+    return st.scal[0];
+  }
+  HIPCHK(launch_state_init(h->d_st, k, s));
+  HIPCHK(launch_norm2(T, Msz, P[0], s));
+  HIPCHK(launch_scale_norm(T, V, Msz, P[0], h->d_st, s));
   for (int j = 0; j < k; j++) {
     double* vj = V + (int64_t)j * Msz;
     if (precision == ATTN_F64) {
@@ -772,21 +877,19 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
     } else {
       throw StatusFail{ATTN_ERR_UNSUPPORTED, "precision form not available for this eigensolve"};
     }
-    HIPCHK(launch_multidot(vj, 1, w, Msz, h->d_red, h->d_st, s));
-    HIPCHK(launch_dot_final(h->d_red, 1, nullptr, 1, h->d_st, j, s));
-    if (j == k - 1) break;
-    HIPCHK(launch_lanczos_update(w, V, Msz, h->d_st, j, h->d_red, s));
-    HIPCHK(launch_dot_final(h->d_red, j + 1, nullptr, 2, h->d_st, j, s));
-    HIPCHK(launch_axpy_dots(w, V, j + 1, Msz, h->d_st, h->d_red, 0, s));
-    HIPCHK(launch_dot_final(h->d_red, j + 1, nullptr, 2, h->d_st, j, s));
-    HIPCHK(launch_axpy_dots(w, V, j + 1, Msz, h->d_st, h->d_red, 1, s));
-    HIPCHK(launch_dot_final(h->d_red, 1, nullptr, 3, h->d_st, j, s));
-    HIPCHK(launch_scale_into(w, V + (int64_t)(j + 1) * Msz, Msz, h->d_st, 0, j, s));
+    HIPCHK(launch_multidot(vj, 1, w, Msz, P[0], h->d_st, s));
+    if (j == k - 1) {
+      HIPCHK(launch_dot_final(P[0], 1, nullptr, 1, h->d_st, j, s));
+      break;
+    }
+    HIPCHK(launch_lanczos_update2(w, V, Msz, h->d_st, j, P[0], P[1], s));
+    HIPCHK(launch_axpy_dots2(w, V, j + 1, Msz, h->d_st, P[1], P[2], 0, s));
+    HIPCHK(launch_axpy_dots2(w, V, j + 1, Msz, h->d_st, P[2], P[3], 1, s));
+    HIPCHK(launch_scale_beta(w, V + (int64_t)(j + 1) * Msz, Msz, h->d_st, j, P[3], s));
   }
   HIPCHK(launch_tridiag(h->d_st, s));
-  HIPCHK(launch_ritz(V, Msz, T, h->d_st, h->d_red, s));
-  HIPCHK(launch_dot_final(h->d_red, 1, nullptr, 4, h->d_st, 0, s));
-  HIPCHK(launch_scale_into(T, T, Msz, h->d_st, 1, 0, s));
+  HIPCHK(launch_ritz(V, Msz, T, h->d_st, P[0], s));
+  HIPCHK(launch_scale_norm(T, T, Msz, P[0], h->d_st, s));
   KrylovState st;
   HIPCHK(hipMemcpyAsync(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -909,7 +1012,7 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
     h->d_w = alloc(h->Mmax);
     h->d_xt = alloc(h->Mmax);
     h->d_tmp = alloc(h->Mmax);
-    h->d_tmp2 = alloc(h->Mmax);
+    h->d_tmp2 = alloc(std::max<int64_t>(h->Mmax, (int64_t)1024 * 1024));
     h->d_x32 = (float*)alloc(h->Mmax);
     h->d_y32 = (float*)alloc(h->Mmax);
     h->part_cap = std::max<int64_t>(part_need, 1);
@@ -920,7 +1023,7 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
     h->d_envcomb = alloc(envcomb_need);
     h->d_Z = alloc(z_need);
     h->d_grpart = alloc(grp_need);
-    h->d_red = alloc((int64_t)128 * kRedBlocks);
+    h->d_red = alloc((int64_t)4 * 64 * kRedBlocks);
     for (int n = 0; n < nn; n++)
       for (int l = 0; l < 3; l++) h->mmax = std::max(h->mmax, tr.nodes[n].dims[l]);
     h->d_qrmat = alloc(6 * (int64_t)h->mmax * h->mmax);
@@ -971,6 +1074,7 @@ attn_status attn_destroy(attn_handle* h) {
     (void)hipSetDevice(h->device);
     (void)hipDeviceSynchronize();
     for (void* p : h->owned) (void)hipFree(p);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   }
   delete h;
   return ATTN_OK;
@@ -1014,12 +1118,46 @@ attn_status attn_get_center(const attn_handle* h, int32_t* node) {
   return ATTN_OK;
 }
 
-attn_status attn_counters(const attn_handle* h, int64_t* n_matvec, int64_t* n_env, int64_t* n_qr) {
+attn_status attn_counters(const attn_handle* h, int64_t* n_matvec, int64_t* n_env, int64_t* n_qr,
+                          double* matvec_flops) {
   if (!h) return ATTN_ERR_ARG;
   if (n_matvec) *n_matvec = h->n_matvec;
   if (n_env) *n_env = h->n_env;
   if (n_qr) *n_qr = h->n_qr;
+  if (matvec_flops) *matvec_flops = h->mv_flops;
   return ATTN_OK;
+}
+
+attn_status attn_profile(attn_handle* h, int32_t enable, int32_t min_dim, double* ms, double* flops,
+                         int64_t* launches) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    HIPCHK(hipSetDevice(h->device));
+    if (enable) {
+      h->prof = true;
+      h->ev_used = 0;
+      h->prof_recs.clear();
+      return ATTN_OK;
+    }
+    HIPCHK(hipDeviceSynchronize());
+    double tms = 0, tfl = 0;
+    int64_t nl = 0;
+    for (auto& r : h->prof_recs) {
+      if (std::min(r.ma, r.mb) < min_dim) continue;
+      float e = 0;
+      HIPCHK(hipEventElapsedTime(&e, h->ev_pool[r.a], h->ev_pool[r.b]));
+      tms += e;
+      tfl += r.flops;
+      nl++;
+    }
+    if (ms) *ms = tms;
+    if (flops) *flops = tfl;
+    if (launches) *launches = nl;
+    h->prof = false;
+    h->ev_used = 0;
+    h->prof_recs.clear();
+    return ATTN_OK;
+  });
 }
 
 attn_status attn_set_tensor(attn_handle* h, int32_t node, const double* host, int64_t len) {
@@ -1318,6 +1456,19 @@ extern "C" attn_status attn_validate(const attn_handle* h) {
     for (auto& g : D.chainB) c.mp(g, M, 8);
     for (auto& g : D.chainC) c.mp(g, M, 8);
     for (auto& sr : D.srcs) c.span(sr.p, M * 8, "reduce source");
+    if (D.d_tiny) {
+      if (M > 1024) c.fail("tiny node too large");
+      for (int sp = 0; sp < 3; sp++) {
+        const int64_t ma = sp == 0 ? D.dims[1] : D.dims[0], mb = sp == 2 ? D.dims[1] : D.dims[2];
+        for (int i = D.tiny_item0[sp]; i < D.tiny_item0[sp] + D.tiny_nitem[sp]; i++) {
+          if (D.tiny_items[i].A) c.span(D.tiny_items[i].A, ma * ma * 8, "tiny A");
+          if (D.tiny_items[i].B) c.span(D.tiny_items[i].B, mb * mb * 8, "tiny B");
+        }
+      }
+      for (auto& q : D.tiny_items3)
+        for (int l = 0; l < 3; l++) c.span(q.op[l], (int64_t)D.dims[l] * D.dims[l] * 8, "tiny op3");
+      c.span(h->d_tmp2, M * M * 8, "dense H_eff");
+    }
     if (D.need_xt) c.span(h->d_xt, M * 8, "transposed input");
     const EnvDev* eds[3] = {&h->env_up[n], &h->env_down[0][n], &h->env_down[1][n]};
     for (const EnvDev* E : eds) {
