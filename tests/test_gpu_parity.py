@@ -114,3 +114,31 @@ def test_uneven_instance_matvec():
             move_both(a, o, n)
             x = rng.standard_normal(o.T[n].shape)
             assert rel(gpu_matvec(a, n, x), o.matvec(n, x)) < 1e-12, (n, o.tree.dims[n])
+
+
+def test_sweep_prefix_16x16_node_by_node():
+    # the first 31 node visits of a sweep of the 16 x 16, m = 64 workload
+    # (every node shape, including three (64, 64, 64) nodes): eigenvalues and
+    # tensors stay within rounding of the oracle.  Over a whole random-start
+    # sweep the single-site updates amplify rounding through ill-conditioned
+    # centre matricisations, so whole-sweep energies are compared on the
+    # smaller instances only.
+    p = config_problem("ising16_m64")
+    a, o = make_pair(p)
+    for n in range(31):
+        move_both(a, o, n)
+        th_o = o.eigsolve(n)
+        th_a, _ = a.eigsolve(n)
+        assert abs(th_a - th_o) <= 1e-11 * abs(th_o), (n, th_a, th_o)
+        ta, to = a.get_tensor(n), o.T[n]
+        assert min(np.abs(ta - to).max(), np.abs(ta + to).max()) < 1e-8, n
+
+
+def test_matvec_heaviest_node_16x16():
+    p = config_problem("ising16_m64")
+    a, o = make_pair(p)
+    full = [n for n in range(o.tree.n_nodes) if o.tree.dims[n] == (64, 64, 64)]
+    n = max(full, key=o.flops)
+    move_both(a, o, n)
+    x = np.random.default_rng(5).standard_normal(o.T[n].shape)
+    assert rel(gpu_matvec(a, n, x), o.matvec(n, x)) < 1e-12
