@@ -40,6 +40,18 @@ template <typename T> __device__ __forceinline__ int drow(int g, int i);
 template <> __device__ __forceinline__ int drow<double>(int g, int i) { return g + 4 * i; }
 template <> __device__ __forceinline__ int drow<float>(int g, int i) { return 4 * g + i; }
 
+// accumulator row of item i in lane group g for the 16x16x32 BF16 product
+__device__ __forceinline__ int drow_bf(int g, int i) { return 4 * g + i; }
+// column held at position pos of a permuted 32-wide chunk, and its inverse
+__device__ __forceinline__ int bf_perm(int pos) {
+  const int j = pos & 7, g = (pos >> 3) & 3;
+  return (pos & ~31) + 16 * (j >> 2) + drow_bf(g, j & 3);
+}
+__device__ __forceinline__ int bf_pinv(int a) {
+  const int r = a & 15, h = (a >> 4) & 1;
+  return (a & ~31) + 8 * (r >> 2) + 4 * h + (r & 3);
+}
+
 // ============================================================================ sandwich
 // One work unit = (task, slice s, first 16-row strip).  The WG stages X_s in LDS;
 // wave w owns rows [16 (strip0 + w), +16) of Y_s.  Per item:
@@ -163,6 +175,125 @@ __global__ __launch_bounds__(256) void k_sandwich_gen(const SWTask* __restrict__
                                                       const T* __restrict__ xbase) {
   const int4 wu = wus[blockIdx.x];
   sandwich_gen_elem<T>(tasks[wu.x], items, wu.y, wu.z + threadIdx.x, xbase);
+}
+
+// ============================================================================ split-BF16 sandwich
+// Same contraction as k_sandwich with every operand split as hi + lo BF16 and
+// three 16x16x32 BF16 products (hi.hi + hi.lo + lo.hi) accumulated in FP32.
+// The K index of every product walks a 32-wide chunk in the order
+//   slot (g, j) of lane group g -> 32 c + 16 (j / 4) + drow_bf(g, j % 4),
+// which is how the stage-1 accumulators spread p over lane groups: stage 2 then
+// takes them as its B operand straight from registers.  Operator blocks come in
+// that order already (fmt 2 of k_convert); X_s is split and permuted in LDS.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_sandwich_bf2(const SWTask* __restrict__ tasks,
+                                                      const SWItem* __restrict__ items,
+                                                      const int4* __restrict__ wus,
+                                                      const float* __restrict__ xbase) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int4 wu = wus[blockIdx.x];
+  const SWTask& t = tasks[wu.x];
+  const int s = wu.y;
+  const int ma = t.ma;
+  constexpr int mb = 16 * NB;
+  const int lda = ma + 8;                      // LDS row = one column b of X_s
+  __bf16* xh = reinterpret_cast<__bf16*>(smem_raw);
+  __bf16* xl = xh + mb * lda;
+  const float* X = (t.x ? (const float*)t.x : xbase) + (int64_t)s * t.xs_slice;
+  for (int e = threadIdx.x; e < ma * mb; e += 256) {
+    const int a = e / mb, b = e - a * mb;
+    const float v = X[(int64_t)a * t.xs_row + b];
+    const __bf16 hi = (__bf16)v;
+    const __bf16 lo = (__bf16)(v - (float)hi);
+    const int pos = bf_pinv(a);
+    xh[b * lda + pos] = hi;
+    xl[b * lda + pos] = lo;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int strip = wu.z + wave;
+  if (strip * 16 >= ma) return;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int arow = strip * 16 + l16;
+  const int64_t mma = (int64_t)ma * ma, mmb = (int64_t)mb * mb;
+  f4 acc[NB];
+#pragma unroll
+  for (int q = 0; q < NB; q++) acc[q] = f4{0, 0, 0, 0};
+  const int iend = t.item0 + t.nitem;
+  for (int it = t.item0; it < iend; it++) {
+    const __bf16* A = (const __bf16*)items[it].A;
+    const __bf16* B = (const __bf16*)items[it].B;
+    const float coef = (float)items[it].coef;
+    f4 t1[NB];
+    if (A) {
+#pragma unroll
+      for (int q = 0; q < NB; q++) t1[q] = f4{0, 0, 0, 0};
+      const bf8* Ah = (const bf8*)(A + (int64_t)arow * ma + 8 * g);
+      const bf8* Al = (const bf8*)(A + mma + (int64_t)arow * ma + 8 * g);
+      for (int c = 0; c < ma / 32; c++) {
+        const bf8 ah = Ah[4 * c], al = Al[4 * c];
+#pragma unroll
+        for (int q = 0; q < NB; q++) {
+          const int off = (16 * q + l16) * lda + 32 * c + 8 * g;
+          const bf8 vh = *(const bf8*)(xh + off);
+          const bf8 vl = *(const bf8*)(xl + off);
+          t1[q] = mfma_bf(vh, ah, t1[q]);
+          t1[q] = mfma_bf(vh, al, t1[q]);
+          t1[q] = mfma_bf(vl, ah, t1[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NB; q++) t1[q] *= coef;
+    } else {
+      const int pa = bf_pinv(arow);
+#pragma unroll
+      for (int q = 0; q < NB; q++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          const int p = 16 * q + drow_bf(g, i);
+          t1[q][i] = ((float)xh[p * lda + pa] + (float)xl[p * lda + pa]) * coef;
+        }
+    }
+    if (B) {
+#pragma unroll
+      for (int c = 0; c < NB / 2; c++) {
+        bf8 th, tl;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const float v = t1[2 * c + j / 4][j % 4];
+          th[j] = (__bf16)v;
+          tl[j] = (__bf16)(v - (float)th[j]);
+        }
+#pragma unroll
+        for (int tq = 0; tq < NB; tq++) {
+          const int64_t off = (int64_t)(16 * tq + l16) * mb + 32 * c + 8 * g;
+          const bf8 bh = *(const bf8*)(B + off);
+          const bf8 bl = *(const bf8*)(B + mmb + off);
+          acc[tq] = mfma_bf(bh, th, acc[tq]);
+          acc[tq] = mfma_bf(bl, th, acc[tq]);
+          acc[tq] = mfma_bf(bh, tl, acc[tq]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; q++) acc[q] += t1[q];
+    }
+  }
+  float* Y = (float*)t.y + (int64_t)s * t.ys_slice + (int64_t)arow * t.ys_row;
+#pragma unroll
+  for (int q = 0; q < NB; q++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int c = 16 * q + drow_bf(g, i);
+      if (t.accumulate) Y[c] += acc[q][i];
+      else Y[c] = acc[q][i];
+    }
 }
 
 // ============================================================================ mode product
@@ -405,10 +536,26 @@ __global__ __launch_bounds__(256) void k_transpose_plr(const T* __restrict__ x, 
   xt[p * ml * mr + l * mr + r] = x[e];
 }
 
-__global__ __launch_bounds__(256) void k_convert_f32(const CVTask* __restrict__ tasks) {
+__global__ __launch_bounds__(256) void k_convert(const CVTask* __restrict__ tasks) {
   const CVTask& t = tasks[blockIdx.y];
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < t.n; e += (int64_t)gridDim.x * 256)
-    ((float*)t.dst)[e] = (float)t.src[e];
+  if (t.fmt == 1) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < t.n; e += (int64_t)gridDim.x * 256)
+      ((float*)t.dst)[e] = (float)t.src[e];
+    return;
+  }
+  // split BF16: thread per destination position (block, row i, permuted position)
+  const int m = t.m;
+  const int64_t mm = (int64_t)m * m;
+  __bf16* dst = (__bf16*)t.dst;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < t.n; e += (int64_t)gridDim.x * 256) {
+    const int64_t b = e / mm, r = e - b * mm;
+    const int i = (int)(r / m), pos = (int)(r - (int64_t)i * m);
+    const double x = t.src[b * mm + (int64_t)bf_perm(pos) * m + i];
+    const __bf16 hi = (__bf16)(float)x;
+    const __bf16 lo = (__bf16)(float)(x - (double)(float)hi);
+    dst[2 * b * mm + r] = hi;
+    dst[2 * b * mm + mm + r] = lo;
+  }
 }
 
 template <typename TS, typename TD>
@@ -1203,9 +1350,34 @@ static hipError_t sand_launch(const SWTask* tasks, const SWItem* items, const in
   return hipGetLastError();
 }
 
+template <int NB>
+static hipError_t sand_bf2_launch(const SWTask* tasks, const SWItem* items, const int4* wus, int nwu,
+                                  int ma, const void* xbase, hipStream_t s) {
+  const size_t lds = (size_t)2 * (16 * NB) * (ma + 8) * sizeof(__bf16);
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute((const void*)k_sandwich_bf2<NB>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL((k_sandwich_bf2<NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus,
+                     (const float*)xbase);
+  return hipGetLastError();
+}
+
 hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const SWItem* items,
                            const int4* wus, int nwu, const void* xbase, hipStream_t s) {
   if (nwu == 0) return hipSuccess;
+  if (dtype == 2) {
+    if (!(ma % 32 == 0 && mb % 32 == 0 && ma <= 128 && mb <= 128)) return hipErrorInvalidValue;
+    switch (mb / 32) {
+      case 1: return sand_bf2_launch<2>(tasks, items, wus, nwu, ma, xbase, s);
+      case 2: return sand_bf2_launch<4>(tasks, items, wus, nwu, ma, xbase, s);
+      case 3: return sand_bf2_launch<6>(tasks, items, wus, nwu, ma, xbase, s);
+      case 4: return sand_bf2_launch<8>(tasks, items, wus, nwu, ma, xbase, s);
+    }
+    return hipErrorInvalidValue;
+  }
   const bool mf = (ma % 16 == 0) && (mb % 16 == 0) && ma <= 128 && mb <= 128;
   if (dtype == 0) {
     if (!mf) {
@@ -1365,8 +1537,8 @@ hipError_t launch_convert(int dtype, const CVTask* tasks, int ntask, int64_t max
   if (ntask == 0) return hipSuccess;
   int64_t g = grid1(maxn);
   if (g > 1024) g = 1024;
-  if (dtype == 1) hipLaunchKernelGGL(k_convert_f32, dim3((unsigned)g, ntask), dim3(256), 0, s, tasks);
-  else return hipErrorInvalidValue;
+  (void)dtype;
+  hipLaunchKernelGGL(k_convert, dim3((unsigned)g, ntask), dim3(256), 0, s, tasks);
   return hipGetLastError();
 }
 

@@ -89,10 +89,17 @@ struct RDSrc {
 };
 
 // ---------------------------------------------------------------- conversion
+// fmt 1: FP64 -> FP32, same (column-major) layout.
+// fmt 2: FP64 -> split BF16 (x = hi + lo up to ~2^-17 |x|) for m x m blocks,
+//        m a multiple of 32: per block, the hi plane then the lo plane, each
+//        row-major with the columns of every 32-wide chunk permuted into the
+//        order in which the BF16 matrix-core kernels walk their K index.
 struct CVTask {
   const double* src;
-  void* dst;       // float (FP32) or two bf16 planes (hi then lo)
-  int64_t n;
+  void* dst;
+  int64_t n;       // elements
+  int32_t m;       // block dimension (fmt 2)
+  int32_t fmt;
 };
 
 // ---------------------------------------------------------------- tiny nodes

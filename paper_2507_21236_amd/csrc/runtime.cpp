@@ -42,6 +42,7 @@ struct StatusFail {
 // A sandwich launch group: tasks with the same (ma, mb).
 struct SWGroup {
   int ma = 0, mb = 0;
+  int fmt = 0;        // low-precision plans: 1 = FP32 blocks, 2 = split-BF16 blocks
   double flops = 0;   // algorithmic flops of one launch
   std::vector<SWTask> tasks;
   std::vector<SWItem> items;
@@ -182,10 +183,21 @@ struct attn_handle {
   double* d_red = nullptr;    // 128 x kRedBlocks
   double* d_qrmat = nullptr;  // G, R0, R1, R2, Rinv, Rt (mmax^2 each)
   double* d_qrR = nullptr;    // R of the last QR (absorbed into the neighbour)
+  void* d_cvtasks = nullptr;  // conversion work list (low-precision forms)
+  int cv_cap = 0;
   int mmax = 1;
   KrylovState* d_st = nullptr;
   // plans
   std::vector<MVDev> mv;
+  // low-precision forms: 4-byte-per-element mirrors of the FP64 stores (FP32,
+  // or BF16 hi/lo planes per block) and copies of every matvec work list
+  bool lowp_ready[2] = {false, false};
+  std::vector<void*> mir[2][2];     // [format - 1][direction][edge]
+  std::vector<int64_t> store_elems[2];
+  void* comb_lp[2] = {nullptr, nullptr};
+  int64_t mvcomb_elems = 0;
+  std::vector<MVDev> mvlp[2];
+  std::vector<std::vector<std::pair<int64_t, int>>> comb_blocks;   // per node: (offset, dim)
   std::vector<EnvDev> env_up, env_down[2];
   std::vector<QRDev> qr[3];   // per leg, per node
   std::vector<ABDev> ab[3];   // absorb into node along leg
@@ -196,7 +208,7 @@ struct attn_handle {
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  struct ProfRec { int a, b; double flops; int ma, mb; };
+  struct ProfRec { int a, b; double flops; int ma, mb, dtype; };
   std::vector<ProfRec> prof_recs;
 };
 
@@ -362,6 +374,8 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
   int64_t total = 0;
   build_comb(h, P.combines, h->d_mvcomb, D.comb, off, total);
   comb_off_out = off;
+  h->comb_blocks[n].clear();
+  for (size_t i = 0; i < P.combines.size(); i++) h->comb_blocks[n].push_back({off[i], P.combines[i].dim});
   int64_t part_used = 0;
   // two-leg items and local operators, grouped by spectator
   for (int sp = 0; sp < 3; sp++) {
@@ -609,11 +623,11 @@ void run_sw_mv(attn_handle* h, std::vector<SWGroup>& gs, int dtype, const void* 
       a = (int)h->ev_used;
       HIPCHK(hipEventRecord(next_event(h), s));
     }
-    HIPCHK(launch_sandwich(dtype, g.ma, g.mb, g.d_tasks, g.d_items, g.d_wus, (int)g.wus.size(), xbase, s));
+    HIPCHK(launch_sandwich(g.fmt == 2 ? 2 : dtype, g.ma, g.mb, g.d_tasks, g.d_items, g.d_wus, (int)g.wus.size(), xbase, s));
     if (a >= 0) {
       b = (int)h->ev_used;
       HIPCHK(hipEventRecord(next_event(h), s));
-      h->prof_recs.push_back({a, b, g.flops, g.ma, g.mb});
+      h->prof_recs.push_back({a, b, g.flops, g.ma, g.mb, g.fmt == 2 ? 2 : dtype});
     }
   }
 }
@@ -635,6 +649,137 @@ void matvec_f64(attn_handle* h, int n, const double* x, double* y, hipStream_t s
     HIPCHK(hipMemsetAsync(y, 0, (size_t)D.dims[0] * D.dims[1] * D.dims[2] * sizeof(double), s));
   } else {
     HIPCHK(launch_reduce_out(0, D.d_srcs, (int)D.srcs.size(), y, 0, D.dims[0], D.dims[1], D.dims[2], s));
+  }
+  h->n_matvec++;
+  h->mv_flops += (double)h->M.mv[n].flops;
+}
+
+// ------------------------------------------------------------------ low-precision forms
+// Mirror formats: 1 = FP32 (same layout as the FP64 blocks), 2 = split BF16
+// (hi and lo planes, permuted row-major, for blocks whose dimension is a
+// multiple of 32).  Both take 4 bytes per element, so a mirror element sits at
+// half the byte offset of its FP64 original.
+bool sw_bf16(int ma, int mb) { return ma % 32 == 0 && mb % 32 == 0 && ma <= 128 && mb <= 128; }
+
+void* to_mirror(attn_handle* h, const void* p, int fmt) {
+  if (!p) return nullptr;
+  const uintptr_t a = (uintptr_t)p;
+  const uintptr_t c0 = (uintptr_t)h->d_mvcomb;
+  if (a >= c0 && a < c0 + (uintptr_t)h->mvcomb_elems * 8) return (char*)h->comb_lp[fmt - 1] + (a - c0) / 2;
+  const Tree& tr = h->M.tree;
+  for (int dir = 0; dir < 2; dir++)
+    for (int e = 0; e < tr.n_edges(); e++) {
+      const uintptr_t b = (uintptr_t)h->store[dir][e];
+      if (b && a >= b && a < b + (uintptr_t)h->store_elems[dir][e] * 8) {
+        void* m = h->mir[fmt - 1][dir][e];
+        if (!m) throw StatusFail{ATTN_ERR_STATE, "internal: block without mirror"};
+        return (char*)m + (a - b) / 2;
+      }
+    }
+  throw StatusFail{ATTN_ERR_STATE, "internal: block outside every store"};
+}
+
+// Build the mirrors and the work lists of precision form `dtype` (1 = FP32,
+// 2 = split BF16; the latter runs its mode products and the sandwich groups
+// whose legs are not multiples of 32 in FP32).
+void ensure_lowp(attn_handle* h, int dtype) {
+  if (h->lowp_ready[dtype - 1]) return;
+  const Tree& tr = h->M.tree;
+  for (int fmt = 1; fmt <= dtype; fmt++) {
+    if (!h->mir[fmt - 1][0].empty()) continue;
+    for (int dir = 0; dir < 2; dir++) {
+      h->mir[fmt - 1][dir].assign(tr.n_edges(), nullptr);
+      for (int e = 0; e < tr.n_edges(); e++)
+        if (h->store[dir][e] && (fmt == 1 || tr.edge_dim(e) % 32 == 0))
+          h->mir[fmt - 1][dir][e] = dev_alloc(h, h->store_elems[dir][e] * 4);
+    }
+    h->comb_lp[fmt - 1] = dev_alloc(h, std::max<int64_t>(h->mvcomb_elems, 1) * 4);
+  }
+  std::vector<MVDev>& LP = h->mvlp[dtype - 1];
+  LP.assign(tr.nodes.size(), MVDev());
+  for (size_t n = 0; n < tr.nodes.size(); n++) {
+    const MVDev& D = h->mv[n];
+    MVDev& L = LP[n];
+    L.need_xt = D.need_xt;
+    std::copy(D.dims, D.dims + 3, L.dims);
+    L.sw = D.sw;
+    for (auto& g : L.sw) {
+      bool bf = dtype == 2 && sw_bf16(g.ma, g.mb);
+      if (bf)
+        for (auto& it : g.items) {
+          if ((uintptr_t)to_mirror(h, it.A, 2) % 16 || (uintptr_t)to_mirror(h, it.B, 2) % 16) bf = false;
+        }
+      g.fmt = bf ? 2 : 1;
+      for (auto& it : g.items) { it.A = to_mirror(h, it.A, g.fmt); it.B = to_mirror(h, it.B, g.fmt); }
+    }
+    const std::vector<MPGroup>* src[3] = {&D.chainA, &D.chainB, &D.chainC};
+    std::vector<MPGroup>* dst[3] = {&L.chainA, &L.chainB, &L.chainC};
+    for (int k = 0; k < 3; k++) {
+      *dst[k] = *src[k];
+      for (auto& g : *dst[k])
+        for (auto& jb : g.jobs) jb.A = to_mirror(h, jb.A, 1);
+    }
+    L.srcs = D.srcs;
+    upload_sw(h, L.sw);
+    upload_mp(h, L.chainA);
+    upload_mp(h, L.chainB);
+    upload_mp(h, L.chainC);
+    L.d_srcs = upload(h, L.srcs);
+  }
+  h->lowp_ready[dtype - 1] = true;
+}
+
+// Conversion list that refreshes the mirrors read by node n's matvec in form
+// `dtype`: its three incoming stores and its combined blocks.
+std::vector<CVTask> lowp_conversions(attn_handle* h, int n, int dtype) {
+  const Tree& tr = h->M.tree;
+  std::vector<CVTask> cv;
+  auto add = [&](const double* src, void* dst, int64_t elems, int dim, int fmt) {
+    if (dst) cv.push_back({src, dst, elems, dim, fmt});
+  };
+  auto add_store = [&](int dir, int e) {
+    if (e < 0 || !h->store[dir][e]) return;
+    const int dim = tr.edge_dim(e);
+    for (int fmt = 1; fmt <= dtype; fmt++)
+      add(h->store[dir][e], h->mir[fmt - 1][dir][e], h->store_elems[dir][e], dim, fmt);
+  };
+  add_store(0, tr.edge_of_child(n, 0));
+  add_store(0, tr.edge_of_child(n, 1));
+  if (n != tr.root) add_store(1, tr.edge_of_node(n));
+  for (auto& cb : h->comb_blocks[n]) {
+    const int64_t el = (int64_t)cb.second * cb.second;
+    for (int fmt = 1; fmt <= dtype; fmt++)
+      if (fmt == 1 || cb.second % 32 == 0)
+        add(h->d_mvcomb + cb.first, (char*)h->comb_lp[fmt - 1] + cb.first * 4, el, cb.second, fmt);
+  }
+  return cv;
+}
+
+void prepare_lowp(attn_handle* h, int n, int dtype, hipStream_t s) {
+  std::vector<CVTask> cv = lowp_conversions(h, n, dtype);
+  int64_t maxn = 0;
+  for (auto& c : cv) maxn = std::max(maxn, c.n);
+  if (cv.size() > (size_t)h->cv_cap) throw StatusFail{ATTN_ERR_STATE, "internal: conversion list too long"};
+  HIPCHK(hipMemcpyAsync(h->d_cvtasks, cv.data(), cv.size() * sizeof(CVTask), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_convert(dtype, (const CVTask*)h->d_cvtasks, (int)cv.size(), maxn, s));
+  // the host list must outlive the asynchronous copy
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// y <- H_eff(n) x in form `dtype` (mirrors current); x is FP32, y FP64
+// (out_dtype 0) or FP32 (out_dtype 1).
+void matvec_lowp(attn_handle* h, int n, int dtype, const float* x, void* y, int out_dtype, hipStream_t s) {
+  MVDev& D = h->mvlp[dtype - 1][n];
+  if (D.need_xt) HIPCHK(launch_transpose_plr(1, x, h->d_xt, D.dims[0], D.dims[1], D.dims[2], s));
+  run_mp(D.chainA, 1, x, s);
+  run_mp(D.chainB, 1, x, s);
+  run_mp(D.chainC, 1, x, s);
+  run_sw_mv(h, D.sw, 1, x, s);
+  const int64_t M = (int64_t)D.dims[0] * D.dims[1] * D.dims[2];
+  if (D.srcs.empty()) {
+    HIPCHK(hipMemsetAsync(y, 0, (size_t)M * (out_dtype == 0 ? 8 : 4), s));
+  } else {
+    HIPCHK(launch_reduce_out(1, D.d_srcs, (int)D.srcs.size(), y, out_dtype, D.dims[0], D.dims[1], D.dims[2], s));
   }
   h->n_matvec++;
   h->mv_flops += (double)h->M.mv[n].flops;
@@ -856,7 +1001,8 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
   double* P[4];
   for (int i = 0; i < 4; i++) P[i] = h->d_red + (int64_t)i * 64 * kRedBlocks;
   run_comb(D.comb, s);
-  if (D.d_tiny && precision == ATTN_F64) {
+  // tiny nodes (dense H_eff, negligible work) stay in FP64 for every form
+  if (D.d_tiny) {
     HIPCHK(launch_tiny_lanczos(D.d_tiny, (int)Msz, h->d_tmp2, T, V, w, h->d_st, k, s));
     h->n_matvec += k;
     h->mv_flops += (double)k * h->M.mv[n].flops;
@@ -867,6 +1013,10 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
     if (nmv) *nmv = k;
     return st.scal[0];
   }
+  if (precision != ATTN_F64) {
+    ensure_lowp(h, precision);
+    prepare_lowp(h, n, precision, s);
+  }
   HIPCHK(launch_state_init(h->d_st, k, s));
   HIPCHK(launch_norm2(T, Msz, P[0], s));
   HIPCHK(launch_scale_norm(T, V, Msz, P[0], h->d_st, s));
@@ -875,7 +1025,8 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
     if (precision == ATTN_F64) {
       matvec_f64(h, n, vj, w, s);
     } else {
-      throw StatusFail{ATTN_ERR_UNSUPPORTED, "precision form not available for this eigensolve"};
+      HIPCHK(launch_cast(vj, 0, h->d_x32, 1, Msz, s));
+      matvec_lowp(h, n, precision, h->d_x32, w, 0, s);
     }
     HIPCHK(launch_multidot(vj, 1, w, Msz, P[0], h->d_st, s));
     if (j == k - 1) {
@@ -952,14 +1103,18 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
     // effective-operator stores
     h->store[0].assign(tr.n_edges(), nullptr);
     h->store[1].assign(tr.n_edges(), nullptr);
+    h->store_elems[0].assign(tr.n_edges(), 0);
+    h->store_elems[1].assign(tr.n_edges(), 0);
     for (int e = 0; e < tr.n_edges(); e++) {
       const int dim = tr.edge_dim(e);
       const int64_t sz = (int64_t)(1 + h->M.n_slots[e]) * dim * dim;
       if (tr.edge_is_site(e)) {
         h->store[0][e] = upload(h, h->M.site_blocks[e]);
+        h->store_elems[0][e] = (int64_t)h->M.site_blocks[e].size();
         continue;
       }
       for (int dir = 0; dir < 2; dir++) {
+        h->store_elems[dir][e] = sz;
         void* q = dev_alloc(h, sz * sizeof(double));
         if (!h->dryrun) HIPCHK(hipMemset(q, 0, sz * sizeof(double)));
         h->store[dir][e] = (double*)q;
@@ -1020,6 +1175,7 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
     h->chain_cap = std::max<int64_t>(chain_need, 1);
     h->d_chain = alloc(h->chain_cap);
     h->d_mvcomb = alloc(mvcomb_need);
+    h->mvcomb_elems = mvcomb_need;
     h->d_envcomb = alloc(envcomb_need);
     h->d_Z = alloc(z_need);
     h->d_grpart = alloc(grp_need);
@@ -1028,9 +1184,12 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
       for (int l = 0; l < 3; l++) h->mmax = std::max(h->mmax, tr.nodes[n].dims[l]);
     h->d_qrmat = alloc(6 * (int64_t)h->mmax * h->mmax);
     h->d_qrR = alloc((int64_t)h->mmax * h->mmax);
+    h->cv_cap = 6 + 2 * (int)std::max<size_t>(1, [&] { size_t mx = 0; for (int n = 0; n < nn; n++) mx = std::max(mx, h->M.mv[n].combines.size()); return mx; }());
+    h->d_cvtasks = dev_alloc(h, (size_t)h->cv_cap * sizeof(CVTask));
     h->d_st = (KrylovState*)dev_alloc(h, sizeof(KrylovState));
     // device plans
     h->mv.assign(nn, MVDev());
+    h->comb_blocks.assign(nn, {});
     h->env_up.assign(nn, EnvDev());
     h->env_down[0].assign(nn, EnvDev());
     h->env_down[1].assign(nn, EnvDev());
@@ -1227,8 +1386,15 @@ attn_status attn_heff_apply(attn_handle* h, int32_t node, int32_t dtype, const v
       matvec_f64(h, node, (const double*)x, (double*)y, s);
       return ATTN_OK;
     }
-    h->err = "dtype not available";
-    return ATTN_ERR_UNSUPPORTED;
+    if (dtype == ATTN_F32 || dtype == ATTN_BF16X2) {
+      ensure_lowp(h, dtype);
+      run_comb(D.comb, s);
+      prepare_lowp(h, node, dtype, s);
+      matvec_lowp(h, node, dtype, (const float*)x, y, 1, s);
+      return ATTN_OK;
+    }
+    h->err = "unknown dtype";
+    return ATTN_ERR_ARG;
   });
 }
 
@@ -1265,6 +1431,7 @@ attn_status attn_eigsolve_node(attn_handle* h, int32_t node, const attn_solver_o
     else { std::memset(&o, 0, sizeof(o)); o.krylov_k = 20; }
     if (o.krylov_k < 1) { h->err = "krylov_k must be >= 1"; return ATTN_ERR_ARG; }
     if (o.solver != ATTN_SOLVER_LANCZOS) { h->err = "solver not available"; return ATTN_ERR_UNSUPPORTED; }
+    if (o.precision < ATTN_F64 || o.precision > ATTN_BF16X2) { h->err = "unknown precision"; return ATTN_ERR_ARG; }
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipSetDevice(h->device));
     int nmv = 0;
@@ -1493,6 +1660,39 @@ extern "C" attn_status attn_validate(const attn_handle* h) {
       }
       const ABDev& A = h->ab[l][n];
       if (A.present) c.mp(A.h_mp, 0, 8);
+    }
+  }
+  // low-precision forms: a dry-run handle builds them here; a device handle
+  // checks the ones it has built
+  attn_handle* hm = const_cast<attn_handle*>(h);
+  for (int dt = 1; dt <= 2 && c.ok; dt++) {
+    if (h->dryrun) {
+      try { ensure_lowp(hm, dt); } catch (const StatusFail& f) { c.fail(f.msg); break; }
+    }
+    if (!h->lowp_ready[dt - 1]) continue;
+    for (int n = 0; n < (int)tr.nodes.size() && c.ok; n++) {
+      const MVDev& D = h->mvlp[dt - 1][n];
+      const int64_t M = (int64_t)D.dims[0] * D.dims[1] * D.dims[2];
+      for (auto& g : D.sw) {
+        c.sw(g, M, 4);
+        if (g.fmt == 2) {
+          if (!sw_bf16(g.ma, g.mb)) c.fail("split-BF16 group with legs not multiples of 32");
+          for (auto& it : g.items)
+            if ((uintptr_t)it.A % 16 || (uintptr_t)it.B % 16) c.fail("split-BF16 block not 16-byte aligned");
+        }
+      }
+      for (auto& g : D.chainA) c.mp(g, M, 4);
+      for (auto& g : D.chainB) c.mp(g, M, 4);
+      for (auto& g : D.chainC) c.mp(g, M, 4);
+      for (auto& sr : D.srcs) c.span(sr.p, M * 4, "reduce source");
+      if (D.need_xt) c.span(h->d_xt, M * 4, "transposed input");
+      const std::vector<CVTask> cv = lowp_conversions(hm, n, dt);
+      if (cv.size() > (size_t)h->cv_cap) c.fail("conversion list too long");
+      for (auto& t : cv) {
+        c.span(t.src, t.n * 8, "conversion source");
+        c.span(t.dst, t.n * 4, "conversion destination");
+        if (t.fmt == 2 && (t.m % 32 || t.n % ((int64_t)t.m * t.m))) c.fail("split-BF16 conversion shape");
+      }
     }
   }
   if (!c.ok) { const_cast<attn_handle*>(h)->err = c.err; return ATTN_ERR_STATE; }

@@ -1,0 +1,99 @@
+"""GPU tests of the low-precision forms of the H_eff matvec (FP32 operands, and
+split BF16 operands with FP32 accumulation) against the FP64 CPU oracle.
+
+Tolerances follow from the arithmetic.  FP32 operands carry a relative
+rounding of 2^-24 and each output element sums a few thousand products over
+about a hundred operator terms whose signs differ, so the relative error of y
+in the 2-norm stays below 1e-5.  Split BF16 keeps about 16 significant bits
+per operand (hi has 8, lo the next 8) and drops the lo.lo product: about
+3 * 2^-17 per product, giving 1e-4 for y.  The Krylov recurrences stay in FP64;
+an eigenvalue then moves by about the matvec error times the norm of H_eff."""
+import numpy as np
+import pytest
+
+from problems import config_problem
+from tests.gpu_util import make_pair, move_both, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16x2": 1e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _lowp_matvec(a, n, x, dtype):
+    import torch
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float32)
+    yt = torch.empty_like(xt)
+    a.heff_apply(n, xt, yt, dtype=dtype)
+    torch.cuda.synchronize()
+    return yt.cpu().numpy().astype(np.float64), xt.cpu().numpy().astype(np.float64)
+
+
+def _forms():
+    from paper_2507_21236_amd import ATTN_F32, ATTN_BF16X2
+    return [("f32", ATTN_F32), ("bf16x2", ATTN_BF16X2)]
+
+
+def test_lowp_matvec_8x8_m32():
+    p = config_problem("ising8_m32")
+    a, o = make_pair(p)
+    rng = np.random.default_rng(11)
+    full = [n for n in range(o.tree.n_nodes) if o.tree.dims[n] == (32, 32, 32)]
+    for n in full[:3] + [o.tree.root, 0]:
+        move_both(a, o, n)
+        x = rng.standard_normal(o.T[n].shape)
+        for name, dt in _forms():
+            y, x32 = _lowp_matvec(a, n, x, dt)
+            r = rel(y, o.matvec(n, x32))
+            print(f"node {n} {o.tree.dims[n]} {name}: rel err {r:.2e}")
+            assert r < TOL[name], (n, name, r)
+
+
+def test_lowp_matvec_heaviest_node_16x16():
+    p = config_problem("ising16_m64")
+    a, o = make_pair(p)
+    full = [n for n in range(o.tree.n_nodes) if o.tree.dims[n] == (64, 64, 64)]
+    n = max(full, key=o.flops)
+    move_both(a, o, n)
+    x = np.random.default_rng(12).standard_normal(o.T[n].shape)
+    for name, dt in _forms():
+        y, x32 = _lowp_matvec(a, n, x, dt)
+        r = rel(y, o.matvec(n, x32))
+        print(f"heaviest node {n} {name}: rel err {r:.2e}")
+        assert r < TOL[name], (name, r)
+
+
+def test_lowp_eigsolve_8x8_m32():
+    from paper_2507_21236_amd import solver_opts
+    p = config_problem("ising8_m32")
+    for name, dt in _forms():
+        a, o = make_pair(p)
+        full = [n for n in range(o.tree.n_nodes) if o.tree.dims[n] == (32, 32, 32)]
+        for n in full[:2] + [o.tree.root]:
+            move_both(a, o, n)
+            th_o = o.eigsolve(n)
+            th_a, _ = a.eigsolve(n, solver_opts(krylov_k=20, precision=dt))
+            # the oracle moves on with its own FP64 tensor
+            a.set_tensor(n, o.T[n])
+            d = abs(th_a - th_o) / abs(th_o)
+            print(f"node {n} {name}: theta {th_a:.12f} oracle {th_o:.12f} rel {d:.2e}")
+            assert d < TOL[name], (n, name, d)
+
+
+def test_lowp_sweeps_8x8_m16_track_fp64():
+    from paper_2507_21236_amd import solver_opts, ATTN_F64
+    p = config_problem("ising8_m16")
+    a, _ = make_pair(p)
+    e64, _ = a.sweep(3, solver_opts(krylov_k=20, precision=ATTN_F64))
+    for name, dt in _forms():
+        b, _ = make_pair(p)
+        e, _ = b.sweep(3, solver_opts(krylov_k=20, precision=dt))
+        d = np.abs(np.asarray(e) - np.asarray(e64)).max() / p.n_sites
+        print(f"{name}: sweep energies {list(e)} vs fp64 {list(e64)}; max |dE|/N {d:.2e}")
+        assert d < 10 * TOL[name], (name, d)
