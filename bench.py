@@ -11,7 +11,13 @@ between consecutive sweeps is <= 1e-7, the live-timed roofline of the dominant k
 (the FP64 two-leg contraction kernel at the full (64, 64) legs) and the FP64
 CPU oracle timed on this host on a bounded sample of the same workload.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f64]
+The low-precision forms (FP32 operands; split hi/lo BF16 operands on the
+BF16 matrix cores with FP32 accumulation; FP64 Krylov in both) are timed on the
+same sweeps after the primary run and reported as speedups over the FP64 path,
+with the energy difference per site of every sweep.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--precision f64|f32|bf16x2] [--forms f32,bf16x2]
                        [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -28,6 +34,11 @@ sys.path.insert(0, ROOT)
 METRIC = ("H_eff matvec TFLOP/s + sweep time to ΔE/N≤1e-7 (16x16 Ising, m=64) "
           "vs FP64 GPU")
 PEAK_FP64 = 78.6   # TFLOP/s, MI355X dense FP64 (vector and matrix)
+# dense matrix-core peaks per form (TFLOP/s); split BF16 spends three BF16
+# products per useful product, so its useful-flop ceiling is a third of 2.5 PF
+PEAKS = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0 / 3}
+KERNELS = {"f64": "k_sandwich<double,4>", "f32": "k_sandwich<float,4>",
+           "bf16x2": "k_sandwich_bf2<4>"}
 
 
 def cpu_baseline(problem, sample_matvecs=3):
@@ -67,7 +78,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="f64", choices=["f64"])
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x2"])
+    ap.add_argument("--forms", default="f32,bf16x2",
+                    help="low-precision forms timed after the primary run ('' for none)")
     ap.add_argument("--config", default="ising16_m64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -78,7 +91,7 @@ def main():
 
     import torch
     from problems import config_problem
-    from paper_2507_21236_amd import AttnHandle, solver_opts, ATTN_F64
+    from paper_2507_21236_amd import AttnHandle, solver_opts, ATTN_F64, ATTN_F32, ATTN_BF16X2
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -92,33 +105,40 @@ def main():
     a = AttnHandle(p)
     print(f"[bench] build {time.time() - t0:.2f} s, effective-operator storage "
           f"{a.env_bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
-    opts = solver_opts(krylov_k=20, precision=ATTN_F64)
-    a.init_state()
-    for w in range(args.warmup):
-        e, s = a.sweep(1, opts)
-        print(f"[bench] warmup sweep {w}: E={e[0]:.12f} {s[0]:.3f} s", file=sys.stderr, flush=True)
-    # timed region: K sweeps from the initial state
-    a.init_state()
-    torch.cuda.synchronize()
-    _, _, _, f0 = a.counters()
-    a.profile_start()
-    energies, secs = [], []
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        e, s = a.sweep(1, opts)
-        energies.append(float(e[0]))
-        secs.append(float(s[0]))
-        print(f"[bench] sweep {k}: E={e[0]:.12f} E/N={e[0] / N:.12f} {s[0]:.3f} s",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    ms_sw, fl_sw, n_sw = a.profile_stop(min_dim=64)
-    _, _, _, f1 = a.counters()
-    mv_flops = f1 - f0
+    prec = {"f64": ATTN_F64, "f32": ATTN_F32, "bf16x2": ATTN_BF16X2}
+
+    def run(form, steps, warmup):
+        opts = solver_opts(krylov_k=20, precision=prec[form])
+        a.init_state()
+        for w in range(warmup):
+            e, s = a.sweep(1, opts)
+            print(f"[bench] {form} warmup sweep {w}: E={e[0]:.12f} {s[0]:.3f} s", file=sys.stderr,
+                  flush=True)
+        # timed region: K sweeps from the initial state
+        a.init_state()
+        torch.cuda.synchronize()
+        _, _, _, f0 = a.counters()
+        a.profile_start()
+        energies, secs = [], []
+        t_start = time.perf_counter()
+        for k in range(steps):
+            e, s = a.sweep(1, opts)
+            energies.append(float(e[0]))
+            secs.append(float(s[0]))
+            print(f"[bench] {form} sweep {k}: E={e[0]:.12f} E/N={e[0] / N:.12f} {s[0]:.3f} s",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t_start
+        prof = a.profile_stop(min_dim=64)
+        _, _, _, f1 = a.counters()
+        return energies, secs, t_total, f1 - f0, prof
+
+    energies, secs, t_total, mv_flops, (ms_sw, fl_sw, n_sw) = run(args.precision, args.steps,
+                                                                   args.warmup)
     value = mv_flops / t_total / 1e12
 
     # time to target: first sweep whose energy change per site from the previous
-    # sweep is <= 1e-7 (consecutive sweeps of this FP64 GPU run)
+    # sweep is <= 1e-7 (consecutive sweeps of this GPU run)
     t_target = None
     cum = secs[0]
     dE_last = None
@@ -130,6 +150,7 @@ def main():
             t_target = cum
 
     achieved = fl_sw / (ms_sw / 1e3) / 1e12 if ms_sw > 0 else 0.0
+    peak = PEAKS[args.precision]
     out = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -141,15 +162,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"f64": "f64", "f32": "f32", "bf16x2": "bf16x2+f32acc"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "ising16x16_h3_m64_de64_seed16", "lattice": "16x16 OBC square",
                    "m": p.m, "disentanglers": len(p.de_sites), "krylov_k": 20,
                    "precision": args.precision},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4),
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None,
-                     "kernel": "k_sandwich<double,4> (two-leg terms and local operators, "
+                     "kernel": KERNELS[args.precision] + " (two-leg terms and local operators, "
                                "legs of dimension 64)",
                      "launches": n_sw, "kernel_ms": round(ms_sw, 3)},
         "sweep_energies": energies,
@@ -159,6 +180,22 @@ def main():
         "time_to_target_criterion": "first sweep with |E_s - E_(s-1)| / N <= 1e-7 (FP64 GPU)",
         "matvec_gflop_timed": round(mv_flops / 1e9, 1),
     }
+    forms = [f for f in args.forms.split(",") if f and f != args.precision]
+    if forms:
+        out["forms"] = {}
+        for form in forms:
+            e_f, s_f, t_f, fl_f, (ms_f, flk_f, _) = run(form, args.steps, args.warmup)
+            out["forms"][form] = {
+                "ms_per_step": round(1e3 * t_f / args.steps, 3),
+                "matvec_tflops": round(fl_f / t_f / 1e12, 4),
+                "speedup_vs_" + args.precision: round(t_total / t_f, 3),
+                "kernel": KERNELS[form],
+                "kernel_tflops": round(flk_f / (ms_f / 1e3) / 1e12, 3) if ms_f > 0 else None,
+                "kernel_frac": round(flk_f / (ms_f / 1e3) / 1e12 / PEAKS[form], 4) if ms_f > 0 else None,
+                "sweep_energies": e_f,
+                "max_abs_dE_per_site_vs_" + args.precision: max(
+                    abs(x - y) for x, y in zip(e_f, energies)) / N,
+            }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)
