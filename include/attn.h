@@ -241,6 +241,57 @@ attn_status attn_isometrize(attn_handle* h, int32_t from, int32_t to, void* stre
 attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* opts,
                        double* energies, double* seconds);
 
+/*
+ * Batched form (not from the paper): independent problem instances, each its
+ * own handle (sizes and bond dimensions may differ, d must agree, legs <= 64),
+ * swept in lock step.  Step t of a batch sweep moves every instance's centre to
+ * its node t (post-order; instances with fewer nodes idle) and optimises it.
+ * The eigensolver work of all instances in a step runs in mixed-shape launches
+ * over one work list (all terms of every active node: two-leg terms and local
+ * operators in one launch, each stage of the three-leg chains in one launch,
+ * every Krylov vector step in one launch); the centre moves of different
+ * instances run concurrently on four streams.  With use_graphs each step is
+ * captured once as a HIP graph and replayed in later sweeps.  With autotune the
+ * work split of the two-leg launches is chosen per leg shape (ma, mb) by timing
+ * candidate splits over all steps at creation.  Without autotuning the split is
+ * the one the single-handle path uses, and batch sweeps then reproduce
+ * attn_sweep of each handle bit for bit.
+ * The batch borrows the handles (they must outlive it and must not be used
+ * while it sweeps).  Each handle must be in the sweep start state: after
+ * attn_init_state or after full sweeps.
+ */
+typedef struct attn_batch attn_batch;
+
+typedef struct attn_batch_opts {
+  int32_t krylov_k;    /* Lanczos matvecs per node (20) */
+  int32_t precision;   /* ATTN_F64 or ATTN_F32 operands; Krylov steps stay FP64 */
+  int32_t use_graphs;  /* 1: capture every step as a HIP graph */
+  int32_t autotune;    /* 1: time candidate work splits per leg shape at creation */
+} attn_batch_opts;
+
+/* opts may be NULL (k = 20, FP32, graphs, no autotuning).  *out is owned by the
+ * caller (attn_batch_destroy).  Errors: ARG, STATE (handle not on a device),
+ * UNSUPPORTED (mixed d or devices, legs above 64, BF16X2), HIP, OOM. */
+attn_status attn_batch_create(attn_handle* const* hs, int32_t n, const attn_batch_opts* opts,
+                              attn_batch** out);
+
+/* n_sweeps lock-step sweeps.  energies[i * n_sweeps + s] = theta at the last
+ * node (root) of instance i in sweep s; seconds[s] = wall time of sweep s.
+ * Either array may be NULL.  Errors: STATE (a handle is not in the sweep start
+ * state), NUMERIC, HIP. */
+attn_status attn_batch_sweep(attn_batch* b, int32_t n_sweeps, double* energies, double* seconds);
+
+/* Number of steps, sandwich work units per sweep-step matvec summed over steps,
+ * and the autotuned splits: tuned[3k..3k+2] = (ma, mb, target workgroups). */
+attn_status attn_batch_info(const attn_batch* b, int32_t* n_steps, int64_t* n_launch_units,
+                            int32_t* n_tuned, int32_t* tuned, int32_t cap);
+
+/* Message of the last error of b (of the last failed attn_batch_create when b
+ * is NULL); owned by the library. */
+const char* attn_batch_last_error(const attn_batch* b);
+
+attn_status attn_batch_destroy(attn_batch* b);
+
 /* Checks on the host that every work unit of every device work list of the
  * handle reads and writes only inside the buffer it was built for.  Meant for
  * ATTN_DRYRUN handles (no GPU needed).  Errors: STATE (message names the first

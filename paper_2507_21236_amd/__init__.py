@@ -85,3 +85,31 @@ class AttnHandle:
         """(ms, flops, launches) of the matvec contraction launches since start."""
         return _lib.attn_profile(self.h, 0, min_dim)
 
+
+
+class AttnBatch:
+    """Lock-step sweeps of several AttnHandle instances (borrowed: keep them
+    alive and do not use them while the batch sweeps)."""
+
+    def __init__(self, handles, krylov_k=20, precision=ATTN_F32, use_graphs=True, autotune=False):
+        self.handles = list(handles)
+        self.b = _lib.attn_batch_create([a.h for a in self.handles], krylov_k, precision,
+                                        use_graphs, autotune)
+
+    def sweep(self, n_sweeps):
+        """(energies [n_instances][n_sweeps], seconds [n_sweeps])"""
+        return _lib.attn_batch_sweep(self.b, len(self.handles), n_sweeps)
+
+    def info(self):
+        return _lib.attn_batch_info(self.b)
+
+    def close(self):
+        if self.b:
+            _lib.attn_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

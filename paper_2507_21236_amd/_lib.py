@@ -59,6 +59,11 @@ class attn_sweep_opts(ctypes.Structure):
     _fields_ = [("solver", attn_solver_opts), ("use_graphs", ctypes.c_int32)]
 
 
+class attn_batch_opts(ctypes.Structure):
+    _fields_ = [("krylov_k", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+
+
 _H = ctypes.c_void_p
 _proto = {
     "attn_build_tpo": (ctypes.c_int32, [ctypes.POINTER(attn_problem), ctypes.POINTER(_H)]),
@@ -84,6 +89,13 @@ _proto = {
                                        ctypes.POINTER(ctypes.c_int64), _f64p]),
     "attn_profile": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_int32, _f64p, _f64p,
                                       ctypes.POINTER(ctypes.c_int64)]),
+    "attn_batch_create": (ctypes.c_int32, [ctypes.POINTER(_H), ctypes.c_int32,
+                                           ctypes.POINTER(attn_batch_opts), ctypes.POINTER(_H)]),
+    "attn_batch_sweep": (ctypes.c_int32, [_H, ctypes.c_int32, _f64p, _f64p]),
+    "attn_batch_info": (ctypes.c_int32, [_H, _i32p, ctypes.POINTER(ctypes.c_int64), _i32p, _i32p,
+                                         ctypes.c_int32]),
+    "attn_batch_last_error": (ctypes.c_char_p, [_H]),
+    "attn_batch_destroy": (ctypes.c_int32, [_H]),
 }
 for _name, (_res, _args) in _proto.items():
     _f = getattr(_lib, _name)
@@ -223,3 +235,40 @@ def attn_profile(h, enable, min_dim=0):
     _check(_lib.attn_profile(h, enable, min_dim, ctypes.byref(ms), ctypes.byref(fl),
                              ctypes.byref(nl)), h)
     return ms.value, fl.value, nl.value
+
+
+def _bcheck(code, b):
+    if code != ATTN_OK:
+        raise AttnError(code, (_lib.attn_batch_last_error(b) or b"").decode())
+
+
+def attn_batch_create(handles, krylov_k=20, precision=ATTN_F32, use_graphs=True, autotune=False):
+    arr = (_H * len(handles))(*handles)
+    o = attn_batch_opts(krylov_k, precision, int(use_graphs), int(autotune))
+    b = _H()
+    _bcheck(_lib.attn_batch_create(arr, len(handles), ctypes.byref(o), ctypes.byref(b)), None)
+    return b.value
+
+
+def attn_batch_sweep(b, n_inst, n_sweeps):
+    e = np.zeros((n_inst, n_sweeps))
+    s = np.zeros(n_sweeps)
+    _bcheck(_lib.attn_batch_sweep(b, n_sweeps, e.ctypes.data_as(_f64p), s.ctypes.data_as(_f64p)), b)
+    return e, s
+
+
+def attn_batch_info(b, cap=64):
+    ns, nt = ctypes.c_int32(), ctypes.c_int32()
+    nu = ctypes.c_int64()
+    tuned = (ctypes.c_int32 * (3 * cap))()
+    _bcheck(_lib.attn_batch_info(b, ctypes.byref(ns), ctypes.byref(nu), ctypes.byref(nt), tuned, cap), b)
+    t = [tuple(tuned[3 * k:3 * k + 3]) for k in range(min(nt.value, cap))]
+    return ns.value, nu.value, t
+
+
+def attn_batch_last_error(b):
+    return (_lib.attn_batch_last_error(b) or b"").decode()
+
+
+def attn_batch_destroy(b):
+    _bcheck(_lib.attn_batch_destroy(b), b)

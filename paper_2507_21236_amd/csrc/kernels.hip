@@ -61,15 +61,11 @@ __device__ __forceinline__ int bf_pinv(int a) {
 // walking K = p in the order {16 tp + drow(j, i) : j = 0..3} for fixed (tp, i),
 // which is exactly how the accumulator layout spreads p over lane groups.
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_sandwich(const SWTask* __restrict__ tasks,
-                                                  const SWItem* __restrict__ items,
-                                                  const int4* __restrict__ wus,
-                                                  const T* __restrict__ xbase) {
+__device__ __forceinline__ void sandwich_mfma(const SWTask& t, const SWItem* __restrict__ items,
+                                              const int4 wu, const T* __restrict__ xbase,
+                                              unsigned char* smem_raw) {
   typedef typename V4<T>::type v4;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int4 wu = wus[blockIdx.x];
-  const SWTask& t = tasks[wu.x];
   const int s = wu.y;
   const int ma = t.ma;
   constexpr int mb = 16 * NB;
@@ -134,6 +130,16 @@ __global__ __launch_bounds__(256) void k_sandwich(const SWTask* __restrict__ tas
       if (t.accumulate) Y[c] += acc[q][i];
       else Y[c] = acc[q][i];
     }
+}
+
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void k_sandwich(const SWTask* __restrict__ tasks,
+                                                  const SWItem* __restrict__ items,
+                                                  const int4* __restrict__ wus,
+                                                  const T* __restrict__ xbase) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int4 wu = wus[blockIdx.x];
+  sandwich_mfma<T, NB>(tasks[wu.x], items, wu, xbase, smem_raw);
 }
 
 // Generic sandwich for dimensions that are not multiples of 16: one thread per
@@ -311,17 +317,13 @@ __device__ __forceinline__ int64_t mode_addr(int j, int d0, int d1, int d2, int 
 // out (+)= sum_jobs coef * A x_j in.  wu = (task, f-tile of 64).  LDS holds the
 // input tile [i'][f]; wave w owns f in [16 w, +16) and every i.
 template <typename T, int NI>
-__global__ __launch_bounds__(256) void k_mode(const MPTask* __restrict__ tasks,
-                                              const MPJob* __restrict__ jobs,
-                                              const int2* __restrict__ wus,
-                                              const T* __restrict__ xbase) {
+__device__ __forceinline__ void mode_mfma(const MPTask& t, const MPJob* __restrict__ jobs,
+                                          const int2 wu, const T* __restrict__ xbase,
+                                          unsigned char* smem_raw) {
   typedef typename V4<T>::type v4;
   constexpr int mj = 16 * NI;
   constexpr int ld = 64 + 2;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int2 wu = wus[blockIdx.x];
-  const MPTask& t = tasks[wu.x];
   const int j = t.j, d0 = t.d0, d1 = t.d1, d2 = t.d2;
   const int64_t f0 = (int64_t)wu.y * 64;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -366,6 +368,16 @@ __global__ __launch_bounds__(256) void k_mode(const MPTask* __restrict__ tasks,
     }
 }
 
+template <typename T, int NI>
+__global__ __launch_bounds__(256) void k_mode(const MPTask* __restrict__ tasks,
+                                              const MPJob* __restrict__ jobs,
+                                              const int2* __restrict__ wus,
+                                              const T* __restrict__ xbase) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 wu = wus[blockIdx.x];
+  mode_mfma<T, NI>(tasks[wu.x], jobs, wu, xbase, smem_raw);
+}
+
 // Generic mode product: one thread per output element.  wu = (task, first element).
 template <typename T>
 __device__ __forceinline__ void mode_gen_elem(const MPTask& t, const MPJob* __restrict__ jobs,
@@ -398,6 +410,78 @@ __global__ __launch_bounds__(256) void k_mode_gen(const MPTask* __restrict__ tas
                                                   const T* __restrict__ xbase) {
   const int2 wu = wus[blockIdx.x];
   mode_gen_elem<T>(tasks[wu.x], jobs, (int64_t)wu.y + threadIdx.x, xbase);
+}
+
+// ============================================================================ mixed-shape launches
+// One launch over the work units of many tasks of different shapes (several
+// nodes of several problem instances): the kind of each unit selects the body.
+// Sandwich: wu.w = NB (legs multiples of 16, mb = 16 NB <= 64) or 0 (generic).
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_sandwich(const SWTask* __restrict__ tasks,
+                                                        const SWItem* __restrict__ items,
+                                                        const int4* __restrict__ wus) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int4 wu = wus[blockIdx.x];
+  const SWTask& t = tasks[wu.x];
+  switch (wu.w) {
+    case 0: sandwich_gen_elem<T>(t, items, wu.y, wu.z + threadIdx.x, nullptr); break;
+    case 1: sandwich_mfma<T, 1>(t, items, wu, nullptr, smem_raw); break;
+    case 2: sandwich_mfma<T, 2>(t, items, wu, nullptr, smem_raw); break;
+    case 3: sandwich_mfma<T, 3>(t, items, wu, nullptr, smem_raw); break;
+    case 4: sandwich_mfma<T, 4>(t, items, wu, nullptr, smem_raw); break;
+    default: break;
+  }
+}
+
+// Mode product: the task's kind (MPTask::pad) is NI (m_j = 16 NI <= 64) or 0 (generic).
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_mode(const MPTask* __restrict__ tasks,
+                                                    const MPJob* __restrict__ jobs,
+                                                    const int2* __restrict__ wus) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int2 wu = wus[blockIdx.x];
+  const MPTask& t = tasks[wu.x];
+  switch (t.pad) {
+    case 0: mode_gen_elem<T>(t, jobs, (int64_t)wu.y + threadIdx.x, nullptr); break;
+    case 1: mode_mfma<T, 1>(t, jobs, wu, nullptr, smem_raw); break;
+    case 2: mode_mfma<T, 2>(t, jobs, wu, nullptr, smem_raw); break;
+    case 3: mode_mfma<T, 3>(t, jobs, wu, nullptr, smem_raw); break;
+    case 4: mode_mfma<T, 4>(t, jobs, wu, nullptr, smem_raw); break;
+    default: break;
+  }
+}
+
+// [l][r][p] -> [p][l][r] for a list of tensors (task blockIdx.y)
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_list(const TRTask* __restrict__ tasks) {
+  const TRTask& t = tasks[blockIdx.y];
+  const int64_t M = (int64_t)t.ml * t.mr * t.mp;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < M; e += (int64_t)gridDim.x * 256) {
+    const int64_t l = e / ((int64_t)t.mr * t.mp);
+    const int64_t rem = e - l * t.mr * t.mp;
+    const int64_t r = rem / t.mp, p = rem - r * t.mp;
+    ((T*)t.xt)[p * t.ml * t.mr + l * t.mr + r] = ((const T*)t.x)[e];
+  }
+}
+
+// y = sum of the partial outputs of each task (fixed order), as k_reduce_out
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_reduce_list(const RDTask* __restrict__ tasks) {
+  const RDTask& t = tasks[blockIdx.y];
+  const int64_t M = (int64_t)t.ml * t.mr * t.mp;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < M; e += (int64_t)gridDim.x * 256) {
+    const int64_t l = e / ((int64_t)t.mr * t.mp);
+    const int64_t rem = e - l * t.mr * t.mp;
+    const int64_t r = rem / t.mp, p = rem - r * t.mp;
+    const int64_t et = p * t.ml * t.mr + l * t.mr + r;
+    double acc = 0;
+    for (int k = 0; k < t.nsrc; k++) acc += (double)((const TI*)t.srcs[k].p)[t.srcs[k].layout ? et : e];
+    ((TO*)t.y)[e] = (TO)acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero(double* __restrict__ p, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) p[e] = 0.0;
 }
 
 // ============================================================================ gram
@@ -576,220 +660,165 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return red[0] + red[1] + red[2] + red[3];
 }
 
-// partial[i][b] = sum over block b's elements of V_i . w   (i < nv; V == nullptr -> w . w)
-__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, int nv,
-                                                  const double* __restrict__ w, int64_t n,
-                                                  double* __restrict__ partial,
-                                                  const KrylovState* __restrict__ st) {
-  __shared__ double red[4];
-  if (st && st->stop) return;
-  const int b = blockIdx.x;
-  for (int i = 0; i < nv; i++) {
-    const double* v = V ? V + (int64_t)i * n : w;
-    double acc = 0;
-    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
-      acc += v[e] * w[e];
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
-  }
-}
+// Every Krylov kernel takes a list of jobs (one per node being solved, possibly
+// of different problem instances) and works on job blockIdx.y, so one launch
+// advances all jobs of a batch by the same step.  Partial sums of a job live
+// in its four areas P0..P3 of 64 x kRedBlocks values.
+__device__ __forceinline__ double* parea(const KJob& J, int i) { return J.red + (int64_t)i * 64 * kRedBlocks; }
 
-// mode 0: out[i] = sum_b partial[i][b]; 1: alpha[j] = ...; 2: h[i] = ...;
-// 3: beta[j] = sqrt(...) with breakdown test and keff update; 4: scal[1] = sqrt(...)
-__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ partial, int nv,
-                                                   double* __restrict__ out, int mode,
-                                                   KrylovState* __restrict__ st, int j) {
-  __shared__ double red[4];
-  if (st && st->stop && mode != 4 && mode != 0) return;
-  for (int i = 0; i < nv; i++) {
-    const double v = partial[i * kRedBlocks + threadIdx.x];   // kRedBlocks == 256
-    const double s = block_sum(v, red);
-    if (threadIdx.x == 0) {
-      if (!isfinite(s) && st) st->status = 1;
-      if (mode == 0) out[i] = s;
-      else if (mode == 1) st->alpha[j] = s;
-      else if (mode == 2) st->h[i] = s;
-      else if (mode == 3) {
-        const double b = sqrt(s);
-        double amax = 0;
-        for (int k = 0; k <= j; k++) amax = fmax(amax, fabs(st->alpha[k]));
-        if (b <= 1e-14 * amax) {
-          st->stop = 1;
-        } else {
-          st->beta[j] = b;
-          st->keff = j + 2;
-        }
-      } else if (mode == 4) st->scal[1] = sqrt(s);
-    }
-  }
-}
-
-// w -= alpha_j v_j + beta_{j-1} v_{j-1}, then partial dots of the new w with V[0..j]
-__global__ __launch_bounds__(256) void k_lanczos_update(double* __restrict__ w,
-                                                        const double* __restrict__ V, int64_t n,
-                                                        const KrylovState* __restrict__ st, int j,
-                                                        double* __restrict__ partial) {
-  __shared__ double red[4];
-  if (st->stop) return;
-  const int b = blockIdx.x;
-  const double a = st->alpha[j];
-  const double bb = j > 0 ? st->beta[j - 1] : 0.0;
-  const double* vj = V + (int64_t)j * n;
-  const double* vm = j > 0 ? V + (int64_t)(j - 1) * n : V;
-  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
-    double x = w[e] - a * vj[e];
-    if (j > 0) x -= bb * vm[e];
-    w[e] = x;
-  }
-  // the same thread touches the same elements below: no barrier needed for w
-  for (int i = 0; i <= j; i++) {
-    const double* v = V + (int64_t)i * n;
-    double acc = 0;
-    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
-      acc += v[e] * w[e];
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
-  }
-}
-
-// w -= sum_{i < nv} h_i V_i; then partial dots with V[0..nv) (or w . w if norm_only)
-__global__ __launch_bounds__(256) void k_axpy_dots(double* __restrict__ w,
-                                                   const double* __restrict__ V, int nv, int64_t n,
-                                                   const KrylovState* __restrict__ st,
-                                                   double* __restrict__ partial, int norm_only) {
-  __shared__ double red[4];
-  __shared__ double hs[128];
-  if (st->stop) return;
-  if (threadIdx.x < nv) hs[threadIdx.x] = st->h[threadIdx.x];
-  __syncthreads();
-  const int b = blockIdx.x;
-  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
-    double x = w[e];
-    for (int i = 0; i < nv; i++) x -= hs[i] * V[(int64_t)i * n + e];
-    w[e] = x;
-  }
-  if (norm_only) {
-    double acc = 0;
-    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
-      acc += w[e] * w[e];
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partial[b] = s;
-    return;
-  }
-  for (int i = 0; i < nv; i++) {
-    const double* v = V + (int64_t)i * n;
-    double acc = 0;
-    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
-      acc += v[e] * w[e];
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
-  }
-}
-
-// out = w / scale; which 0: scale = beta[j] (skipped after breakdown), 1: scal[1]
-__global__ __launch_bounds__(256) void k_scale_into(const double* __restrict__ w,
-                                                    double* __restrict__ out, int64_t n,
-                                                    const KrylovState* __restrict__ st, int which,
-                                                    int j) {
-  if (which == 0 && st->stop) return;
-  const double sc = which == 0 ? st->beta[j] : st->scal[1];
-  const double inv = 1.0 / sc;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
-    out[e] = w[e] * inv;
-}
-
-// ---- fused Lanczos steps: every workgroup first reduces the partial sums of
-// the previous kernel itself (fixed order, identical in every workgroup), so
-// no separate reduction launch is needed between the steps.
+// The fused steps first reduce the partial sums of the previous kernel in
+// every workgroup (fixed order, identical everywhere), so no separate
+// reduction launch sits between them.
 __device__ __forceinline__ double sum_partials(const double* __restrict__ p, double* red) {
   return block_sum(p[threadIdx.x], red);   // kRedBlocks == blockDim.x == 256
 }
 
-__global__ __launch_bounds__(256) void k_state_init(KrylovState* __restrict__ st, int kmax) {
+__device__ __forceinline__ void write_copies(const KJob& J, int64_t e, double v) {
+  if (J.x64) J.x64[e] = v;
+  if (J.x32) J.x32[e] = (float)v;
+}
+
+__global__ __launch_bounds__(256) void k_kinit(const KJob* __restrict__ jobs, int kmax) {
+  KrylovState* st = jobs[blockIdx.y].st;
   const int t = threadIdx.x;
   if (t < 128) { st->alpha[t] = 0; st->beta[t] = 0; st->h[t] = 0; st->y[t] = 0; }
   if (t < 8) st->scal[t] = 0;
   if (t == 0) { st->kmax = kmax; st->keff = 1; st->stop = 0; st->status = 0; }
 }
 
-// alpha_j = sum(partial_a); w -= alpha_j v_j + beta_{j-1} v_{j-1}; partial dots V[0..j].w
-__global__ __launch_bounds__(256) void k_lanczos_update2(double* __restrict__ w,
-                                                         const double* __restrict__ V, int64_t n,
-                                                         KrylovState* __restrict__ st, int j,
-                                                         const double* __restrict__ partial_a,
-                                                         double* __restrict__ partial) {
+// P0 = partial sums of ||T||^2
+__global__ __launch_bounds__(256) void k_knorm(const KJob* __restrict__ jobs) {
   __shared__ double red[4];
+  const KJob& J = jobs[blockIdx.y];
+  double acc = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
+    acc += J.T[e] * J.T[e];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) parea(J, 0)[blockIdx.x] = s;
+}
+
+// mode 0: V_0 = T / ||T|| (and the copies); mode 1: T <- T / ||T||.  ||T||^2 from P0.
+__global__ __launch_bounds__(256) void k_kscale(const KJob* __restrict__ jobs, int mode) {
+  __shared__ double red[4];
+  const KJob& J = jobs[blockIdx.y];
+  const double nr = sqrt(sum_partials(parea(J, 0), red));
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !(nr > 0 && isfinite(nr))) J.st->status = 1;
+  const double inv = 1.0 / nr;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)gridDim.x * 256) {
+    const double v = J.T[e] * inv;
+    if (mode == 0) { J.V[e] = v; write_copies(J, e, v); }
+    else J.T[e] = v;
+  }
+}
+
+// P0 = partial sums of v_j . w
+__global__ __launch_bounds__(256) void k_kdot(const KJob* __restrict__ jobs, int j) {
+  __shared__ double red[4];
+  const KJob& J = jobs[blockIdx.y];
+  if (J.st->stop) return;
+  const double* v = J.V + (int64_t)j * J.n;
+  double acc = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
+    acc += v[e] * J.w[e];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) parea(J, 0)[blockIdx.x] = s;
+}
+
+// alpha_j = sum P0 (last step, no update follows)
+__global__ __launch_bounds__(256) void k_kalpha(const KJob* __restrict__ jobs, int j) {
+  __shared__ double red[4];
+  const KJob& J = jobs[blockIdx.y];
+  if (J.st->stop) return;
+  const double a = sum_partials(parea(J, 0), red);
+  if (threadIdx.x == 0) {
+    J.st->alpha[j] = a;
+    if (!isfinite(a)) J.st->status = 1;
+  }
+}
+
+// alpha_j = sum P0; w -= alpha_j v_j + beta_{j-1} v_{j-1}; P1 = partial dots V[0..j] . w
+__global__ __launch_bounds__(256) void k_kupdate(const KJob* __restrict__ jobs, int j) {
+  __shared__ double red[4];
+  const KJob& J = jobs[blockIdx.y];
+  KrylovState* st = J.st;
   if (st->stop) return;
-  const double a = sum_partials(partial_a, red);
+  const int64_t n = J.n;
+  double* w = J.w;
+  const double a = sum_partials(parea(J, 0), red);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->alpha[j] = a;
     if (!isfinite(a)) st->status = 1;
   }
   const int b = blockIdx.x;
   const double bb = j > 0 ? st->beta[j - 1] : 0.0;
-  const double* vj = V + (int64_t)j * n;
-  const double* vm = j > 0 ? V + (int64_t)(j - 1) * n : V;
+  const double* vj = J.V + (int64_t)j * n;
+  const double* vm = j > 0 ? J.V + (int64_t)(j - 1) * n : J.V;
   for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
     double x = w[e] - a * vj[e];
     if (j > 0) x -= bb * vm[e];
     w[e] = x;
   }
+  // the same thread touches the same elements below: no barrier needed for w
+  double* out = parea(J, 1);
   for (int i = 0; i <= j; i++) {
-    const double* v = V + (int64_t)i * n;
+    const double* v = J.V + (int64_t)i * n;
     double acc = 0;
     for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
       acc += v[e] * w[e];
     const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
+    if (threadIdx.x == 0) out[i * kRedBlocks + b] = s;
   }
 }
 
-// h = sums of partial_in (nv vectors); w -= sum h_i V_i; partial dots (or norm)
-__global__ __launch_bounds__(256) void k_axpy_dots2(double* __restrict__ w,
-                                                    const double* __restrict__ V, int nv, int64_t n,
-                                                    const KrylovState* __restrict__ st,
-                                                    const double* __restrict__ partial_in,
-                                                    double* __restrict__ partial, int norm_only) {
+// classical Gram-Schmidt pass against V[0..j]: h = sums of P(pin); w -= sum h_i V_i;
+// then P(pin + 1) = partial dots V[0..j] . w, or ||w||^2 when norm_only
+__global__ __launch_bounds__(256) void k_kortho(const KJob* __restrict__ jobs, int j, int pin,
+                                                int norm_only) {
   __shared__ double red[4];
   __shared__ double hs[128];
-  if (st->stop) return;
+  const KJob& J = jobs[blockIdx.y];
+  if (J.st->stop) return;
+  const int nv = j + 1;
+  const int64_t n = J.n;
+  double* w = J.w;
+  const double* pi = parea(J, pin);
   for (int i = 0; i < nv; i++) {
-    const double hv = sum_partials(partial_in + i * kRedBlocks, red);
+    const double hv = sum_partials(pi + i * kRedBlocks, red);
     if (threadIdx.x == 0) hs[i] = hv;
   }
   __syncthreads();
   const int b = blockIdx.x;
   for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
     double x = w[e];
-    for (int i = 0; i < nv; i++) x -= hs[i] * V[(int64_t)i * n + e];
+    for (int i = 0; i < nv; i++) x -= hs[i] * J.V[(int64_t)i * n + e];
     w[e] = x;
   }
+  double* po = parea(J, pin + 1);
   if (norm_only) {
     double acc = 0;
     for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
       acc += w[e] * w[e];
     const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partial[b] = s;
+    if (threadIdx.x == 0) po[b] = s;
     return;
   }
   for (int i = 0; i < nv; i++) {
-    const double* v = V + (int64_t)i * n;
+    const double* v = J.V + (int64_t)i * n;
     double acc = 0;
     for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
       acc += v[e] * w[e];
     const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partial[i * kRedBlocks + b] = s;
+    if (threadIdx.x == 0) po[i * kRedBlocks + b] = s;
   }
 }
 
-// beta_j = sqrt(sum partial); breakdown test; V_{j+1} = w / beta_j
-__global__ __launch_bounds__(256) void k_scale_beta(const double* __restrict__ w,
-                                                    double* __restrict__ out, int64_t n,
-                                                    KrylovState* __restrict__ st, int j,
-                                                    const double* __restrict__ partial) {
+// beta_j = sqrt(sum P3); breakdown test; V_{j+1} = w / beta_j (and the copies)
+__global__ __launch_bounds__(256) void k_kbeta(const KJob* __restrict__ jobs, int j) {
   __shared__ double red[4];
+  const KJob& J = jobs[blockIdx.y];
+  KrylovState* st = J.st;
   if (st->stop) return;
-  const double b = sqrt(sum_partials(partial, red));
+  const double b = sqrt(sum_partials(parea(J, 3), red));
   double amax = 0;
   for (int k = 0; k <= j; k++) amax = fmax(amax, fabs(st->alpha[k]));
   const bool brk = !(b > 1e-14 * amax);
@@ -801,21 +830,12 @@ __global__ __launch_bounds__(256) void k_scale_beta(const double* __restrict__ w
   }
   if (brk) return;
   const double inv = 1.0 / b;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
-    out[e] = w[e] * inv;
-}
-
-// out = x / sqrt(sum partial)
-__global__ __launch_bounds__(256) void k_scale_norm(const double* __restrict__ x,
-                                                    double* __restrict__ out, int64_t n,
-                                                    const double* __restrict__ partial,
-                                                    KrylovState* __restrict__ st) {
-  __shared__ double red[4];
-  const double nr = sqrt(sum_partials(partial, red));
-  if (blockIdx.x == 0 && threadIdx.x == 0 && !(nr > 0 && isfinite(nr))) st->status = 1;
-  const double inv = 1.0 / nr;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
-    out[e] = x[e] * inv;
+  double* out = J.V + (int64_t)(j + 1) * J.n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)gridDim.x * 256) {
+    const double v = J.w[e] * inv;
+    out[e] = v;
+    write_copies(J, e, v);
+  }
 }
 
 // Lowest eigenpair of the keff x keff symmetric tridiagonal matrix
@@ -941,15 +961,11 @@ __device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restr
   }
 }
 
-__global__ __launch_bounds__(64) void k_tridiag(KrylovState* __restrict__ st) {
+__global__ __launch_bounds__(64) void k_ktridiag(const KJob* __restrict__ jobs) {
   __shared__ double lds[512];
-  tridiag_solve_wave(st, lds);
+  tridiag_solve_wave(jobs[blockIdx.y].st, lds);
 }
 
-// ---- tiny nodes: the whole Lanczos eigensolve in one workgroup.  The matvec
-// interprets the node's work lists (generic kernels only) phase by phase with
-// barriers in between; the vector steps are the same as in the multi-kernel
-// path, with workgroup reductions.
 // ---- tiny nodes (M <= 1024): H_eff is assembled densely once per eigensolve
 // (the same operator as the factorised matvec: every item's Kronecker product
 // written out entry by entry), then the Lanczos steps run in one workgroup
@@ -958,10 +974,11 @@ __device__ __forceinline__ double blk(const double* O, int m, int i, int ip) {
   return O ? O[(int64_t)ip * m + i] : (i == ip ? 1.0 : 0.0);
 }
 
-// H^T[j][i] = H[i][j] (H is symmetric), one thread per entry
-__global__ __launch_bounds__(256) void k_tiny_assemble(const TinyPlan* __restrict__ plan,
-                                                       double* __restrict__ H) {
-  const TinyPlan P = *plan;
+// H^T[j][i] = H[i][j] (H is symmetric), one thread per entry; job blockIdx.y
+__global__ __launch_bounds__(256) void k_tiny_assemble(const TJob* __restrict__ jobs) {
+  const TJob& J = jobs[blockIdx.y];
+  const TinyPlan P = *J.plan;
+  double* __restrict__ H = J.H;
   const int d0 = P.d0, d1 = P.d1, d2 = P.d2;
   const int M = d0 * d1 * d2;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -990,11 +1007,14 @@ __global__ __launch_bounds__(256) void k_tiny_assemble(const TinyPlan* __restric
   H[e] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_tiny_lanczos(const double* __restrict__ H, int M,
-                                                      double* __restrict__ T,
-                                                      double* __restrict__ V,
-                                                      double* __restrict__ w,
-                                                      KrylovState* __restrict__ st, int k) {
+__global__ __launch_bounds__(256) void k_tiny_lanczos(const TJob* __restrict__ jobs, int kreq) {
+  const TJob& J = jobs[blockIdx.x];
+  const double* __restrict__ H = J.H;
+  double* __restrict__ T = J.T;
+  double* __restrict__ V = J.V;
+  double* __restrict__ w = J.w;
+  KrylovState* __restrict__ st = J.st;
+  const int M = J.M, k = kreq < M ? kreq : M;
   __shared__ double red[4];
   __shared__ double hs[64];
   __shared__ double xs[1024];
@@ -1076,25 +1096,24 @@ __global__ __launch_bounds__(256) void k_tiny_lanczos(const double* __restrict__
 }
 
 // out = sum_i y_i V_i with partial ||out||^2
-__global__ __launch_bounds__(256) void k_ritz(const double* __restrict__ V, int64_t n,
-                                              double* __restrict__ out,
-                                              const KrylovState* __restrict__ st,
-                                              double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_kritz(const KJob* __restrict__ jobs) {
   __shared__ double red[4];
   __shared__ double ys[128];
+  const KJob& J = jobs[blockIdx.y];
+  const KrylovState* st = J.st;
   const int k = st->keff;
   if (threadIdx.x < k) ys[threadIdx.x] = st->y[threadIdx.x];
   __syncthreads();
   const int b = blockIdx.x;
   double acc2 = 0;
-  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
+  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256) {
     double x = 0;
-    for (int i = 0; i < k; i++) x += ys[i] * V[(int64_t)i * n + e];
-    out[e] = x;
+    for (int i = 0; i < k; i++) x += ys[i] * J.V[(int64_t)i * J.n + e];
+    J.T[e] = x;
     acc2 += x * x;
   }
   const double s = block_sum(acc2, red);
-  if (threadIdx.x == 0) partial[b] = s;
+  if (threadIdx.x == 0) parea(J, 0)[b] = s;
 }
 
 // ============================================================================ QR helpers
@@ -1339,12 +1358,6 @@ template <typename T, int NB>
 static hipError_t sand_launch(const SWTask* tasks, const SWItem* items, const int4* wus, int nwu,
                               int ma, const void* xbase, hipStream_t s) {
   const size_t lds = (size_t)ma * (16 * NB + 2) * sizeof(T);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_sandwich<T, NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
-    attr_set = true;
-  }
   hipLaunchKernelGGL((k_sandwich<T, NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus,
                      (const T*)xbase);
   return hipGetLastError();
@@ -1354,12 +1367,6 @@ template <int NB>
 static hipError_t sand_bf2_launch(const SWTask* tasks, const SWItem* items, const int4* wus, int nwu,
                                   int ma, const void* xbase, hipStream_t s) {
   const size_t lds = (size_t)2 * (16 * NB) * (ma + 8) * sizeof(__bf16);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_sandwich_bf2<NB>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
   hipLaunchKernelGGL((k_sandwich_bf2<NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus,
                      (const float*)xbase);
   return hipGetLastError();
@@ -1419,12 +1426,6 @@ template <typename T, int NI>
 static hipError_t mode_launch(const MPTask* tasks, const MPJob* jobs, const int2* wus, int nwu,
                               const void* xbase, hipStream_t s) {
   const size_t lds = (size_t)16 * NI * 66 * sizeof(T);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_mode<T, NI>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
-    attr_set = true;
-  }
   hipLaunchKernelGGL((k_mode<T, NI>), dim3(nwu), dim3(256), lds, s, tasks, jobs, wus,
                      (const T*)xbase);
   return hipGetLastError();
@@ -1462,12 +1463,6 @@ hipError_t launch_mode(int dtype, int mj, bool mfma, const MPTask* tasks, const 
 template <int NI>
 static hipError_t gram_launch(const GRTask* tasks, int ntask, hipStream_t s) {
   const size_t lds = (size_t)2 * 64 * (16 * NI + 2) * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_gram<NI>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        160 * 1024);
-    attr_set = true;
-  }
   hipLaunchKernelGGL(k_gram<NI>, dim3(ntask), dim3(256), lds, s, tasks);
   return hipGetLastError();
 }
@@ -1558,106 +1553,66 @@ hipError_t launch_cast(const void* src, int src_dtype, void* dst, int dst_dtype,
   return hipGetLastError();
 }
 
-hipError_t launch_multidot(const double* V, int nv, const double* w, int64_t n, double* partial,
-                           const KrylovState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(256), 0, s, V, nv, w, n, partial, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_dot_final(const double* partial, int nv, double* out, int mode,
-                            KrylovState* st, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, s, partial, nv, out, mode, st, j);
-  return hipGetLastError();
-}
-
-hipError_t launch_lanczos_update(double* w, const double* V, int64_t n, KrylovState* st, int j,
-                                 double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_lanczos_update, dim3(kRedBlocks), dim3(256), 0, s, w, V, n, st, j, partial);
-  return hipGetLastError();
-}
-
-hipError_t launch_axpy_dots(double* w, const double* V, int nv, int64_t n, KrylovState* st,
-                            double* partial, int norm_only, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy_dots, dim3(kRedBlocks), dim3(256), 0, s, w, V, nv, n, st, partial,
-                     norm_only);
-  return hipGetLastError();
-}
-
-hipError_t launch_scale_into(const double* w, double* out, int64_t n, KrylovState* st, int which,
-                             int j, hipStream_t s) {
+static inline unsigned gridv(int64_t n) {
   int64_t g = grid1(n);
-  if (g > 2048) g = 2048;
-  hipLaunchKernelGGL(k_scale_into, dim3((unsigned)g), dim3(256), 0, s, w, out, n, st, which, j);
+  return (unsigned)(g > 1024 ? 1024 : (g < 1 ? 1 : g));
+}
+
+hipError_t launch_kinit(const KJob* jobs, int nj, int kmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_kinit, dim3(1, nj), dim3(256), 0, s, jobs, kmax);
   return hipGetLastError();
 }
 
-hipError_t launch_state_init(KrylovState* st, int kmax, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(256), 0, s, st, kmax);
+hipError_t launch_knorm(const KJob* jobs, int nj, hipStream_t s) {
+  hipLaunchKernelGGL(k_knorm, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 
-hipError_t launch_lanczos_update2(double* w, const double* V, int64_t n, KrylovState* st, int j,
-                                  const double* partial_a, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_lanczos_update2, dim3(kRedBlocks), dim3(256), 0, s, w, V, n, st, j,
-                     partial_a, partial);
+hipError_t launch_kscale(const KJob* jobs, int nj, int64_t nmax, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_kscale, dim3(gridv(nmax), nj), dim3(256), 0, s, jobs, mode);
   return hipGetLastError();
 }
 
-hipError_t launch_axpy_dots2(double* w, const double* V, int nv, int64_t n, KrylovState* st,
-                             const double* partial_in, double* partial, int norm_only,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy_dots2, dim3(kRedBlocks), dim3(256), 0, s, w, V, nv, n, st,
-                     partial_in, partial, norm_only);
+hipError_t launch_kdot(const KJob* jobs, int nj, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_kdot, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs, j);
   return hipGetLastError();
 }
 
-hipError_t launch_scale_beta(const double* w, double* out, int64_t n, KrylovState* st, int j,
-                             const double* partial, hipStream_t s) {
-  int64_t g = grid1(n);
-  if (g > 1024) g = 1024;
-  hipLaunchKernelGGL(k_scale_beta, dim3((unsigned)g), dim3(256), 0, s, w, out, n, st, j, partial);
+hipError_t launch_kalpha(const KJob* jobs, int nj, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_kalpha, dim3(1, nj), dim3(256), 0, s, jobs, j);
   return hipGetLastError();
 }
 
-hipError_t launch_scale_norm(const double* x, double* out, int64_t n, const double* partial,
-                             KrylovState* st, hipStream_t s) {
-  int64_t g = grid1(n);
-  if (g > 1024) g = 1024;
-  hipLaunchKernelGGL(k_scale_norm, dim3((unsigned)g), dim3(256), 0, s, x, out, n, partial, st);
+hipError_t launch_kupdate(const KJob* jobs, int nj, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_kupdate, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs, j);
   return hipGetLastError();
 }
 
-hipError_t launch_tiny_lanczos(const TinyPlan* plan, int M, double* H, double* T, double* V,
-                               double* w, KrylovState* st, int k, hipStream_t s) {
-  hipLaunchKernelGGL(k_tiny_assemble, dim3((unsigned)(((int64_t)M * M + 255) / 256)), dim3(256), 0, s,
-                     plan, H);
-  hipLaunchKernelGGL(k_tiny_lanczos, dim3(1), dim3(256), 0, s, H, M, T, V, w, st, k);
+hipError_t launch_kortho(const KJob* jobs, int nj, int j, int pin, int norm_only, hipStream_t s) {
+  hipLaunchKernelGGL(k_kortho, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs, j, pin, norm_only);
   return hipGetLastError();
 }
 
-hipError_t launch_tridiag(KrylovState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(64), 0, s, st);
+hipError_t launch_kbeta(const KJob* jobs, int nj, int j, int64_t nmax, hipStream_t s) {
+  hipLaunchKernelGGL(k_kbeta, dim3(gridv(nmax), nj), dim3(256), 0, s, jobs, j);
   return hipGetLastError();
 }
 
-hipError_t launch_ritz(const double* V, int64_t n, double* out, KrylovState* st, double* partial,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_ritz, dim3(kRedBlocks), dim3(256), 0, s, V, n, out, st, partial);
+hipError_t launch_ktridiag(const KJob* jobs, int nj, hipStream_t s) {
+  hipLaunchKernelGGL(k_ktridiag, dim3(1, nj), dim3(64), 0, s, jobs);
   return hipGetLastError();
 }
 
-hipError_t launch_norm2(const double* x, int64_t n, double* partial, hipStream_t s) {
-  hipLaunchKernelGGL(k_multidot, dim3(kRedBlocks), dim3(256), 0, s, (const double*)nullptr, 1, x,
-                     n, partial, (const KrylovState*)nullptr);
+hipError_t launch_kritz(const KJob* jobs, int nj, hipStream_t s) {
+  hipLaunchKernelGGL(k_kritz, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs);
   return hipGetLastError();
 }
 
-hipError_t launch_normalize(double* x, int64_t n, double* partial, KrylovState* st, hipStream_t s) {
-  hipError_t e = launch_norm2(x, n, partial, s);
-  if (e != hipSuccess) return e;
-  e = launch_dot_final(partial, 1, nullptr, 4, st, 0, s);
-  if (e != hipSuccess) return e;
-  return launch_scale_into(x, x, n, st, 1, 0, s);
+hipError_t launch_tiny(const TJob* jobs, int nj, int maxM, int kreq, hipStream_t s) {
+  hipLaunchKernelGGL(k_tiny_assemble, dim3((unsigned)(((int64_t)maxM * maxM + 255) / 256), nj), dim3(256),
+                     0, s, jobs);
+  hipLaunchKernelGGL(k_tiny_lanczos, dim3(nj), dim3(256), 0, s, jobs, kreq);
+  return hipGetLastError();
 }
 
 hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, int shift_mode,
@@ -1669,12 +1624,6 @@ hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, i
     case 64: hipLaunchKernelGGL(k_chol_inv_reg<64>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
     default: break;
   }
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              150 * 1024);
-    attr_set = true;
-  }
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), (size_t)n * (n + 1) * sizeof(double), s, G,
                      n, R, RinvRow, shift_mode, rows, st);
   return hipGetLastError();
@@ -1682,12 +1631,6 @@ hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, i
 
 hipError_t launch_qr_small(double* T, int d0, int d1, int d2, int j, double* Rout, KrylovState* st,
                            hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_qr_small, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              150 * 1024);
-    attr_set = true;
-  }
   const size_t lds = (size_t)d0 * d1 * d2 * sizeof(double);
   hipLaunchKernelGGL(k_qr_small, dim3(1), dim3(256), lds, s, T, d0, d1, d2, j, Rout, st);
   return hipGetLastError();
@@ -1696,6 +1639,80 @@ hipError_t launch_qr_small(double* T, int d0, int d1, int d2, int j, double* Rou
 hipError_t launch_small_matmul(const double* A, const double* B, double* C, int n, hipStream_t s) {
   hipLaunchKernelGGL(k_small_matmul, dim3((unsigned)((n * n + 63) / 64)), dim3(64), 0, s, A, B, C, n);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- mixed-shape launchers
+hipError_t launch_batch_sandwich(int dtype, const SWTask* tasks, const SWItem* items, const int4* wus,
+                                 int nwu, size_t lds, hipStream_t s) {
+  if (nwu == 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_batch_sandwich<double>, dim3(nwu), dim3(256), lds, s, tasks, items, wus);
+  else
+    hipLaunchKernelGGL(k_batch_sandwich<float>, dim3(nwu), dim3(256), lds, s, tasks, items, wus);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_mode(int dtype, const MPTask* tasks, const MPJob* jobs, const int2* wus, int nwu,
+                             size_t lds, hipStream_t s) {
+  if (nwu == 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_batch_mode<double>, dim3(nwu), dim3(256), lds, s, tasks, jobs, wus);
+  else
+    hipLaunchKernelGGL(k_batch_mode<float>, dim3(nwu), dim3(256), lds, s, tasks, jobs, wus);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_list(int dtype, const TRTask* tasks, int ntask, int64_t maxM, hipStream_t s) {
+  if (ntask == 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_transpose_list<double>, dim3(gridv(maxM), ntask), dim3(256), 0, s, tasks);
+  else
+    hipLaunchKernelGGL(k_transpose_list<float>, dim3(gridv(maxM), ntask), dim3(256), 0, s, tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_list(int dtype_in, const RDTask* tasks, int ntask, int64_t maxM, hipStream_t s) {
+  if (ntask == 0) return hipSuccess;
+  if (dtype_in == 0)
+    hipLaunchKernelGGL((k_reduce_list<double, double>), dim3(gridv(maxM), ntask), dim3(256), 0, s, tasks);
+  else
+    hipLaunchKernelGGL((k_reduce_list<float, double>), dim3(gridv(maxM), ntask), dim3(256), 0, s, tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(gridv(n)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+// Raise the dynamic-LDS limit of every kernel that uses it (call before any
+// stream capture: attribute changes are not stream operations).
+hipError_t prepare_kernel_attributes() {
+  const void* fns[] = {
+      (const void*)k_batch_sandwich<double>, (const void*)k_batch_sandwich<float>,
+      (const void*)k_batch_mode<double>, (const void*)k_batch_mode<float>,
+      (const void*)k_sandwich<double, 1>, (const void*)k_sandwich<double, 2>,
+      (const void*)k_sandwich<double, 3>, (const void*)k_sandwich<double, 4>,
+      (const void*)k_sandwich<double, 5>, (const void*)k_sandwich<double, 6>,
+      (const void*)k_sandwich<double, 7>, (const void*)k_sandwich<double, 8>,
+      (const void*)k_sandwich<float, 1>, (const void*)k_sandwich<float, 2>,
+      (const void*)k_sandwich<float, 3>, (const void*)k_sandwich<float, 4>,
+      (const void*)k_sandwich<float, 5>, (const void*)k_sandwich<float, 6>,
+      (const void*)k_sandwich<float, 7>, (const void*)k_sandwich<float, 8>,
+      (const void*)k_sandwich_bf2<2>, (const void*)k_sandwich_bf2<4>,
+      (const void*)k_sandwich_bf2<6>, (const void*)k_sandwich_bf2<8>,
+      (const void*)k_mode<double, 1>, (const void*)k_mode<double, 2>, (const void*)k_mode<double, 3>,
+      (const void*)k_mode<double, 4>, (const void*)k_mode<double, 5>, (const void*)k_mode<double, 6>,
+      (const void*)k_mode<double, 7>, (const void*)k_mode<double, 8>,
+      (const void*)k_mode<float, 1>, (const void*)k_mode<float, 2>, (const void*)k_mode<float, 3>,
+      (const void*)k_mode<float, 4>, (const void*)k_mode<float, 5>, (const void*)k_mode<float, 6>,
+      (const void*)k_mode<float, 7>, (const void*)k_mode<float, 8>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace attn

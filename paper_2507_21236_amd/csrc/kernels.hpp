@@ -88,6 +88,18 @@ struct RDSrc {
   int32_t pad;
 };
 
+// list forms (one task per tensor, several problem instances per launch)
+struct RDTask {
+  const RDSrc* srcs;
+  void* y;             // FP64
+  int32_t nsrc, ml, mr, mp;
+};
+struct TRTask {        // [l][r][p] -> [p][l][r]
+  const void* x;
+  void* xt;
+  int32_t ml, mr, mp, pad;
+};
+
 // ---------------------------------------------------------------- conversion
 // fmt 1: FP64 -> FP32, same (column-major) layout.
 // fmt 2: FP64 -> split BF16 (x = hi + lo up to ~2^-17 |x|) for m x m blocks,
@@ -100,6 +112,32 @@ struct CVTask {
   int64_t n;       // elements
   int32_t m;       // block dimension (fmt 2)
   int32_t fmt;
+};
+
+// ---------------------------------------------------------------- Krylov
+// Lanczos / QR scalar state kept on the device (no host round trip per step).
+struct KrylovState {
+  double alpha[128];
+  double beta[128];
+  double h[128];
+  double y[128];      // eigenvector of the tridiagonal matrix
+  double scal[8];     // [0] = theta, [1] = norm scratch, [2] = shift
+  int32_t kmax;       // number of matvecs requested
+  int32_t keff;       // number of Lanczos vectors kept
+  int32_t stop;       // breakdown reached
+  int32_t status;     // 0 ok, 1 non-finite, 2 factorisation breakdown
+};
+
+// One Lanczos eigensolve (one node of one problem instance).
+struct KJob {
+  double* V;          // Krylov basis, row-major [k + 1][n]
+  double* w;          // matvec output / residual
+  double* T;          // node tensor: start vector in, normalised Ritz vector out
+  double* red;        // four partial-sum areas P0..P3 of 64 x 256 values
+  KrylovState* st;
+  double* x64;        // optional copy of the newest basis vector (FP64)
+  float* x32;         // optional copy of the newest basis vector (FP32)
+  int64_t n;
 };
 
 // ---------------------------------------------------------------- tiny nodes
@@ -117,6 +155,17 @@ struct TinyPlan {
   int32_t item0[3], nitem[3];
   int32_t n3;
   int32_t d0, d1, d2;
+};
+
+// Dense eigensolve of one tiny node: H (M x M scratch), basis V, residual w.
+struct TJob {
+  const TinyPlan* plan;
+  double* H;
+  double* T;
+  double* V;
+  double* w;
+  KrylovState* st;
+  int32_t M, pad;
 };
 
 }  // namespace attn

@@ -7,19 +7,6 @@
 
 namespace attn {
 
-// Lanczos / QR scalar state kept on the device (no host round trip per step).
-struct KrylovState {
-  double alpha[128];
-  double beta[128];
-  double h[128];
-  double y[128];      // eigenvector of the tridiagonal matrix
-  double scal[8];     // [0] = theta, [1] = norm scratch, [2] = shift
-  int32_t kmax;       // number of matvecs requested
-  int32_t keff;       // number of Lanczos vectors kept
-  int32_t stop;       // breakdown reached
-  int32_t status;     // 0 ok, 1 non-finite, 2 factorisation breakdown
-};
-
 // Reduction scratch: per vector, per block partial sums.
 constexpr int kRedBlocks = 256;
 
@@ -39,35 +26,30 @@ hipError_t launch_convert(int dtype, const CVTask* tasks, int ntask, int64_t max
 hipError_t launch_cast(const void* src, int src_dtype, void* dst, int dst_dtype, int64_t n,
                        hipStream_t s);
 
-// Krylov helpers (all FP64).  Vectors are length n, V is row-major [nv][n].
-hipError_t launch_multidot(const double* V, int nv, const double* w, int64_t n, double* partial,
-                           const KrylovState* st, hipStream_t s);
-hipError_t launch_dot_final(const double* partial, int nv, double* out, int mode,
-                            KrylovState* st, int j, hipStream_t s);
-hipError_t launch_lanczos_update(double* w, const double* V, int64_t n, KrylovState* st, int j,
-                                 double* partial, hipStream_t s);
-hipError_t launch_axpy_dots(double* w, const double* V, int nv, int64_t n, KrylovState* st,
-                            double* partial, int norm_only, hipStream_t s);
-hipError_t launch_scale_into(const double* w, double* out, int64_t n, KrylovState* st, int which,
-                             int j, hipStream_t s);
-hipError_t launch_tridiag(KrylovState* st, hipStream_t s);
-hipError_t launch_tiny_lanczos(const TinyPlan* plan, int M, double* H, double* T, double* V,
-                               double* w, KrylovState* st, int k, hipStream_t s);
-hipError_t launch_ritz(const double* V, int64_t n, double* out, KrylovState* st, double* partial,
-                       hipStream_t s);
-hipError_t launch_normalize(double* x, int64_t n, double* partial, KrylovState* st, hipStream_t s);
-hipError_t launch_norm2(const double* x, int64_t n, double* partial, hipStream_t s);
+// Krylov steps (FP64) over a list of jobs, one launch for all of them.  Each
+// job reads/writes its own partial-sum areas P0..P3 (see KJob).
+hipError_t launch_kinit(const KJob* jobs, int nj, int kmax, hipStream_t s);
+hipError_t launch_knorm(const KJob* jobs, int nj, hipStream_t s);
+hipError_t launch_kscale(const KJob* jobs, int nj, int64_t nmax, int mode, hipStream_t s);
+hipError_t launch_kdot(const KJob* jobs, int nj, int j, hipStream_t s);
+hipError_t launch_kalpha(const KJob* jobs, int nj, int j, hipStream_t s);
+hipError_t launch_kupdate(const KJob* jobs, int nj, int j, hipStream_t s);
+hipError_t launch_kortho(const KJob* jobs, int nj, int j, int pin, int norm_only, hipStream_t s);
+hipError_t launch_kbeta(const KJob* jobs, int nj, int j, int64_t nmax, hipStream_t s);
+hipError_t launch_ktridiag(const KJob* jobs, int nj, hipStream_t s);
+hipError_t launch_kritz(const KJob* jobs, int nj, hipStream_t s);
+hipError_t launch_tiny(const TJob* jobs, int nj, int maxM, int kreq, hipStream_t s);
 
-hipError_t launch_state_init(KrylovState* st, int kmax, hipStream_t s);
-hipError_t launch_lanczos_update2(double* w, const double* V, int64_t n, KrylovState* st, int j,
-                                  const double* partial_a, double* partial, hipStream_t s);
-hipError_t launch_axpy_dots2(double* w, const double* V, int nv, int64_t n, KrylovState* st,
-                             const double* partial_in, double* partial, int norm_only,
-                             hipStream_t s);
-hipError_t launch_scale_beta(const double* w, double* out, int64_t n, KrylovState* st, int j,
-                             const double* partial, hipStream_t s);
-hipError_t launch_scale_norm(const double* x, double* out, int64_t n, const double* partial,
-                             KrylovState* st, hipStream_t s);
+// Mixed-shape launches over the tasks of several nodes / problem instances
+// (LDS in bytes: the largest any unit of the launch needs).
+hipError_t launch_batch_sandwich(int dtype, const SWTask* tasks, const SWItem* items, const int4* wus,
+                                 int nwu, size_t lds, hipStream_t s);
+hipError_t launch_batch_mode(int dtype, const MPTask* tasks, const MPJob* jobs, const int2* wus, int nwu,
+                             size_t lds, hipStream_t s);
+hipError_t launch_transpose_list(int dtype, const TRTask* tasks, int ntask, int64_t maxM, hipStream_t s);
+hipError_t launch_reduce_list(int dtype_in, const RDTask* tasks, int ntask, int64_t maxM, hipStream_t s);
+hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+hipError_t prepare_kernel_attributes();
 
 // QR helpers
 hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, int shift_mode,

@@ -2,217 +2,16 @@
 // C interface declared in attn.h.  All arithmetic of the path runs in the
 // kernels of kernels.hip; this file only allocates, uploads work lists and
 // enqueues launches.
-#include <hip/hip_runtime_api.h>
-
-#include <algorithm>
-#include <chrono>
-#include <functional>
-#include <cmath>
-#include <cstring>
-#include <string>
-#include <vector>
-
-#include "attn.h"
-#include "kernels.hpp"
-#include "launch.hpp"
-#include "model.hpp"
+#include "runtime.hpp"
 
 using namespace attn;
+using namespace rt;
 
 namespace {
-
 thread_local std::string g_build_error;
-
-struct HipFail {
-  hipError_t e;
-  const char* what;
-};
-
-#define HIPCHK(x)                                 \
-  do {                                            \
-    hipError_t _e = (x);                          \
-    if (_e != hipSuccess) throw HipFail{_e, #x};  \
-  } while (0)
-
-struct StatusFail {
-  attn_status st;
-  std::string msg;
-};
-
-// A sandwich launch group: tasks with the same (ma, mb).
-struct SWGroup {
-  int ma = 0, mb = 0;
-  int fmt = 0;        // low-precision plans: 1 = FP32 blocks, 2 = split-BF16 blocks
-  double flops = 0;   // algorithmic flops of one launch
-  std::vector<SWTask> tasks;
-  std::vector<SWItem> items;
-  std::vector<int4> wus;
-  SWTask* d_tasks = nullptr;
-  SWItem* d_items = nullptr;
-  int4* d_wus = nullptr;
-};
-
-struct MPGroup {
-  int mj = 0;
-  bool mfma = false;
-  std::vector<MPTask> tasks;
-  std::vector<MPJob> jobs;
-  std::vector<int2> wus;
-  MPTask* d_tasks = nullptr;
-  MPJob* d_jobs = nullptr;
-  int2* d_wus = nullptr;
-};
-
-struct CBPlan {
-  std::vector<CBTask> tasks;
-  std::vector<CBTerm> terms;
-  CBTask* d_tasks = nullptr;
-  CBTerm* d_terms = nullptr;
-  int maxn = 0;
-};
-
-struct GRPlan {
-  int mj = 0;
-  bool mfma = false;
-  std::vector<GRTask> tasks;
-  std::vector<GRReduce> reds;
-  GRTask* d_tasks = nullptr;
-  GRReduce* d_reds = nullptr;
-};
-
-struct MVDev {
-  TinyPlan* d_tiny = nullptr;   // set when the whole plan runs in one workgroup
-  std::vector<SWItem> tiny_items;
-  int tiny_item0[3] = {0, 0, 0}, tiny_nitem[3] = {0, 0, 0};
-  std::vector<Item3> tiny_items3;
-  CBPlan comb;
-  std::vector<SWGroup> sw;
-  std::vector<MPGroup> chainA, chainB, chainC;   // one group per mj
-  std::vector<RDSrc> srcs;
-  RDSrc* d_srcs = nullptr;
-  bool need_xt = false;
-  int dims[3] = {0, 0, 0};
-};
-
-struct EnvChunk {
-  std::vector<SWGroup> sw;
-  GRPlan gr;
-  std::vector<std::pair<double*, int64_t>> zero_blocks;
-};
-
-struct EnvDev {
-  bool present = false;
-  bool transpose = false;
-  int dims[3] = {0, 0, 0};
-  CBPlan comb;
-  std::vector<EnvChunk> chunks;
-  int node = -1, leg = -1, out_edge = -1, out_dir = 0;
-};
-
-// QR of a node tensor with one leg as the column index (three CholeskyQR passes)
-struct QRDev {
-  bool present = false;
-  int mj = 0, nfc = 0, nwus = 0;
-  bool gmf = false, mmf = false;
-  int64_t rows = 0, Msz = 0;
-  GRTask* d_gt[3] = {nullptr, nullptr, nullptr};
-  GRReduce* d_gr = nullptr;
-  MPTask* d_mt[3] = {nullptr, nullptr, nullptr};
-  MPJob* d_mj[3] = {nullptr, nullptr, nullptr};
-  int2* d_wus = nullptr;
-  std::vector<GRTask> h_gt[3];
-  std::vector<GRReduce> h_gr;
-  MPGroup h_mp[3];   // host copies for validation
-};
-
-// T <- R x_leg T through a temporary
-struct ABDev {
-  bool present = false;
-  int mj = 0, nwus = 0;
-  bool mmf = false;
-  int64_t Msz = 0;
-  MPTask* d_mt = nullptr;
-  MPJob* d_mj = nullptr;
-  int2* d_wus = nullptr;
-  MPGroup h_mp;   // host copy for validation
-};
-
-bool mode_mfma_ok(int mj, int64_t M) { return mj % 16 == 0 && mj <= 128 && (M / mj) % 64 == 0; }
-bool gram_mfma_ok(int mj, int64_t M) { return mj % 16 == 0 && mj <= 128 && (M / mj) % 64 == 0; }
-
 }  // namespace
 
-struct attn_handle {
-  Model M;
-  std::string err;
-  bool host_only = false;
-  bool dryrun = false;
-  bool dead = false;
-  uintptr_t fake_next = (uintptr_t)1 << 40;
-  std::vector<std::pair<uintptr_t, size_t>> allocs;
-  int device = 0;
-  std::vector<void*> owned;
-  // tensors
-  double* d_T = nullptr;
-  std::vector<int64_t> T_off;
-  std::vector<int64_t> T_len;
-  // effective-operator stores per edge and direction
-  std::vector<double*> store[2];
-  std::vector<char> valid[2];
-  std::vector<int> iso;       // per node: leg it is isometric toward, -1 = centre
-  int center = -1;
-  bool state_ready = false;
-  // scratch
-  int64_t Mmax = 0;
-  int kcap = 65;   // at most 64 Krylov vectors (+1)
-  double* d_V = nullptr;      // (kcap) x Mmax
-  double* d_w = nullptr;
-  double* d_xt = nullptr;
-  double* d_tmp = nullptr;
-  double* d_tmp2 = nullptr;
-  float* d_x32 = nullptr;
-  float* d_y32 = nullptr;
-  double* d_part = nullptr;   // mv partial outputs
-  int64_t part_cap = 0;
-  double* d_chain = nullptr;
-  int64_t chain_cap = 0;
-  double* d_mvcomb = nullptr;
-  double* d_envcomb = nullptr;
-  double* d_Z = nullptr;
-  double* d_grpart = nullptr;
-  double* d_red = nullptr;    // 128 x kRedBlocks
-  double* d_qrmat = nullptr;  // G, R0, R1, R2, Rinv, Rt (mmax^2 each)
-  double* d_qrR = nullptr;    // R of the last QR (absorbed into the neighbour)
-  void* d_cvtasks = nullptr;  // conversion work list (low-precision forms)
-  int cv_cap = 0;
-  int mmax = 1;
-  KrylovState* d_st = nullptr;
-  // plans
-  std::vector<MVDev> mv;
-  // low-precision forms: 4-byte-per-element mirrors of the FP64 stores (FP32,
-  // or BF16 hi/lo planes per block) and copies of every matvec work list
-  bool lowp_ready[2] = {false, false};
-  std::vector<void*> mir[2][2];     // [format - 1][direction][edge]
-  std::vector<int64_t> store_elems[2];
-  void* comb_lp[2] = {nullptr, nullptr};
-  int64_t mvcomb_elems = 0;
-  std::vector<MVDev> mvlp[2];
-  std::vector<std::vector<std::pair<int64_t, int>>> comb_blocks;   // per node: (offset, dim)
-  std::vector<EnvDev> env_up, env_down[2];
-  std::vector<QRDev> qr[3];   // per leg, per node
-  std::vector<ABDev> ab[3];   // absorb into node along leg
-  // counters
-  int64_t n_matvec = 0, n_env = 0, n_qr = 0;
-  double mv_flops = 0;
-  // live timing of the matvec sandwich launches (HIP events on the launch stream)
-  bool prof = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  struct ProfRec { int a, b; double flops; int ma, mb, dtype; };
-  std::vector<ProfRec> prof_recs;
-};
-
-namespace {
+namespace rt {
 
 // ------------------------------------------------------------------ device memory
 // Every device buffer goes through dev_alloc so that a dry-run build can lay
@@ -229,14 +28,6 @@ void* dev_alloc(attn_handle* h, size_t bytes) {
   }
   h->allocs.push_back({(uintptr_t)p, bytes});
   return p;
-}
-
-template <typename T>
-T* upload(attn_handle* h, const std::vector<T>& v) {
-  if (v.empty()) return nullptr;
-  void* p = dev_alloc(h, v.size() * sizeof(T));
-  if (!h->dryrun) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-  return (T*)p;
 }
 
 // ------------------------------------------------------------------ pointers
@@ -646,7 +437,7 @@ void matvec_f64(attn_handle* h, int n, const double* x, double* y, hipStream_t s
   run_mp(D.chainC, 0, x, s);
   run_sw_mv(h, D.sw, 0, x, s);
   if (D.srcs.empty()) {
-    HIPCHK(hipMemsetAsync(y, 0, (size_t)D.dims[0] * D.dims[1] * D.dims[2] * sizeof(double), s));
+    HIPCHK(launch_zero(y, (int64_t)D.dims[0] * D.dims[1] * D.dims[2], s));
   } else {
     HIPCHK(launch_reduce_out(0, D.d_srcs, (int)D.srcs.size(), y, 0, D.dims[0], D.dims[1], D.dims[2], s));
   }
@@ -821,7 +612,7 @@ void run_env(attn_handle* h, EnvDev& D, hipStream_t s) {
   if (D.transpose)
     HIPCHK(launch_transpose_plr(0, h->d_T + h->T_off[D.node], h->d_xt, D.dims[0], D.dims[1], D.dims[2], s));
   for (auto& ch : D.chunks) {
-    for (auto& zb : ch.zero_blocks) HIPCHK(hipMemsetAsync(zb.first, 0, zb.second * sizeof(double), s));
+    for (auto& zb : ch.zero_blocks) HIPCHK(launch_zero(zb.first, zb.second, s));
     run_sw(ch.sw, 0, nullptr, s);
     HIPCHK(launch_gram(ch.gr.mj, ch.gr.mfma, ch.gr.d_tasks, (int)ch.gr.tasks.size(), s));
     HIPCHK(launch_gram_reduce(ch.gr.d_reds, (int)ch.gr.reds.size(), ch.gr.mj, s));
@@ -980,7 +771,7 @@ void check_state(attn_handle* h, hipStream_t s, const char* where) {
 }
 
 void reset_state(attn_handle* h, int kmax, hipStream_t s) {
-  HIPCHK(launch_state_init(h->d_st, kmax, s));
+  HIPCHK(launch_kinit(h->d_kjobs64 + h->M.tree.root, 1, kmax, s));
 }
 
 attn_status need_device(attn_handle* h) {
@@ -993,17 +784,12 @@ attn_status need_device(attn_handle* h) {
 double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStream_t s) {
   MVDev& D = h->mv[n];
   const int64_t Msz = (int64_t)D.dims[0] * D.dims[1] * D.dims[2];
-  const int k = (int)std::min<int64_t>(std::min(kreq, h->kcap - 1), Msz);
-  double* T = h->d_T + h->T_off[n];
-  double* V = h->d_V;
-  double* w = h->d_w;
-  // four partial-sum areas (64 vectors x kRedBlocks each) used round robin
-  double* P[4];
-  for (int i = 0; i < 4; i++) P[i] = h->d_red + (int64_t)i * 64 * kRedBlocks;
+  const int kk = std::min(kreq, h->kcap - 1);
+  const int k = (int)std::min<int64_t>(kk, Msz);
   run_comb(D.comb, s);
   // tiny nodes (dense H_eff, negligible work) stay in FP64 for every form
   if (D.d_tiny) {
-    HIPCHK(launch_tiny_lanczos(D.d_tiny, (int)Msz, h->d_tmp2, T, V, w, h->d_st, k, s));
+    HIPCHK(launch_tiny(h->d_tjobs + n, 1, (int)Msz, kk, s));
     h->n_matvec += k;
     h->mv_flops += (double)k * h->M.mv[n].flops;
     KrylovState st;
@@ -1017,30 +803,28 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
     ensure_lowp(h, precision);
     prepare_lowp(h, n, precision, s);
   }
-  HIPCHK(launch_state_init(h->d_st, k, s));
-  HIPCHK(launch_norm2(T, Msz, P[0], s));
-  HIPCHK(launch_scale_norm(T, V, Msz, P[0], h->d_st, s));
+  // the low-precision job also writes an FP32 copy of each new basis vector
+  const KJob* J = (precision == ATTN_F64 ? h->d_kjobs64 : h->d_kjobs32) + n;
+  double* V = h->d_V;
+  HIPCHK(launch_kinit(J, 1, k, s));
+  HIPCHK(launch_knorm(J, 1, s));
+  HIPCHK(launch_kscale(J, 1, Msz, 0, s));
   for (int j = 0; j < k; j++) {
-    double* vj = V + (int64_t)j * Msz;
-    if (precision == ATTN_F64) {
-      matvec_f64(h, n, vj, w, s);
-    } else {
-      HIPCHK(launch_cast(vj, 0, h->d_x32, 1, Msz, s));
-      matvec_lowp(h, n, precision, h->d_x32, w, 0, s);
-    }
-    HIPCHK(launch_multidot(vj, 1, w, Msz, P[0], h->d_st, s));
+    if (precision == ATTN_F64) matvec_f64(h, n, V + (int64_t)j * Msz, h->d_w, s);
+    else matvec_lowp(h, n, precision, h->d_x32, h->d_w, 0, s);
+    HIPCHK(launch_kdot(J, 1, j, s));
     if (j == k - 1) {
-      HIPCHK(launch_dot_final(P[0], 1, nullptr, 1, h->d_st, j, s));
+      HIPCHK(launch_kalpha(J, 1, j, s));
       break;
     }
-    HIPCHK(launch_lanczos_update2(w, V, Msz, h->d_st, j, P[0], P[1], s));
-    HIPCHK(launch_axpy_dots2(w, V, j + 1, Msz, h->d_st, P[1], P[2], 0, s));
-    HIPCHK(launch_axpy_dots2(w, V, j + 1, Msz, h->d_st, P[2], P[3], 1, s));
-    HIPCHK(launch_scale_beta(w, V + (int64_t)(j + 1) * Msz, Msz, h->d_st, j, P[3], s));
+    HIPCHK(launch_kupdate(J, 1, j, s));
+    HIPCHK(launch_kortho(J, 1, j, 1, 0, s));
+    HIPCHK(launch_kortho(J, 1, j, 2, 1, s));
+    HIPCHK(launch_kbeta(J, 1, j, Msz, s));
   }
-  HIPCHK(launch_tridiag(h->d_st, s));
-  HIPCHK(launch_ritz(V, Msz, T, h->d_st, P[0], s));
-  HIPCHK(launch_scale_norm(T, T, Msz, P[0], h->d_st, s));
+  HIPCHK(launch_ktridiag(J, 1, s));
+  HIPCHK(launch_kritz(J, 1, s));
+  HIPCHK(launch_kscale(J, 1, Msz, 1, s));
   KrylovState st;
   HIPCHK(hipMemcpyAsync(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1049,7 +833,7 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
   return st.scal[0];
 }
 
-}  // namespace
+}  // namespace rt
 
 // ====================================================================== C interface
 extern "C" {
@@ -1088,7 +872,10 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
     return ATTN_OK;
   }
   try {
-    if (!h->dryrun) HIPCHK(hipSetDevice(h->device));
+    if (!h->dryrun) {
+      HIPCHK(hipSetDevice(h->device));
+      HIPCHK(prepare_kernel_attributes());
+    }
     // tensors
     int64_t tot = 0;
     for (int n = 0; n < nn; n++) {
@@ -1213,6 +1000,23 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
       if (n != tr.root) build_env_dev(h, h->M.env_up[n], h->env_up[n]);
       for (int sd = 0; sd < 2; sd++) build_env_dev(h, h->M.env_down[sd][n], h->env_down[sd][n]);
     }
+    // eigensolver job descriptors, one per node (the FP32 one also keeps an
+    // FP32 copy of the newest basis vector for the low-precision matvec)
+    std::vector<KJob> kj64(nn), kj32(nn);
+    std::vector<TJob> tj(nn);
+    for (int n = 0; n < nn; n++) {
+      const int64_t Msz = h->T_len[n];
+      double* T = h->d_T + h->T_off[n];
+      kj64[n] = KJob{h->d_V, h->d_w, T, h->d_red, h->d_st, nullptr, nullptr, Msz};
+      kj32[n] = kj64[n];
+      kj32[n].x32 = h->d_x32;
+      tj[n] = TJob{h->mv[n].d_tiny, h->d_tmp2, T, h->d_V, h->d_w, h->d_st, (int32_t)Msz, 0};
+    }
+    h->h_kjobs = kj64;
+    h->h_tjobs = tj;
+    h->d_kjobs64 = upload(h, kj64);
+    h->d_kjobs32 = upload(h, kj32);
+    h->d_tjobs = upload(h, tj);
     if (!h->dryrun) HIPCHK(hipDeviceSynchronize());
   } catch (const HipFail& e) {
     g_build_error = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
@@ -1460,8 +1264,8 @@ attn_status attn_init_state(attn_handle* h, const double* raw, int64_t len, void
       if (n == tr.root) continue;
       qr_node(h, n, 2, s);   // Q replaces the block, R is discarded
     }
-    double* T = h->d_T + h->T_off[tr.root];
-    HIPCHK(launch_normalize(T, h->T_len[tr.root], h->d_red, h->d_st, s));
+    HIPCHK(launch_knorm(h->d_kjobs64 + tr.root, 1, s));
+    HIPCHK(launch_kscale(h->d_kjobs64 + tr.root, 1, h->T_len[tr.root], 1, s));
     for (int n = 0; n < nn; n++) h->iso[n] = 2;
     h->iso[tr.root] = -1;
     h->center = tr.root;
@@ -1637,6 +1441,21 @@ extern "C" attn_status attn_validate(const attn_handle* h) {
       c.span(h->d_tmp2, M * M * 8, "dense H_eff");
     }
     if (D.need_xt) c.span(h->d_xt, M * 8, "transposed input");
+    {
+      const KJob& J = h->h_kjobs[n];
+      if (J.n != M) c.fail("eigensolve job size");
+      c.span(J.T, M * 8, "job tensor");
+      c.span(J.V, (int64_t)h->kcap * M * 8, "job basis");
+      c.span(J.w, M * 8, "job residual");
+      c.span(h->d_x32, M * 4, "job FP32 copy");
+      c.span(J.red, (int64_t)4 * 64 * kRedBlocks * 8, "job partial sums");
+      c.span(J.st, sizeof(KrylovState), "job state");
+      if (D.d_tiny) {
+        const TJob& tj = h->h_tjobs[n];
+        if (tj.M != M || tj.plan != D.d_tiny) c.fail("tiny job");
+        c.span(tj.H, M * M * 8, "tiny H");
+      }
+    }
     const EnvDev* eds[3] = {&h->env_up[n], &h->env_down[0][n], &h->env_down[1][n]};
     for (const EnvDev* E : eds) {
       if (!E->present) continue;

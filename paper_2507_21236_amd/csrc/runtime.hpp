@@ -1,0 +1,243 @@
+// Internal declarations of the runtime shared by runtime.cpp (single-handle
+// entry points) and batch.cpp (lock-step batches of handles): device plans,
+// the handle itself and the helpers that enqueue its work.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "attn.h"
+#include "kernels.hpp"
+#include "launch.hpp"
+#include "model.hpp"
+
+namespace rt {
+using namespace attn;
+
+
+struct HipFail {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIPCHK(x)                                 \
+  do {                                            \
+    hipError_t _e = (x);                          \
+    if (_e != hipSuccess) throw HipFail{_e, #x};  \
+  } while (0)
+
+struct StatusFail {
+  attn_status st;
+  std::string msg;
+};
+
+// A sandwich launch group: tasks with the same (ma, mb).
+struct SWGroup {
+  int ma = 0, mb = 0;
+  int fmt = 0;        // low-precision plans: 1 = FP32 blocks, 2 = split-BF16 blocks
+  double flops = 0;   // algorithmic flops of one launch
+  std::vector<SWTask> tasks;
+  std::vector<SWItem> items;
+  std::vector<int4> wus;
+  SWTask* d_tasks = nullptr;
+  SWItem* d_items = nullptr;
+  int4* d_wus = nullptr;
+};
+
+struct MPGroup {
+  int mj = 0;
+  bool mfma = false;
+  std::vector<MPTask> tasks;
+  std::vector<MPJob> jobs;
+  std::vector<int2> wus;
+  MPTask* d_tasks = nullptr;
+  MPJob* d_jobs = nullptr;
+  int2* d_wus = nullptr;
+};
+
+struct CBPlan {
+  std::vector<CBTask> tasks;
+  std::vector<CBTerm> terms;
+  CBTask* d_tasks = nullptr;
+  CBTerm* d_terms = nullptr;
+  int maxn = 0;
+};
+
+struct GRPlan {
+  int mj = 0;
+  bool mfma = false;
+  std::vector<GRTask> tasks;
+  std::vector<GRReduce> reds;
+  GRTask* d_tasks = nullptr;
+  GRReduce* d_reds = nullptr;
+};
+
+struct MVDev {
+  TinyPlan* d_tiny = nullptr;   // set when the whole plan runs in one workgroup
+  std::vector<SWItem> tiny_items;
+  int tiny_item0[3] = {0, 0, 0}, tiny_nitem[3] = {0, 0, 0};
+  std::vector<Item3> tiny_items3;
+  CBPlan comb;
+  std::vector<SWGroup> sw;
+  std::vector<MPGroup> chainA, chainB, chainC;   // one group per mj
+  std::vector<RDSrc> srcs;
+  RDSrc* d_srcs = nullptr;
+  bool need_xt = false;
+  int dims[3] = {0, 0, 0};
+};
+
+struct EnvChunk {
+  std::vector<SWGroup> sw;
+  GRPlan gr;
+  std::vector<std::pair<double*, int64_t>> zero_blocks;
+};
+
+struct EnvDev {
+  bool present = false;
+  bool transpose = false;
+  int dims[3] = {0, 0, 0};
+  CBPlan comb;
+  std::vector<EnvChunk> chunks;
+  int node = -1, leg = -1, out_edge = -1, out_dir = 0;
+};
+
+// QR of a node tensor with one leg as the column index (three CholeskyQR passes)
+struct QRDev {
+  bool present = false;
+  int mj = 0, nfc = 0, nwus = 0;
+  bool gmf = false, mmf = false;
+  int64_t rows = 0, Msz = 0;
+  GRTask* d_gt[3] = {nullptr, nullptr, nullptr};
+  GRReduce* d_gr = nullptr;
+  MPTask* d_mt[3] = {nullptr, nullptr, nullptr};
+  MPJob* d_mj[3] = {nullptr, nullptr, nullptr};
+  int2* d_wus = nullptr;
+  std::vector<GRTask> h_gt[3];
+  std::vector<GRReduce> h_gr;
+  MPGroup h_mp[3];   // host copies for validation
+};
+
+// T <- R x_leg T through a temporary
+struct ABDev {
+  bool present = false;
+  int mj = 0, nwus = 0;
+  bool mmf = false;
+  int64_t Msz = 0;
+  MPTask* d_mt = nullptr;
+  MPJob* d_mj = nullptr;
+  int2* d_wus = nullptr;
+  MPGroup h_mp;   // host copy for validation
+};
+
+inline bool mode_mfma_ok(int mj, int64_t M) { return mj % 16 == 0 && mj <= 128 && (M / mj) % 64 == 0; }
+inline bool gram_mfma_ok(int mj, int64_t M) { return mj % 16 == 0 && mj <= 128 && (M / mj) % 64 == 0; }
+
+}  // namespace rt
+
+using namespace attn;   // internal header: the runtime sources use both namespaces
+using namespace rt;
+
+struct attn_handle {
+  Model M;
+  std::string err;
+  bool host_only = false;
+  bool dryrun = false;
+  bool dead = false;
+  uintptr_t fake_next = (uintptr_t)1 << 40;
+  std::vector<std::pair<uintptr_t, size_t>> allocs;
+  int device = 0;
+  std::vector<void*> owned;
+  // tensors
+  double* d_T = nullptr;
+  std::vector<int64_t> T_off;
+  std::vector<int64_t> T_len;
+  // effective-operator stores per edge and direction
+  std::vector<double*> store[2];
+  std::vector<char> valid[2];
+  std::vector<int> iso;       // per node: leg it is isometric toward, -1 = centre
+  int center = -1;
+  bool state_ready = false;
+  // scratch
+  int64_t Mmax = 0;
+  int kcap = 65;   // at most 64 Krylov vectors (+1)
+  double* d_V = nullptr;      // (kcap) x Mmax
+  double* d_w = nullptr;
+  double* d_xt = nullptr;
+  double* d_tmp = nullptr;
+  double* d_tmp2 = nullptr;
+  float* d_x32 = nullptr;
+  float* d_y32 = nullptr;
+  double* d_part = nullptr;   // mv partial outputs
+  int64_t part_cap = 0;
+  double* d_chain = nullptr;
+  int64_t chain_cap = 0;
+  double* d_mvcomb = nullptr;
+  double* d_envcomb = nullptr;
+  double* d_Z = nullptr;
+  double* d_grpart = nullptr;
+  double* d_red = nullptr;    // 128 x kRedBlocks
+  double* d_qrmat = nullptr;  // G, R0, R1, R2, Rinv, Rt (mmax^2 each)
+  double* d_qrR = nullptr;    // R of the last QR (absorbed into the neighbour)
+  void* d_cvtasks = nullptr;  // conversion work list (low-precision forms)
+  int cv_cap = 0;
+  int mmax = 1;
+  KrylovState* d_st = nullptr;
+  KJob* d_kjobs64 = nullptr;  // per node: eigensolve descriptors (FP64 / with FP32 copy)
+  KJob* d_kjobs32 = nullptr;
+  TJob* d_tjobs = nullptr;    // per node: dense tiny-node eigensolve
+  std::vector<KJob> h_kjobs;  // host copies for validation
+  std::vector<TJob> h_tjobs;
+  // plans
+  std::vector<MVDev> mv;
+  // low-precision forms: 4-byte-per-element mirrors of the FP64 stores (FP32,
+  // or BF16 hi/lo planes per block) and copies of every matvec work list
+  bool lowp_ready[2] = {false, false};
+  std::vector<void*> mir[2][2];     // [format - 1][direction][edge]
+  std::vector<int64_t> store_elems[2];
+  void* comb_lp[2] = {nullptr, nullptr};
+  int64_t mvcomb_elems = 0;
+  std::vector<MVDev> mvlp[2];
+  std::vector<std::vector<std::pair<int64_t, int>>> comb_blocks;   // per node: (offset, dim)
+  std::vector<EnvDev> env_up, env_down[2];
+  std::vector<QRDev> qr[3];   // per leg, per node
+  std::vector<ABDev> ab[3];   // absorb into node along leg
+  // counters
+  int64_t n_matvec = 0, n_env = 0, n_qr = 0;
+  double mv_flops = 0;
+  // live timing of the matvec sandwich launches (HIP events on the launch stream)
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct ProfRec { int a, b; double flops; int ma, mb, dtype; };
+  std::vector<ProfRec> prof_recs;
+};
+
+
+// ---------------------------------------------------------------- shared helpers (runtime.cpp)
+namespace rt {
+void* dev_alloc(attn_handle* h, size_t bytes);
+template <typename T>
+T* upload(attn_handle* h, const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  void* p = dev_alloc(h, v.size() * sizeof(T));
+  if (!h->dryrun) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return (T*)p;
+}
+double* block_ptr(attn_handle* h, const BRef& b, double* comb_base, const std::vector<int64_t>& comb_off);
+void slice_geom(int spect, const int* dm, int& ma, int& mb, int& ns, int64_t& sl, int64_t& row);
+bool sw_mfma(int ma, int mb);
+void run_comb(CBPlan& P, hipStream_t s);
+void* to_mirror(attn_handle* h, const void* p, int fmt);
+void ensure_lowp(attn_handle* h, int dtype);
+std::vector<CVTask> lowp_conversions(attn_handle* h, int n, int dtype);
+int leg_toward(const Tree& tr, int a, int b);
+void run_env(attn_handle* h, EnvDev& D, hipStream_t s);
+void qr_node(attn_handle* h, int n, int leg, hipStream_t s);
+void absorb(attn_handle* h, int q, int leg, hipStream_t s);
+}  // namespace rt

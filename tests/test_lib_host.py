@@ -116,3 +116,18 @@ def test_device_calls_on_host_only_handle_fail_cleanly():
     assert e.value.code == -8
     with pytest.raises(AttnError):
         _lib.attn_node_info(a.h, 99)
+
+
+def test_batch_create_rejects_bad_input_on_host():
+    from paper_2507_21236_amd import AttnBatch
+    a = AttnHandle(config_problem("ising4_m8"), flags=ATTN_HOST_ONLY)
+    with pytest.raises(AttnError) as e:
+        AttnBatch([a])
+    assert e.value.code == -8          # STATE: handle cannot run on the device
+    assert "device" in str(e.value)
+    with pytest.raises(AttnError) as e:
+        _lib.attn_batch_create([], 20)
+    assert e.value.code == -1          # ARG: no handles
+    with pytest.raises(AttnError) as e:
+        _lib.attn_batch_create([a.h, a.h], 20)
+    assert e.value.code in (-1, -8)
