@@ -14,7 +14,9 @@ CPU oracle timed on this host on a bounded sample of the same workload.
 The low-precision forms (FP32 operands; split hi/lo BF16 operands on the
 BF16 matrix cores with FP32 accumulation; FP64 Krylov in both) are timed on the
 same sweeps after the primary run and reported as speedups over the FP64 path,
-with the energy difference per site of every sweep.
+with the energy difference per site of every sweep.  The batched form (32
+uneven seeded instances swept in lock step through mixed-shape launches and
+HIP graphs) is compared with per-instance sweeps of the same instances.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
                        [--precision f64|f32|bf16x2] [--forms f32,bf16x2]
@@ -73,6 +75,86 @@ def cpu_baseline(problem, sample_matvecs=3):
                        f"not timed")}
 
 
+def batched_form(sweeps, warmup):
+    """32 uneven instances (L in {8, 12, 16}, m in {16, 32, 48, 64}, seeded):
+    plain per-instance FP64 sweeps vs lock-step batched sweeps (mixed-shape
+    launches, HIP graphs, autotuned splits) in FP32 and FP64."""
+    import numpy as np
+    import torch
+    from problems import batch_instances
+    from paper_2507_21236_amd import AttnHandle, AttnBatch, solver_opts, ATTN_F64, ATTN_F32
+    ps = batch_instances(32)
+    t0 = time.time()
+    hs = [AttnHandle(p) for p in ps]
+    print(f"[bench] batched form: built 32 handles in {time.time() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+
+    def per_instance(prec):
+        tot = 0.0
+        es = []
+        for a in hs:
+            a.init_state()
+            for _ in range(warmup):
+                a.sweep(1, solver_opts(krylov_k=20, precision=prec))
+            a.init_state()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            e, _ = a.sweep(sweeps, solver_opts(krylov_k=20, precision=prec))
+            torch.cuda.synchronize()
+            tot += time.perf_counter() - t
+            es.append(e)
+        return tot / sweeps, es
+
+    def batched(prec):
+        for a in hs:
+            a.init_state()
+        t = time.perf_counter()
+        b = AttnBatch(hs, krylov_k=20, precision=prec, use_graphs=True, autotune=True)
+        t_create = time.perf_counter() - t
+        for _ in range(warmup):   # also captures the step graphs
+            b.sweep(1)
+        for a in hs:
+            a.init_state()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        e, _ = b.sweep(sweeps)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / sweeps
+        tuned = b.info()[2]
+        b.close()
+        return dt, e, t_create, tuned
+
+    seq64, e_seq64 = per_instance(ATTN_F64)
+    print(f"[bench] per-instance FP64 sweeps: {seq64:.3f} s per sweep of all 32", file=sys.stderr,
+          flush=True)
+    seq32, e_seq32 = per_instance(ATTN_F32)
+    print(f"[bench] per-instance FP32 sweeps: {seq32:.3f} s", file=sys.stderr, flush=True)
+    b32, e_b32, c32, tuned = batched(ATTN_F32)
+    print(f"[bench] batched FP32 sweeps: {b32:.3f} s (create + autotune {c32:.1f} s)",
+          file=sys.stderr, flush=True)
+    b64, e_b64, c64, _ = batched(ATTN_F64)
+    print(f"[bench] batched FP64 sweeps: {b64:.3f} s", file=sys.stderr, flush=True)
+    n_sites = np.array([p.n_sites for p in ps], dtype=float)
+    d32 = max(float(np.max(np.abs(e_b32[i] - e_seq32[i]))) / n_sites[i] for i in range(len(ps)))
+    d64 = max(float(np.max(np.abs(e_b64[i] - e_seq64[i]))) / n_sites[i] for i in range(len(ps)))
+    out = {"instances": "32 seeded OBC square Ising, L in {8,12,16}, h ~ U[2.5,3.5], "
+                        "m in {16,32,48,64}, L^2/4 disentanglers",
+           "sweeps_timed": sweeps,
+           "per_instance_f64_s_per_sweep": round(seq64, 4),
+           "per_instance_f32_s_per_sweep": round(seq32, 4),
+           "batched_f32_s_per_sweep": round(b32, 4),
+           "batched_f64_s_per_sweep": round(b64, 4),
+           "speedup_batched_f32_vs_per_instance_f64": round(seq64 / b32, 3),
+           "speedup_batched_f64_vs_per_instance_f64": round(seq64 / b64, 3),
+           "max_abs_dE_per_site_batched_f32_vs_per_instance_f32": d32,
+           "max_abs_dE_per_site_batched_f64_vs_per_instance_f64": d64,
+           "autotuned_splits_ma_mb_target": tuned,
+           "batch_create_s": round(c32, 2)}
+    for a in hs:
+        a.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +165,8 @@ def main():
                     help="low-precision forms timed after the primary run ('' for none)")
     ap.add_argument("--config", default="ising16_m64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-sweeps", type=int, default=2,
+                    help="timed sweeps of the batched-form comparison (0 to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is a "
@@ -196,6 +280,9 @@ def main():
                 "max_abs_dE_per_site_vs_" + args.precision: max(
                     abs(x - y) for x, y in zip(e_f, energies)) / N,
             }
+    if args.batch_sweeps > 0:
+        out["forms"] = out.get("forms", {})
+        out["forms"]["batched"] = batched_form(args.batch_sweeps, 1)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)
