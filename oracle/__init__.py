@@ -15,6 +15,11 @@ Modules and the parts of the paper they follow:
 * ``terms``  -- disentangler layer contracted into every term, h' = U^T h U
                 (Sec. 4.2, algorithm "Contract disentangler layer"; ordering of
                 the rotation as read in the design doc), and operator-Schmidt splits.
+* ``davidson`` -- an eigensolver form that is not from the paper: the H_eff
+                diagonal, Davidson's method with Jacobi or learned pointwise
+                corrections, the exact Jacobi-Davidson correction, the MLP
+                model, its gradient and Adam updates (published methods cited
+                in the module).
 * ``ttn``    -- isometric TTN, effective operators kept term by term
                 (Sec. 3.3.2), the generalised matvec (Sec. 4.3.2), Lanczos,
                 QR isometrisation (Sec. 3.1) and the sweep (Sec. 4).
