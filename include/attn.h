@@ -242,6 +242,66 @@ attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* 
                        double* energies, double* seconds);
 
 /*
+ * Davidson form (not from the paper, which uses Lanczos): attn_eigsolve_node
+ * with opts->solver = ATTN_SOLVER_DAVIDSON runs Davidson's method in FP64
+ * (contractions in opts->precision): basis of at most min(krylov_k, 32)
+ * vectors, restart to the lowest opts->restart Ritz vectors, stop at residual
+ * norm <= opts->tol or after opts->max_iter matvecs.  Corrections:
+ * ATTN_PRECOND_JACOBI, t_i = -r_i / (diag_i - theta) with the H_eff diagonal
+ * assembled from the diagonals of the operators of every term; or
+ * ATTN_PRECOND_LEARNED, a pointwise model t_i = o(f_i) ||r||_inf / ||diag||_inf
+ * of the features f_i = ((diag_i - theta)/||diag||_inf, r_i/||r||_inf,
+ * theta/||diag||_inf): three tanh layers of width 64, FP16 parameters, FP32
+ * arithmetic.  The learned correction falls back to Jacobi for the rest of a
+ * solve when it is not finite, adds nothing to the basis, or reduces the
+ * residual less than the running Jacobi rate for two consecutive iterations.
+ */
+
+/* Number of model parameters: W1[3][64], b1[64], W2[64][64], b2[64],
+ * W3[64][64], b3[64], W4[64], b4 (row-major; layer k maps h to tanh(h W + b)). */
+#define ATTN_MLP_PARAMS 8641
+
+/* Load the model (FP32 host array of ATTN_MLP_PARAMS values, stored as FP16).
+ * Errors: SHAPE (n), STATE (no device), HIP. */
+attn_status attn_precond_set_weights(attn_handle* h, const float* params, int64_t n);
+
+/* Davidson counters since the handle was built: iterations, fallbacks to
+ * Jacobi, residual norm at the end of the last Davidson solve and the running
+ * Jacobi reduction rate.  Pointers may be NULL. */
+attn_status attn_solver_stats(const attn_handle* h, int64_t* dav_iters, int64_t* fallbacks,
+                              double* last_rnorm, double* jacobi_rate);
+
+/* diag(H_eff(node)) into the device array `diag` (M doubles, layout of T_n).
+ * node must be the centre with current effective operators.  Asynchronous. */
+attn_status attn_heff_diagonal(attn_handle* h, int32_t node, double* diag, void* stream);
+
+/* Training data of the learned correction at the centre `node`: n_pairs
+ * Davidson iterations with Jacobi corrections from T_n; at each, the exact
+ * Jacobi-Davidson correction t* (solution of (1 - uu^T)(H - theta)(1 - uu^T) t = -r,
+ * t orthogonal to u) by projected conjugate gradients to relative residual
+ * cg_tol (at most cg_max matvecs).  Writes the features (device float
+ * [n_pairs][M][3]) and the scaled targets t* ||diag||_inf / ||r||_inf (device
+ * float [n_pairs][M]); cg_res[p] (host, may be NULL) = achieved relative CG
+ * residual.  T_n is left unchanged.  Synchronises `stream`. */
+attn_status attn_precond_harvest(attn_handle* h, int32_t node, int32_t n_pairs, double cg_tol,
+                                 int32_t cg_max, float* feats, float* targets, double* cg_res,
+                                 void* stream);
+
+/* Train the model on n points (device features [n][3], targets [n]): `steps`
+ * Adam steps (lr; beta 0.9, 0.999; eps 1e-8) on consecutive batches of `batch`
+ * points (a multiple of 64; batch k uses points [(k mod (n / batch)) batch, +batch)),
+ * mean-squared-error loss, hand-written FP32 kernels.  params (host,
+ * ATTN_MLP_PARAMS) is the start point and receives the result; loss (host,
+ * `steps` values, may be NULL) the batch losses.  Errors: ARG, HIP. */
+attn_status attn_mlp_train(const float* feats, const float* targets, int64_t n, int32_t steps,
+                           int32_t batch, float lr, float* params, float* loss, void* stream);
+
+/* Model outputs o for n feature triples (device in/out) with the FP16-rounded
+ * parameters (host FP32).  Synchronises `stream`. */
+attn_status attn_mlp_eval(const float* params, const float* feats, float* out, int64_t n,
+                          void* stream);
+
+/*
  * Batched form (not from the paper): independent problem instances, each its
  * own handle (sizes and bond dimensions may differ, d must agree, legs <= 64),
  * swept in lock step.  Step t of a batch sweep moves every instance's centre to

@@ -12,7 +12,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (ATTN_F64, ATTN_F32, ATTN_BF16X2, ATTN_DE_STRICT, ATTN_HOST_ONLY, ATTN_DRYRUN,
-                   AttnError, solver_opts)
+                   ATTN_SOLVER_LANCZOS, ATTN_SOLVER_DAVIDSON, ATTN_PRECOND_JACOBI,
+                   ATTN_PRECOND_LEARNED, ATTN_MLP_PARAMS, AttnError, solver_opts)
 
 
 class AttnHandle:
@@ -72,6 +73,27 @@ class AttnHandle:
     def sweep(self, n_sweeps, opts=None):
         return _lib.attn_sweep(self.h, n_sweeps, opts)
 
+    def set_precond_weights(self, params):
+        _lib.attn_precond_set_weights(self.h, params)
+
+    def solver_stats(self):
+        """(Davidson iterations, fallbacks to Jacobi, last residual norm, Jacobi rate)"""
+        return _lib.attn_solver_stats(self.h)
+
+    def heff_diagonal(self, node, out, stream=None):
+        """out: float64 torch tensor on the device with M elements"""
+        _lib.attn_heff_diagonal(self.h, node, out.data_ptr(), stream)
+
+    def harvest(self, node, n_pairs, cg_tol=1e-10, cg_max=2000):
+        """(features [n_pairs * M, 3], targets [n_pairs * M]) float32 torch
+        tensors on the device, and the achieved CG residuals."""
+        import torch
+        M = int(np.prod(self.node_info(node)[0]))
+        f = torch.empty((n_pairs * M, 3), dtype=torch.float32, device="cuda")
+        t = torch.empty(n_pairs * M, dtype=torch.float32, device="cuda")
+        res = _lib.attn_precond_harvest(self.h, node, n_pairs, cg_tol, cg_max, f.data_ptr(), t.data_ptr())
+        return f, t, res
+
     def validate(self):
         _lib.attn_validate(self.h)
 
@@ -113,3 +135,17 @@ class AttnBatch:
             self.close()
         except Exception:
             pass
+
+
+def mlp_train(feats, targets, params, steps=2000, batch=4096, lr=1e-3):
+    """Train the correction model on device tensors (feats [n, 3], targets [n],
+    float32); returns (params, per-step batch losses)."""
+    n = int(targets.numel())
+    return _lib.attn_mlp_train(feats.data_ptr(), targets.data_ptr(), n, steps, batch, lr, params)
+
+
+def mlp_eval(params, feats):
+    import torch
+    out = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+    _lib.attn_mlp_eval(params, feats.data_ptr(), out.data_ptr(), int(feats.shape[0]))
+    return out

@@ -35,6 +35,8 @@ ATTN_DRYRUN = 4
 ATTN_F64, ATTN_F32, ATTN_BF16X2 = 0, 1, 2
 ATTN_SOLVER_LANCZOS, ATTN_SOLVER_DAVIDSON = 0, 1
 ATTN_PRECOND_NONE, ATTN_PRECOND_JACOBI, ATTN_PRECOND_LEARNED = 0, 1, 2
+ATTN_MLP_PARAMS = 8641
+_f32p = ctypes.POINTER(ctypes.c_float)
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -89,6 +91,18 @@ _proto = {
                                        ctypes.POINTER(ctypes.c_int64), _f64p]),
     "attn_profile": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_int32, _f64p, _f64p,
                                       ctypes.POINTER(ctypes.c_int64)]),
+    "attn_precond_set_weights": (ctypes.c_int32, [_H, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
+    "attn_solver_stats": (ctypes.c_int32, [_H, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                           _f64p, _f64p]),
+    "attn_heff_diagonal": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "attn_precond_harvest": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, _f64p,
+                                              ctypes.c_void_p]),
+    "attn_mlp_train": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_float, ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]),
+    "attn_mlp_eval": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p]),
     "attn_batch_create": (ctypes.c_int32, [ctypes.POINTER(_H), ctypes.c_int32,
                                            ctypes.POINTER(attn_batch_opts), ctypes.POINTER(_H)]),
     "attn_batch_sweep": (ctypes.c_int32, [_H, ctypes.c_int32, _f64p, _f64p]),
@@ -272,3 +286,43 @@ def attn_batch_last_error(b):
 
 def attn_batch_destroy(b):
     _bcheck(_lib.attn_batch_destroy(b), b)
+
+
+def attn_precond_set_weights(h, params):
+    p = _arr(params, np.float32)
+    _check(_lib.attn_precond_set_weights(h, p.ctypes.data_as(_f32p), p.size), h)
+
+
+def attn_solver_stats(h):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    c, d = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.attn_solver_stats(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)), h)
+    return a.value, b.value, c.value, d.value
+
+
+def attn_heff_diagonal(h, node, diag_ptr, stream=None):
+    _check(_lib.attn_heff_diagonal(h, node, diag_ptr, stream), h)
+
+
+def attn_precond_harvest(h, node, n_pairs, cg_tol, cg_max, feats_ptr, targets_ptr, stream=None):
+    res = np.zeros(n_pairs)
+    _check(_lib.attn_precond_harvest(h, node, n_pairs, cg_tol, cg_max, feats_ptr, targets_ptr,
+                                     res.ctypes.data_as(_f64p), stream), h)
+    return res
+
+
+def attn_mlp_train(feats_ptr, targets_ptr, n, steps, batch, lr, params, stream=None):
+    p = np.array(params, dtype=np.float32, copy=True)
+    loss = np.zeros(steps, dtype=np.float32)
+    code = _lib.attn_mlp_train(feats_ptr, targets_ptr, n, steps, batch, lr, p.ctypes.data_as(_f32p),
+                               loss.ctypes.data_as(_f32p), stream)
+    if code != ATTN_OK:
+        raise AttnError(code, "attn_mlp_train failed")
+    return p, loss
+
+
+def attn_mlp_eval(params, feats_ptr, out_ptr, n, stream=None):
+    p = _arr(params, np.float32)
+    code = _lib.attn_mlp_eval(p.ctypes.data_as(_f32p), feats_ptr, out_ptr, n, stream)
+    if code != ATTN_OK:
+        raise AttnError(code, "attn_mlp_eval failed")

@@ -1116,6 +1116,630 @@ __global__ __launch_bounds__(256) void k_kritz(const KJob* __restrict__ jobs) {
   if (threadIdx.x == 0) parea(J, 0)[b] = s;
 }
 
+// ============================================================================ Davidson form
+// Davidson's method for the local eigenproblem (an eigensolver form beside the
+// Lanczos method; E. R. Davidson, J. Comput. Phys. 17 (1975)): Rayleigh-Ritz on
+// an orthonormal basis V with W = H V, residual of the lowest Ritz pair,
+// correction from the H_eff diagonal (Jacobi) or from a pointwise model of
+// the exact Jacobi-Davidson correction, two classical Gram-Schmidt passes.
+__device__ __forceinline__ double* darea(const DJob& J, int i) { return J.red + (int64_t)i * kDavMax * kRedBlocks; }
+
+__device__ __forceinline__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  return fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// diag(H_eff): every two-leg item and local operator contributes coef times
+// the product of its operators' diagonals (identity -> 1), every expanded
+// three-leg product the product of three diagonals.  A4 = partial max |diag|.
+__global__ __launch_bounds__(256) void k_heff_diag(const TinyPlan* __restrict__ plan, const DJob* __restrict__ job) {
+  __shared__ double red[4];
+  const DJob& J = *job;
+  const TinyPlan P = *plan;
+  const int d0 = P.d0, d1 = P.d1, d2 = P.d2;
+  double mx = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)gridDim.x * 256) {
+    const int l = (int)(e / ((int64_t)d1 * d2)), r = (int)((e / d2) % d1), p = (int)(e % d2);
+    double acc = 0;
+    for (int it = P.item0[0]; it < P.item0[0] + P.nitem[0]; it++)
+      acc += P.items[it].coef * blk((const double*)P.items[it].A, d1, r, r) * blk((const double*)P.items[it].B, d2, p, p);
+    for (int it = P.item0[1]; it < P.item0[1] + P.nitem[1]; it++)
+      acc += P.items[it].coef * blk((const double*)P.items[it].A, d0, l, l) * blk((const double*)P.items[it].B, d2, p, p);
+    for (int it = P.item0[2]; it < P.item0[2] + P.nitem[2]; it++)
+      acc += P.items[it].coef * blk((const double*)P.items[it].A, d0, l, l) * blk((const double*)P.items[it].B, d1, r, r);
+    for (int it = 0; it < P.n3; it++) {
+      const Item3& q = P.items3[it];
+      acc += q.coef * blk((const double*)q.op[0], d0, l, l) * blk((const double*)q.op[1], d1, r, r) *
+             blk((const double*)q.op[2], d2, p, p);
+    }
+    J.diag[e] = acc;
+    mx = fmax(mx, fabs(acc));
+  }
+  const double m = block_max(mx, red);
+  if (threadIdx.x == 0) darea(J, 4)[blockIdx.x] = m;
+}
+
+// A1[i] = partial sums of V_i . W_{k-1}, i < k
+__global__ __launch_bounds__(256) void k_dav_dots(const DJob* __restrict__ job, int k) {
+  __shared__ double red[4];
+  const DJob& J = *job;
+  const double* w = J.W + (int64_t)(k - 1) * J.n;
+  for (int i = 0; i < k; i++) {
+    const double* v = J.V + (int64_t)i * J.n;
+    double acc = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
+      acc += v[e] * w[e];
+    const double sm = block_sum(acc, red);
+    if (threadIdx.x == 0) darea(J, 1)[i * kRedBlocks + blockIdx.x] = sm;
+  }
+}
+
+// Complete column k-1 of G and diagonalise G (k x k) by the cyclic Jacobi
+// method with round-robin pairs (all disjoint rotations of a round at once:
+// rows first, then columns).  One workgroup.
+__global__ __launch_bounds__(256) void k_dav_eig(const DJob* __restrict__ job, int k) {
+  __shared__ double red[4];
+  __shared__ double A[kDavMax][kDavMax + 1];
+  __shared__ double Yl[kDavMax][kDavMax + 1];
+  __shared__ double rc[kDavMax / 2], rs[kDavMax / 2];
+  __shared__ int rp[kDavMax / 2], rq[kDavMax / 2];
+  __shared__ int order[kDavMax];
+  __shared__ double offs;
+  const DJob& J = *job;
+  DavState* ds = J.ds;
+  const int tid = threadIdx.x;
+  for (int i = 0; i < k; i++) {
+    const double g = sum_partials(darea(J, 1) + i * kRedBlocks, red);
+    if (tid == 0) {
+      ds->G[(k - 1) * kDavMax + i] = g;
+      ds->G[i * kDavMax + (k - 1)] = g;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += 256) {
+    const int i = e / k, j = e - i * k;
+    A[i][j] = 0.5 * (ds->G[j * kDavMax + i] + ds->G[i * kDavMax + j]);
+    Yl[i][j] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int kk = k + (k & 1);
+  const int np = kk / 2;
+  for (int sweep = 0; sweep < 20 && k > 1; sweep++) {
+    if (tid == 0) {
+      double off = 0, fro = 0;
+      for (int i = 0; i < k; i++)
+        for (int j = 0; j < k; j++) {
+          fro += A[i][j] * A[i][j];
+          if (j > i) off += A[i][j] * A[i][j];
+        }
+      offs = off <= 1e-32 * fro ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (offs != 0.0) break;
+    for (int round = 0; round < kk - 1; round++) {
+      if (tid < np) {
+        // round-robin schedule: player 0 fixed, the others rotate
+        auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + round) % (kk - 1); };
+        int p = player(tid), q = player(kk - 1 - tid);
+        if (p > q) { const int x = p; p = q; q = x; }
+        double c = 1.0, s = 0.0;
+        if (q < k) {
+          const double apq = A[p][q];
+          if (apq != 0.0) {
+            const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+            const double t = th == 0.0 ? 1.0 : (th > 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        } else {
+          q = p;   // dummy pair
+        }
+        rp[tid] = p; rq[tid] = q; rc[tid] = c; rs[tid] = s;
+      }
+      __syncthreads();
+      for (int w = tid; w < np * k; w += 256) {   // rows p, q
+        const int pi = w / k, j = w - pi * k;
+        const int p = rp[pi], q = rq[pi];
+        if (p == q) continue;
+        const double c = rc[pi], s = rs[pi];
+        const double ap = A[p][j], aq = A[q][j];
+        A[p][j] = c * ap - s * aq;
+        A[q][j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      for (int w = tid; w < np * k; w += 256) {   // columns p, q of A and Y
+        const int pi = w / k, i = w - pi * k;
+        const int p = rp[pi], q = rq[pi];
+        if (p == q) continue;
+        const double c = rc[pi], s = rs[pi];
+        const double ap = A[i][p], aq = A[i][q];
+        A[i][p] = c * ap - s * aq;
+        A[i][q] = s * ap + c * aq;
+        const double yp = Yl[i][p], yq = Yl[i][q];
+        Yl[i][p] = c * yp - s * yq;
+        Yl[i][q] = s * yp + c * yq;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    for (int i = 0; i < k; i++) order[i] = i;
+    for (int i = 0; i < k; i++)
+      for (int j = i + 1; j < k; j++)
+        if (A[order[j]][order[j]] < A[order[i]][order[i]]) { const int x = order[i]; order[i] = order[j]; order[j] = x; }
+    for (int i = 0; i < k; i++) ds->ev[i] = A[order[i]][order[i]];
+    ds->theta = A[order[0]][order[0]];
+    if (!isfinite(ds->theta)) ds->status = 1;
+  }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += 256) {
+    const int i = e / k, j = e - i * k;
+    ds->Y[j * kDavMax + i] = Yl[i][order[j]];
+  }
+}
+
+// u = V y_0, r = W y_0 - theta u; A0 = ||r||^2, A2 = max |r|, A3 = ||u||^2 (partials)
+__global__ __launch_bounds__(256) void k_dav_resid(const DJob* __restrict__ job, int k) {
+  __shared__ double red[4];
+  __shared__ double y[kDavMax];
+  const DJob& J = *job;
+  if (threadIdx.x < k) y[threadIdx.x] = J.ds->Y[threadIdx.x];
+  __syncthreads();
+  const double th = J.ds->theta;
+  double r2 = 0, rmax = 0, u2 = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256) {
+    double uu = 0, wy = 0;
+    for (int i = 0; i < k; i++) {
+      uu += y[i] * J.V[(int64_t)i * J.n + e];
+      wy += y[i] * J.W[(int64_t)i * J.n + e];
+    }
+    const double rr = wy - th * uu;
+    J.u[e] = uu;
+    J.r[e] = rr;
+    r2 += rr * rr;
+    u2 += uu * uu;
+    rmax = fmax(rmax, fabs(rr));
+  }
+  const double a = block_sum(r2, red);
+  if (threadIdx.x == 0) darea(J, 0)[blockIdx.x] = a;
+  const double b = block_sum(u2, red);
+  if (threadIdx.x == 0) darea(J, 3)[blockIdx.x] = b;
+  const double c = block_max(rmax, red);
+  if (threadIdx.x == 0) darea(J, 2)[blockIdx.x] = c;
+}
+
+// the norms every correction kernel starts from (same fixed-order reduction in
+// every workgroup); block 0 records them and the convergence test
+__device__ __forceinline__ bool dav_prologue(const DJob& J, double tol, double* red, double& th,
+                                             double& rinf, double& dinf) {
+  const double r2 = sum_partials(darea(J, 0), red);
+  rinf = fmax(block_max(darea(J, 2)[threadIdx.x], red), 1e-300);
+  dinf = fmax(block_max(darea(J, 4)[threadIdx.x], red), 1e-300);
+  th = J.ds->theta;
+  const double rn = sqrt(r2);
+  const bool conv = rn <= tol;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    J.ds->rnorm = rn;
+    J.ds->rinf = rinf;
+    J.ds->dinf = dinf;
+    J.ds->converged = conv ? 1 : 0;
+    J.ds->tbad = 0;
+    J.ds->status = isfinite(rn) ? 0 : 1;
+  }
+  return conv;
+}
+
+// t and the first Gram-Schmidt dots (A5[i] = V_i . t) and A7 = ||t||^2
+__device__ __forceinline__ void dav_epilogue(const DJob& J, int k, double* red) {
+  for (int i = 0; i < k; i++) {
+    const double* v = J.V + (int64_t)i * J.n;
+    double acc = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
+      acc += v[e] * J.t[e];
+    const double sm = block_sum(acc, red);
+    if (threadIdx.x == 0) darea(J, 5)[i * kRedBlocks + blockIdx.x] = sm;
+  }
+  double acc = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
+    acc += J.t[e] * J.t[e];
+  const double sm = block_sum(acc, red);
+  if (threadIdx.x == 0) darea(J, 7)[blockIdx.x] = sm;
+}
+
+// Jacobi correction t_i = -r_i / (diag_i - theta), |diag_i - theta| >= 1e-8 max(1, |theta|)
+__global__ __launch_bounds__(256) void k_dav_jacobi(const DJob* __restrict__ job, int k, double tol) {
+  __shared__ double red[4];
+  const DJob& J = *job;
+  double th, rinf, dinf;
+  if (dav_prologue(J, tol, red, th, rinf, dinf)) return;
+  const double eps = 1e-8 * fmax(1.0, fabs(th));
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256) {
+    double den = J.diag[e] - th;
+    if (fabs(den) < eps) den = den < 0 ? -eps : eps;
+    J.t[e] = -J.r[e] / den;
+  }
+  dav_epilogue(J, k, red);
+}
+
+// Pointwise model: features ((diag - theta)/s, r/||r||_inf, theta/s), s = ||diag||_inf,
+// three tanh layers of width 64 (FP16 parameters, FP32 arithmetic), linear output o,
+// t = o ||r||_inf / s.
+__device__ __forceinline__ float mlp_eval(const float* __restrict__ w, float f0, float f1, float f2) {
+  const float* W1 = w;
+  const float* b1 = W1 + 3 * kMlpHidden;
+  const float* W2 = b1 + kMlpHidden;
+  const float* b2 = W2 + kMlpHidden * kMlpHidden;
+  const float* W3 = b2 + kMlpHidden;
+  const float* b3 = W3 + kMlpHidden * kMlpHidden;
+  const float* W4 = b3 + kMlpHidden;
+  const float b4 = W4[kMlpHidden];
+  float h1[kMlpHidden], h2[kMlpHidden];
+#pragma unroll
+  for (int j = 0; j < kMlpHidden; j++)
+    h1[j] = tanhf(b1[j] + f0 * W1[j] + f1 * W1[kMlpHidden + j] + f2 * W1[2 * kMlpHidden + j]);
+#pragma unroll
+  for (int j = 0; j < kMlpHidden; j++) {
+    float a = b2[j];
+#pragma unroll
+    for (int i = 0; i < kMlpHidden; i++) a += h1[i] * W2[i * kMlpHidden + j];
+    h2[j] = tanhf(a);
+  }
+  float o = b4;
+#pragma unroll 4
+  for (int j = 0; j < kMlpHidden; j++) {
+    float a = b3[j];
+#pragma unroll
+    for (int i = 0; i < kMlpHidden; i++) a += h2[i] * W3[i * kMlpHidden + j];
+    o += W4[j] * tanhf(a);
+  }
+  return o;
+}
+
+__global__ __launch_bounds__(256) void k_dav_learned(const DJob* __restrict__ job, int k, double tol) {
+  __shared__ double red[4];
+  __shared__ float w[kMlpParams];
+  const DJob& J = *job;
+  double th, rinf, dinf;
+  if (dav_prologue(J, tol, red, th, rinf, dinf)) return;
+  const _Float16* wp = (const _Float16*)J.mlp;
+  for (int i = threadIdx.x; i < kMlpParams; i += 256) w[i] = (float)wp[i];
+  __syncthreads();
+  const float is = (float)(1.0 / dinf), ir = (float)(1.0 / rinf), f2 = (float)(th / dinf);
+  const double scale = rinf / dinf;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256) {
+    const float f0 = (float)(J.diag[e] - th) * is;
+    const float f1 = (float)J.r[e] * ir;
+    J.t[e] = (double)mlp_eval(w, f0, f1, f2) * scale;
+  }
+  dav_epilogue(J, k, red);
+}
+
+// reduce A7 -> tnorm2; flag a non-finite correction
+__global__ __launch_bounds__(256) void k_dav_check(const DJob* __restrict__ job) {
+  __shared__ double red[4];
+  const DJob& J = *job;
+  const double t2 = sum_partials(darea(J, 7), red);
+  if (threadIdx.x == 0) {
+    J.ds->tnorm2 = t2;
+    if (!J.ds->converged && !isfinite(t2)) J.ds->tbad = 1;
+  }
+}
+
+// Gram-Schmidt pass on t against V[0..k): coefficients from area pin, then new
+// dots into pin + 1 (or ||t||^2 into A7 when last)
+__global__ __launch_bounds__(256) void k_dav_ortho(const DJob* __restrict__ job, int k, int pin, int last) {
+  __shared__ double red[4];
+  __shared__ double hs[kDavMax];
+  const DJob& J = *job;
+  for (int i = 0; i < k; i++) {
+    const double hv = sum_partials(darea(J, pin) + i * kRedBlocks, red);
+    if (threadIdx.x == 0) hs[i] = hv;
+  }
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256) {
+    double x = J.t[e];
+    for (int i = 0; i < k; i++) x -= hs[i] * J.V[(int64_t)i * J.n + e];
+    J.t[e] = x;
+  }
+  if (last) {
+    double acc = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
+      acc += J.t[e] * J.t[e];
+    const double sm = block_sum(acc, red);
+    if (threadIdx.x == 0) darea(J, 7)[blockIdx.x] = sm;
+    return;
+  }
+  for (int i = 0; i < k; i++) {
+    const double* v = J.V + (int64_t)i * J.n;
+    double acc = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
+      acc += v[e] * J.t[e];
+    const double sm = block_sum(acc, red);
+    if (threadIdx.x == 0) darea(J, pin + 1)[i * kRedBlocks + blockIdx.x] = sm;
+  }
+}
+
+// V[slot] = t / ||t|| (A7); breakdown when ||t|| vanishes
+__global__ __launch_bounds__(256) void k_dav_append(const DJob* __restrict__ job, int slot) {
+  __shared__ double red[4];
+  const DJob& J = *job;
+  const double nt = sqrt(sum_partials(darea(J, 7), red));
+  const bool brk = !(nt > 1e-300) || !isfinite(nt);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && brk) J.ds->status = 2;
+  if (brk) return;
+  const double inv = 1.0 / nt;
+  double* out = J.V + (int64_t)slot * J.n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)gridDim.x * 256)
+    out[e] = J.t[e] * inv;
+}
+
+// restart: Vt[j] = V Y[:, j], Vt[nr + j] = W Y[:, j] (j < nr); G = diag(ev[0..nr))
+__global__ __launch_bounds__(256) void k_dav_restart(const DJob* __restrict__ job, int k, int nr) {
+  __shared__ double Ys[kDavMax * kDavMax];
+  const DJob& J = *job;
+  for (int e = threadIdx.x; e < kDavMax * kDavMax; e += 256) Ys[e] = J.ds->Y[e];
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)gridDim.x * 256)
+    for (int j = 0; j < nr; j++) {
+      double a = 0, b = 0;
+      for (int i = 0; i < k; i++) {
+        const double y = Ys[j * kDavMax + i];
+        a += y * J.V[(int64_t)i * J.n + e];
+        b += y * J.W[(int64_t)i * J.n + e];
+      }
+      J.Vt[(int64_t)j * J.n + e] = a;
+      J.Vt[(int64_t)(nr + j) * J.n + e] = b;
+    }
+  if (blockIdx.x == 0)
+    for (int e = threadIdx.x; e < kDavMax * kDavMax; e += 256) {
+      const int i = e % kDavMax, j = e / kDavMax;
+      J.ds->G[e] = (i == j && i < nr) ? J.ds->ev[i] : 0.0;
+    }
+}
+
+// T = u / ||u|| (A3)
+__global__ __launch_bounds__(256) void k_dav_final(const DJob* __restrict__ job) {
+  __shared__ double red[4];
+  const DJob& J = *job;
+  const double nu = sqrt(sum_partials(darea(J, 3), red));
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !(nu > 0 && isfinite(nu))) J.ds->status = 1;
+  const double inv = 1.0 / nu;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)gridDim.x * 256)
+    J.T[e] = J.u[e] * inv;
+}
+
+__global__ __launch_bounds__(256) void k_dav_init(const DJob* __restrict__ job) {
+  DavState* ds = job->ds;
+  for (int e = threadIdx.x; e < kDavMax * kDavMax; e += 256) { ds->G[e] = 0; ds->Y[e] = 0; }
+  if (threadIdx.x < kDavMax) ds->ev[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    ds->theta = 0; ds->rnorm = 0; ds->rinf = 0; ds->dinf = 0; ds->tnorm2 = 0;
+    ds->converged = 0; ds->tbad = 0; ds->status = 0;
+  }
+}
+
+// V[0] = T / ||T||
+__global__ __launch_bounds__(256) void k_dav_start(const DJob* __restrict__ job, int phase) {
+  __shared__ double red[4];
+  const DJob& J = *job;
+  if (phase == 0) {
+    double acc = 0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
+      acc += J.T[e] * J.T[e];
+    const double sm = block_sum(acc, red);
+    if (threadIdx.x == 0) darea(J, 3)[blockIdx.x] = sm;
+    return;
+  }
+  const double nr = sqrt(sum_partials(darea(J, 3), red));
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !(nr > 0 && isfinite(nr))) J.ds->status = 1;
+  const double inv = 1.0 / nr;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
+    J.V[e] = J.T[e] * inv;
+}
+
+// FP32 -> FP16 parameter copy
+__global__ __launch_bounds__(256) void k_to_half(const float* __restrict__ s, _Float16* __restrict__ d, int n) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < n) d[e] = (_Float16)s[e];
+}
+
+// ============================================================================ correction model: training
+// Mean-squared-error training of the pointwise model with hand-written kernels
+// (FP32 master parameters, Adam).  Parameter layout: W1 [3][64], b1, W2 [64][64],
+// b2, W3 [64][64], b3, W4 [64], b4 (row-major, h_next = tanh(h W + b)).
+// k_mlp_grad: one wavefront = 64 points; forward, backward by the chain rule,
+// per-workgroup gradient sums into gpart[block][kMlpParams + 1] (last = sum e^2).
+__global__ __launch_bounds__(64) void k_mlp_grad(const float* __restrict__ w, const float* __restrict__ feats,
+                                                 const float* __restrict__ targets, int64_t off, int batch,
+                                                 float* __restrict__ gpart) {
+  constexpr int H = kMlpHidden, LD = kMlpHidden + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float* h1 = reinterpret_cast<float*>(smem_raw);
+  float* h2 = h1 + 64 * LD;
+  float* h3 = h2 + 64 * LD;
+  float* d1 = h3 + 64 * LD;
+  float* d2 = d1 + 64 * LD;
+  float* d3 = d2 + 64 * LD;
+  float* fs = d3 + 64 * LD;        // [64][3]
+  float* gos = fs + 64 * 3;        // [64]
+  float* es = gos + 64;            // [64]
+  const float* W1 = w;
+  const float* b1 = W1 + 3 * H;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + H * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + H * H;
+  const float* W4 = b3 + H;
+  const float b4 = W4[H];
+  const int t = threadIdx.x;
+  const int64_t pt = off + (int64_t)blockIdx.x * 64 + t;
+  const float f0 = feats[pt * 3], f1 = feats[pt * 3 + 1], f2 = feats[pt * 3 + 2];
+  fs[t * 3] = f0; fs[t * 3 + 1] = f1; fs[t * 3 + 2] = f2;
+  float a[H];
+#pragma unroll
+  for (int j = 0; j < H; j++) {
+    a[j] = tanhf(b1[j] + f0 * W1[j] + f1 * W1[H + j] + f2 * W1[2 * H + j]);
+    h1[t * LD + j] = a[j];
+  }
+  float c[H];
+#pragma unroll
+  for (int j = 0; j < H; j++) {
+    float x = b2[j];
+#pragma unroll
+    for (int i = 0; i < H; i++) x += a[i] * W2[i * H + j];
+    c[j] = tanhf(x);
+    h2[t * LD + j] = c[j];
+  }
+  float o = b4;
+#pragma unroll
+  for (int j = 0; j < H; j++) {
+    float x = b3[j];
+#pragma unroll
+    for (int i = 0; i < H; i++) x += c[i] * W3[i * H + j];
+    const float y = tanhf(x);
+    h3[t * LD + j] = y;
+    o += W4[j] * y;
+  }
+  const float e = o - targets[pt];
+  const float go = 2.0f * e / (float)batch;
+  gos[t] = go;
+  es[t] = e * e;
+  // backward for this point
+#pragma unroll
+  for (int j = 0; j < H; j++) {
+    const float y = h3[t * LD + j];
+    d3[t * LD + j] = go * W4[j] * (1.0f - y * y);
+  }
+#pragma unroll 4
+  for (int i = 0; i < H; i++) {
+    float x = 0;
+#pragma unroll
+    for (int j = 0; j < H; j++) x += d3[t * LD + j] * W3[i * H + j];
+    const float y = h2[t * LD + i];
+    d2[t * LD + i] = x * (1.0f - y * y);
+  }
+#pragma unroll 4
+  for (int i = 0; i < H; i++) {
+    float x = 0;
+#pragma unroll
+    for (int j = 0; j < H; j++) x += d2[t * LD + j] * W2[i * H + j];
+    const float y = h1[t * LD + i];
+    d1[t * LD + i] = x * (1.0f - y * y);
+  }
+  __syncthreads();
+  // parameter gradients summed over the 64 points: thread t owns column j = t
+  float* g = gpart + (int64_t)blockIdx.x * (kMlpParams + 1);
+  const int j = t;
+  {
+    float s0 = 0, s1 = 0, s2 = 0, sb = 0;
+    for (int p = 0; p < 64; p++) {
+      const float dd = d1[p * LD + j];
+      s0 += fs[p * 3] * dd; s1 += fs[p * 3 + 1] * dd; s2 += fs[p * 3 + 2] * dd; sb += dd;
+    }
+    g[j] = s0; g[H + j] = s1; g[2 * H + j] = s2; g[3 * H + j] = sb;
+  }
+  float* gW2 = g + 4 * H;
+  float* gb2 = gW2 + H * H;
+  float* gW3 = gb2 + H;
+  float* gb3 = gW3 + H * H;
+  float* gW4 = gb3 + H;
+  for (int i = 0; i < H; i++) {
+    float x2 = 0, x3 = 0;
+    for (int p = 0; p < 64; p++) {
+      x2 += h1[p * LD + i] * d2[p * LD + j];
+      x3 += h2[p * LD + i] * d3[p * LD + j];
+    }
+    gW2[i * H + j] = x2;
+    gW3[i * H + j] = x3;
+  }
+  float sb2 = 0, sb3 = 0, s4 = 0;
+  for (int p = 0; p < 64; p++) {
+    sb2 += d2[p * LD + j];
+    sb3 += d3[p * LD + j];
+    s4 += h3[p * LD + j] * gos[p];
+  }
+  gb2[j] = sb2; gb3[j] = sb3; gW4[j] = s4;
+  if (t == 0) {
+    float sg = 0, se = 0;
+    for (int p = 0; p < 64; p++) { sg += gos[p]; se += es[p]; }
+    gW4[H] = sg;               // b4
+    g[kMlpParams] = se;        // sum of squared errors
+  }
+}
+
+// grad[i] = sum over blocks (fixed order) of gpart[b][i]
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float* __restrict__ gpart, int nblk, float* __restrict__ grad) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i > kMlpParams) return;
+  float acc = 0;
+  for (int b = 0; b < nblk; b++) acc += gpart[(int64_t)b * (kMlpParams + 1) + i];
+  grad[i] = acc;
+}
+
+// Adam step `step` (from 1); loss[step - 1] = mean squared error of the batch
+__global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ w, const float* __restrict__ grad,
+                                                  float* __restrict__ m, float* __restrict__ v, int step,
+                                                  float lr, int batch, float* __restrict__ loss) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i == 0 && loss) loss[step - 1] = grad[kMlpParams] / (float)batch;
+  if (i >= kMlpParams) return;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float g = grad[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * g;
+  const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / (1.0f - powf(b1, (float)step));
+  const float vh = vi / (1.0f - powf(b2, (float)step));
+  w[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// inference of the model on given features (FP16 parameters)
+__global__ __launch_bounds__(256) void k_mlp_eval(const _Float16* __restrict__ wp, const float* __restrict__ feats,
+                                                  float* __restrict__ out, int64_t n) {
+  __shared__ float w[kMlpParams];
+  for (int i = threadIdx.x; i < kMlpParams; i += 256) w[i] = (float)wp[i];
+  __syncthreads();
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    out[e] = mlp_eval(w, feats[e * 3], feats[e * 3 + 1], feats[e * 3 + 2]);
+}
+
+// ---- exact Jacobi-Davidson corrections (training data): small vector kernels
+__global__ __launch_bounds__(256) void k_vdot(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                                              double* __restrict__ partial) {
+  __shared__ double red[4];
+  double acc = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) acc += a[e] * b[e];
+  const double sm = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm;
+}
+
+// y = alpha x + beta y
+__global__ __launch_bounds__(256) void k_axpby(double alpha, const double* __restrict__ x, double beta,
+                                               double* __restrict__ y, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    y[e] = beta == 0.0 ? alpha * x[e] : alpha * x[e] + beta * y[e];   // y is not read when beta = 0
+}
+
+// training pair of one Davidson iteration: features of every entry and the
+// exact correction x scaled like the model output
+__global__ __launch_bounds__(256) void k_harvest_write(const double* __restrict__ diag, const double* __restrict__ r,
+                                                       const double* __restrict__ x, double theta, double s,
+                                                       double rinf, float* __restrict__ feats,
+                                                       float* __restrict__ targets, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    feats[e * 3] = (float)((diag[e] - theta) / s);
+    feats[e * 3 + 1] = (float)(r[e] / rinf);
+    feats[e * 3 + 2] = (float)(theta / s);
+    targets[e] = (float)(x[e] * s / rinf);
+  }
+}
+
 // ============================================================================ QR helpers
 // Cholesky of G + shift*I = L L^T (R = L^T upper with positive diagonal) and
 // the inverse of R, one workgroup.  L and X = L^{-1} are kept in LDS as packed
@@ -1707,12 +2331,78 @@ hipError_t prepare_kernel_attributes() {
       (const void*)k_mode<double, 7>, (const void*)k_mode<double, 8>,
       (const void*)k_mode<float, 1>, (const void*)k_mode<float, 2>, (const void*)k_mode<float, 3>,
       (const void*)k_mode<float, 4>, (const void*)k_mode<float, 5>, (const void*)k_mode<float, 6>,
-      (const void*)k_mode<float, 7>, (const void*)k_mode<float, 8>};
+      (const void*)k_mode<float, 7>, (const void*)k_mode<float, 8>, (const void*)k_mlp_grad};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// ---------------------------------------------------------------- Davidson launchers
+hipError_t launch_heff_diag(const TinyPlan* plan, const DJob* job, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_heff_diag, dim3(kRedBlocks), dim3(256), 0, s, plan, job);
+  (void)n;
+  return hipGetLastError();
+}
+hipError_t launch_dav(int op, const DJob* job, int k, int arg, double tol, hipStream_t s) {
+  switch (op) {
+    case 0: hipLaunchKernelGGL(k_dav_init, dim3(1), dim3(256), 0, s, job); break;
+    case 1: hipLaunchKernelGGL(k_dav_start, dim3(kRedBlocks), dim3(256), 0, s, job, arg); break;
+    case 2: hipLaunchKernelGGL(k_dav_dots, dim3(kRedBlocks), dim3(256), 0, s, job, k); break;
+    case 3: hipLaunchKernelGGL(k_dav_eig, dim3(1), dim3(256), 0, s, job, k); break;
+    case 4: hipLaunchKernelGGL(k_dav_resid, dim3(kRedBlocks), dim3(256), 0, s, job, k); break;
+    case 5: hipLaunchKernelGGL(k_dav_jacobi, dim3(kRedBlocks), dim3(256), 0, s, job, k, tol); break;
+    case 6: hipLaunchKernelGGL(k_dav_learned, dim3(kRedBlocks), dim3(256), 0, s, job, k, tol); break;
+    case 7: hipLaunchKernelGGL(k_dav_check, dim3(1), dim3(256), 0, s, job); break;
+    case 8: hipLaunchKernelGGL(k_dav_ortho, dim3(kRedBlocks), dim3(256), 0, s, job, k, arg, 0); break;
+    case 9: hipLaunchKernelGGL(k_dav_ortho, dim3(kRedBlocks), dim3(256), 0, s, job, k, arg, 1); break;
+    case 10: hipLaunchKernelGGL(k_dav_append, dim3(kRedBlocks), dim3(256), 0, s, job, arg); break;
+    case 11: hipLaunchKernelGGL(k_dav_restart, dim3(kRedBlocks), dim3(256), 0, s, job, k, arg); break;
+    case 12: hipLaunchKernelGGL(k_dav_final, dim3(kRedBlocks), dim3(256), 0, s, job); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_to_half(const float* src, void* dst, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_half, dim3((n + 255) / 256), dim3(256), 0, s, src, (_Float16*)dst, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- correction model launchers
+size_t mlp_grad_lds() { return (size_t)(6 * 64 * (kMlpHidden + 1) + 64 * 3 + 64 + 64) * sizeof(float); }
+
+hipError_t launch_mlp_train_step(float* w, const float* feats, const float* targets, int64_t off, int batch,
+                                 float* gpart, float* grad, float* m, float* v, int step, float lr, float* loss,
+                                 hipStream_t s) {
+  const int nblk = batch / 64;
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(64), mlp_grad_lds(), s, w, feats, targets, off, batch, gpart);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, s, gpart, nblk, grad);
+  hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, w, grad, m, v, step, lr, batch,
+                     loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_eval(const void* w16, const float* feats, float* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_eval, dim3(gridv(n)), dim3(256), 0, s, (const _Float16*)w16, feats, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_vdot(const double* a, const double* b, int64_t n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(k_vdot, dim3(kRedBlocks), dim3(256), 0, s, a, b, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double alpha, const double* x, double beta, double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(gridv(n)), dim3(256), 0, s, alpha, x, beta, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_harvest_write(const double* diag, const double* r, const double* x, double theta, double sc,
+                                double rinf, float* feats, float* targets, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_harvest_write, dim3(gridv(n)), dim3(256), 0, s, diag, r, x, theta, sc, rinf, feats,
+                     targets, n);
+  return hipGetLastError();
 }
 
 }  // namespace attn

@@ -168,4 +168,37 @@ struct TJob {
   int32_t M, pad;
 };
 
+// ---------------------------------------------------------------- Davidson form
+constexpr int kDavMax = 32;          // largest basis
+constexpr int kMlpHidden = 64;
+constexpr int kMlpParams = 3 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 + 1;   // 8641
+
+// Davidson scalar state (device).  G and Y are column-major with leading dimension kDavMax.
+struct DavState {
+  double G[kDavMax * kDavMax];   // V^T H V
+  double Y[kDavMax * kDavMax];   // its eigenvectors, columns by ascending eigenvalue
+  double ev[kDavMax];
+  double theta, rnorm, rinf, dinf, tnorm2;
+  int32_t converged;             // ||r|| <= tol
+  int32_t tbad;                  // correction not finite
+  int32_t status;                // 1 non-finite, 2 breakdown
+  int32_t pad;
+};
+
+// One Davidson eigensolve.  red holds 8 partial-sum areas of kDavMax x 256 values.
+struct DJob {
+  double* V;          // basis [kDavMax][n]
+  double* W;          // H V  [kDavMax][n]
+  double* Vt;         // restart scratch [2 * restart][n]
+  double* u;          // Ritz vector
+  double* r;          // residual
+  double* t;          // correction
+  double* diag;       // diag(H_eff)
+  double* T;          // node tensor (start vector in, Ritz vector out)
+  double* red;
+  DavState* ds;
+  const void* mlp;    // FP16 parameters of the correction model (learned mode)
+  int64_t n;
+};
+
 }  // namespace attn

@@ -51,6 +51,28 @@ hipError_t launch_reduce_list(int dtype_in, const RDTask* tasks, int ntask, int6
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t prepare_kernel_attributes();
 
+// Davidson form.  op: 0 init, 1 start (arg = phase 0/1), 2 dots of W[k-1],
+// 3 Rayleigh-Ritz (Jacobi eigensolver), 4 Ritz vector and residual, 5 Jacobi
+// correction, 6 learned correction, 7 correction check, 8/9 Gram-Schmidt pass
+// (arg = input area; 9 = last pass), 10 append (arg = slot), 11 restart
+// (arg = vectors kept), 12 final Ritz vector into T.
+hipError_t launch_heff_diag(const TinyPlan* plan, const DJob* job, int64_t n, hipStream_t s);
+hipError_t launch_dav(int op, const DJob* job, int k, int arg, double tol, hipStream_t s);
+hipError_t launch_to_half(const float* src, void* dst, int n, hipStream_t s);
+
+// Correction model: one Adam training step on batch points [off, off + batch)
+// (batch a multiple of 64; gpart: batch / 64 x (kMlpParams + 1) floats,
+// grad: kMlpParams + 1); inference on given features; small vector kernels of
+// the exact-correction solver.
+hipError_t launch_mlp_train_step(float* w, const float* feats, const float* targets, int64_t off, int batch,
+                                 float* gpart, float* grad, float* m, float* v, int step, float lr, float* loss,
+                                 hipStream_t s);
+hipError_t launch_mlp_eval(const void* w16, const float* feats, float* out, int64_t n, hipStream_t s);
+hipError_t launch_vdot(const double* a, const double* b, int64_t n, double* partial, hipStream_t s);
+hipError_t launch_axpby(double alpha, const double* x, double beta, double* y, int64_t n, hipStream_t s);
+hipError_t launch_harvest_write(const double* diag, const double* r, const double* x, double theta, double sc,
+                                double rinf, float* feats, float* targets, int64_t n, hipStream_t s);
+
 // QR helpers
 hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, int shift_mode,
                            int64_t rows, KrylovState* st, hipStream_t s);

@@ -256,8 +256,9 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
   upload_mp(h, D.chainB);
   upload_mp(h, D.chainC);
   D.d_srcs = upload(h, D.srcs);
-  // tiny nodes: H_eff assembled densely (M <= 1024)
-  if (Msz <= 1024) {
+  // explicit item lists: the dense H_eff of tiny nodes (M <= 1024) and the
+  // H_eff diagonal of every node
+  {
     TinyPlan tp;
     std::memset(&tp, 0, sizeof(tp));
     std::vector<SWItem> titems;
@@ -290,7 +291,8 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
     D.tiny_items3 = it3;
     tp.n3 = (int)it3.size();
     tp.d0 = dm[0]; tp.d1 = dm[1]; tp.d2 = dm[2];
-    D.d_tiny = upload(h, std::vector<TinyPlan>{tp});
+    D.d_plan = upload(h, std::vector<TinyPlan>{tp});
+    if (Msz <= 1024) D.d_tiny = D.d_plan;
   }
 }
 
@@ -833,6 +835,124 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
   return st.scal[0];
 }
 
+
+// ------------------------------------------------------------------ Davidson form
+void ensure_davidson(attn_handle* h) {
+  if (h->d_djobs) return;
+  const Tree& tr = h->M.tree;
+  const int nn = (int)tr.nodes.size();
+  const int64_t Mx = h->Mmax;
+  auto alloc = [&](int64_t n_doubles) { return (double*)dev_alloc(h, std::max<int64_t>(n_doubles, 1) * 8); };
+  double* W = alloc((int64_t)kDavMax * Mx);
+  double* Vt = alloc((int64_t)2 * kDavMax * Mx);
+  double* u = alloc(Mx);
+  double* r = alloc(Mx);
+  double* t = alloc(Mx);
+  double* dg = alloc(Mx);
+  double* red = alloc((int64_t)8 * kDavMax * kRedBlocks);
+  h->d_dav = (DavState*)dev_alloc(h, sizeof(DavState));
+  if (!h->d_mlp) h->d_mlp = dev_alloc(h, kMlpParams * 2);
+  h->h_djobs.resize(nn);
+  for (int n = 0; n < nn; n++)
+    h->h_djobs[n] = DJob{h->d_V, W, Vt, u, r, t, dg, h->d_T + h->T_off[n], red, h->d_dav, h->d_mlp, h->T_len[n]};
+  h->d_djobs = upload(h, h->h_djobs);
+}
+
+// Davidson eigensolve at node n (the centre).  precond: ATTN_PRECOND_JACOBI or
+// ATTN_PRECOND_LEARNED (falls back to Jacobi when the model's correction is
+// not finite, or when its residual reduction is worse than the running Jacobi
+// rate for two consecutive iterations).
+double davidson(attn_handle* h, int n, const attn_solver_opts& o, int* nmv_out, hipStream_t s) {
+  ensure_davidson(h);
+  MVDev& D = h->mv[n];
+  const int64_t Msz = h->T_len[n];
+  const int restart = std::max(1, std::min(o.restart > 0 ? o.restart : 8, kDavMax / 2));
+  const int maxsub = std::max(restart + 2, std::min(o.krylov_k, kDavMax));
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  const double tol = o.tol > 0 ? o.tol : 1e-7;
+  const DJob* J = h->d_djobs + n;
+  const DJob& Jh = h->h_djobs[n];
+  bool learned = o.precond == ATTN_PRECOND_LEARNED;
+  run_comb(D.comb, s);
+  if (o.precision != ATTN_F64) {
+    ensure_lowp(h, o.precision);
+    prepare_lowp(h, n, o.precision, s);
+  }
+  HIPCHK(launch_dav(0, J, 0, 0, tol, s));
+  HIPCHK(launch_heff_diag(D.d_plan, J, Msz, s));
+  HIPCHK(launch_dav(1, J, 0, 0, tol, s));
+  HIPCHK(launch_dav(1, J, 0, 1, tol, s));
+  int k = 1, nmv = 0, bad = 0;
+  double prev = -1.0, rate_sum = 0;
+  int rate_n = 0;
+  DavState st;
+  for (int it = 0; it < max_iter; it++) {
+    double* v = Jh.V + (int64_t)(k - 1) * Msz;
+    double* w = Jh.W + (int64_t)(k - 1) * Msz;
+    if (o.precision == ATTN_F64) {
+      matvec_f64(h, n, v, w, s);
+    } else {
+      HIPCHK(launch_cast(v, 0, h->d_x32, 1, Msz, s));
+      matvec_lowp(h, n, o.precision, h->d_x32, w, 0, s);
+    }
+    nmv++;
+    HIPCHK(launch_dav(2, J, k, 0, tol, s));
+    HIPCHK(launch_dav(3, J, k, 0, tol, s));
+    HIPCHK(launch_dav(4, J, k, 0, tol, s));
+    HIPCHK(launch_dav(learned ? 6 : 5, J, k, 0, tol, s));
+    HIPCHK(launch_dav(7, J, k, 0, tol, s));
+    HIPCHK(hipMemcpyAsync(&st, h->d_dav, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->n_dav_iter++;
+    if (st.status == 1) throw StatusFail{ATTN_ERR_NUMERIC, "non-finite value in the Davidson eigensolver"};
+    if (st.converged) break;
+    if (learned && st.tbad) {   // model output not finite: Jacobi for the rest of the solve
+      learned = false;
+      h->n_fallback++;
+      HIPCHK(launch_dav(5, J, k, 0, tol, s));
+    } else if (learned && prev > 0) {
+      bad = st.rnorm / prev > h->jacobi_rate ? bad + 1 : 0;
+      if (bad >= 2) { learned = false; h->n_fallback++; }
+    }
+    if (!learned && prev > 0) { rate_sum += st.rnorm / prev; rate_n++; }
+    prev = st.rnorm;
+    HIPCHK(launch_dav(8, J, k, 5, tol, s));
+    HIPCHK(launch_dav(9, J, k, 6, tol, s));
+    if (k == maxsub) {
+      HIPCHK(launch_dav(11, J, k, restart, tol, s));
+      HIPCHK(hipMemcpyAsync(Jh.V, Jh.Vt, (size_t)restart * Msz * 8, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(Jh.W, Jh.Vt + (int64_t)restart * Msz, (size_t)restart * Msz * 8,
+                            hipMemcpyDeviceToDevice, s));
+      k = restart;
+    }
+    HIPCHK(launch_dav(10, J, k, k, tol, s));
+    HIPCHK(hipMemcpyAsync(&st, h->d_dav, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st.status == 2 && learned) {
+      // the model's correction adds nothing to the basis: Jacobi from here on
+      // (r is unchanged; the Jacobi prologue clears the status)
+      learned = false;
+      h->n_fallback++;
+      HIPCHK(launch_dav(5, J, k, 0, tol, s));
+      HIPCHK(launch_dav(8, J, k, 5, tol, s));
+      HIPCHK(launch_dav(9, J, k, 6, tol, s));
+      HIPCHK(launch_dav(10, J, k, k, tol, s));
+      HIPCHK(hipMemcpyAsync(&st, h->d_dav, sizeof(st), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    if (st.status == 2) break;   // the correction lies in the basis: nothing left to add
+    k++;
+  }
+  if (rate_n > 0) h->jacobi_rate = 0.5 * h->jacobi_rate + 0.5 * (rate_sum / rate_n);
+  HIPCHK(launch_dav(12, J, k, 0, tol, s));
+  HIPCHK(hipMemcpyAsync(&st, h->d_dav, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (st.status == 1 || !std::isfinite(st.theta)) throw StatusFail{ATTN_ERR_NUMERIC, "non-finite value in the Davidson eigensolver"};
+  h->last_rnorm = st.rnorm;
+  h->n_matvec += nmv;
+  if (nmv_out) *nmv_out = nmv;
+  return st.theta;
+}
 }  // namespace rt
 
 // ====================================================================== C interface
@@ -1234,12 +1354,17 @@ attn_status attn_eigsolve_node(attn_handle* h, int32_t node, const attn_solver_o
     if (opts) o = *opts;
     else { std::memset(&o, 0, sizeof(o)); o.krylov_k = 20; }
     if (o.krylov_k < 1) { h->err = "krylov_k must be >= 1"; return ATTN_ERR_ARG; }
-    if (o.solver != ATTN_SOLVER_LANCZOS) { h->err = "solver not available"; return ATTN_ERR_UNSUPPORTED; }
+    if (o.solver != ATTN_SOLVER_LANCZOS && o.solver != ATTN_SOLVER_DAVIDSON) { h->err = "unknown solver"; return ATTN_ERR_ARG; }
+    if (o.solver == ATTN_SOLVER_DAVIDSON && o.precond == ATTN_PRECOND_LEARNED && !h->mlp_ready) {
+      h->err = "learned preconditioner requested before attn_precond_set_weights";
+      return ATTN_ERR_STATE;
+    }
     if (o.precision < ATTN_F64 || o.precision > ATTN_BF16X2) { h->err = "unknown precision"; return ATTN_ERR_ARG; }
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipSetDevice(h->device));
     int nmv = 0;
-    const double th = lanczos(h, node, o.krylov_k, o.precision, &nmv, s);
+    const double th = o.solver == ATTN_SOLVER_DAVIDSON ? davidson(h, node, o, &nmv, s)
+                                                       : lanczos(h, node, o.krylov_k, o.precision, &nmv, s);
     invalidate_from(h, node);
     if (theta) *theta = th;
     if (n_matvec) *n_matvec = nmv;
@@ -1279,6 +1404,237 @@ attn_status attn_init_state(attn_handle* h, const double* raw, int64_t len, void
     h->state_ready = true;
     return ATTN_OK;
   });
+}
+
+attn_status attn_precond_set_weights(attn_handle* h, const float* params, int64_t n) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (!params || n != kMlpParams) { h->err = "expected " + std::to_string(kMlpParams) + " parameters"; return ATTN_ERR_SHAPE; }
+    HIPCHK(hipSetDevice(h->device));
+    if (!h->d_mlp) h->d_mlp = dev_alloc(h, kMlpParams * 2);
+    float* tmp = nullptr;
+    HIPCHK(hipMalloc(&tmp, kMlpParams * sizeof(float)));
+    hipError_t e1 = hipMemcpy(tmp, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+    hipError_t e2 = e1 == hipSuccess ? launch_to_half(tmp, h->d_mlp, kMlpParams, nullptr) : e1;
+    hipError_t e3 = e2 == hipSuccess ? hipDeviceSynchronize() : e2;
+    (void)hipFree(tmp);
+    HIPCHK(e3);
+    h->mlp_ready = true;
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_solver_stats(const attn_handle* h, int64_t* dav_iters, int64_t* fallbacks, double* last_rnorm,
+                              double* jacobi_rate) {
+  if (!h) return ATTN_ERR_ARG;
+  if (dav_iters) *dav_iters = h->n_dav_iter;
+  if (fallbacks) *fallbacks = h->n_fallback;
+  if (last_rnorm) *last_rnorm = h->last_rnorm;
+  if (jacobi_rate) *jacobi_rate = h->jacobi_rate;
+  return ATTN_OK;
+}
+
+attn_status attn_heff_diagonal(attn_handle* h, int32_t node, double* diag, void* stream) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (node < 0 || node >= (int)h->M.tree.nodes.size() || !diag) { h->err = "bad node or NULL pointer"; return ATTN_ERR_ARG; }
+    if (node != h->center) { h->err = "node is not the isometry centre"; return ATTN_ERR_STATE; }
+    if (!incoming_valid(h, node)) { h->err = "stale effective operators at the node"; return ATTN_ERR_STATE; }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->device));
+    ensure_davidson(h);
+    run_comb(h->mv[node].comb, s);
+    HIPCHK(launch_heff_diag(h->mv[node].d_plan, h->d_djobs + node, h->T_len[node], s));
+    HIPCHK(hipMemcpyAsync(diag, h->h_djobs[node].diag, h->T_len[node] * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_precond_harvest(attn_handle* h, int32_t node, int32_t n_pairs, double cg_tol, int32_t cg_max,
+                                 float* feats, float* targets, double* cg_res, void* stream) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    const Tree& tr = h->M.tree;
+    if (node < 0 || node >= (int)tr.nodes.size() || n_pairs < 1 || !feats || !targets || cg_max < 1) {
+      h->err = "bad arguments";
+      return ATTN_ERR_ARG;
+    }
+    if (node != h->center) { h->err = "node is not the isometry centre"; return ATTN_ERR_STATE; }
+    if (!incoming_valid(h, node)) { h->err = "stale effective operators at the node"; return ATTN_ERR_STATE; }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipSetDevice(h->device));
+    ensure_davidson(h);
+    const int64_t M = h->T_len[node];
+    const DJob* J = h->d_djobs + node;
+    const DJob& Jh = h->h_djobs[node];
+    // MINRES work vectors and partial sums
+    double* vec[9];
+    for (int i = 0; i < 9; i++) vec[i] = (double*)dev_alloc(h, M * 8);
+    double* part = (double*)dev_alloc(h, kRedBlocks * 8);
+    std::vector<double> hp(kRedBlocks);
+    auto dot = [&](const double* a, const double* b) {
+      HIPCHK(launch_vdot(a, b, M, part, s));
+      HIPCHK(hipMemcpyAsync(hp.data(), part, kRedBlocks * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double acc = 0;
+      for (double v : hp) acc += v;
+      return acc;
+    };
+    MVDev& D = h->mv[node];
+    run_comb(D.comb, s);
+    // keep T_n: the Davidson iterations below only generate residuals
+    double* Tsave = (double*)dev_alloc(h, M * 8);
+    HIPCHK(hipMemcpyAsync(Tsave, Jh.T, M * 8, hipMemcpyDeviceToDevice, s));
+    const double tol = 0.0;
+    HIPCHK(launch_dav(0, J, 0, 0, tol, s));
+    HIPCHK(launch_heff_diag(D.d_plan, J, M, s));
+    HIPCHK(launch_dav(1, J, 0, 0, tol, s));
+    HIPCHK(launch_dav(1, J, 0, 1, tol, s));
+    int k = 1;
+    DavState st;
+    for (int pair = 0; pair < n_pairs; pair++) {
+      matvec_f64(h, node, Jh.V + (int64_t)(k - 1) * M, Jh.W + (int64_t)(k - 1) * M, s);
+      HIPCHK(launch_dav(2, J, k, 0, tol, s));
+      HIPCHK(launch_dav(3, J, k, 0, tol, s));
+      HIPCHK(launch_dav(4, J, k, 0, tol, s));
+      HIPCHK(launch_dav(5, J, k, 0, tol, s));   // Jacobi correction (continues the iteration)
+      HIPCHK(launch_dav(7, J, k, 0, tol, s));
+      HIPCHK(hipMemcpyAsync(&st, h->d_dav, sizeof(st), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (st.status) throw StatusFail{ATTN_ERR_NUMERIC, "non-finite value while harvesting"};
+      const double theta = st.theta;
+      // u normalised in place
+      const double un = std::sqrt(dot(Jh.u, Jh.u));
+      HIPCHK(launch_axpby(0.0, Jh.u, 1.0 / un, Jh.u, M, s));
+      // MINRES (C. C. Paige, M. A. Saunders, SIAM J. Numer. Anal. 12 (1975)) on the
+      // symmetric, in general indefinite system (1 - u u^T)(H - theta)(1 - u u^T) x = -r
+      // restricted to the complement of u (-r is orthogonal to u)
+      double *x = vec[0], *r1 = vec[1], *r2 = vec[2], *y = vec[3], *v = vec[4], *wo = vec[5], *wn = vec[6];
+      HIPCHK(launch_zero(x, M, s));
+      HIPCHK(launch_zero(wo, M, s));
+      HIPCHK(launch_zero(wn, M, s));
+      HIPCHK(launch_axpby(-1.0, Jh.r, 0.0, r1, M, s));
+      const double ur = dot(Jh.u, r1);
+      HIPCHK(launch_axpby(-ur, Jh.u, 1.0, r1, M, s));
+      HIPCHK(launch_axpby(1.0, r1, 0.0, r2, M, s));
+      HIPCHK(launch_axpby(1.0, r1, 0.0, y, M, s));
+      const double beta1 = std::sqrt(dot(r1, r1));
+      double beta = beta1, oldb = 0, dbar = 0, epsln = 0, phibar = beta1, cs = -1, sn = 0;
+      int it = 0;
+      for (; it < cg_max && phibar > cg_tol * beta1 && beta > 0; it++) {
+        HIPCHK(launch_axpby(1.0 / beta, y, 0.0, v, M, s));
+        matvec_f64(h, node, v, y, s);
+        HIPCHK(launch_axpby(-theta, v, 1.0, y, M, s));
+        const double uy = dot(Jh.u, y);
+        HIPCHK(launch_axpby(-uy, Jh.u, 1.0, y, M, s));
+        if (it > 0) HIPCHK(launch_axpby(-beta / oldb, r1, 1.0, y, M, s));
+        const double alfa = dot(v, y);
+        HIPCHK(launch_axpby(-alfa / beta, r2, 1.0, y, M, s));
+        std::swap(r1, r2);      // r1 <- r2
+        std::swap(r2, y);       // r2 <- y (y now holds the free buffer)
+        oldb = beta;
+        beta = std::sqrt(dot(r2, r2));
+        const double oldeps = epsln;
+        const double delta = cs * dbar + sn * alfa;
+        const double gbar = sn * dbar - cs * alfa;
+        epsln = sn * beta;
+        dbar = -cs * beta;
+        const double gamma = std::max(std::sqrt(gbar * gbar + beta * beta), 1e-300);
+        cs = gbar / gamma;
+        sn = beta / gamma;
+        const double phi = cs * phibar;
+        phibar = sn * phibar;
+        // w_new = (v - oldeps w_older - delta w_newer) / gamma, written over w_older
+        HIPCHK(launch_axpby(-delta / gamma, wn, -oldeps / gamma, wo, M, s));
+        HIPCHK(launch_axpby(1.0 / gamma, v, 1.0, wo, M, s));
+        std::swap(wo, wn);
+        HIPCHK(launch_axpby(phi, wn, 1.0, x, M, s));
+        HIPCHK(launch_axpby(1.0, r2, 0.0, y, M, s));   // next Lanczos vector (unnormalised)
+      }
+      // true residual of the projected system
+      matvec_f64(h, node, x, y, s);
+      HIPCHK(launch_axpby(-theta, x, 1.0, y, M, s));
+      const double ux = dot(Jh.u, y);
+      HIPCHK(launch_axpby(-ux, Jh.u, 1.0, y, M, s));
+      HIPCHK(launch_axpby(1.0, Jh.r, 1.0, y, M, s));
+      const double ru = dot(Jh.u, Jh.r);
+      HIPCHK(launch_axpby(-ru, Jh.u, 1.0, y, M, s));
+      const double rr = dot(y, y);
+      const double bn = beta1;
+      if (cg_res) cg_res[pair] = std::sqrt(rr) / bn;
+      HIPCHK(launch_harvest_write(Jh.diag, Jh.r, vec[0], theta, st.dinf, st.rinf, feats + (int64_t)pair * M * 3,
+                                  targets + (int64_t)pair * M, M, s));
+      // continue the Davidson iteration with the Jacobi correction
+      HIPCHK(launch_dav(8, J, k, 5, tol, s));
+      HIPCHK(launch_dav(9, J, k, 6, tol, s));
+      if (k == kDavMax) {
+        HIPCHK(launch_dav(11, J, k, 8, tol, s));
+        HIPCHK(hipMemcpyAsync(Jh.V, Jh.Vt, (size_t)8 * M * 8, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(Jh.W, Jh.Vt + 8 * M, (size_t)8 * M * 8, hipMemcpyDeviceToDevice, s));
+        k = 8;
+      }
+      HIPCHK(launch_dav(10, J, k, k, tol, s));
+      k++;
+    }
+    HIPCHK(hipMemcpyAsync(Jh.T, Tsave, M * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    // scratch of this call is released with the handle (dev_alloc); drop it now
+    std::vector<void*> tmp(vec, vec + 9);
+    tmp.push_back(part);
+    tmp.push_back(Tsave);
+    for (void* ptr : tmp) {
+      auto it2 = std::find(h->owned.begin(), h->owned.end(), ptr);
+      if (it2 != h->owned.end()) { h->owned.erase(it2); (void)hipFree(ptr); }
+      for (size_t a = 0; a < h->allocs.size(); a++)
+        if (h->allocs[a].first == (uintptr_t)ptr) { h->allocs.erase(h->allocs.begin() + a); break; }
+    }
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_mlp_train(const float* feats, const float* targets, int64_t n, int32_t steps, int32_t batch,
+                           float lr, float* params, float* loss, void* stream) {
+  if (!feats || !targets || !params || steps < 1 || batch < 64 || batch % 64 || n < batch) return ATTN_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *gpart = nullptr, *dl = nullptr;
+  hipError_t e = prepare_kernel_attributes();
+  auto al = [&](float** p, size_t cnt) { if (e == hipSuccess) e = hipMalloc(p, cnt * sizeof(float)); };
+  al(&w, kMlpParams);
+  al(&m, kMlpParams);
+  al(&v, kMlpParams);
+  al(&grad, kMlpParams + 1);
+  al(&gpart, (size_t)(batch / 64) * (kMlpParams + 1));
+  al(&dl, steps);
+  if (e == hipSuccess) e = hipMemcpy(w, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m, 0, kMlpParams * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(v, 0, kMlpParams * sizeof(float));
+  const int64_t nb = n / batch;
+  for (int st = 1; st <= steps && e == hipSuccess; st++) {
+    const int64_t off = ((st - 1) % nb) * batch;
+    e = launch_mlp_train_step(w, feats, targets, off, batch, gpart, grad, m, v, st, lr, dl, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(params, w, kMlpParams * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && loss) e = hipMemcpy(loss, dl, steps * sizeof(float), hipMemcpyDeviceToHost);
+  for (float* p : {w, m, v, grad, gpart, dl})
+    if (p) (void)hipFree(p);
+  return e == hipSuccess ? ATTN_OK : ATTN_ERR_HIP;
+}
+
+attn_status attn_mlp_eval(const float* params, const float* feats, float* out, int64_t n, void* stream) {
+  if (!params || !feats || !out || n < 0) return ATTN_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  float* tmp = nullptr;
+  void* w16 = nullptr;
+  hipError_t e = hipMalloc(&tmp, kMlpParams * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&w16, kMlpParams * 2);
+  if (e == hipSuccess) e = hipMemcpy(tmp, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = launch_to_half(tmp, w16, kMlpParams, s);
+  if (e == hipSuccess && n > 0) e = launch_mlp_eval(w16, feats, out, n, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (tmp) (void)hipFree(tmp);
+  if (w16) (void)hipFree(w16);
+  return e == hipSuccess ? ATTN_OK : ATTN_ERR_HIP;
 }
 
 attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* opts,
@@ -1427,8 +1783,8 @@ extern "C" attn_status attn_validate(const attn_handle* h) {
     for (auto& g : D.chainB) c.mp(g, M, 8);
     for (auto& g : D.chainC) c.mp(g, M, 8);
     for (auto& sr : D.srcs) c.span(sr.p, M * 8, "reduce source");
-    if (D.d_tiny) {
-      if (M > 1024) c.fail("tiny node too large");
+    {
+      if (D.d_tiny && M > 1024) c.fail("tiny node too large");
       for (int sp = 0; sp < 3; sp++) {
         const int64_t ma = sp == 0 ? D.dims[1] : D.dims[0], mb = sp == 2 ? D.dims[1] : D.dims[2];
         for (int i = D.tiny_item0[sp]; i < D.tiny_item0[sp] + D.tiny_nitem[sp]; i++) {
@@ -1438,7 +1794,7 @@ extern "C" attn_status attn_validate(const attn_handle* h) {
       }
       for (auto& q : D.tiny_items3)
         for (int l = 0; l < 3; l++) c.span(q.op[l], (int64_t)D.dims[l] * D.dims[l] * 8, "tiny op3");
-      c.span(h->d_tmp2, M * M * 8, "dense H_eff");
+      if (D.d_tiny) c.span(h->d_tmp2, M * M * 8, "dense H_eff");
     }
     if (D.need_xt) c.span(h->d_xt, M * 8, "transposed input");
     {

@@ -79,7 +79,8 @@ struct GRPlan {
 };
 
 struct MVDev {
-  TinyPlan* d_tiny = nullptr;   // set when the whole plan runs in one workgroup
+  TinyPlan* d_plan = nullptr;   // every item written out (dense tiny H_eff, diagonal)
+  TinyPlan* d_tiny = nullptr;   // == d_plan when the whole eigensolve runs in one workgroup
   std::vector<SWItem> tiny_items;
   int tiny_item0[3] = {0, 0, 0}, tiny_nitem[3] = {0, 0, 0};
   std::vector<Item3> tiny_items3;
@@ -192,6 +193,15 @@ struct attn_handle {
   KJob* d_kjobs32 = nullptr;
   TJob* d_tjobs = nullptr;    // per node: dense tiny-node eigensolve
   std::vector<KJob> h_kjobs;  // host copies for validation
+  // Davidson form (allocated at its first use)
+  DJob* d_djobs = nullptr;    // per node
+  std::vector<DJob> h_djobs;
+  DavState* d_dav = nullptr;
+  void* d_mlp = nullptr;      // FP16 parameters of the learned correction model
+  bool mlp_ready = false;
+  double jacobi_rate = 0.9;   // running per-iteration residual reduction of Jacobi-mode solves
+  int64_t n_dav_iter = 0, n_fallback = 0;
+  double last_rnorm = 0;
   std::vector<TJob> h_tjobs;
   // plans
   std::vector<MVDev> mv;
