@@ -142,3 +142,24 @@ def test_matvec_heaviest_node_16x16():
     move_both(a, o, n)
     x = np.random.default_rng(5).standard_normal(o.T[n].shape)
     assert rel(gpu_matvec(a, n, x), o.matvec(n, x)) < 1e-12
+
+
+def test_sweeps_16x16_track_oracle_golden():
+    # whole sweeps of the 16 x 16, m = 64 workload against the oracle's sweep
+    # energies (tests/golden, written by make_reference.py from the oracle only).
+    # Node by node the two agree to rounding (test above); over a sweep the
+    # single-site updates amplify rounding through ill-conditioned centre
+    # matricisations, so the bound is set well above the observed ~1e-6 per site
+    # and well below the ~1e-1 per site changes between sweeps
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "ising16_m64_oracle.json")
+    ref = json.load(open(path))["energies"]
+    p = config_problem("ising16_m64")
+    from paper_2507_21236_amd import AttnHandle
+    a = AttnHandle(p)
+    a.init_state()
+    e, _ = a.sweep(len(ref))
+    for s, (x, y) in enumerate(zip(e, ref)):
+        print(f"sweep {s}: GPU {x:.10f} oracle {y:.10f} |dE|/N {abs(x - y) / p.n_sites:.2e}")
+        assert abs(x - y) / p.n_sites < 1e-5, (s, x, y)
