@@ -16,7 +16,10 @@ BF16 matrix cores with FP32 accumulation; FP64 Krylov in both) are timed on the
 same sweeps after the primary run and reported as speedups over the FP64 path,
 with the energy difference per site of every sweep.  The batched form (32
 uneven seeded instances swept in lock step through mixed-shape launches and
-HIP graphs) is compared with per-instance sweeps of the same instances.
+HIP graphs) is compared with per-instance sweeps of the same instances.  The
+learned form (Davidson with a pointwise correction model trained on exact
+Jacobi-Davidson corrections of this workload) is compared with Davidson-Jacobi
+and with the plain Lanczos sweep from the state after one sweep.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
                        [--precision f64|f32|bf16x2] [--forms f32,bf16x2]
@@ -155,6 +158,77 @@ def batched_form(sweeps, warmup):
     return out
 
 
+def learned_form(a, p, tol, n_nodes=2, pairs=6, steps=1500):
+    """Davidson with Jacobi and with learned corrections vs the plain Lanczos
+    sweep, from the state after one FP64 sweep.  The model is trained first on
+    exact Jacobi-Davidson corrections harvested at full nodes of the same
+    workload (hand-written kernels, not timed as part of the sweeps)."""
+    import numpy as np
+    import torch
+    from paper_2507_21236_amd import (solver_opts, mlp_train, ATTN_F64, ATTN_SOLVER_DAVIDSON,
+                                      ATTN_PRECOND_JACOBI, ATTN_PRECOND_LEARNED, ATTN_MLP_PARAMS)
+    N = p.n_sites
+    plain = solver_opts(krylov_k=20, precision=ATTN_F64)
+
+    def start():
+        a.init_state()
+        a.sweep(1, plain)
+
+    start()
+    full = [n for n in range(a.n_nodes) if a.node_info(n)[0] == (64, 64, 64)]
+    t0 = time.time()
+    feats, targs, res_all = [], [], []
+    for n in full[:n_nodes]:
+        a.move_center(n)
+        f, t, res = a.harvest(n, pairs, cg_tol=1e-8, cg_max=300)
+        feats.append(f)
+        targs.append(t)
+        res_all += [float(x) for x in res]
+    f = torch.cat(feats)
+    t = torch.cat(targs)
+    perm = torch.randperm(f.shape[0], generator=torch.Generator().manual_seed(0)).cuda()
+    f, t = f[perm].contiguous(), t[perm].contiguous()
+    t_harvest = time.time() - t0
+    w0 = (np.random.default_rng(11).standard_normal(ATTN_MLP_PARAMS) * 0.1).astype(np.float32)
+    t0 = time.time()
+    w, loss = mlp_train(f, t, w0, steps=steps, batch=8192, lr=2e-3)
+    t_train = time.time() - t0
+    print(f"[bench] learned form: harvested {f.shape[0]} points in {t_harvest:.1f} s "
+          f"(MINRES residuals {min(res_all):.1e}..{max(res_all):.1e}), trained {steps} steps in "
+          f"{t_train:.1f} s, loss {loss[0]:.3e} -> {loss[-1]:.3e}", file=sys.stderr, flush=True)
+    a.set_precond_weights(w)
+    out = {"sweep_tol_residual": tol, "harvest_points": int(f.shape[0]), "harvest_s": round(t_harvest, 2),
+           "train_steps": steps, "train_s": round(t_train, 2),
+           "train_loss_first_last": [float(loss[0]), float(loss[-1])]}
+    runs = {"lanczos_k20": plain,
+            "davidson_jacobi": solver_opts(solver=ATTN_SOLVER_DAVIDSON, krylov_k=32, tol=tol,
+                                           precond=ATTN_PRECOND_JACOBI, max_iter=400, restart=8),
+            "davidson_learned": solver_opts(solver=ATTN_SOLVER_DAVIDSON, krylov_k=32, tol=tol,
+                                            precond=ATTN_PRECOND_LEARNED, max_iter=400, restart=8)}
+    for name, o in runs.items():
+        start()
+        it0, fb0, _, _ = a.solver_stats()
+        nmv0 = a.counters()[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e, s = a.sweep(1, o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        it1, fb1, _, _ = a.solver_stats()
+        out[name] = {"sweep_s": round(dt, 4), "matvecs": int(a.counters()[0] - nmv0),
+                     "energy": float(e[0]), "E_per_site": float(e[0]) / N,
+                     "fallbacks_to_jacobi": int(fb1 - fb0)}
+        print(f"[bench] {name}: {dt:.3f} s, E={e[0]:.10f}, matvecs {out[name]['matvecs']}, "
+              f"fallbacks {fb1 - fb0}", file=sys.stderr, flush=True)
+    base = out["lanczos_k20"]["sweep_s"]
+    for name in ("davidson_jacobi", "davidson_learned"):
+        out[name]["speedup_vs_lanczos_k20"] = round(base / out[name]["sweep_s"], 3)
+        out[name]["dE_per_site_vs_lanczos_k20"] = (out[name]["energy"] - out["lanczos_k20"]["energy"]) / N
+    out["speedup_learned_vs_jacobi"] = round(out["davidson_jacobi"]["sweep_s"] /
+                                             out["davidson_learned"]["sweep_s"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +239,8 @@ def main():
                     help="low-precision forms timed after the primary run ('' for none)")
     ap.add_argument("--config", default="ising16_m64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned-tol", type=float, default=1e-5,
+                    help="Davidson residual tolerance of the learned-form comparison (0 to skip)")
     ap.add_argument("--batch-sweeps", type=int, default=2,
                     help="timed sweeps of the batched-form comparison (0 to skip)")
     args = ap.parse_args()
@@ -280,6 +356,9 @@ def main():
                 "max_abs_dE_per_site_vs_" + args.precision: max(
                     abs(x - y) for x, y in zip(e_f, energies)) / N,
             }
+    if args.learned_tol > 0:
+        out["forms"] = out.get("forms", {})
+        out["forms"]["learned"] = learned_form(a, p, args.learned_tol)
     if args.batch_sweeps > 0:
         out["forms"] = out.get("forms", {})
         out["forms"]["batched"] = batched_form(args.batch_sweeps, 1)

@@ -230,6 +230,10 @@ attn_status attn_eigsolve_node(attn_handle* h, int32_t node, const attn_solver_o
  */
 attn_status attn_isometrize(attn_handle* h, int32_t from, int32_t to, void* stream);
 
+/* Move the isometry centre to `target` link by link (attn_isometrize then
+ * attn_update_env for every link of the tree path).  Errors: as those calls. */
+attn_status attn_move_center(attn_handle* h, int32_t target, void* stream);
+
 /*
  * a6. Sweep (Sec. 4, step 3): n_sweeps sweeps over all nodes in post-order;
  * the centre moves link by link (attn_isometrize then attn_update_env) and

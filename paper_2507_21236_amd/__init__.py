@@ -56,6 +56,9 @@ class AttnHandle:
     def center(self):
         return _lib.attn_get_center(self.h)
 
+    def move_center(self, target, stream=None):
+        _lib.attn_move_center(self.h, target, stream)
+
     def isometrize(self, frm, to, stream=None):
         _lib.attn_isometrize(self.h, frm, to, stream)
 

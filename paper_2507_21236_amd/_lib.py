@@ -83,6 +83,7 @@ _proto = {
     "attn_eigsolve_node": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.POINTER(attn_solver_opts),
                                             _f64p, _i32p, ctypes.c_void_p]),
     "attn_isometrize": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "attn_move_center": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_void_p]),
     "attn_sweep": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.POINTER(attn_sweep_opts), _f64p,
                                     _f64p]),
     "attn_validate": (ctypes.c_int32, [_H]),
@@ -326,3 +327,7 @@ def attn_mlp_eval(params, feats_ptr, out_ptr, n, stream=None):
     code = _lib.attn_mlp_eval(p.ctypes.data_as(_f32p), feats_ptr, out_ptr, n, stream)
     if code != ATTN_OK:
         raise AttnError(code, "attn_mlp_eval failed")
+
+
+def attn_move_center(h, target, stream=None):
+    _check(_lib.attn_move_center(h, target, stream), h)

@@ -1637,6 +1637,30 @@ attn_status attn_mlp_eval(const float* params, const float* feats, float* out, i
   return e == hipSuccess ? ATTN_OK : ATTN_ERR_HIP;
 }
 
+attn_status attn_move_center(attn_handle* h, int32_t target, void* stream) {
+  if (!h) return ATTN_ERR_ARG;
+  const Tree& tr = h->M.tree;
+  if (target < 0 || target >= (int)tr.nodes.size()) { h->err = "bad node"; return ATTN_ERR_ARG; }
+  if (h->center < 0) { h->err = "no isometry centre (state not initialised)"; return ATTN_ERR_STATE; }
+  int a = h->center, b = target;
+  auto depth = [&](int x) { int dd = 0; while (tr.nodes[x].parent >= 0) { x = tr.nodes[x].parent; dd++; } return dd; };
+  int da = depth(a), db = depth(b);
+  std::vector<int> pa{a}, pb{b};
+  while (da > db) { a = tr.nodes[a].parent; pa.push_back(a); da--; }
+  while (db > da) { b = tr.nodes[b].parent; pb.push_back(b); db--; }
+  while (a != b) { a = tr.nodes[a].parent; pa.push_back(a); b = tr.nodes[b].parent; pb.push_back(b); }
+  pb.pop_back();
+  std::vector<int> path = pa;
+  for (int i = (int)pb.size() - 1; i >= 0; i--) path.push_back(pb[i]);
+  for (size_t i = 0; i + 1 < path.size(); i++) {
+    attn_status st = attn_isometrize(h, path[i], path[i + 1], stream);
+    if (st) return st;
+    st = attn_update_env(h, path[i], leg_toward(tr, path[i], path[i + 1]), stream);
+    if (st) return st;
+  }
+  return ATTN_OK;
+}
+
 attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* opts,
                        double* energies, double* seconds) {
   if (!h) return ATTN_ERR_ARG;
@@ -1649,25 +1673,9 @@ attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* 
     auto t0 = std::chrono::steady_clock::now();
     double th = 0;
     for (int n = 0; n < (int)tr.nodes.size(); n++) {
-      // centre path: up to the lowest common ancestor, then down
-      std::vector<int> up, down;
-      int a = h->center, b = n;
-      auto depth = [&](int x) { int dd = 0; while (tr.nodes[x].parent >= 0) { x = tr.nodes[x].parent; dd++; } return dd; };
-      int da = depth(a), db = depth(b);
-      std::vector<int> pa{a}, pb{b};
-      while (da > db) { a = tr.nodes[a].parent; pa.push_back(a); da--; }
-      while (db > da) { b = tr.nodes[b].parent; pb.push_back(b); db--; }
-      while (a != b) { a = tr.nodes[a].parent; pa.push_back(a); b = tr.nodes[b].parent; pb.push_back(b); }
-      pb.pop_back();
-      std::vector<int> path = pa;
-      for (int i = (int)pb.size() - 1; i >= 0; i--) path.push_back(pb[i]);
-      for (size_t i = 0; i + 1 < path.size(); i++) {
-        attn_status st = attn_isometrize(h, path[i], path[i + 1], nullptr);
-        if (st) return st;
-        st = attn_update_env(h, path[i], leg_toward(tr, path[i], path[i + 1]), nullptr);
-        if (st) return st;
-      }
-      attn_status st = attn_eigsolve_node(h, n, &so, &th, nullptr, nullptr);
+      attn_status st = attn_move_center(h, n, nullptr);
+      if (st) return st;
+      st = attn_eigsolve_node(h, n, &so, &th, nullptr, nullptr);
       if (st) return st;
     }
     if (hipDeviceSynchronize() != hipSuccess) { h->err = "device synchronisation failed"; return ATTN_ERR_HIP; }
