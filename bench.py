@@ -239,6 +239,8 @@ def main():
                     help="low-precision forms timed after the primary run ('' for none)")
     ap.add_argument("--config", default="ising16_m64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run five plain 1 GiB device-to-device copies (HBM counter calibration)")
     ap.add_argument("--learned-tol", type=float, default=1e-5,
                     help="Davidson residual tolerance of the learned-form comparison (0 to skip)")
     ap.add_argument("--batch-sweeps", type=int, default=2,
@@ -250,6 +252,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("copied 5 x 1 GiB", flush=True)
+        return
     from problems import config_problem
     from paper_2507_21236_amd import AttnHandle, solver_opts, ATTN_F64, ATTN_F32, ATTN_BF16X2
 

@@ -60,32 +60,23 @@ __device__ __forceinline__ int bf_pinv(int a) {
 // Stage 2 consumes the stage-1 accumulators directly as the B operand by
 // walking K = p in the order {16 tp + drow(j, i) : j = 0..3} for fixed (tp, i),
 // which is exactly how the accumulator layout spreads p over lane groups.
+// The rows of Y_s owned by this wave for items [i0, i1), written to y.
 template <typename T, int NB>
-__device__ __forceinline__ void sandwich_mfma(const SWTask& t, const SWItem* __restrict__ items,
-                                              const int4 wu, const T* __restrict__ xbase,
-                                              unsigned char* smem_raw) {
+__device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __restrict__ items, int i0, int i1,
+                                              void* y, int accumulate, int s, int strip0, const T* lds) {
   typedef typename V4<T>::type v4;
-  T* lds = reinterpret_cast<T*>(smem_raw);
-  const int s = wu.y;
   const int ma = t.ma;
   constexpr int mb = 16 * NB;
   constexpr int ld = mb + 2;
-  const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)s * t.xs_slice;
-  for (int e = threadIdx.x; e < ma * mb; e += 256) {
-    const int a = e / mb, b = e - a * mb;
-    lds[a * ld + b] = X[(int64_t)a * t.xs_row + b];
-  }
-  __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int strip = wu.z + wave;
+  const int strip = strip0 + wave;
   if (strip * 16 >= ma) return;
   const int l16 = lane & 15, l4 = lane >> 4;
   const int arow = strip * 16 + l16;
   v4 acc[NB];
 #pragma unroll
   for (int q = 0; q < NB; q++) acc[q] = v4{0, 0, 0, 0};
-  const int iend = t.item0 + t.nitem;
-  for (int it = t.item0; it < iend; it++) {
+  for (int it = i0; it < i1; it++) {
     const T* A = (const T*)items[it].A;
     const T* B = (const T*)items[it].B;
     const T coef = (T)items[it].coef;
@@ -121,25 +112,51 @@ __device__ __forceinline__ void sandwich_mfma(const SWTask& t, const SWItem* __r
       for (int q = 0; q < NB; q++) acc[q] += t1[q];
     }
   }
-  T* Y = (T*)t.y + (int64_t)s * t.ys_slice + (int64_t)arow * t.ys_row;
+  T* Y = (T*)y + (int64_t)s * t.ys_slice + (int64_t)arow * t.ys_row;
 #pragma unroll
   for (int q = 0; q < NB; q++)
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       const int c = 16 * q + drow<T>(l4, i);
-      if (t.accumulate) Y[c] += acc[q][i];
+      if (accumulate) Y[c] += acc[q][i];
       else Y[c] = acc[q][i];
     }
+}
+
+
+template <typename T, int NB>
+__device__ __forceinline__ void sandwich_mfma(const SWTask& t, const SWItem* __restrict__ items,
+                                              const int4 wu, const T* __restrict__ xbase,
+                                              unsigned char* smem_raw, const SWOut* __restrict__ outs = nullptr) {
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int s = wu.y;
+  const int ma = t.ma;
+  constexpr int mb = 16 * NB;
+  constexpr int ld = mb + 2;
+  const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)s * t.xs_slice;
+  for (int e = threadIdx.x; e < ma * mb; e += 256) {
+    const int a = e / mb, b = e - a * mb;
+    lds[a * ld + b] = X[(int64_t)a * t.xs_row + b];
+  }
+  __syncthreads();
+  if (outs && t.pad) {   // several outputs: items of output o go to outs[o].y
+    for (int o = t.item0; o < t.item0 + t.nitem; o++)
+      sandwich_rows<T, NB>(t, items, outs[o].item0, outs[o].item0 + outs[o].nitem, outs[o].y, t.accumulate, s,
+                           wu.z, lds);
+  } else {
+    sandwich_rows<T, NB>(t, items, t.item0, t.item0 + t.nitem, t.y, t.accumulate, s, wu.z, lds);
+  }
 }
 
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_sandwich(const SWTask* __restrict__ tasks,
                                                   const SWItem* __restrict__ items,
                                                   const int4* __restrict__ wus,
-                                                  const T* __restrict__ xbase) {
+                                                  const T* __restrict__ xbase,
+                                                  const SWOut* __restrict__ outs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int4 wu = wus[blockIdx.x];
-  sandwich_mfma<T, NB>(tasks[wu.x], items, wu, xbase, smem_raw);
+  sandwich_mfma<T, NB>(tasks[wu.x], items, wu, xbase, smem_raw, outs);
 }
 
 // Generic sandwich for dimensions that are not multiples of 16: one thread per
@@ -1980,10 +1997,10 @@ static inline unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 template <typename T, int NB>
 static hipError_t sand_launch(const SWTask* tasks, const SWItem* items, const int4* wus, int nwu,
-                              int ma, const void* xbase, hipStream_t s) {
+                              int ma, const void* xbase, hipStream_t s, const SWOut* outs) {
   const size_t lds = (size_t)ma * (16 * NB + 2) * sizeof(T);
   hipLaunchKernelGGL((k_sandwich<T, NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus,
-                     (const T*)xbase);
+                     (const T*)xbase, outs);
   return hipGetLastError();
 }
 
@@ -1997,7 +2014,7 @@ static hipError_t sand_bf2_launch(const SWTask* tasks, const SWItem* items, cons
 }
 
 hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const SWItem* items,
-                           const int4* wus, int nwu, const void* xbase, hipStream_t s) {
+                           const int4* wus, int nwu, const void* xbase, hipStream_t s, const SWOut* outs) {
   if (nwu == 0) return hipSuccess;
   if (dtype == 2) {
     if (!(ma % 32 == 0 && mb % 32 == 0 && ma <= 128 && mb <= 128)) return hipErrorInvalidValue;
@@ -2017,14 +2034,14 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
       return hipGetLastError();
     }
     switch (mb / 16) {
-      case 1: return sand_launch<double, 1>(tasks, items, wus, nwu, ma, xbase, s);
-      case 2: return sand_launch<double, 2>(tasks, items, wus, nwu, ma, xbase, s);
-      case 3: return sand_launch<double, 3>(tasks, items, wus, nwu, ma, xbase, s);
-      case 4: return sand_launch<double, 4>(tasks, items, wus, nwu, ma, xbase, s);
-      case 5: return sand_launch<double, 5>(tasks, items, wus, nwu, ma, xbase, s);
-      case 6: return sand_launch<double, 6>(tasks, items, wus, nwu, ma, xbase, s);
-      case 7: return sand_launch<double, 7>(tasks, items, wus, nwu, ma, xbase, s);
-      case 8: return sand_launch<double, 8>(tasks, items, wus, nwu, ma, xbase, s);
+      case 1: return sand_launch<double, 1>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 2: return sand_launch<double, 2>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 3: return sand_launch<double, 3>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 4: return sand_launch<double, 4>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 5: return sand_launch<double, 5>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 6: return sand_launch<double, 6>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 7: return sand_launch<double, 7>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 8: return sand_launch<double, 8>(tasks, items, wus, nwu, ma, xbase, s, outs);
     }
   } else {
     if (!mf) {
@@ -2033,14 +2050,14 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
       return hipGetLastError();
     }
     switch (mb / 16) {
-      case 1: return sand_launch<float, 1>(tasks, items, wus, nwu, ma, xbase, s);
-      case 2: return sand_launch<float, 2>(tasks, items, wus, nwu, ma, xbase, s);
-      case 3: return sand_launch<float, 3>(tasks, items, wus, nwu, ma, xbase, s);
-      case 4: return sand_launch<float, 4>(tasks, items, wus, nwu, ma, xbase, s);
-      case 5: return sand_launch<float, 5>(tasks, items, wus, nwu, ma, xbase, s);
-      case 6: return sand_launch<float, 6>(tasks, items, wus, nwu, ma, xbase, s);
-      case 7: return sand_launch<float, 7>(tasks, items, wus, nwu, ma, xbase, s);
-      case 8: return sand_launch<float, 8>(tasks, items, wus, nwu, ma, xbase, s);
+      case 1: return sand_launch<float, 1>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 2: return sand_launch<float, 2>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 3: return sand_launch<float, 3>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 4: return sand_launch<float, 4>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 5: return sand_launch<float, 5>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 6: return sand_launch<float, 6>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 7: return sand_launch<float, 7>(tasks, items, wus, nwu, ma, xbase, s, outs);
+      case 8: return sand_launch<float, 8>(tasks, items, wus, nwu, ma, xbase, s, outs);
     }
   }
   return hipErrorInvalidValue;

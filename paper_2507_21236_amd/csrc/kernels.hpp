@@ -26,9 +26,15 @@ struct SWTask {
   int64_t xs_slice, xs_row;
   int64_t ys_slice, ys_row;
   int32_t ma, mb;
-  int32_t item0, nitem;
+  int32_t item0, nitem;   // items, or (pad = 1) outputs
   int32_t accumulate;
-  int32_t pad;
+  int32_t pad;            // 1: several outputs per task (SWOut list)
+};
+
+// One output of a several-output task: items [item0, item0 + nitem) -> y (same geometry).
+struct SWOut {
+  void* y;
+  int32_t item0, nitem;
 };
 
 // ---------------------------------------------------------------- mode product

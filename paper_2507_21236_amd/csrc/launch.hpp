@@ -10,8 +10,11 @@ namespace attn {
 // Reduction scratch: per vector, per block partial sums.
 constexpr int kRedBlocks = 256;
 
+// outs (MFMA shapes only): tasks with pad = 1 write several outputs, items of
+// output o = outs[task.item0 + k] going to its own y
 hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const SWItem* items,
-                           const int4* wus, int nwu, const void* xbase, hipStream_t s);
+                           const int4* wus, int nwu, const void* xbase, hipStream_t s,
+                           const SWOut* outs = nullptr);
 hipError_t launch_mode(int dtype, int mj, bool mfma, const MPTask* tasks, const MPJob* jobs,
                        const int2* wus, int nwu, const void* xbase, hipStream_t s);
 hipError_t launch_gram(int mj, bool mfma, const GRTask* tasks, int ntask, hipStream_t s);

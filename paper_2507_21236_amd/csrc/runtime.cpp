@@ -87,7 +87,12 @@ void add_sw_task(SWGroup& g, SWTask t, int ns) {
   const int ti = (int)g.tasks.size();
   g.tasks.push_back(t);
   const double M = (double)ns * t.ma * t.mb;
-  for (int i = t.item0; i < t.item0 + t.nitem; i++)
+  int i0 = t.item0, i1 = t.item0 + t.nitem;
+  if (t.pad) {   // several outputs: their items are consecutive
+    i0 = g.outs[t.item0].item0;
+    i1 = g.outs[t.item0 + t.nitem - 1].item0 + g.outs[t.item0 + t.nitem - 1].nitem;
+  }
+  for (int i = i0; i < i1; i++)
     g.flops += 2.0 * M * ((g.items[i].A ? t.ma : 0) + (g.items[i].B ? t.mb : 0));
   if (sw_mfma(t.ma, t.mb)) {
     for (int s = 0; s < ns; s++)
@@ -128,9 +133,51 @@ void add_mp_task(MPGroup& g, MPTask t) {
   }
 }
 
-void upload_sw(attn_handle* h, std::vector<SWGroup>& gs) {
+// Workgroups are handed to the eight XCDs (each with its own L2) round robin by
+// workgroup index.  Order the work units so that all units of one task (one
+// group of operator blocks) land on the same XCD: tasks are assigned to XCDs
+// greedily by unit count, and position i of the launch takes the next unit of
+// XCD i mod 8 (or of any XCD with units left once that one is drained).
+template <typename U>
+void xcd_order(std::vector<U>& wus) {
+  constexpr int kXcd = 8;
+  if (wus.size() < 2 * kXcd) return;
+  int ntask = 0;
+  for (const U& u : wus) ntask = std::max(ntask, u.x + 1);
+  std::vector<int64_t> cnt(ntask, 0);
+  for (const U& u : wus) cnt[u.x]++;
+  std::vector<int> order(ntask);
+  for (int t = 0; t < ntask; t++) order[t] = t;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
+  std::vector<int> xcd_of(ntask, 0);
+  int64_t load[kXcd] = {0};
+  for (int t : order) {
+    int best = 0;
+    for (int x = 1; x < kXcd; x++)
+      if (load[x] < load[best]) best = x;
+    xcd_of[t] = best;
+    load[best] += cnt[t];
+  }
+  std::vector<std::vector<U>> q(kXcd);
+  for (const U& u : wus) q[xcd_of[u.x]].push_back(u);
+  size_t pos[kXcd] = {0};
+  std::vector<U> out;
+  out.reserve(wus.size());
+  for (size_t i = 0; i < wus.size(); i++) {
+    int x = (int)(i % kXcd);
+    if (pos[x] == q[x].size())
+      for (int y = 0; y < kXcd; y++)
+        if (pos[y] < q[y].size()) { x = y; break; }
+    out.push_back(q[x][pos[x]++]);
+  }
+  wus.swap(out);
+}
+
+void upload_sw(attn_handle* h, std::vector<SWGroup>& gs, bool by_xcd = false) {
   for (auto& g : gs) {
+    if (by_xcd) xcd_order(g.wus);
     g.d_tasks = upload(h, g.tasks);
+    g.d_outs = upload(h, g.outs);
     g.d_items = upload(h, g.items);
     g.d_wus = upload(h, g.wus);
   }
@@ -251,7 +298,7 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
   if (part_used > h->part_cap || chain_used > h->chain_cap)
     throw StatusFail{ATTN_ERR_STATE, "internal: scratch sizing"};
   upload_comb(h, D.comb);
-  upload_sw(h, D.sw);
+  upload_sw(h, D.sw, true);
   upload_mp(h, D.chainA);
   upload_mp(h, D.chainB);
   upload_mp(h, D.chainC);
@@ -301,6 +348,50 @@ int64_t env_chunk_outputs(attn_handle* h, int64_t Msz) {
   return std::max<int64_t>(1, std::min<int64_t>(4096, budget / (Msz * 8)));
 }
 
+// Geometry of an effective-operator update: tensor dims as contracted (leg 2
+// is transposed to the front), contracted leg j, sandwich shape and slices.
+struct EnvGeom {
+  bool tr_in;
+  int dm[3], j, mj, ma, mb, ns;
+  int64_t Msz, sl, row;
+};
+
+EnvGeom env_geom(const Model& M, const EnvPlan& P) {
+  const Node& nd = M.tree.nodes[P.node];
+  int spect = P.leg;
+  for (const EnvOut& o : P.outs)
+    if (!o.items.empty()) { spect = o.items[0].spect; break; }
+  EnvGeom g;
+  g.tr_in = P.leg == 2;
+  g.dm[0] = g.tr_in ? nd.dims[2] : nd.dims[0];
+  g.dm[1] = g.tr_in ? nd.dims[0] : nd.dims[1];
+  g.dm[2] = g.tr_in ? nd.dims[1] : nd.dims[2];
+  g.Msz = (int64_t)g.dm[0] * g.dm[1] * g.dm[2];
+  g.j = g.tr_in ? 0 : P.leg;
+  g.mj = g.dm[g.j];
+  slice_geom(g.tr_in ? 0 : spect, g.dm, g.ma, g.mb, g.ns, g.sl, g.row);
+  return g;
+}
+
+// Pieces per output: on the matrix cores an output whose item count exceeds
+// the balanced share of one task is split into pieces (separate partial Z
+// tensors, summed by the gram reduction) so that no task dominates the launch.
+std::vector<int> env_pieces(const Model& M, const EnvPlan& P, int& cap_out) {
+  const EnvGeom g = env_geom(M, P);
+  std::vector<int> pc(P.outs.size(), 0);
+  int64_t W = 0;
+  for (size_t o = 0; o < P.outs.size(); o++) W += (int64_t)P.outs[o].items.size();
+  const int64_t strips = std::max(1, (g.ma / 16 + 3) / 4);
+  const int64_t ntask = std::max<int64_t>(1, (2048 + g.ns * strips - 1) / (g.ns * strips));
+  const int cap = sw_mfma(g.ma, g.mb) ? (int)std::max<int64_t>(4, (W + ntask - 1) / ntask) : 1 << 30;
+  for (size_t o = 0; o < P.outs.size(); o++) {
+    const int w = (int)P.outs[o].items.size();
+    pc[o] = w == 0 ? 0 : (w + cap - 1) / cap;
+  }
+  cap_out = cap;
+  return pc;
+}
+
 void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
   if (P.node < 0) return;
   const Model& M = h->M;
@@ -308,16 +399,12 @@ void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
   // toward the parent the tensor is first transposed to [p][l][r] so that the
   // (l, r) slices are contiguous; the contracted leg is then the first one.
   // At the root (m_p = 1) the items may use p as spectator: no transpose needed.
-  int spect = P.leg;
-  for (const EnvOut& o : P.outs)
-    if (!o.items.empty()) { spect = o.items[0].spect; break; }
-  const bool tr_in = P.leg == 2;
-  const int dm[3] = {tr_in ? nd.dims[2] : nd.dims[0], tr_in ? nd.dims[0] : nd.dims[1],
-                     tr_in ? nd.dims[1] : nd.dims[2]};
-  const int64_t Msz = (int64_t)dm[0] * dm[1] * dm[2];
-  const int j = tr_in ? 0 : P.leg;
-  const int sw_spect = tr_in ? 0 : spect;
-  const int mj = dm[j];
+  const EnvGeom geo = env_geom(M, P);
+  const bool tr_in = geo.tr_in;
+  const int* dm = geo.dm;
+  const int64_t Msz = geo.Msz;
+  const int j = geo.j, mj = geo.mj, ma = geo.ma, mb = geo.mb, ns = geo.ns;
+  const int64_t sl = geo.sl, row = geo.row;
   D.transpose = tr_in;
   std::copy(nd.dims, nd.dims + 3, D.dims);
   D.present = true;
@@ -328,7 +415,7 @@ void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
   upload_comb(h, D.comb);
   double* T = tr_in ? h->d_xt : h->d_T + h->T_off[P.node];
   double* base = h->store[P.out_dir][P.out_edge];
-  const int64_t per = env_chunk_outputs(h, Msz);
+  const int64_t per = env_chunk_outputs(h, Msz);   // Z tensors per chunk
   const int64_t F = Msz / mj;
   const bool gmf = gram_mfma_ok(mj, Msz);
   int64_t fchunk = F;
@@ -338,14 +425,24 @@ void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
     while (F % fchunk) fchunk += 64;
   }
   const int nfc = (int)(F / fchunk);
-  int ma, mb, ns;
-  int64_t sl, row;
-  slice_geom(sw_spect, dm, ma, mb, ns, sl, row);
-  for (size_t o0 = 0; o0 < P.outs.size(); o0 += per) {
-    const size_t o1 = std::min(P.outs.size(), o0 + (size_t)per);
+  int cap = 0;
+  const std::vector<int> pieces = env_pieces(M, P, cap);
+  const bool multi = sw_mfma(ma, mb);
+  const int64_t strips = std::max(1, (ma / 16 + 3) / 4);
+  size_t o0 = 0;
+  while (o0 < P.outs.size()) {
+    // chunk: consecutive outputs whose pieces fit the Z budget
+    size_t o1 = o0;
+    int64_t nz = 0;
+    while (o1 < P.outs.size() && (nz + pieces[o1] <= per || o1 == o0)) { nz += pieces[o1]; o1++; }
     EnvChunk ch;
     ch.gr.mj = mj;
     ch.gr.mfma = gmf;
+    // virtual outputs: (output, first item, item count, Z slot); partial grams
+    // of all pieces of an output are consecutive and reduced together
+    struct VOut { size_t o; int i0, ni; int64_t z; };
+    std::vector<VOut> vouts;
+    int64_t zslot = 0, pslot = 0;
     for (size_t o = o0; o < o1; o++) {
       const EnvOut& out = P.outs[o];
       double* blk = base + (int64_t)(out.slot + 1) * mj * mj;
@@ -353,39 +450,91 @@ void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
         ch.zero_blocks.push_back({blk, (int64_t)mj * mj});
         continue;
       }
-      double* Z = h->d_Z + (int64_t)(o - o0) * Msz;
+      const int w = (int)out.items.size(), np = pieces[o];
+      double* part = h->d_grpart + pslot * mj * mj;
+      for (int k = 0; k < np; k++) {
+        const int i0 = (int)((int64_t)w * k / np), i1 = (int)((int64_t)w * (k + 1) / np);
+        vouts.push_back({o, i0, i1 - i0, zslot});
+        double* Z = h->d_Z + zslot * Msz;
+        for (int c = 0; c < nfc; c++) {
+          GRTask gt;
+          gt.X = T; gt.Z = Z; gt.partial = h->d_grpart + (pslot + (int64_t)k * nfc + c) * mj * mj;
+          gt.d0 = dm[0]; gt.d1 = dm[1]; gt.d2 = dm[2]; gt.j = j;
+          gt.f0 = (int)(c * fchunk); gt.f1 = (int)((c + 1) * fchunk);
+          ch.gr.tasks.push_back(gt);
+        }
+        zslot++;
+      }
+      GRReduce rd;
+      rd.partial = part; rd.out = blk; rd.m = mj; rd.npart = np * nfc;
+      rd.coef = 1.0; rd.accumulate = 0; rd.pad = 0;
+      ch.gr.reds.push_back(rd);
+      pslot += (int64_t)np * nfc;
+    }
+    // tasks: on the matrix cores several virtual outputs share a task (one
+    // staging of each slice of T serves all of them), packed longest first into
+    // the least loaded task and issued heaviest first; otherwise one per task
+    std::vector<std::vector<size_t>> packs;
+    if (multi && !vouts.empty()) {
+      const int64_t ntask = std::max<int64_t>(1, std::min<int64_t>((int64_t)vouts.size(),
+                                                                   (2048 + ns * strips - 1) / (ns * strips)));
+      std::vector<size_t> byw(vouts.size());
+      for (size_t v = 0; v < vouts.size(); v++) byw[v] = v;
+      std::stable_sort(byw.begin(), byw.end(), [&](size_t a, size_t b) { return vouts[a].ni > vouts[b].ni; });
+      std::vector<std::vector<size_t>> pk(ntask);
+      std::vector<int64_t> load(ntask, 0);
+      for (size_t v : byw) {
+        int64_t best = 0;
+        for (int64_t q = 1; q < ntask; q++)
+          if (load[q] < load[best]) best = q;
+        pk[best].push_back(v);
+        load[best] += vouts[v].ni;
+      }
+      std::vector<int64_t> idx(ntask);
+      for (int64_t q = 0; q < ntask; q++) idx[q] = q;
+      std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return load[a] > load[b]; });
+      for (int64_t q : idx)
+        if (!pk[q].empty()) packs.push_back(pk[q]);
+    } else {
+      for (size_t v = 0; v < vouts.size(); v++) packs.push_back({v});
+    }
+    for (const std::vector<size_t>& pk : packs) {
       SWGroup& g = group_for(ch.sw, ma, mb);
       SWTask t;
       std::memset(&t, 0, sizeof(t));
-      t.x = T; t.y = Z;
+      t.x = T; t.y = h->d_Z + vouts[pk[0]].z * Msz;
       t.xs_slice = sl; t.xs_row = row; t.ys_slice = sl; t.ys_row = row;
       t.ma = ma; t.mb = mb;
-      t.item0 = (int)g.items.size();
-      for (const Item2& it : out.items) {
-        SWItem si;
-        si.A = block_ptr(h, it.A, h->d_envcomb, off);
-        si.B = block_ptr(h, it.B, h->d_envcomb, off);
-        si.coef = it.coef;
-        g.items.push_back(si);
+      if (multi) {
+        t.pad = 1;
+        t.item0 = (int)g.outs.size();
+        t.nitem = (int)pk.size();
+      } else {
+        t.item0 = (int)g.items.size();
       }
-      t.nitem = (int)out.items.size();
+      int nit = 0;
+      for (size_t v : pk) {
+        const VOut& vo = vouts[v];
+        const EnvOut& out = P.outs[vo.o];
+        if (multi) g.outs.push_back({h->d_Z + vo.z * Msz, (int)g.items.size(), vo.ni});
+        for (int i = vo.i0; i < vo.i0 + vo.ni; i++) {
+          const Item2& it = out.items[i];
+          SWItem si;
+          si.A = block_ptr(h, it.A, h->d_envcomb, off);
+          si.B = block_ptr(h, it.B, h->d_envcomb, off);
+          si.coef = it.coef;
+          g.items.push_back(si);
+          nit++;
+        }
+      }
+      if (!multi) t.nitem = nit;
       add_sw_task(g, t, ns);
-      double* part = h->d_grpart + (int64_t)(o - o0) * nfc * mj * mj;
-      for (int c = 0; c < nfc; c++) {
-        GRTask gt;
-        gt.X = T; gt.Z = Z; gt.partial = part + (int64_t)c * mj * mj;
-        gt.d0 = dm[0]; gt.d1 = dm[1]; gt.d2 = dm[2]; gt.j = j;
-        gt.f0 = (int)(c * fchunk); gt.f1 = (int)((c + 1) * fchunk);
-        ch.gr.tasks.push_back(gt);
-      }
-      GRReduce r;
-      r.partial = part; r.out = blk; r.m = mj; r.npart = nfc; r.coef = 1.0; r.accumulate = 0; r.pad = 0;
-      ch.gr.reds.push_back(r);
     }
     upload_sw(h, ch.sw);
     ch.gr.d_tasks = upload(h, ch.gr.tasks);
     ch.gr.d_reds = upload(h, ch.gr.reds);
     D.chunks.push_back(std::move(ch));
+    o0 = o1;
   }
 }
 
@@ -396,7 +545,8 @@ void run_comb(CBPlan& P, hipStream_t s) {
 
 void run_sw(std::vector<SWGroup>& gs, int dtype, const void* xbase, hipStream_t s) {
   for (auto& g : gs)
-    HIPCHK(launch_sandwich(dtype, g.ma, g.mb, g.d_tasks, g.d_items, g.d_wus, (int)g.wus.size(), xbase, s));
+    HIPCHK(launch_sandwich(dtype, g.ma, g.mb, g.d_tasks, g.d_items, g.d_wus, (int)g.wus.size(), xbase, s,
+                           g.d_outs));
 }
 
 hipEvent_t next_event(attn_handle* h) {
@@ -513,7 +663,7 @@ void ensure_lowp(attn_handle* h, int dtype) {
         for (auto& jb : g.jobs) jb.A = to_mirror(h, jb.A, 1);
     }
     L.srcs = D.srcs;
-    upload_sw(h, L.sw);
+    upload_sw(h, L.sw, true);
     upload_mp(h, L.chainA);
     upload_mp(h, L.chainB);
     upload_mp(h, L.chainC);
@@ -1060,7 +1210,14 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
         for (auto& c : ep->combines) c2 += (int64_t)c.dim * c.dim;
         envcomb_need = std::max(envcomb_need, c2);
         const int64_t per = env_chunk_outputs(h, Msz);
-        const int64_t nout = std::min<int64_t>(per, (int64_t)ep->outs.size());
+        int cap = 0;
+        const std::vector<int> pcs = env_pieces(h->M, *ep, cap);
+        int64_t nz = 0;
+        for (int pc : pcs) nz += pc;
+        // a chunk holds at most `per` pieces, or one output with more
+        int64_t maxp = 0;
+        for (int pc : pcs) maxp = std::max<int64_t>(maxp, pc);
+        const int64_t nout = std::max<int64_t>(1, std::max(std::min<int64_t>(per, nz), maxp));
         z_need = std::max(z_need, nout * Msz);
         const int mj = dm[ep->leg];
         grp_need = std::max(grp_need, nout * 8 * (int64_t)mj * mj + (int64_t)mj * mj);
@@ -1724,10 +1881,23 @@ struct Checker {
       if (t.x) span(t.x, xext * esz, "sandwich x");
       else if (xext > xbase_len) fail("sandwich: x beyond the input vector");
       span(t.y, (wu.y * t.ys_slice + (t.ma - 1) * t.ys_row + t.mb) * esz, "sandwich y");
-      if (t.item0 < 0 || t.item0 + t.nitem > (int)g.items.size()) { fail("sandwich: item range"); return; }
-      for (int i = t.item0; i < t.item0 + t.nitem; i++) {
-        if (g.items[i].A) span(g.items[i].A, (int64_t)t.ma * t.ma * esz, "sandwich A");
-        if (g.items[i].B) span(g.items[i].B, (int64_t)t.mb * t.mb * esz, "sandwich B");
+      std::vector<std::pair<int, int>> ranges;
+      if (t.pad) {
+        if (!mf) { fail("sandwich: several outputs on the generic kernel"); return; }
+        if (t.item0 < 0 || t.item0 + t.nitem > (int)g.outs.size()) { fail("sandwich: output range"); return; }
+        for (int o = t.item0; o < t.item0 + t.nitem; o++) {
+          span(g.outs[o].y, (wu.y * t.ys_slice + (t.ma - 1) * t.ys_row + t.mb) * esz, "sandwich y (output)");
+          ranges.push_back({g.outs[o].item0, g.outs[o].nitem});
+        }
+      } else {
+        ranges.push_back({t.item0, t.nitem});
+      }
+      for (auto& rg : ranges) {
+        if (rg.first < 0 || rg.first + rg.second > (int)g.items.size()) { fail("sandwich: item range"); return; }
+        for (int i = rg.first; i < rg.first + rg.second; i++) {
+          if (g.items[i].A) span(g.items[i].A, (int64_t)t.ma * t.ma * esz, "sandwich A");
+          if (g.items[i].B) span(g.items[i].B, (int64_t)t.mb * t.mb * esz, "sandwich B");
+        }
       }
       if (!ok) return;
     }

@@ -45,9 +45,11 @@ struct SWGroup {
   std::vector<SWTask> tasks;
   std::vector<SWItem> items;
   std::vector<int4> wus;
+  std::vector<SWOut> outs;   // tasks with several outputs
   SWTask* d_tasks = nullptr;
   SWItem* d_items = nullptr;
   int4* d_wus = nullptr;
+  SWOut* d_outs = nullptr;
 };
 
 struct MPGroup {
