@@ -564,6 +564,72 @@ __global__ __launch_bounds__(256) void k_gram(const GRTask* __restrict__ tasks) 
   }
 }
 
+// Gram for contracted leg j = 0 or 1 with 16 | d2: the 16 free indices
+// [f0, f0 + 16) of one row i are contiguous, so each lane loads 4 consecutive
+// values of X and of Z straight into registers (no LDS) and the K order of the
+// 16x16x4 products is lane-local: step kk of lane group g takes f0 + 4 g + kk
+// for both operands.  Wave w owns the output tiles w, w + 4, ... (row tile tj,
+// column tile tk); loads of the next f block are issued before the products.
+template <int NI>
+__global__ __launch_bounds__(256) void k_gram_nt(const GRTask* __restrict__ tasks) {
+  constexpr int mj = 16 * NI;
+  constexpr int NT = NI * NI;
+  constexpr int MAXT = (NT + 3) / 4;
+  const GRTask& t = tasks[blockIdx.x];
+  const int j = t.j, d1 = t.d1, d2 = t.d2;
+  const double* X = (const double*)t.X;
+  const double* Z = (const double*)t.Z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int64_t F = (int64_t)t.d0 * d1 * d2 / mj;
+  // element (row i, free f) for f in a 16-aligned block
+  auto addr = [&](int i, int64_t f) -> int64_t {
+    if (j == 0) return (int64_t)i * F + f;
+    const int64_t a = f / d2, c = f - a * d2;
+    return a * d1 * d2 + (int64_t)i * d2 + c;
+  };
+  d4 acc[MAXT];
+#pragma unroll
+  for (int q = 0; q < MAXT; q++) acc[q] = d4{0, 0, 0, 0};
+  int tj[MAXT], tk[MAXT];
+#pragma unroll
+  for (int q = 0; q < MAXT; q++) {
+    const int tt = wave + 4 * q;
+    tj[q] = tt < NT ? tt / NI : -1;
+    tk[q] = tt < NT ? tt - (tt / NI) * NI : 0;
+  }
+  d4 xr[MAXT], zr[MAXT], xn[MAXT], zn[MAXT];
+  auto load = [&](int64_t f0, d4* xv, d4* zv) {
+#pragma unroll
+    for (int q = 0; q < MAXT; q++) {
+      if (tj[q] < 0) continue;
+      xv[q] = *(const d4*)(X + addr(16 * tj[q] + l16, f0 + 4 * l4));
+      if (q > 0 && tk[q] == tk[q - 1]) zv[q] = zv[q - 1];   // the wave's column tile is loaded once
+      else zv[q] = *(const d4*)(Z + addr(16 * tk[q] + l16, f0 + 4 * l4));
+    }
+  };
+  int64_t f0 = t.f0;
+  if (f0 < t.f1) load(f0, xr, zr);
+  for (; f0 < t.f1; f0 += 16) {
+    if (f0 + 16 < t.f1) load(f0 + 16, xn, zn);
+#pragma unroll
+    for (int q = 0; q < MAXT; q++) {
+      if (tj[q] < 0) continue;
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) acc[q] = mfma16(xr[q][kk], zr[q][kk], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < MAXT; q++) { xr[q] = xn[q]; zr[q] = zn[q]; }
+  }
+  double* P = (double*)t.partial;
+#pragma unroll
+  for (int q = 0; q < MAXT; q++) {
+    if (tj[q] < 0) continue;
+#pragma unroll
+    for (int i = 0; i < 4; i++) P[(int64_t)(16 * tk[q] + l16) * mj + 16 * tj[q] + drow<double>(l4, i)] = acc[q][i];
+  }
+}
+
 // Generic gram: one thread per output element (j, j'), loop over the f range.
 __global__ __launch_bounds__(256) void k_gram_gen(const GRTask* __restrict__ tasks, int maxm) {
   const GRTask& t = tasks[blockIdx.y];
@@ -2108,8 +2174,17 @@ static hipError_t gram_launch(const GRTask* tasks, int ntask, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_gram(int mj, bool mfma, const GRTask* tasks, int ntask, hipStream_t s) {
+hipError_t launch_gram(int mj, bool mfma, const GRTask* tasks, int ntask, hipStream_t s, bool nt) {
   if (ntask == 0) return hipSuccess;
+  if (mfma && nt) {
+    switch (mj / 16) {
+      case 1: hipLaunchKernelGGL(k_gram_nt<1>, dim3(ntask), dim3(256), 0, s, tasks); return hipGetLastError();
+      case 2: hipLaunchKernelGGL(k_gram_nt<2>, dim3(ntask), dim3(256), 0, s, tasks); return hipGetLastError();
+      case 3: hipLaunchKernelGGL(k_gram_nt<3>, dim3(ntask), dim3(256), 0, s, tasks); return hipGetLastError();
+      case 4: hipLaunchKernelGGL(k_gram_nt<4>, dim3(ntask), dim3(256), 0, s, tasks); return hipGetLastError();
+      default: break;
+    }
+  }
   if (!mfma) {
     hipLaunchKernelGGL(k_gram_gen, dim3(grid1((int64_t)mj * mj), ntask), dim3(256), 0, s, tasks, mj);
     return hipGetLastError();

@@ -343,6 +343,19 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
   }
 }
 
+// The register-direct gram kernel applies when every task contracts leg 0 or 1
+// of a tensor whose last leg is a multiple of 16, over 16-aligned free ranges,
+// with 32-byte aligned operands and m_j <= 64.
+bool gram_nt_ok(const std::vector<GRTask>& ts, bool mfma) {
+  if (!mfma || ts.empty()) return false;
+  for (const GRTask& t : ts) {
+    const int mj = t.j == 0 ? t.d0 : (t.j == 1 ? t.d1 : t.d2);
+    if (t.j > 1 || mj > 64 || t.d2 % 16 || t.f0 % 16 || t.f1 % 16) return false;
+    if ((uintptr_t)t.X % 32 || (uintptr_t)t.Z % 32) return false;
+  }
+  return true;
+}
+
 int64_t env_chunk_outputs(attn_handle* h, int64_t Msz) {
   const int64_t budget = (int64_t)2 << 30;   // bytes of Z scratch
   return std::max<int64_t>(1, std::min<int64_t>(4096, budget / (Msz * 8)));
@@ -530,6 +543,7 @@ void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
       if (!multi) t.nitem = nit;
       add_sw_task(g, t, ns);
     }
+    ch.gr.nt = gram_nt_ok(ch.gr.tasks, gmf);
     upload_sw(h, ch.sw);
     ch.gr.d_tasks = upload(h, ch.gr.tasks);
     ch.gr.d_reds = upload(h, ch.gr.reds);
@@ -766,7 +780,7 @@ void run_env(attn_handle* h, EnvDev& D, hipStream_t s) {
   for (auto& ch : D.chunks) {
     for (auto& zb : ch.zero_blocks) HIPCHK(launch_zero(zb.first, zb.second, s));
     run_sw(ch.sw, 0, nullptr, s);
-    HIPCHK(launch_gram(ch.gr.mj, ch.gr.mfma, ch.gr.d_tasks, (int)ch.gr.tasks.size(), s));
+    HIPCHK(launch_gram(ch.gr.mj, ch.gr.mfma, ch.gr.d_tasks, (int)ch.gr.tasks.size(), s, ch.gr.nt));
     HIPCHK(launch_gram_reduce(ch.gr.d_reds, (int)ch.gr.reds.size(), ch.gr.mj, s));
   }
   h->n_env++;
@@ -810,6 +824,7 @@ void build_qr_dev(attn_handle* h, int n, int leg, QRDev& Q) {
       gt[c].d0 = dm[0]; gt[c].d1 = dm[1]; gt[c].d2 = dm[2]; gt[c].j = leg;
       gt[c].f0 = (int)(c * fchunk); gt[c].f1 = (int)((c + 1) * fchunk);
     }
+    Q.gnt = gram_nt_ok(gt, Q.gmf) && (pass == 0 || Q.gnt);
     Q.d_gt[pass] = upload(h, gt);
     Q.h_gt[pass] = gt;
     MPTask mt{dst, dm[0], dm[1], dm[2], leg, 0, 1, 0, 0};
@@ -874,7 +889,7 @@ void qr_node(attn_handle* h, int n, int leg, hipStream_t s) {
   double* Rt = G + 5 * nn;
   double* T = h->d_T + h->T_off[n];
   for (int pass = 0; pass < 3; pass++) {
-    HIPCHK(launch_gram(mj, Q.gmf, Q.d_gt[pass], Q.nfc, s));
+    HIPCHK(launch_gram(mj, Q.gmf, Q.d_gt[pass], Q.nfc, s, Q.gnt));
     HIPCHK(launch_gram_reduce(Q.d_gr, 1, mj, s));
     HIPCHK(launch_chol_inv(G, mj, R[pass], Rinv, pass == 0 ? 1 : 0, Q.rows, h->d_st, s));
     HIPCHK(launch_mode(0, mj, Q.mmf, Q.d_mt[pass], Q.d_mj[pass], Q.d_wus, Q.nwus, nullptr, s));

@@ -74,6 +74,7 @@ struct CBPlan {
 struct GRPlan {
   int mj = 0;
   bool mfma = false;
+  bool nt = false;   // register-direct gram kernel
   std::vector<GRTask> tasks;
   std::vector<GRReduce> reds;
   GRTask* d_tasks = nullptr;
@@ -114,7 +115,7 @@ struct EnvDev {
 struct QRDev {
   bool present = false;
   int mj = 0, nfc = 0, nwus = 0;
-  bool gmf = false, mmf = false;
+  bool gmf = false, mmf = false, gnt = false;
   int64_t rows = 0, Msz = 0;
   GRTask* d_gt[3] = {nullptr, nullptr, nullptr};
   GRReduce* d_gr = nullptr;
