@@ -319,6 +319,131 @@ __global__ __launch_bounds__(256) void k_sandwich_bf2(const SWTask* __restrict__
     }
 }
 
+// Wave-per-slice form for legs <= 64 (ma = 16 MA, mb = 16 NB, both multiples
+// of 32): each wave computes a whole slice Y_s with all MA row strips in
+// registers, so every fragment of A and B serves MA (or NB) products instead
+// of one, and the split X_s stays in registers for the whole item loop (no
+// LDS).  wu = (task, first slice, -, number of slices <= 4): wave w takes
+// slice first + w.
+template <int MA, int NB>
+__global__ __launch_bounds__(256) void k_sandwich_bf2w(const SWTask* __restrict__ tasks,
+                                                       const SWItem* __restrict__ items,
+                                                       const int4* __restrict__ wus,
+                                                       const float* __restrict__ xbase) {
+  constexpr int ma = 16 * MA, mb = 16 * NB, CA = ma / 32, CB = mb / 32;
+  const int4 wu = wus[blockIdx.x];
+  const SWTask& t = tasks[wu.x];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave >= wu.w) return;
+  const int s = wu.y + wave;
+  const int l16 = lane & 15, g = lane >> 4;
+  const float* X = (t.x ? (const float*)t.x : xbase) + (int64_t)s * t.xs_slice;
+  bf8 xh[CA][NB], xl[CA][NB];
+#pragma unroll
+  for (int c = 0; c < CA; c++)
+#pragma unroll
+    for (int q = 0; q < NB; q++)
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const float v = X[(int64_t)bf_perm(32 * c + 8 * g + j) * t.xs_row + 16 * q + l16];
+        const __bf16 hi = (__bf16)v;
+        xh[c][q][j] = hi;
+        xl[c][q][j] = (__bf16)(v - (float)hi);
+      }
+  const int64_t mma = (int64_t)ma * ma, mmb = (int64_t)mb * mb;
+  f4 acc[MA][NB];
+#pragma unroll
+  for (int a = 0; a < MA; a++)
+#pragma unroll
+    for (int q = 0; q < NB; q++) acc[a][q] = f4{0, 0, 0, 0};
+  const int iend = t.item0 + t.nitem;
+  for (int it = t.item0; it < iend; it++) {
+    const __bf16* A = (const __bf16*)items[it].A;
+    const __bf16* B = (const __bf16*)items[it].B;
+    const float coef = (float)items[it].coef;
+    f4 t1[MA][NB];
+    if (A) {
+#pragma unroll
+      for (int a = 0; a < MA; a++)
+#pragma unroll
+        for (int q = 0; q < NB; q++) t1[a][q] = f4{0, 0, 0, 0};
+#pragma unroll
+      for (int c = 0; c < CA; c++) {
+        bf8 ah[MA], al[MA];
+#pragma unroll
+        for (int a = 0; a < MA; a++) {
+          const int64_t off = (int64_t)(16 * a + l16) * ma + 32 * c + 8 * g;
+          ah[a] = *(const bf8*)(A + off);
+          al[a] = *(const bf8*)(A + mma + off);
+        }
+#pragma unroll
+        for (int a = 0; a < MA; a++)
+#pragma unroll
+          for (int q = 0; q < NB; q++) {
+            t1[a][q] = mfma_bf(xh[c][q], ah[a], t1[a][q]);
+            t1[a][q] = mfma_bf(xh[c][q], al[a], t1[a][q]);
+            t1[a][q] = mfma_bf(xl[c][q], ah[a], t1[a][q]);
+          }
+      }
+#pragma unroll
+      for (int a = 0; a < MA; a++)
+#pragma unroll
+        for (int q = 0; q < NB; q++) t1[a][q] *= coef;
+    } else {
+#pragma unroll
+      for (int a = 0; a < MA; a++)
+#pragma unroll
+        for (int q = 0; q < NB; q++)
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+            t1[a][q][i] = coef * X[(int64_t)(16 * a + l16) * t.xs_row + 16 * q + drow_bf(g, i)];
+    }
+    if (B) {
+#pragma unroll
+      for (int c = 0; c < CB; c++) {
+        bf8 th[MA], tl[MA];
+#pragma unroll
+        for (int a = 0; a < MA; a++)
+#pragma unroll
+          for (int jj = 0; jj < 8; jj++) {
+            const float v = t1[a][2 * c + jj / 4][jj % 4];
+            th[a][jj] = (__bf16)v;
+            tl[a][jj] = (__bf16)(v - (float)th[a][jj]);
+          }
+#pragma unroll
+        for (int tq = 0; tq < NB; tq++) {
+          const int64_t off = (int64_t)(16 * tq + l16) * mb + 32 * c + 8 * g;
+          const bf8 bh = *(const bf8*)(B + off);
+          const bf8 bl = *(const bf8*)(B + mmb + off);
+#pragma unroll
+          for (int a = 0; a < MA; a++) {
+            acc[a][tq] = mfma_bf(bh, th[a], acc[a][tq]);
+            acc[a][tq] = mfma_bf(bl, th[a], acc[a][tq]);
+            acc[a][tq] = mfma_bf(bh, tl[a], acc[a][tq]);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < MA; a++)
+#pragma unroll
+        for (int q = 0; q < NB; q++) acc[a][q] += t1[a][q];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < MA; a++) {
+    float* Y = (float*)t.y + (int64_t)s * t.ys_slice + (int64_t)(16 * a + l16) * t.ys_row;
+#pragma unroll
+    for (int q = 0; q < NB; q++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int c = 16 * q + drow_bf(g, i);
+        if (t.accumulate) Y[c] += acc[a][q][i];
+        else Y[c] = acc[a][q][i];
+      }
+  }
+}
+
 // ============================================================================ mode product
 // Element (i, f) of a (d0, d1, d2) tensor contracted on leg j, where f runs over
 // the two other legs in order.
@@ -2082,6 +2207,18 @@ static hipError_t sand_bf2_launch(const SWTask* tasks, const SWItem* items, cons
 hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const SWItem* items,
                            const int4* wus, int nwu, const void* xbase, hipStream_t s, const SWOut* outs) {
   if (nwu == 0) return hipSuccess;
+  if (dtype == 3) {   // split BF16, one slice per wave (legs 32 or 64)
+#define BF2W(MA, NB)                                                                               \
+  hipLaunchKernelGGL((k_sandwich_bf2w<MA, NB>), dim3(nwu), dim3(256), 0, s, tasks, items, wus,     \
+                     (const float*)xbase);                                                         \
+  return hipGetLastError();
+    if (ma == 32 && mb == 32) { BF2W(2, 2) }
+    if (ma == 32 && mb == 64) { BF2W(2, 4) }
+    if (ma == 64 && mb == 32) { BF2W(4, 2) }
+    if (ma == 64 && mb == 64) { BF2W(4, 4) }
+#undef BF2W
+    return hipErrorInvalidValue;
+  }
   if (dtype == 2) {
     if (!(ma % 32 == 0 && mb % 32 == 0 && ma <= 128 && mb <= 128)) return hipErrorInvalidValue;
     switch (mb / 32) {

@@ -580,11 +580,11 @@ void run_sw_mv(attn_handle* h, std::vector<SWGroup>& gs, int dtype, const void* 
       a = (int)h->ev_used;
       HIPCHK(hipEventRecord(next_event(h), s));
     }
-    HIPCHK(launch_sandwich(g.fmt == 2 ? 2 : dtype, g.ma, g.mb, g.d_tasks, g.d_items, g.d_wus, (int)g.wus.size(), xbase, s));
+    HIPCHK(launch_sandwich(g.fmt >= 2 ? g.fmt : dtype, g.ma, g.mb, g.d_tasks, g.d_items, g.d_wus, (int)g.wus.size(), xbase, s));
     if (a >= 0) {
       b = (int)h->ev_used;
       HIPCHK(hipEventRecord(next_event(h), s));
-      h->prof_recs.push_back({a, b, g.flops, g.ma, g.mb, g.fmt == 2 ? 2 : dtype});
+      h->prof_recs.push_back({a, b, g.flops, g.ma, g.mb, g.fmt >= 2 ? g.fmt : dtype});
     }
   }
 }
@@ -668,6 +668,16 @@ void ensure_lowp(attn_handle* h, int dtype) {
         }
       g.fmt = bf ? 2 : 1;
       for (auto& it : g.items) { it.A = to_mirror(h, it.A, g.fmt); it.B = to_mirror(h, it.B, g.fmt); }
+      if (bf && g.ma <= 64 && g.mb <= 64) {
+        // one slice per wave: units of up to four consecutive slices of a task
+        std::vector<int> ns_of(g.tasks.size(), 0);
+        for (const int4& wu : g.wus) ns_of[wu.x] = std::max(ns_of[wu.x], wu.y + 1);
+        std::vector<int4> w2;
+        for (size_t ti = 0; ti < g.tasks.size(); ti++)
+          for (int s0 = 0; s0 < ns_of[ti]; s0 += 4) w2.push_back(make_int4((int)ti, s0, 0, std::min(4, ns_of[ti] - s0)));
+        g.wus.swap(w2);
+        g.fmt = 3;
+      }
     }
     const std::vector<MPGroup>* src[3] = {&D.chainA, &D.chainB, &D.chainC};
     std::vector<MPGroup>* dst[3] = {&L.chainA, &L.chainB, &L.chainC};
@@ -2043,7 +2053,17 @@ extern "C" attn_status attn_validate(const attn_handle* h) {
       const int64_t M = (int64_t)D.dims[0] * D.dims[1] * D.dims[2];
       for (auto& g : D.sw) {
         c.sw(g, M, 4);
-        if (g.fmt == 2) {
+        if (g.fmt == 3)
+          for (const int4& wu : g.wus) {
+            const SWTask& t = g.tasks[wu.x];
+            if (wu.w < 1 || wu.w > 4) c.fail("split-BF16 unit slice count");
+            // the last slice of the unit, whole (ma x mb) slab
+            const int64_t last = (int64_t)(wu.y + wu.w - 1);
+            if (t.x) c.span(t.x, (last * t.xs_slice + (t.ma - 1) * t.xs_row + t.mb) * 4, "split-BF16 x");
+            else if (last * t.xs_slice + (t.ma - 1) * t.xs_row + t.mb > M) c.fail("split-BF16 x beyond the input");
+            c.span(t.y, (last * t.ys_slice + (t.ma - 1) * t.ys_row + t.mb) * 4, "split-BF16 y");
+          }
+        if (g.fmt >= 2) {
           if (!sw_bf16(g.ma, g.mb)) c.fail("split-BF16 group with legs not multiples of 32");
           for (auto& it : g.items)
             if ((uintptr_t)it.A % 16 || (uintptr_t)it.B % 16) c.fail("split-BF16 block not 16-byte aligned");
