@@ -322,20 +322,29 @@ __global__ __launch_bounds__(256) void k_sandwich_bf2(const SWTask* __restrict__
 // Wave-per-slice form for legs <= 64 (ma = 16 MA, mb = 16 NB, both multiples
 // of 32): each wave computes a whole slice Y_s with all MA row strips in
 // registers, so every fragment of A and B serves MA (or NB) products instead
-// of one, and the split X_s stays in registers for the whole item loop (no
-// LDS).  wu = (task, first slice, -, number of slices <= 4): wave w takes
-// slice first + w.
+// of one; the split X_s stays in registers for the whole item loop.  The four
+// waves (four slices) share the item's operator blocks through LDS: the blocks
+// of item i + 1 are loaded from memory into registers while item i is
+// computed from LDS, then written to the other LDS buffer (double buffering,
+// one barrier per item).  wu = (task, first slice, -, number of slices <= 4).
 template <int MA, int NB>
 __global__ __launch_bounds__(256) void k_sandwich_bf2w(const SWTask* __restrict__ tasks,
                                                        const SWItem* __restrict__ items,
                                                        const int4* __restrict__ wus,
                                                        const float* __restrict__ xbase) {
   constexpr int ma = 16 * MA, mb = 16 * NB, CA = ma / 32, CB = mb / 32;
+  constexpr int lda = ma + 8, ldb = mb + 8;         // padded LDS rows (conflict-free 16-byte reads)
+  constexpr int SA = ma * lda, SB = mb * ldb;       // bf16 per plane in LDS
+  constexpr int BUF = 2 * SA + 2 * SB;              // one item: A hi, A lo, B hi, B lo
+  constexpr int NA = ma * ma / 8, NBC = mb * mb / 8;  // 16-byte chunks per plane in memory
+  constexpr int NTOT = 2 * NA + 2 * NBC, NPT = (NTOT + 255) / 256;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __bf16* lds = reinterpret_cast<__bf16*>(smem_raw);
   const int4 wu = wus[blockIdx.x];
   const SWTask& t = tasks[wu.x];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (wave >= wu.w) return;
-  const int s = wu.y + wave;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const bool active = wave < wu.w;
+  const int s = wu.y + (active ? wave : 0);
   const int l16 = lane & 15, g = lane >> 4;
   const float* X = (t.x ? (const float*)t.x : xbase) + (int64_t)s * t.xs_slice;
   bf8 xh[CA][NB], xl[CA][NB];
@@ -345,91 +354,130 @@ __global__ __launch_bounds__(256) void k_sandwich_bf2w(const SWTask* __restrict_
     for (int q = 0; q < NB; q++)
 #pragma unroll
       for (int j = 0; j < 8; j++) {
-        const float v = X[(int64_t)bf_perm(32 * c + 8 * g + j) * t.xs_row + 16 * q + l16];
+        const float v = active ? X[(int64_t)bf_perm(32 * c + 8 * g + j) * t.xs_row + 16 * q + l16] : 0.0f;
         const __bf16 hi = (__bf16)v;
         xh[c][q][j] = hi;
         xl[c][q][j] = (__bf16)(v - (float)hi);
       }
-  const int64_t mma = (int64_t)ma * ma, mmb = (int64_t)mb * mb;
+  bf8 pre[NPT];
+  auto fetch = [&](int it) {
+    const __bf16* A = (const __bf16*)items[it].A;
+    const __bf16* B = (const __bf16*)items[it].B;
+#pragma unroll
+    for (int r = 0; r < NPT; r++) {
+      const int ch = tid + 256 * r;
+      const __bf16* src = nullptr;
+      if (ch < 2 * NA) src = A ? A + (int64_t)ch * 8 : nullptr;
+      else if (ch < NTOT) src = B ? B + (int64_t)(ch - 2 * NA) * 8 : nullptr;
+      if (src) pre[r] = *(const bf8*)src;
+    }
+  };
+  auto store = [&](int buf) {
+    __bf16* L = lds + buf * BUF;
+#pragma unroll
+    for (int r = 0; r < NPT; r++) {
+      const int ch = tid + 256 * r;
+      if (ch < 2 * NA) {
+        const int e = ch * 8, plane = e / (ma * ma), w = e - plane * ma * ma;
+        *(bf8*)(L + plane * SA + (w / ma) * lda + w % ma) = pre[r];
+      } else if (ch < NTOT) {
+        const int e = (ch - 2 * NA) * 8, plane = e / (mb * mb), w = e - plane * mb * mb;
+        *(bf8*)(L + 2 * SA + plane * SB + (w / mb) * ldb + w % mb) = pre[r];
+      }
+    }
+  };
   f4 acc[MA][NB];
 #pragma unroll
   for (int a = 0; a < MA; a++)
 #pragma unroll
     for (int q = 0; q < NB; q++) acc[a][q] = f4{0, 0, 0, 0};
-  const int iend = t.item0 + t.nitem;
-  for (int it = t.item0; it < iend; it++) {
-    const __bf16* A = (const __bf16*)items[it].A;
-    const __bf16* B = (const __bf16*)items[it].B;
+  const int i0 = t.item0, i1 = t.item0 + t.nitem;
+  if (i0 < i1) {
+    fetch(i0);
+    store(0);
+  }
+  __syncthreads();
+  for (int it = i0; it < i1; it++) {
+    const int buf = (it - i0) & 1;
+    if (it + 1 < i1) fetch(it + 1);
+    const bool hasA = items[it].A != nullptr, hasB = items[it].B != nullptr;
     const float coef = (float)items[it].coef;
-    f4 t1[MA][NB];
-    if (A) {
-#pragma unroll
-      for (int a = 0; a < MA; a++)
-#pragma unroll
-        for (int q = 0; q < NB; q++) t1[a][q] = f4{0, 0, 0, 0};
-#pragma unroll
-      for (int c = 0; c < CA; c++) {
-        bf8 ah[MA], al[MA];
-#pragma unroll
-        for (int a = 0; a < MA; a++) {
-          const int64_t off = (int64_t)(16 * a + l16) * ma + 32 * c + 8 * g;
-          ah[a] = *(const bf8*)(A + off);
-          al[a] = *(const bf8*)(A + mma + off);
-        }
+    const __bf16* LA = lds + buf * BUF;
+    const __bf16* LB = LA + 2 * SA;
+    if (active) {
+      f4 t1[MA][NB];
+      if (hasA) {
 #pragma unroll
         for (int a = 0; a < MA; a++)
 #pragma unroll
-          for (int q = 0; q < NB; q++) {
-            t1[a][q] = mfma_bf(xh[c][q], ah[a], t1[a][q]);
-            t1[a][q] = mfma_bf(xh[c][q], al[a], t1[a][q]);
-            t1[a][q] = mfma_bf(xl[c][q], ah[a], t1[a][q]);
-          }
-      }
+          for (int q = 0; q < NB; q++) t1[a][q] = f4{0, 0, 0, 0};
 #pragma unroll
-      for (int a = 0; a < MA; a++)
-#pragma unroll
-        for (int q = 0; q < NB; q++) t1[a][q] *= coef;
-    } else {
-#pragma unroll
-      for (int a = 0; a < MA; a++)
-#pragma unroll
-        for (int q = 0; q < NB; q++)
-#pragma unroll
-          for (int i = 0; i < 4; i++)
-            t1[a][q][i] = coef * X[(int64_t)(16 * a + l16) * t.xs_row + 16 * q + drow_bf(g, i)];
-    }
-    if (B) {
-#pragma unroll
-      for (int c = 0; c < CB; c++) {
-        bf8 th[MA], tl[MA];
-#pragma unroll
-        for (int a = 0; a < MA; a++)
-#pragma unroll
-          for (int jj = 0; jj < 8; jj++) {
-            const float v = t1[a][2 * c + jj / 4][jj % 4];
-            th[a][jj] = (__bf16)v;
-            tl[a][jj] = (__bf16)(v - (float)th[a][jj]);
-          }
-#pragma unroll
-        for (int tq = 0; tq < NB; tq++) {
-          const int64_t off = (int64_t)(16 * tq + l16) * mb + 32 * c + 8 * g;
-          const bf8 bh = *(const bf8*)(B + off);
-          const bf8 bl = *(const bf8*)(B + mmb + off);
+        for (int c = 0; c < CA; c++) {
+          bf8 ah[MA], al[MA];
 #pragma unroll
           for (int a = 0; a < MA; a++) {
-            acc[a][tq] = mfma_bf(bh, th[a], acc[a][tq]);
-            acc[a][tq] = mfma_bf(bl, th[a], acc[a][tq]);
-            acc[a][tq] = mfma_bf(bh, tl[a], acc[a][tq]);
+            const int off = (16 * a + l16) * lda + 32 * c + 8 * g;
+            ah[a] = *(const bf8*)(LA + off);
+            al[a] = *(const bf8*)(LA + SA + off);
+          }
+#pragma unroll
+          for (int a = 0; a < MA; a++)
+#pragma unroll
+            for (int q = 0; q < NB; q++) {
+              t1[a][q] = mfma_bf(xh[c][q], ah[a], t1[a][q]);
+              t1[a][q] = mfma_bf(xh[c][q], al[a], t1[a][q]);
+              t1[a][q] = mfma_bf(xl[c][q], ah[a], t1[a][q]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < MA; a++)
+#pragma unroll
+          for (int q = 0; q < NB; q++) t1[a][q] *= coef;
+      } else {
+#pragma unroll
+        for (int a = 0; a < MA; a++)
+#pragma unroll
+          for (int q = 0; q < NB; q++)
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+              t1[a][q][i] = coef * X[(int64_t)(16 * a + l16) * t.xs_row + 16 * q + drow_bf(g, i)];
+      }
+      if (hasB) {
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          bf8 th[MA], tl[MA];
+#pragma unroll
+          for (int a = 0; a < MA; a++)
+#pragma unroll
+            for (int jj = 0; jj < 8; jj++) {
+              const float v = t1[a][2 * c + jj / 4][jj % 4];
+              th[a][jj] = (__bf16)v;
+              tl[a][jj] = (__bf16)(v - (float)th[a][jj]);
+            }
+#pragma unroll
+          for (int tq = 0; tq < NB; tq++) {
+            const int off = (16 * tq + l16) * ldb + 32 * c + 8 * g;
+            const bf8 bh = *(const bf8*)(LB + off);
+            const bf8 bl = *(const bf8*)(LB + SB + off);
+#pragma unroll
+            for (int a = 0; a < MA; a++) {
+              acc[a][tq] = mfma_bf(bh, th[a], acc[a][tq]);
+              acc[a][tq] = mfma_bf(bl, th[a], acc[a][tq]);
+              acc[a][tq] = mfma_bf(bh, tl[a], acc[a][tq]);
+            }
           }
         }
+      } else {
+#pragma unroll
+        for (int a = 0; a < MA; a++)
+#pragma unroll
+          for (int q = 0; q < NB; q++) acc[a][q] += t1[a][q];
       }
-    } else {
-#pragma unroll
-      for (int a = 0; a < MA; a++)
-#pragma unroll
-        for (int q = 0; q < NB; q++) acc[a][q] += t1[a][q];
     }
+    if (it + 1 < i1) store(buf ^ 1);
+    __syncthreads();
   }
+  if (!active) return;
 #pragma unroll
   for (int a = 0; a < MA; a++) {
     float* Y = (float*)t.y + (int64_t)s * t.ys_slice + (int64_t)(16 * a + l16) * t.ys_row;
@@ -443,6 +491,9 @@ __global__ __launch_bounds__(256) void k_sandwich_bf2w(const SWTask* __restrict_
       }
   }
 }
+
+template <int MA, int NB>
+constexpr size_t bf2w_lds() { return (size_t)2 * (2 * 16 * MA * (16 * MA + 8) + 2 * 16 * NB * (16 * NB + 8)) * 2; }
 
 // ============================================================================ mode product
 // Element (i, f) of a (d0, d1, d2) tensor contracted on leg j, where f runs over
@@ -518,6 +569,52 @@ __global__ __launch_bounds__(256) void k_mode(const MPTask* __restrict__ tasks,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 wu = wus[blockIdx.x];
   mode_mfma<T, NI>(tasks[wu.x], jobs, wu, xbase, smem_raw);
+}
+
+// Mode product for contracted leg j = 0 or 1 with 16 | d2: a 16-wide tile of
+// the free index is contiguous in memory for every i', so both operands are
+// loaded straight into registers (no LDS, no barriers).  wu = (task, 64-wide
+// free tile); wave w owns free indices [16 w, +16) and all m_j rows.
+template <typename T, int NI>
+__global__ __launch_bounds__(256) void k_mode_nt(const MPTask* __restrict__ tasks, const MPJob* __restrict__ jobs,
+                                                 const int2* __restrict__ wus, const T* __restrict__ xbase) {
+  typedef typename V4<T>::type v4;
+  constexpr int mj = 16 * NI;
+  const int2 wu = wus[blockIdx.x];
+  const MPTask& t = tasks[wu.x];
+  const int j = t.j, d1 = t.d1, d2 = t.d2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int64_t F = (int64_t)t.d0 * d1 * d2 / mj;
+  const int64_t f = (int64_t)wu.y * 64 + 16 * wave + l16;
+  // (i, f) -> address; the tile's f share one a-row when j = 1
+  int64_t fo, fs;   // address = fo + i * fs
+  if (j == 0) { fo = f; fs = F; }
+  else { const int64_t a = f / d2, c = f - a * d2; fo = a * d1 * d2 + c; fs = d2; }
+  v4 acc[NI];
+#pragma unroll
+  for (int q = 0; q < NI; q++) acc[q] = v4{0, 0, 0, 0};
+  for (int jb = t.job0; jb < t.job0 + t.njob; jb++) {
+    const T* in = jobs[jb].in ? (const T*)jobs[jb].in : xbase;
+    const T* A = (const T*)jobs[jb].A + l16;
+    const T coef = (T)jobs[jb].coef;
+#pragma unroll 4
+    for (int k0 = 0; k0 < mj; k0 += 4) {
+      const T bop = in[fo + (int64_t)(k0 + l4) * fs] * coef;
+      const T* Ak = A + (int64_t)(k0 + l4) * mj;
+#pragma unroll
+      for (int q = 0; q < NI; q++) acc[q] = mfma16(Ak[16 * q], bop, acc[q]);
+    }
+  }
+  T* out = (T*)t.out;
+#pragma unroll
+  for (int q = 0; q < NI; q++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int64_t ad = fo + (int64_t)(16 * q + drow<T>(l4, i)) * fs;
+      if (t.accumulate) out[ad] += acc[q][i];
+      else out[ad] = acc[q][i];
+    }
 }
 
 // Generic mode product: one thread per output element.  wu = (task, first element).
@@ -1054,35 +1151,67 @@ __global__ __launch_bounds__(256) void k_kbeta(const KJob* __restrict__ jobs, in
 //  * eigenvector by inverse iteration with T - theta I (Gaussian elimination
 //    with partial pivoting on the tridiagonal system, three iterations);
 //  * normalised, sign fixed as described at the end of the kernel.
-__device__ int sturm_count(const double* a, const double* b, int k, double x) {
-  int cnt = 0;
-  double q = a[0] - x;
-  if (q < 0) cnt++;
+// Number of eigenvalues of the symmetric tridiagonal (a, b) below x, from the
+// signs of the leading principal minors p_i = (a_i - x) p_{i-1} - b_{i-1}^2
+// p_{i-2} (a Sturm sequence): every negative ratio p_i / p_{i-1} counts one
+// eigenvalue, and a zero minor takes the sign of the one before it.  There is
+// no division, so a step costs one dependent FMA; the pair (p_{i-1}, p_i) is
+// rescaled by a power of two whenever it leaves [2^-400, 2^400], which changes
+// no sign and no ratio.  b2 holds the squares b_i^2.
+constexpr int kTriLds = 10 * 64;
+constexpr size_t kTinyLdsMax = 144 * 1024;   // dynamic LDS of the tiny-node Lanczos kernel
+
+__device__ int sturm_count(const double* a, const double* b2, int k, double x) {
+  double pm = 1.0, pc = a[0] - x;
+  bool neg = pc < 0.0;   // sign carried by the last nonzero minor
+  int cnt = neg;
+#pragma unroll 8
   for (int i = 1; i < k; i++) {
-    if (q == 0.0) q = 1e-300;
-    q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
-    if (q < 0) cnt++;
+    const double pn = (a[i] - x) * pc - b2[i - 1] * pm;
+    if (pn != 0.0) {
+      const bool nn = pn < 0.0;
+      cnt += nn != neg;
+      neg = nn;
+    }
+    pm = pc;
+    pc = pn;
+    const double m = fmax(fabs(pm), fabs(pc));
+    if (m > 0x1p400) {
+      pm *= 0x1p-400;
+      pc *= 0x1p-400;
+    } else if (m < 0x1p-400) {
+      pm *= 0x1p400;
+      pc *= 0x1p400;
+    }
   }
   return cnt;
 }
 
-// Run by one full wavefront (64 lanes); lds must hold 8 * 64 doubles.
+// Lowest eigenpair of the keff x keff Lanczos tridiagonal in st, run by one
+// full wavefront (64 lanes); lds must hold kTriLds doubles.  The eigenvalue by
+// multisection (64 Sturm counts per round) and bisection to the last bit, the
+// eigenvector by three rounds of inverse iteration on one LU factorisation
+// (partial pivoting) of T - theta I.
 __device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restrict__ lds) {
   const int lane = threadIdx.x & 63;
   const int k = st->keff;
   double* a = lds;
   double* b = lds + 64;
-  double* y = lds + 128;
-  double* d = lds + 192;
-  double* du = lds + 256;
-  double* du2 = lds + 320;
-  double* dl = lds + 384;
-  double* rhs = lds + 448;
+  double* b2 = lds + 128;
+  double* y = lds + 192;
+  double* d = lds + 256;
+  double* du = lds + 320;
+  double* du2 = lds + 384;
+  double* f = lds + 448;
+  double* rd = lds + 512;
+  double* sw = lds + 576;
   if (lane < k) a[lane] = st->alpha[lane];
-  if (lane + 1 < k) b[lane] = st->beta[lane];
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  if (lane + 1 < k) {
+    const double bl = st->beta[lane];
+    b[lane] = bl;
+    b2[lane] = bl * bl;
+  }
+  wave_sync();
   double lo = a[0], hi = a[0], nrm = 0;
   for (int i = 0; i < k; i++) {
     const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < k ? fabs(b[i]) : 0.0);
@@ -1094,7 +1223,7 @@ __device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restr
   for (int it = 0; it < 40; it++) {
     const double w = hi - lo;
     const double x = lo + w * (double)(lane + 1) / 65.0;
-    const bool has = (x > lo && x < hi) ? sturm_count(a, b, k, x) >= 1 : (x >= hi);
+    const bool has = (x > lo && x < hi) ? sturm_count(a, b2, k, x) >= 1 : (x >= hi);
     const unsigned long long m = __ballot(has);
     const int first = m ? __ffsll((long long)m) - 1 : 64;
     const double nhi = first < 64 ? lo + w * (double)(first + 1) / 65.0 : hi;
@@ -1108,52 +1237,71 @@ __device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restr
   for (int it = 0; it < 64; it++) {
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
-    if (sturm_count(a, b, k, mid) >= 1) hi = mid;
+    if (sturm_count(a, b2, k, mid) >= 1) hi = mid;
     else lo = mid;
   }
   const double theta = hi;
+  const double tiny = 1e-300 + 2.2e-16 * nrm * 1e-3;
   if (lane == 0) {
-    const double tiny = 1e-300 + 2.2e-16 * nrm * 1e-3;
-    for (int i = 0; i < k; i++) y[i] = 1.0;
-    for (int rep = 0; rep < 3; rep++) {
-      for (int i = 0; i < k; i++) {
-        d[i] = a[i] - theta;
-        rhs[i] = y[i];
-        du[i] = (i + 1 < k) ? b[i] : 0.0;
-        dl[i] = (i + 1 < k) ? b[i] : 0.0;
-        du2[i] = 0.0;
-      }
-      for (int i = 0; i + 1 < k; i++) {
-        if (fabs(d[i]) >= fabs(dl[i])) {
-          if (d[i] == 0.0) d[i] = tiny;
-          const double f = dl[i] / d[i];
-          d[i + 1] -= f * du[i];
-          rhs[i + 1] -= f * rhs[i];
-          dl[i] = 0.0;
-        } else {
-          const double f = d[i] / dl[i];
-          d[i] = dl[i];
-          const double t1 = d[i + 1];
-          d[i + 1] = du[i] - f * t1;
-          du[i] = t1;
-          if (i + 2 < k) {
-            du2[i] = du[i + 1];
-            du[i + 1] = -f * du2[i];
-          }
-          const double tr = rhs[i];
-          rhs[i] = rhs[i + 1];
-          rhs[i + 1] = tr - f * rhs[i + 1];
+    // T - theta I = P L U: U with diagonal d and superdiagonals du, du2,
+    // multipliers f, row swaps sw
+    for (int i = 0; i < k; i++) {
+      d[i] = a[i] - theta;
+      du[i] = (i + 1 < k) ? b[i] : 0.0;
+      du2[i] = 0.0;
+    }
+    for (int i = 0; i + 1 < k; i++) {
+      const double li = b[i];
+      if (fabs(d[i]) >= fabs(li)) {
+        if (d[i] == 0.0) d[i] = tiny;
+        const double fi = li / d[i];
+        f[i] = fi;
+        sw[i] = 0.0;
+        d[i + 1] -= fi * du[i];
+      } else {
+        const double fi = d[i] / li;
+        f[i] = fi;
+        sw[i] = 1.0;
+        d[i] = li;
+        const double t1 = d[i + 1];
+        d[i + 1] = du[i] - fi * t1;
+        du[i] = t1;
+        if (i + 2 < k) {
+          du2[i] = du[i + 1];
+          du[i + 1] = -fi * du2[i];
         }
       }
-      if (d[k - 1] == 0.0) d[k - 1] = tiny;
-      for (int i = k - 1; i >= 0; i--) {
-        double v = rhs[i];
-        if (i + 1 < k) v -= du[i] * y[i + 1];
-        if (i + 2 < k) v -= du2[i] * y[i + 2];
-        y[i] = v / (d[i] == 0.0 ? tiny : d[i]);
+    }
+    if (d[k - 1] == 0.0) d[k - 1] = tiny;
+  }
+  wave_sync();
+  if (lane < k) rd[lane] = 1.0 / d[lane];
+  wave_sync();
+  if (lane == 0) {
+    for (int i = 0; i < k; i++) y[i] = 1.0;
+    for (int rep = 0; rep < 3; rep++) {
+      // forward: y <- L^{-1} P y, in place
+      double cur = y[0];
+      for (int i = 0; i + 1 < k; i++) {
+        const double nx = y[i + 1];
+        if (sw[i] == 0.0) {
+          y[i] = cur;
+          cur = nx - f[i] * cur;
+        } else {
+          y[i] = nx;
+          cur = cur - f[i] * nx;
+        }
       }
-      double n2 = 0;
-      for (int i = 0; i < k; i++) n2 += y[i] * y[i];
+      y[k - 1] = cur;
+      // backward: y <- U^{-1} y
+      double y1 = 0.0, y2 = 0.0, n2 = 0.0;
+      for (int i = k - 1; i >= 0; i--) {
+        const double v = (y[i] - du[i] * y1 - du2[i] * y2) * rd[i];
+        y[i] = v;
+        n2 += v * v;
+        y2 = y1;
+        y1 = v;
+      }
       const double inv = 1.0 / sqrt(n2);
       for (int i = 0; i < k; i++) y[i] *= inv;
     }
@@ -1170,7 +1318,7 @@ __device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restr
 }
 
 __global__ __launch_bounds__(64) void k_ktridiag(const KJob* __restrict__ jobs) {
-  __shared__ double lds[512];
+  __shared__ double lds[kTriLds];
   tridiag_solve_wave(jobs[blockIdx.y].st, lds);
 }
 
@@ -1215,92 +1363,116 @@ __global__ __launch_bounds__(256) void k_tiny_assemble(const TJob* __restrict__ 
   H[e] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_tiny_lanczos(const TJob* __restrict__ jobs, int kreq) {
+// Tiny-node Lanczos: one workgroup of 1024 threads per job, one thread per
+// vector entry (M <= 1024).  The dense matvec splits the columns over
+// S = min(M, 1024 / M) slices whose partial sums are added in a fixed order;
+// every Gram-Schmidt dot product is taken by one wavefront, 16 at a time.
+// Dynamic LDS: partial sums [1024], then V [k][M] and w [M] when they fit in
+// the vcap bytes that follow (else V and w stay in the job's global buffers;
+// the arithmetic is the same either way).
+__device__ __forceinline__ double block_sum_waves(double v, double* red, int nw) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0;
+  for (int i = 0; i < nw; i++) s += red[i];
+  return s;
+}
+
+__global__ __launch_bounds__(1024) void k_tiny_lanczos_lds(const TJob* __restrict__ jobs, int kreq,
+                                                           int64_t vcap) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  __shared__ double hs[64];
+  __shared__ double tri_lds[kTriLds];
   const TJob& J = jobs[blockIdx.x];
   const double* __restrict__ H = J.H;
   double* __restrict__ T = J.T;
-  double* __restrict__ V = J.V;
-  double* __restrict__ w = J.w;
   KrylovState* __restrict__ st = J.st;
   const int M = J.M, k = kreq < M ? kreq : M;
-  __shared__ double red[4];
-  __shared__ double hs[64];
-  __shared__ double xs[1024];
-  __shared__ double tri_lds[512];
-  const int t = threadIdx.x;
+  double* part = reinterpret_cast<double*>(smem_raw);
+  const bool in_lds = (int64_t)(k + 1) * M * (int64_t)sizeof(double) <= vcap;
+  double* V = in_lds ? part + 1024 : J.V;
+  double* w = in_lds ? V + (int64_t)k * M : J.w;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int S = max(1, min(M, 1024 / M));
+  const bool mine = t < M;
   if (t == 0) { st->kmax = k; st->keff = 1; st->stop = 0; st->status = 0; }
-  double s2 = 0;
-  for (int e = t; e < M; e += 256) s2 += T[e] * T[e];
-  const double nrm = sqrt(block_sum(s2, red));
-  for (int e = t; e < M; e += 256) V[e] = T[e] / nrm;
+  const double t0 = mine ? T[t] : 0.0;
+  const double nrm = sqrt(block_sum_waves(t0 * t0, red, 16));
+  if (mine) V[t] = t0 / nrm;
   __syncthreads();
   double beta_prev = 0, amax = 0;
   int keff = 1;
   for (int j = 0; j < k; j++) {
-    const double* vj = V + (int64_t)j * M;
-    for (int e = t; e < M; e += 256) xs[e] = vj[e];
-    __syncthreads();
-    for (int i = t; i < M; i += 256) {   // w = H v_j
+    const double* x = V + (int64_t)j * M;
+    if (t < S * M) {   // w = H x, slice sl of the columns
+      const int r = t % M, sl = t / M;
       double acc = 0;
-      for (int c = 0; c < M; c++) acc += H[(int64_t)c * M + i] * xs[c];
-      w[i] = acc;
+      for (int c = sl; c < M; c += S) acc += H[(int64_t)c * M + r] * x[c];
+      part[sl * M + r] = acc;
     }
     __syncthreads();
-    double a = 0;
-    for (int e = t; e < M; e += 256) a += xs[e] * w[e];
-    a = block_sum(a, red);
+    double wv = 0, xv = 0;
+    if (mine) {
+      for (int sl = 0; sl < S; sl++) wv += part[sl * M + t];
+      xv = x[t];
+    }
+    const double a = block_sum_waves(xv * wv, red, 16);
     if (t == 0) st->alpha[j] = a;
     amax = fmax(amax, fabs(a));
     if (j == k - 1) break;
-    const double* vm = j > 0 ? V + (int64_t)(j - 1) * M : V;
-    for (int e = t; e < M; e += 256) {
-      double xv = w[e] - a * xs[e];
-      if (j > 0) xv -= beta_prev * vm[e];
-      w[e] = xv;
+    if (mine) {
+      wv -= a * xv;
+      if (j > 0) wv -= beta_prev * V[(int64_t)(j - 1) * M + t];
+      w[t] = wv;
     }
     __syncthreads();
     for (int pass = 0; pass < 2; pass++) {
-      for (int i = 0; i <= j; i++) {
+      for (int i = wave; i <= j; i += 16) {   // hs[i] = V_i . w
         double d = 0;
-        for (int e = t; e < M; e += 256) d += V[(int64_t)i * M + e] * w[e];
-        d = block_sum(d, red);
-        if (t == 0) hs[i] = d;
+        for (int e = lane; e < M; e += 64) d += V[(int64_t)i * M + e] * w[e];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+        if (lane == 0) hs[i] = d;
       }
       __syncthreads();
-      for (int e = t; e < M; e += 256) {
-        double xv = w[e];
-        for (int i = 0; i <= j; i++) xv -= hs[i] * V[(int64_t)i * M + e];
-        w[e] = xv;
+      if (mine) {
+        for (int i = 0; i <= j; i++) wv -= hs[i] * V[(int64_t)i * M + t];
+        w[t] = wv;
       }
       __syncthreads();
     }
-    double b2 = 0;
-    for (int e = t; e < M; e += 256) b2 += w[e] * w[e];
-    const double b = sqrt(block_sum(b2, red));
+    const double b = sqrt(block_sum_waves(wv * wv, red, 16));
     if (!(b > 1e-14 * amax)) break;
     if (t == 0) st->beta[j] = b;
     beta_prev = b;
     keff = j + 2;
-    for (int e = t; e < M; e += 256) V[(int64_t)(j + 1) * M + e] = w[e] / b;
+    if (mine) V[(int64_t)(j + 1) * M + t] = wv / b;
     __syncthreads();
   }
   if (t == 0) st->keff = keff;
   __syncthreads();
   if (t < 64) tridiag_solve_wave(st, tri_lds);
   __syncthreads();
-  const int kk = keff;
-  if (t < kk) hs[t] = st->y[t];
+  if (t < keff) hs[t] = st->y[t];
   __syncthreads();
-  double n2 = 0;
-  for (int e = t; e < M; e += 256) {
-    double xv = 0;
-    for (int i = 0; i < kk; i++) xv += hs[i] * V[(int64_t)i * M + e];
-    w[e] = xv;
-    n2 += xv * xv;
-  }
-  const double nr = sqrt(block_sum(n2, red));
-  for (int e = t; e < M; e += 256) T[e] = w[e] / nr;
+  double u = 0;
+  if (mine)
+    for (int i = 0; i < keff; i++) u += hs[i] * V[(int64_t)i * M + t];
+  const double nr = sqrt(block_sum_waves(u * u, red, 16));
+  if (mine) T[t] = u / nr;
   if (t == 0 && !(nr > 0 && isfinite(nr))) st->status = 1;
+}
+
+// bytes for V and w of the largest job, capped
+int64_t tiny_vcap(int maxM, int kreq) {
+  const int64_t k = kreq < maxM ? kreq : maxM;
+  const int64_t need = (k + 1) * maxM * (int64_t)sizeof(double);
+  const int64_t cap = (int64_t)kTinyLdsMax - 1024 * (int64_t)sizeof(double);
+  return need < cap ? need : cap;
 }
 
 // out = sum_i y_i V_i with partial ||out||^2
@@ -1957,65 +2129,116 @@ __global__ __launch_bounds__(256) void k_harvest_write(const double* __restrict_
 // of Fukaya et al.), making the factorisation safe for ill-conditioned input.
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// (a) n = 16, 32, 48 or 64: one wavefront, lane j keeps column j of L (and
-//     later column j of L^{-1}) in registers; column k is published in LDS at
-//     step k and every lane updates its own column from broadcast reads.
+// (a) n = 16, 32, 48 or 64: one wavefront.  Lane j keeps column j of the
+//     symmetric trailing matrix in registers (both triangles, so that row k,
+//     the broadcast operand of step k, is held one entry per lane); row k is
+//     published in LDS by the update of step k - 1 and read back as
+//     broadcasts.  Steps go in blocks of 16 with a rolled loop inside each
+//     block (a fully unrolled factorisation does not fit the instruction
+//     cache); the update of a block's steps covers every row from the block
+//     start on, so the broadcast reads of a step are issued together (rows
+//     already eliminated receive updates that are never read).  L is kept
+//     column-major in LDS; X = L^{-1} column j is formed in lane j by forward
+//     substitution with the columns of L broadcast, each finished entry stored
+//     as it is produced.
+template <int N, int I0>
+__device__ __forceinline__ void bcast_axpy(double (&v)[N], const double* __restrict__ src, double a) {
+  // v[i] -= src[i] * a for i in [I0, N), reads issued in chunks of 16
+#pragma unroll
+  for (int i0 = I0; i0 < N; i0 += 16) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; u++)
+      if (i0 + u < N) t[u] = src[i0 + u];
+#pragma unroll
+    for (int u = 0; u < 16; u++)
+      if (i0 + u < N) v[i0 + u] = fma(-t[u], a, v[i0 + u]);
+  }
+}
+
+template <int N, int KB>
+__device__ __forceinline__ void chol_steps(double (&c)[N], double* Lc, double (*rowbuf)[64], double* sb,
+                                           int lane, bool own, int& bad) {
+  constexpr int LD = N + 1;
+#pragma unroll 1
+  for (int k = 16 * KB; k < 16 * KB + 16; k++) {
+    const int cur = k & 1;
+    const double rk = rowbuf[cur][lane];                  // A(k, lane)
+    const double d = rowbuf[cur][k];
+    if (!(d > 0.0) || !isfinite(d)) bad = 1;
+    const double piv = sqrt(fmax(d, 1e-300));
+    const double inv = 1.0 / piv;
+    const double rks = rk * inv;                          // L(lane, k) for lane > k
+    const double ljk = (own && lane > k) ? rks : 0.0;
+    sb[lane] = rks;
+    if (own) Lc[k * LD + lane] = lane == k ? piv : ljk;   // column k of L (zero above the diagonal)
+    wave_sync();
+    bcast_axpy<N, 16 * KB + 1>(c, sb, ljk);
+#pragma unroll
+    for (int i = 16 * KB + 1; i < 16 * KB + 17 && i < N; i++)
+      if (i == k + 1) rowbuf[cur ^ 1][lane] = c[i];
+    wave_sync();
+  }
+  if constexpr (16 * KB + 16 < N) chol_steps<N, KB + 1>(c, Lc, rowbuf, sb, lane, own, bad);
+}
+
+template <int N, int PB>
+__device__ __forceinline__ void trinv_steps(double (&x)[N], const double* Lc, double (*xbuf)[64],
+                                            double* __restrict__ RinvRow, int lane, bool own) {
+  constexpr int LD = N + 1;
+#pragma unroll 1
+  for (int p = 16 * PB; p < 16 * PB + 16; p++) {
+    const int cur = p & 1;
+    const double* col = Lc + p * LD;
+    const double xp = xbuf[cur][lane] / col[p];           // X(p, lane)
+    if (own) RinvRow[(int64_t)lane * N + p] = xp;
+    bcast_axpy<N, 16 * PB + 1>(x, col, xp);
+#pragma unroll
+    for (int i = 16 * PB + 1; i < 16 * PB + 17 && i < N; i++)
+      if (i == p + 1) xbuf[cur ^ 1][lane] = x[i];
+  }
+  if constexpr (16 * PB + 16 < N) trinv_steps<N, PB + 1>(x, Lc, xbuf, RinvRow, lane, own);
+}
+
 template <int N>
 __global__ __launch_bounds__(64) void k_chol_inv_reg(const double* __restrict__ G,
                                                      double* __restrict__ R,
                                                      double* __restrict__ RinvRow, int shift_mode,
                                                      int64_t rows, KrylovState* __restrict__ st) {
-  __shared__ double Ls[N * N];
+  static_assert(N % 16 == 0 && N <= 64, "one lane per column, blocks of 16 steps");
+  constexpr int LD = N + 1;           // odd stride: strided reads of Lc are free of bank conflicts
+  __shared__ double Lc[N * LD];       // Lc[k * LD + j] = L(j, k)
+  __shared__ double rowbuf[2][64];    // row k of the trailing matrix (double buffered)
+  __shared__ double sb[64];           // scaled row k = column k of L
   const int lane = threadIdx.x;
-  double tr = (lane < N) ? G[(int64_t)lane * N + lane] : 0.0;
+  const bool own = lane < N;
+  double tr = own ? G[(int64_t)lane * N + lane] : 0.0;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
   const double shift =
       shift_mode ? 11.0 * ((double)rows * N + (double)N * (N + 1)) * 1.1102230246251565e-16 * tr : 0.0;
+  // c[i] = A(i, lane) from the lower triangle of G (column-major)
   double c[N];
 #pragma unroll
   for (int i = 0; i < N; i++)
-    c[i] = (lane < N && i >= lane) ? G[(int64_t)lane * N + i] + (i == lane ? shift : 0.0) : 0.0;
-  int bad = 0;
-#pragma unroll
-  for (int k = 0; k < N; k++) {
-    if (lane == k) {
-      if (!(c[k] > 0.0) || !isfinite(c[k])) bad = 1;
-      const double piv = sqrt(fmax(c[k], 1e-300));
-      const double inv = 1.0 / piv;
-      c[k] = piv;
-#pragma unroll
-      for (int i = k + 1; i < N; i++) c[i] *= inv;
-#pragma unroll
-      for (int i = k; i < N; i++) Ls[i * N + k] = c[i];
-    }
-    wave_sync();
-    if (lane > k && lane < N) {
-      const double ljk = Ls[lane * N + k];
-#pragma unroll
-      for (int i = k + 1; i < N; i++)
-        if (i >= lane) c[i] -= Ls[i * N + k] * ljk;
-    }
-  }
+    c[i] = own ? (i >= lane ? G[(int64_t)lane * N + i] : G[(int64_t)i * N + lane]) + (i == lane ? shift : 0.0)
+               : 0.0;
+  rowbuf[0][lane] = c[0];
   wave_sync();
-  // column lane of X = L^{-1} by forward substitution
+  int bad = 0;
+  chol_steps<N, 0>(c, Lc, rowbuf, sb, lane, own, bad);
+  // R = L^T column-major: R(lane, j) = L(j, lane)
+  if (own)
+    for (int j = 0; j < N; j++) R[(int64_t)j * N + lane] = Lc[lane * LD + j];
+  // X = L^{-1}, column lane: x(i) = (delta(i, lane) - sum_{p < i} L(i, p) x(p)) / L(i, i),
+  // the sum taken in increasing p.  RinvRow = R^{-1} row-major = X^T, so row
+  // lane of RinvRow is column lane of X.
   double x[N];
 #pragma unroll
-  for (int i = 0; i < N; i++) {
-    double v = (i == lane) ? 1.0 : 0.0;
-#pragma unroll
-    for (int j = 0; j < i; j++)
-      if (j >= lane) v -= Ls[i * N + j] * x[j];
-    x[i] = (i >= lane) ? v / Ls[i * N + i] : 0.0;
-  }
-  if (lane < N) {
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-      R[(int64_t)lane * N + i] = (i <= lane) ? Ls[lane * N + i] : 0.0;   // R = L^T, column lane
-      RinvRow[(int64_t)lane * N + i] = x[i];                              // row lane of R^{-1}
-    }
-  }
-  if (bad && st) st->status = 2;
+  for (int i = 0; i < N; i++) x[i] = (i == lane) ? 1.0 : 0.0;
+  rowbuf[0][lane] = x[0];
+  trinv_steps<N, 0>(x, Lc, rowbuf, RinvRow, lane, own);
+  if (lane == 0 && bad && st) st->status = 2;
 }
 
 // (b) other n (<= 128): LDS-resident packed triangles, rank-1 updates over a
@@ -2208,14 +2431,17 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
                            const int4* wus, int nwu, const void* xbase, hipStream_t s, const SWOut* outs) {
   if (nwu == 0) return hipSuccess;
   if (dtype == 3) {   // split BF16, one slice per wave (legs 32 or 64)
-#define BF2W(MA, NB)                                                                               \
-  hipLaunchKernelGGL((k_sandwich_bf2w<MA, NB>), dim3(nwu), dim3(256), 0, s, tasks, items, wus,     \
-                     (const float*)xbase);                                                         \
-  return hipGetLastError();
-    if (ma == 32 && mb == 32) { BF2W(2, 2) }
-    if (ma == 32 && mb == 64) { BF2W(2, 4) }
-    if (ma == 64 && mb == 32) { BF2W(4, 2) }
-    if (ma == 64 && mb == 64) { BF2W(4, 4) }
+#define BF2W(MA, NB)                                                                             \
+  {                                                                                              \
+    const size_t lds = bf2w_lds<MA, NB>();                                                       \
+    hipLaunchKernelGGL((k_sandwich_bf2w<MA, NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus, \
+                       (const float*)xbase);                                                     \
+    return hipGetLastError();                                                                    \
+  }
+    if (ma == 32 && mb == 32) BF2W(2, 2)
+    if (ma == 32 && mb == 64) BF2W(2, 4)
+    if (ma == 64 && mb == 32) BF2W(4, 2)
+    if (ma == 64 && mb == 64) BF2W(4, 4)
 #undef BF2W
     return hipErrorInvalidValue;
   }
@@ -2276,8 +2502,17 @@ static hipError_t mode_launch(const MPTask* tasks, const MPJob* jobs, const int2
 }
 
 hipError_t launch_mode(int dtype, int mj, bool mfma, const MPTask* tasks, const MPJob* jobs,
-                       const int2* wus, int nwu, const void* xbase, hipStream_t s) {
+                       const int2* wus, int nwu, const void* xbase, hipStream_t s, bool nt) {
   if (nwu == 0) return hipSuccess;
+  if (mfma && nt && mj <= 64) {
+#define MNT(T, NI) hipLaunchKernelGGL((k_mode_nt<T, NI>), dim3(nwu), dim3(256), 0, s, tasks, jobs, wus, (const T*)xbase); return hipGetLastError();
+    if (dtype == 0) {
+      switch (mj / 16) { case 1: MNT(double, 1) case 2: MNT(double, 2) case 3: MNT(double, 3) case 4: MNT(double, 4) }
+    } else {
+      switch (mj / 16) { case 1: MNT(float, 1) case 2: MNT(float, 2) case 3: MNT(float, 3) case 4: MNT(float, 4) }
+    }
+#undef MNT
+  }
   if (!mfma) {
     if (dtype == 0)
       hipLaunchKernelGGL(k_mode_gen<double>, dim3(nwu), dim3(256), 0, s, tasks, jobs, wus,
@@ -2464,7 +2699,10 @@ hipError_t launch_kritz(const KJob* jobs, int nj, hipStream_t s) {
 hipError_t launch_tiny(const TJob* jobs, int nj, int maxM, int kreq, hipStream_t s) {
   hipLaunchKernelGGL(k_tiny_assemble, dim3((unsigned)(((int64_t)maxM * maxM + 255) / 256), nj), dim3(256),
                      0, s, jobs);
-  hipLaunchKernelGGL(k_tiny_lanczos, dim3(nj), dim3(256), 0, s, jobs, kreq);
+  if (maxM > 1024) return hipErrorInvalidValue;
+  const int64_t vcap = tiny_vcap(maxM, kreq);
+  hipLaunchKernelGGL(k_tiny_lanczos_lds, dim3(nj), dim3(1024), (size_t)(vcap + 1024 * sizeof(double)), s, jobs,
+                     kreq, vcap);
   return hipGetLastError();
 }
 
@@ -2554,6 +2792,8 @@ hipError_t prepare_kernel_attributes() {
       (const void*)k_sandwich<float, 5>, (const void*)k_sandwich<float, 6>,
       (const void*)k_sandwich<float, 7>, (const void*)k_sandwich<float, 8>,
       (const void*)k_sandwich_bf2<2>, (const void*)k_sandwich_bf2<4>,
+      (const void*)k_sandwich_bf2w<2, 2>, (const void*)k_sandwich_bf2w<2, 4>,
+      (const void*)k_sandwich_bf2w<4, 2>, (const void*)k_sandwich_bf2w<4, 4>,
       (const void*)k_sandwich_bf2<6>, (const void*)k_sandwich_bf2<8>,
       (const void*)k_mode<double, 1>, (const void*)k_mode<double, 2>, (const void*)k_mode<double, 3>,
       (const void*)k_mode<double, 4>, (const void*)k_mode<double, 5>, (const void*)k_mode<double, 6>,
@@ -2565,7 +2805,8 @@ hipError_t prepare_kernel_attributes() {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_tiny_lanczos_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kTinyLdsMax);
 }
 
 // ---------------------------------------------------------------- Davidson launchers

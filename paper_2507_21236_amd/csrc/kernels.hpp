@@ -148,7 +148,7 @@ struct KJob {
 
 // ---------------------------------------------------------------- tiny nodes
 // Whole matvec plan of a node whose contractions all use the generic kernels,
-// executed inside one workgroup (see k_tiny_lanczos).
+// executed inside one workgroup (see k_tiny_lanczos_lds).
 // Three-operator product item (one operator per leg) of a three-leg term.
 struct Item3 {
   const void* op[3];

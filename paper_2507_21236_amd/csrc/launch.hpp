@@ -15,8 +15,9 @@ constexpr int kRedBlocks = 256;
 hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const SWItem* items,
                            const int4* wus, int nwu, const void* xbase, hipStream_t s,
                            const SWOut* outs = nullptr);
+// nt: every task has j in {0, 1} and 16 | d2 (register-direct kernel, m_j <= 64)
 hipError_t launch_mode(int dtype, int mj, bool mfma, const MPTask* tasks, const MPJob* jobs,
-                       const int2* wus, int nwu, const void* xbase, hipStream_t s);
+                       const int2* wus, int nwu, const void* xbase, hipStream_t s, bool nt = false);
 // nt: every task has j in {0, 1}, 16 | d2 and 16-aligned free ranges (register-direct kernel, mj <= 64)
 hipError_t launch_gram(int mj, bool mfma, const GRTask* tasks, int ntask, hipStream_t s, bool nt = false);
 hipError_t launch_gram_reduce(const GRReduce* r, int nr, int maxm, hipStream_t s);

@@ -183,8 +183,20 @@ void upload_sw(attn_handle* h, std::vector<SWGroup>& gs, bool by_xcd = false) {
   }
 }
 
+// the register-direct mode kernel applies when every task contracts leg 0 or 1
+// of a tensor whose last leg is a multiple of 16 (m_j <= 64)
+bool mode_nt_ok(const std::vector<MPTask>& ts, bool mfma) {
+  if (!mfma || ts.empty()) return false;
+  for (const MPTask& t : ts) {
+    const int mj = t.j == 0 ? t.d0 : (t.j == 1 ? t.d1 : t.d2);
+    if (t.j > 1 || mj > 64 || t.d2 % 16) return false;
+  }
+  return true;
+}
+
 void upload_mp(attn_handle* h, std::vector<MPGroup>& gs) {
   for (auto& g : gs) {
+    g.nt = mode_nt_ok(g.tasks, g.mfma);
     g.d_tasks = upload(h, g.tasks);
     g.d_jobs = upload(h, g.jobs);
     g.d_wus = upload(h, g.wus);
@@ -591,7 +603,7 @@ void run_sw_mv(attn_handle* h, std::vector<SWGroup>& gs, int dtype, const void* 
 
 void run_mp(std::vector<MPGroup>& gs, int dtype, const void* xbase, hipStream_t s) {
   for (auto& g : gs)
-    HIPCHK(launch_mode(dtype, g.mj, g.mfma, g.d_tasks, g.d_jobs, g.d_wus, (int)g.wus.size(), xbase, s));
+    HIPCHK(launch_mode(dtype, g.mj, g.mfma, g.d_tasks, g.d_jobs, g.d_wus, (int)g.wus.size(), xbase, s, g.nt));
 }
 
 // y <- H_eff(n) x (FP64), combines must be current
@@ -843,6 +855,7 @@ void build_qr_dev(attn_handle* h, int n, int leg, QRDev& Q) {
     Q.d_mj[pass] = upload(h, std::vector<MPJob>{mjb});
     Q.h_mp[pass].mj = mj;
     Q.h_mp[pass].mfma = Q.mmf;
+    Q.mnt = mode_nt_ok({mt}, Q.mmf);
     Q.h_mp[pass].tasks = {mt};
     Q.h_mp[pass].jobs = {mjb};
     Q.h_mp[pass].wus = wus;
@@ -869,6 +882,7 @@ void build_ab_dev(attn_handle* h, int q, int leg, ABDev& A) {
   A.d_mj = upload(h, std::vector<MPJob>{mjb});
   A.h_mp.mj = mj;
   A.h_mp.mfma = A.mmf;
+  A.mnt = mode_nt_ok({mt}, A.mmf);
   A.h_mp.tasks = {mt};
   A.h_mp.jobs = {mjb};
   A.h_mp.wus = wus;
@@ -902,7 +916,7 @@ void qr_node(attn_handle* h, int n, int leg, hipStream_t s) {
     HIPCHK(launch_gram(mj, Q.gmf, Q.d_gt[pass], Q.nfc, s, Q.gnt));
     HIPCHK(launch_gram_reduce(Q.d_gr, 1, mj, s));
     HIPCHK(launch_chol_inv(G, mj, R[pass], Rinv, pass == 0 ? 1 : 0, Q.rows, h->d_st, s));
-    HIPCHK(launch_mode(0, mj, Q.mmf, Q.d_mt[pass], Q.d_mj[pass], Q.d_wus, Q.nwus, nullptr, s));
+    HIPCHK(launch_mode(0, mj, Q.mmf, Q.d_mt[pass], Q.d_mj[pass], Q.d_wus, Q.nwus, nullptr, s, Q.mnt));
   }
   // passes write tmp, T, tmp: the result is in tmp
   HIPCHK(hipMemcpyAsync(T, h->d_tmp, Q.Msz * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -915,7 +929,7 @@ void qr_node(attn_handle* h, int n, int leg, hipStream_t s) {
 void absorb(attn_handle* h, int q, int leg, hipStream_t s) {
   ABDev& A = h->ab[leg][q];
   if (!A.present) throw StatusFail{ATTN_ERR_STATE, "internal: no absorb plan for this leg"};
-  HIPCHK(launch_mode(0, A.mj, A.mmf, A.d_mt, A.d_mj, A.d_wus, A.nwus, nullptr, s));
+  HIPCHK(launch_mode(0, A.mj, A.mmf, A.d_mt, A.d_mj, A.d_wus, A.nwus, nullptr, s, A.mnt));
   HIPCHK(hipMemcpyAsync(h->d_T + h->T_off[q], h->d_tmp2, A.Msz * sizeof(double), hipMemcpyDeviceToDevice, s));
 }
 

@@ -55,6 +55,7 @@ struct SWGroup {
 struct MPGroup {
   int mj = 0;
   bool mfma = false;
+  bool nt = false;   // register-direct kernel
   std::vector<MPTask> tasks;
   std::vector<MPJob> jobs;
   std::vector<int2> wus;
@@ -115,7 +116,7 @@ struct EnvDev {
 struct QRDev {
   bool present = false;
   int mj = 0, nfc = 0, nwus = 0;
-  bool gmf = false, mmf = false, gnt = false;
+  bool gmf = false, mmf = false, gnt = false, mnt = false;
   int64_t rows = 0, Msz = 0;
   GRTask* d_gt[3] = {nullptr, nullptr, nullptr};
   GRReduce* d_gr = nullptr;
@@ -131,7 +132,7 @@ struct QRDev {
 struct ABDev {
   bool present = false;
   int mj = 0, nwus = 0;
-  bool mmf = false;
+  bool mmf = false, mnt = false;
   int64_t Msz = 0;
   MPTask* d_mt = nullptr;
   MPJob* d_mj = nullptr;
