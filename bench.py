@@ -43,7 +43,16 @@ PEAK_FP64 = 78.6   # TFLOP/s, MI355X dense FP64 (vector and matrix)
 # products per useful product, so its useful-flop ceiling is a third of 2.5 PF
 PEAKS = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0 / 3}
 KERNELS = {"f64": "k_sandwich<double,4>", "f32": "k_sandwich<float,4>",
-           "bf16x2": "k_sandwich_bf2<4>"}
+           "bf16x2": "k_sandwich_bf2w<4,4>"}
+# HBM bytes per launch of the FP64 contraction kernel at legs of dimension 64,
+# averaged like the live timing over the 620 matvec launches of a sweep of
+# this workload (440 launches of 3072 workgroups, 160 of 2176, 20 at the root):
+# rocprofv3 --pmc FETCH_SIZE (x 2) and WRITE_SIZE (x 1) on
+# `bench.py --traffic-probe`, the factors read off a plain 1 GiB device copy
+# (profiles/k_sandwich_f64_legs64_hbm_traffic.md).  The writes are the
+# kernel's partial outputs (one per item chunk); the reads are X and the
+# operator blocks.  Valid for the kernel as measured: None once it changes.
+TRAFFIC_F64 = {"read": 111.0e6, "write": 90.0e6}
 
 
 def cpu_baseline(problem, sample_matvecs=3):
@@ -241,6 +250,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run five plain 1 GiB device-to-device copies (HBM counter calibration)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only apply H_eff once at every node with two legs of dimension 64 (the "
+                         "launches of the dominant kernel in a sweep), on a stream of its own, "
+                         "for HBM counter runs")
     ap.add_argument("--learned-tol", type=float, default=1e-5,
                     help="Davidson residual tolerance of the learned-form comparison (0 to skip)")
     ap.add_argument("--batch-sweeps", type=int, default=2,
@@ -276,6 +289,24 @@ def main():
     print(f"[bench] build {time.time() - t0:.2f} s, effective-operator storage "
           f"{a.env_bytes / 1e9:.2f} GB", file=sys.stderr, flush=True)
     prec = {"f64": ATTN_F64, "f32": ATTN_F32, "bf16x2": ATTN_BF16X2}
+    if args.traffic_probe:
+        a.init_state()
+        side = torch.cuda.Stream()
+        gen = torch.Generator(device="cuda").manual_seed(0)
+        nodes = [n for n in range(a.n_nodes) if tuple(a.node_info(n)[0][:2]) == (64, 64)]
+        for n in nodes:
+            a.move_center(n)
+            dims = a.node_info(n)[0]
+            x = torch.randn(int(dims[0]) * int(dims[1]) * int(dims[2]), dtype=torch.float64,
+                            device="cuda", generator=gen)
+            y = torch.empty_like(x)
+            torch.cuda.synchronize()
+            a.heff_apply(n, x, y, stream=side.cuda_stream)
+            torch.cuda.synchronize()
+        print(f"[bench] traffic probe: H_eff applied once at {len(nodes)} nodes {nodes}",
+              file=sys.stderr, flush=True)
+        a.close()
+        return
 
     def run(form, steps, warmup):
         opts = solver_opts(krylov_k=20, precision=prec[form])
@@ -339,7 +370,9 @@ def main():
                    "precision": args.precision},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": None,
+                     "traffic": (TRAFFIC_F64["read"] + TRAFFIC_F64["write"]
+                                 if args.precision == "f64" else None),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "kernel": KERNELS[args.precision] + " (two-leg terms and local operators, "
                                "legs of dimension 64)",
                      "launches": n_sw, "kernel_ms": round(ms_sw, 3)},

@@ -20,6 +20,15 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with "
                       "`python paper_2507_21236_amd/build.py` (hipcc, gfx950)")
 
+# PyTorch ships its own HIP runtime (same soname, loaded by its own path).  If
+# libattn.so came first it would bind to the system runtime and torch would
+# then load a second one into the process; importing torch first makes the
+# library bind to torch's runtime, so device pointers and streams are shared.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 ATTN_OK = 0

@@ -142,7 +142,7 @@ void add_sandwich(attn_batch* b, attn_handle* h, int n, const void* x, attn_batc
     const int64_t units = mf ? (int64_t)ns * ((ma / 16 + 3) / 4) : (int64_t)ns * ((ma * mb + 255) / 256);
     int64_t c = target_for(b, ma, mb) / std::max<int64_t>(1, units);
     c = std::max<int64_t>(1, std::min<int64_t>(c, (int64_t)its.size()));
-    const int nch = (int)std::min<int64_t>(c, 32);
+    const int nch = (int)std::min<int64_t>(c, chunk_cap(Msz));
     for (int ci = 0; ci < nch; ci++) {
       const size_t i0 = its.size() * ci / nch, i1 = its.size() * (ci + 1) / nch;
       if (i1 == i0) continue;
@@ -173,6 +173,7 @@ void add_sandwich(attn_batch* b, attn_handle* h, int n, const void* x, attn_batc
       } else {
         for (int s = 0; s < ns; s++)
           for (int e = 0; e < ma * mb; e += 256) m.sw_wus.push_back(make_int4(ti, s, e, 0));
+        m.sw_lds = std::max(m.sw_lds, gen_slice_lds(ma, mb, esz));
       }
       srcs.push_back({h->d_part + part_used, trans ? 1 : 0, 0});
       part_used += Msz;

@@ -191,13 +191,74 @@ __device__ __forceinline__ void sandwich_gen_elem(const SWTask& t, const SWItem*
   else *Y = acc;
 }
 
+// Small slices (ma mb <= 256, one work unit per slice): the slice, the stage-1
+// product and each item's blocks are staged in LDS, so an item costs a few
+// LDS passes instead of chains of dependent global loads.  Same arithmetic
+// and summation order as sandwich_gen_elem (a zero entry of B adds a zero).
+template <typename T>
+__device__ __forceinline__ void sandwich_gen_slice(const SWTask& t, const SWItem* __restrict__ items, int s,
+                                                   const T* __restrict__ xbase, T* lds) {
+  const int ma = t.ma, mb = t.mb, n = ma * mb;
+  T* Xs = lds;
+  T* T1 = Xs + n;
+  T* As = T1 + n;
+  T* Bs = As + ma * ma;
+  const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)s * t.xs_slice;
+  const int e = threadIdx.x;
+  const bool mine = e < n;
+  const int ap = mine ? e / mb : 0, bp = mine ? e - ap * mb : 0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const int a = q / mb, b = q - a * mb;
+    Xs[q] = X[(int64_t)a * t.xs_row + b];
+  }
+  T acc = 0;
+  for (int it = t.item0; it < t.item0 + t.nitem; it++) {
+    const T* A = (const T*)items[it].A;
+    const T* B = (const T*)items[it].B;
+    __syncthreads();
+    if (A)
+      for (int q = threadIdx.x; q < ma * ma; q += blockDim.x) As[q] = A[q];
+    if (B)
+      for (int q = threadIdx.x; q < mb * mb; q += blockDim.x) Bs[q] = B[q];
+    __syncthreads();
+    if (mine) {   // stage 1: T1(ap, bp) = sum_a A(a, ap) X(a, bp)
+      T col = 0;
+      if (A) {
+        for (int a = 0; a < ma; a++) col += As[a * ma + ap] * Xs[a * mb + bp];
+      } else {
+        col = Xs[ap * mb + bp];
+      }
+      T1[e] = col;
+    }
+    __syncthreads();
+    if (mine) {   // stage 2: sum_b B(b, bp) T1(ap, b)
+      T sum = 0;
+      if (B) {
+        for (int b = 0; b < mb; b++) sum += Bs[b * mb + bp] * T1[ap * mb + b];
+      } else {
+        sum = T1[ap * mb + bp];
+      }
+      acc += (T)items[it].coef * sum;
+    }
+  }
+  if (!mine) return;
+  T* Y = (T*)t.y + (int64_t)s * t.ys_slice + (int64_t)ap * t.ys_row + bp;
+  if (t.accumulate) *Y += acc;
+  else *Y = acc;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_sandwich_gen(const SWTask* __restrict__ tasks,
                                                       const SWItem* __restrict__ items,
                                                       const int4* __restrict__ wus,
                                                       const T* __restrict__ xbase) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int4 wu = wus[blockIdx.x];
-  sandwich_gen_elem<T>(tasks[wu.x], items, wu.y, wu.z + threadIdx.x, xbase);
+  const SWTask& t = tasks[wu.x];
+  if (gen_slice_lds(t.ma, t.mb, sizeof(T)))
+    sandwich_gen_slice<T>(t, items, wu.y, xbase, reinterpret_cast<T*>(smem_raw));
+  else
+    sandwich_gen_elem<T>(t, items, wu.y, wu.z + threadIdx.x, xbase);
 }
 
 // ============================================================================ split-BF16 sandwich
@@ -663,7 +724,12 @@ __global__ __launch_bounds__(256) void k_batch_sandwich(const SWTask* __restrict
   const int4 wu = wus[blockIdx.x];
   const SWTask& t = tasks[wu.x];
   switch (wu.w) {
-    case 0: sandwich_gen_elem<T>(t, items, wu.y, wu.z + threadIdx.x, nullptr); break;
+    case 0:
+      if (gen_slice_lds(t.ma, t.mb, sizeof(T)))
+        sandwich_gen_slice<T>(t, items, wu.y, nullptr, reinterpret_cast<T*>(smem_raw));
+      else
+        sandwich_gen_elem<T>(t, items, wu.y, wu.z + threadIdx.x, nullptr);
+      break;
     case 1: sandwich_mfma<T, 1>(t, items, wu, nullptr, smem_raw); break;
     case 2: sandwich_mfma<T, 2>(t, items, wu, nullptr, smem_raw); break;
     case 3: sandwich_mfma<T, 3>(t, items, wu, nullptr, smem_raw); break;
@@ -906,6 +972,7 @@ __global__ __launch_bounds__(256) void k_reduce_out(const RDSrc* __restrict__ sr
   const int64_t r = rem / mp, p = rem - r * mp;
   const int64_t et = p * ml * mr + l * mr + r;
   double acc = 0;
+#pragma unroll 8
   for (int k = 0; k < nsrc; k++) {
     const TI* src = (const TI*)srcs[k].p;
     acc += (double)(srcs[k].layout ? src[et] : src[e]);
@@ -1041,6 +1108,62 @@ __global__ __launch_bounds__(256) void k_kalpha(const KJob* __restrict__ jobs, i
   }
 }
 
+// Block sums of C per-thread values at once, each in block_sum's order (wave
+// shuffle tree, then the four waves in order); the sum of value q is returned
+// in thread q.  red holds 4 C doubles.
+template <int C>
+__device__ __forceinline__ double block_sums(double (&v)[C], double* red) {
+#pragma unroll
+  for (int q = 0; q < C; q++)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < C; q++) red[wave * C + q] = v[q];
+  __syncthreads();
+  const int q = threadIdx.x < C ? threadIdx.x : 0;
+  return red[q] + red[C + q] + red[2 * C + q] + red[3 * C + q];
+}
+
+constexpr int kDotChunk = 8;
+
+// out[i * kRedBlocks + b] = this block's partial dot V_i . w for i < nv, eight
+// vectors per pass over the block's elements (same per-thread order as one
+// vector at a time).
+__device__ __forceinline__ void block_dots(const KJob& J, const double* __restrict__ w, int nv, double* out,
+                                           double* red) {
+  const int64_t n = J.n;
+  const int b = blockIdx.x;
+  for (int i0 = 0; i0 < nv; i0 += kDotChunk) {
+    double acc[kDotChunk];
+#pragma unroll
+    for (int q = 0; q < kDotChunk; q++) acc[q] = 0.0;
+    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
+      const double we = w[e];
+#pragma unroll
+      for (int q = 0; q < kDotChunk; q++)
+        if (i0 + q < nv) acc[q] += J.V[(int64_t)(i0 + q) * n + e] * we;
+    }
+    const double s = block_sums<kDotChunk>(acc, red);
+    if (threadIdx.x < kDotChunk && i0 + (int)threadIdx.x < nv) out[(i0 + threadIdx.x) * kRedBlocks + b] = s;
+  }
+}
+
+// hs[i] = sum of the kRedBlocks partials p[i * kRedBlocks + .] for i < nv
+// (sum_partials of each, eight at a time)
+__device__ __forceinline__ void sums_of_partials(const double* __restrict__ p, int nv, double* hs, double* red) {
+  for (int i0 = 0; i0 < nv; i0 += kDotChunk) {
+    double v[kDotChunk];
+#pragma unroll
+    for (int q = 0; q < kDotChunk; q++) v[q] = i0 + q < nv ? p[(i0 + q) * kRedBlocks + threadIdx.x] : 0.0;
+    const double s = block_sums<kDotChunk>(v, red);
+    if (threadIdx.x < kDotChunk && i0 + (int)threadIdx.x < nv) hs[i0 + threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
 // alpha_j = sum P0; w -= alpha_j v_j + beta_{j-1} v_{j-1}; P1 = partial dots V[0..j] . w
 __global__ __launch_bounds__(256) void k_kupdate(const KJob* __restrict__ jobs, int j) {
   __shared__ double red[4];
@@ -1064,15 +1187,8 @@ __global__ __launch_bounds__(256) void k_kupdate(const KJob* __restrict__ jobs, 
     w[e] = x;
   }
   // the same thread touches the same elements below: no barrier needed for w
-  double* out = parea(J, 1);
-  for (int i = 0; i <= j; i++) {
-    const double* v = J.V + (int64_t)i * n;
-    double acc = 0;
-    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
-      acc += v[e] * w[e];
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) out[i * kRedBlocks + b] = s;
-  }
+  __shared__ double red8[4 * kDotChunk];
+  block_dots(J, w, j + 1, parea(J, 1), red8);
 }
 
 // classical Gram-Schmidt pass against V[0..j]: h = sums of P(pin); w -= sum h_i V_i;
@@ -1086,12 +1202,8 @@ __global__ __launch_bounds__(256) void k_kortho(const KJob* __restrict__ jobs, i
   const int nv = j + 1;
   const int64_t n = J.n;
   double* w = J.w;
-  const double* pi = parea(J, pin);
-  for (int i = 0; i < nv; i++) {
-    const double hv = sum_partials(pi + i * kRedBlocks, red);
-    if (threadIdx.x == 0) hs[i] = hv;
-  }
-  __syncthreads();
+  __shared__ double red8[4 * kDotChunk];
+  sums_of_partials(parea(J, pin), nv, hs, red8);
   const int b = blockIdx.x;
   for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
     double x = w[e];
@@ -1107,14 +1219,7 @@ __global__ __launch_bounds__(256) void k_kortho(const KJob* __restrict__ jobs, i
     if (threadIdx.x == 0) po[b] = s;
     return;
   }
-  for (int i = 0; i < nv; i++) {
-    const double* v = J.V + (int64_t)i * n;
-    double acc = 0;
-    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
-      acc += v[e] * w[e];
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) po[i * kRedBlocks + b] = s;
-  }
+  block_dots(J, w, nv, po, red8);
 }
 
 // beta_j = sqrt(sum P3); breakdown test; V_{j+1} = w / beta_j (and the copies)
@@ -1151,37 +1256,34 @@ __global__ __launch_bounds__(256) void k_kbeta(const KJob* __restrict__ jobs, in
 //  * eigenvector by inverse iteration with T - theta I (Gaussian elimination
 //    with partial pivoting on the tridiagonal system, three iterations);
 //  * normalised, sign fixed as described at the end of the kernel.
+constexpr int kTriLds = 11 * 64;
+constexpr size_t kTinyLdsMax = 144 * 1024;   // dynamic LDS of the tiny-node Lanczos kernel
+
 // Number of eigenvalues of the symmetric tridiagonal (a, b) below x, from the
 // signs of the leading principal minors p_i = (a_i - x) p_{i-1} - b_{i-1}^2
 // p_{i-2} (a Sturm sequence): every negative ratio p_i / p_{i-1} counts one
 // eigenvalue, and a zero minor takes the sign of the one before it.  There is
-// no division, so a step costs one dependent FMA; the pair (p_{i-1}, p_i) is
-// rescaled by a power of two whenever it leaves [2^-400, 2^400], which changes
-// no sign and no ratio.  b2 holds the squares b_i^2.
-constexpr int kTriLds = 10 * 64;
-constexpr size_t kTinyLdsMax = 144 * 1024;   // dynamic LDS of the tiny-node Lanczos kernel
-
+// no division and no branch on data, so a step costs one dependent FMA.  The
+// caller scales a, b and x by a power of two (exact) so that |a_i - x| <= 2
+// and b_i^2 <= 1: the minors then grow by less than 2^2 per step, and every
+// eighth step the pair (p_{i-1}, p_i) is brought back into [2^-200, 2^200]
+// by a power of two, which changes no sign and no ratio.  b2 holds b_i^2.
 __device__ int sturm_count(const double* a, const double* b2, int k, double x) {
   double pm = 1.0, pc = a[0] - x;
-  bool neg = pc < 0.0;   // sign carried by the last nonzero minor
+  int neg = pc < 0.0;   // sign carried by the last nonzero minor
   int cnt = neg;
-#pragma unroll 8
   for (int i = 1; i < k; i++) {
     const double pn = (a[i] - x) * pc - b2[i - 1] * pm;
-    if (pn != 0.0) {
-      const bool nn = pn < 0.0;
-      cnt += nn != neg;
-      neg = nn;
-    }
+    const int nn = pn < 0.0, nz = pn != 0.0;
+    cnt += nz & (nn ^ neg);
+    neg = nz ? nn : neg;
     pm = pc;
     pc = pn;
-    const double m = fmax(fabs(pm), fabs(pc));
-    if (m > 0x1p400) {
-      pm *= 0x1p-400;
-      pc *= 0x1p-400;
-    } else if (m < 0x1p-400) {
-      pm *= 0x1p400;
-      pc *= 0x1p400;
+    if ((i & 7) == 0) {
+      const double m = fmax(fabs(pm), fabs(pc));
+      const double sc = m > 0x1p200 ? 0x1p-200 : (m < 0x1p-200 ? 0x1p200 : 1.0);
+      pm *= sc;
+      pc *= sc;
     }
   }
   return cnt;
@@ -1205,12 +1307,9 @@ __device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restr
   double* f = lds + 448;
   double* rd = lds + 512;
   double* sw = lds + 576;
+  double* as = lds + 640;   // a scaled for the Sturm counts
   if (lane < k) a[lane] = st->alpha[lane];
-  if (lane + 1 < k) {
-    const double bl = st->beta[lane];
-    b[lane] = bl;
-    b2[lane] = bl * bl;
-  }
+  if (lane + 1 < k) b[lane] = st->beta[lane];
   wave_sync();
   double lo = a[0], hi = a[0], nrm = 0;
   for (int i = 0; i < k; i++) {
@@ -1219,11 +1318,21 @@ __device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restr
     hi = fmax(hi, a[i] + r);
     nrm = fmax(nrm, fabs(a[i]) + r);
   }
+  // power-of-two scale sg with nrm * sg <= 1 for the Sturm counts (exact)
+  int ex = 0;
+  (void)frexp(nrm, &ex);
+  const double sg = (nrm > 0.0 && isfinite(nrm)) ? ldexp(1.0, -ex) : 1.0;
+  if (lane < k) as[lane] = a[lane] * sg;
+  if (lane + 1 < k) {
+    const double bs = b[lane] * sg;
+    b2[lane] = bs * bs;
+  }
+  wave_sync();
   // multisection: 64 Sturm counts per step, bracket [lo, hi] keeps lambda_min
   for (int it = 0; it < 40; it++) {
     const double w = hi - lo;
     const double x = lo + w * (double)(lane + 1) / 65.0;
-    const bool has = (x > lo && x < hi) ? sturm_count(a, b2, k, x) >= 1 : (x >= hi);
+    const bool has = (x > lo && x < hi) ? sturm_count(as, b2, k, x * sg) >= 1 : (x >= hi);
     const unsigned long long m = __ballot(has);
     const int first = m ? __ffsll((long long)m) - 1 : 64;
     const double nhi = first < 64 ? lo + w * (double)(first + 1) / 65.0 : hi;
@@ -1237,7 +1346,7 @@ __device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restr
   for (int it = 0; it < 64; it++) {
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
-    if (sturm_count(a, b2, k, mid) >= 1) hi = mid;
+    if (sturm_count(as, b2, k, mid * sg) >= 1) hi = mid;
     else lo = mid;
   }
   const double theta = hi;
@@ -1363,10 +1472,12 @@ __global__ __launch_bounds__(256) void k_tiny_assemble(const TJob* __restrict__ 
   H[e] = acc;
 }
 
-// Tiny-node Lanczos: one workgroup of 1024 threads per job, one thread per
-// vector entry (M <= 1024).  The dense matvec splits the columns over
+// Tiny-node Lanczos: one workgroup per job, one thread per vector entry
+// (M <= blockDim.x <= 1024).  The dense matvec splits the columns over
 // S = min(M, 1024 / M) slices whose partial sums are added in a fixed order;
-// every Gram-Schmidt dot product is taken by one wavefront, 16 at a time.
+// every Gram-Schmidt dot product is taken by one wavefront.  Block sums add
+// the per-wave partials in wave order, and waves past M contribute zeros, so
+// the results do not depend on the workgroup size.
 // Dynamic LDS: partial sums [1024], then V [k][M] and w [M] when they fit in
 // the vcap bytes that follow (else V and w stay in the job's global buffers;
 // the arithmetic is the same either way).
@@ -1397,21 +1508,30 @@ __global__ __launch_bounds__(1024) void k_tiny_lanczos_lds(const TJob* __restric
   double* V = in_lds ? part + 1024 : J.V;
   double* w = in_lds ? V + (int64_t)k * M : J.w;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int nthr = blockDim.x, nw = nthr >> 6;   // M <= nthr
   const int S = max(1, min(M, 1024 / M));
   const bool mine = t < M;
   if (t == 0) { st->kmax = k; st->keff = 1; st->stop = 0; st->status = 0; }
   const double t0 = mine ? T[t] : 0.0;
-  const double nrm = sqrt(block_sum_waves(t0 * t0, red, 16));
+  const double nrm = sqrt(block_sum_waves(t0 * t0, red, nw));
   if (mine) V[t] = t0 / nrm;
   __syncthreads();
   double beta_prev = 0, amax = 0;
   int keff = 1;
   for (int j = 0; j < k; j++) {
     const double* x = V + (int64_t)j * M;
-    if (t < S * M) {   // w = H x, slice sl of the columns
-      const int r = t % M, sl = t / M;
+    for (int q = t; q < S * M; q += nthr) {   // w = H x, slice sl of the columns
+      const int r = q % M, sl = q / M;
       double acc = 0;
-      for (int c = sl; c < M; c += S) acc += H[(int64_t)c * M + r] * x[c];
+      int c = sl;
+      for (; c + 7 * S < M; c += 8 * S) {   // eight loads in flight
+        double hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) hv[u] = H[(int64_t)(c + u * S) * M + r];
+#pragma unroll
+        for (int u = 0; u < 8; u++) acc += hv[u] * x[c + u * S];
+      }
+      for (; c < M; c += S) acc += H[(int64_t)c * M + r] * x[c];
       part[sl * M + r] = acc;
     }
     __syncthreads();
@@ -1420,7 +1540,7 @@ __global__ __launch_bounds__(1024) void k_tiny_lanczos_lds(const TJob* __restric
       for (int sl = 0; sl < S; sl++) wv += part[sl * M + t];
       xv = x[t];
     }
-    const double a = block_sum_waves(xv * wv, red, 16);
+    const double a = block_sum_waves(xv * wv, red, nw);
     if (t == 0) st->alpha[j] = a;
     amax = fmax(amax, fabs(a));
     if (j == k - 1) break;
@@ -1431,7 +1551,7 @@ __global__ __launch_bounds__(1024) void k_tiny_lanczos_lds(const TJob* __restric
     }
     __syncthreads();
     for (int pass = 0; pass < 2; pass++) {
-      for (int i = wave; i <= j; i += 16) {   // hs[i] = V_i . w
+      for (int i = wave; i <= j; i += nw) {   // hs[i] = V_i . w
         double d = 0;
         for (int e = lane; e < M; e += 64) d += V[(int64_t)i * M + e] * w[e];
 #pragma unroll
@@ -1445,7 +1565,7 @@ __global__ __launch_bounds__(1024) void k_tiny_lanczos_lds(const TJob* __restric
       }
       __syncthreads();
     }
-    const double b = sqrt(block_sum_waves(wv * wv, red, 16));
+    const double b = sqrt(block_sum_waves(wv * wv, red, nw));
     if (!(b > 1e-14 * amax)) break;
     if (t == 0) st->beta[j] = b;
     beta_prev = b;
@@ -1462,7 +1582,7 @@ __global__ __launch_bounds__(1024) void k_tiny_lanczos_lds(const TJob* __restric
   double u = 0;
   if (mine)
     for (int i = 0; i < keff; i++) u += hs[i] * V[(int64_t)i * M + t];
-  const double nr = sqrt(block_sum_waves(u * u, red, 16));
+  const double nr = sqrt(block_sum_waves(u * u, red, nw));
   if (mine) T[t] = u / nr;
   if (t == 0 && !(nr > 0 && isfinite(nr))) st->status = 1;
 }
@@ -2458,8 +2578,8 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
   const bool mf = (ma % 16 == 0) && (mb % 16 == 0) && ma <= 128 && mb <= 128;
   if (dtype == 0) {
     if (!mf) {
-      hipLaunchKernelGGL(k_sandwich_gen<double>, dim3(nwu), dim3(256), 0, s, tasks, items, wus,
-                         (const double*)xbase);
+      hipLaunchKernelGGL(k_sandwich_gen<double>, dim3(nwu), dim3(256), gen_slice_lds(ma, mb, 8), s, tasks, items,
+                         wus, (const double*)xbase);
       return hipGetLastError();
     }
     switch (mb / 16) {
@@ -2474,8 +2594,8 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
     }
   } else {
     if (!mf) {
-      hipLaunchKernelGGL(k_sandwich_gen<float>, dim3(nwu), dim3(256), 0, s, tasks, items, wus,
-                         (const float*)xbase);
+      hipLaunchKernelGGL(k_sandwich_gen<float>, dim3(nwu), dim3(256), gen_slice_lds(ma, mb, 4), s, tasks, items,
+                         wus, (const float*)xbase);
       return hipGetLastError();
     }
     switch (mb / 16) {
@@ -2701,7 +2821,10 @@ hipError_t launch_tiny(const TJob* jobs, int nj, int maxM, int kreq, hipStream_t
                      0, s, jobs);
   if (maxM > 1024) return hipErrorInvalidValue;
   const int64_t vcap = tiny_vcap(maxM, kreq);
-  hipLaunchKernelGGL(k_tiny_lanczos_lds, dim3(nj), dim3(1024), (size_t)(vcap + 1024 * sizeof(double)), s, jobs,
+  // enough threads for one per entry and for the matvec's S x M partial sums
+  const int pairs = std::min(maxM * maxM, 1024);
+  const int nthr = std::max(64, std::min(1024, (std::max(pairs, maxM) + 63) / 64 * 64));
+  hipLaunchKernelGGL(k_tiny_lanczos_lds, dim3(nj), dim3(nthr), (size_t)(vcap + 1024 * sizeof(double)), s, jobs,
                      kreq, vcap);
   return hipGetLastError();
 }

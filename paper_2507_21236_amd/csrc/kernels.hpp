@@ -88,6 +88,16 @@ struct CBTask {
 
 // ---------------------------------------------------------------- reduction of partial outputs
 // y[l][r][p] = sum_k src_k, src_k in layout 0 ([l][r][p]) or 1 ([p][l][r])
+// LDS bytes of the slice form of the generic sandwich (slice, stage-1
+// product and one item's blocks), or 0 where the per-element form is used
+// (more than 256 entries per slice, or more than 32 KiB).  The work units of
+// a generic group are one per 256 entries of a slice either way.
+constexpr size_t gen_slice_lds(int ma, int mb, size_t esz) {
+  return (ma * mb <= 256 && (size_t)(2 * ma * mb + ma * ma + mb * mb) * esz <= 32768)
+             ? (size_t)(2 * ma * mb + ma * ma + mb * mb) * esz
+             : 0;
+}
+
 struct RDSrc {
   const void* p;
   int32_t layout;

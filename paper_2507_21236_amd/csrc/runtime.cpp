@@ -203,11 +203,11 @@ void upload_mp(attn_handle* h, std::vector<MPGroup>& gs) {
   }
 }
 
-int chunks_for(size_t nitems, int64_t units_per_chunk) {
+int chunks_for(size_t nitems, int64_t units_per_chunk, int64_t Msz) {
   // aim at roughly 1024 workgroups for the whole launch
   int64_t c = (int64_t)1024 / std::max<int64_t>(1, units_per_chunk);
   c = std::max<int64_t>(1, std::min<int64_t>(c, (int64_t)nitems));
-  c = std::min<int64_t>(c, 32);
+  c = std::min<int64_t>(c, chunk_cap(Msz));
   return (int)c;
 }
 
@@ -238,7 +238,7 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
     slice_geom(sp, dm, ma, mb, ns, sl, row);
     const int64_t units = sw_mfma(ma, mb) ? (int64_t)ns * ((ma / 16 + 3) / 4)
                                           : (int64_t)ns * ((ma * mb + 255) / 256);
-    const int nch = chunks_for(its.size(), units);
+    const int nch = chunks_for(its.size(), units, Msz);
     SWGroup& g = group_for(D.sw, ma, mb);
     for (int c = 0; c < nch; c++) {
       const size_t i0 = its.size() * c / nch, i1 = its.size() * (c + 1) / nch;
@@ -1232,7 +1232,7 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
         int64_t sl, row;
         slice_geom(sp, dm, ma, mb, ns, sl, row);
         const int64_t units = sw_mfma(ma, mb) ? (int64_t)ns * ((ma / 16 + 3) / 4) : (int64_t)ns * ((ma * mb + 255) / 256);
-        nparts += chunks_for(cnt, units);
+        nparts += chunks_for(cnt, units, Msz);
       }
       part_need = std::max(part_need, nparts * Msz);
       int64_t cn = 0;

@@ -246,6 +246,12 @@ T* upload(attn_handle* h, const std::vector<T>& v) {
 double* block_ptr(attn_handle* h, const BRef& b, double* comb_base, const std::vector<int64_t>& comb_off);
 void slice_geom(int spect, const int* dm, int& ma, int& mb, int& ns, int64_t& sl, int64_t& row);
 bool sw_mfma(int ma, int mb);
+// Most item chunks (workgroup sets with their own partial output) of one
+// sandwich group of a matvec: small nodes get more, so that their few slices
+// still spread over the chip.
+inline int64_t chunk_cap(int64_t Msz) {
+  return Msz >= 65536 ? 32 : std::min<int64_t>(128, std::max<int64_t>(32, ((int64_t)1 << 19) / Msz));
+}
 void run_comb(CBPlan& P, hipStream_t s);
 void* to_mirror(attn_handle* h, const void* p, int fmt);
 void ensure_lowp(attn_handle* h, int dtype);

@@ -131,3 +131,11 @@ def test_batch_create_rejects_bad_input_on_host():
     with pytest.raises(AttnError) as e:
         _lib.attn_batch_create([a.h, a.h], 20)
     assert e.value.code in (-1, -8)
+
+
+def test_binding_loads_torch_before_library():
+    # torch carries its own HIP runtime; the binding imports it before loading
+    # libattn.so so that one runtime serves both in a process
+    import sys
+    assert "torch" in sys.modules
+    assert _lib.LIB_PATH.endswith("libattn.so")
