@@ -635,44 +635,48 @@ __global__ __launch_bounds__(256) void k_mode(const MPTask* __restrict__ tasks,
 // Mode product for contracted leg j = 0 or 1 with 16 | d2: a 16-wide tile of
 // the free index is contiguous in memory for every i', so both operands are
 // loaded straight into registers (no LDS, no barriers).  wu = (task, 64-wide
-// free tile); wave w owns free indices [16 w, +16) and all m_j rows.
-template <typename T, int NI>
+// free block); the block is split over blockIdx.y into QS sub-blocks, and a
+// workgroup's four waves take (4 / QS) tiles of 16 free indices times QS
+// groups of output rows (QS = 1: each wave all m_j rows of its own tile).
+// Every output entry sums its products in the same order whatever QS is.
+template <typename T, int NI, int QS>
 __global__ __launch_bounds__(256) void k_mode_nt(const MPTask* __restrict__ tasks, const MPJob* __restrict__ jobs,
                                                  const int2* __restrict__ wus, const T* __restrict__ xbase) {
   typedef typename V4<T>::type v4;
-  constexpr int mj = 16 * NI;
+  constexpr int mj = 16 * NI, NQ = NI / QS;   // output row blocks per wave
   const int2 wu = wus[blockIdx.x];
   const MPTask& t = tasks[wu.x];
   const int j = t.j, d1 = t.d1, d2 = t.d2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, l4 = lane >> 4;
+  const int tile = (4 / QS) * blockIdx.y + wave / QS, q0 = (wave % QS) * NQ;
   const int64_t F = (int64_t)t.d0 * d1 * d2 / mj;
-  const int64_t f = (int64_t)wu.y * 64 + 16 * wave + l16;
+  const int64_t f = (int64_t)wu.y * 64 + 16 * tile + l16;
   // (i, f) -> address; the tile's f share one a-row when j = 1
   int64_t fo, fs;   // address = fo + i * fs
   if (j == 0) { fo = f; fs = F; }
   else { const int64_t a = f / d2, c = f - a * d2; fo = a * d1 * d2 + c; fs = d2; }
-  v4 acc[NI];
+  v4 acc[NQ];
 #pragma unroll
-  for (int q = 0; q < NI; q++) acc[q] = v4{0, 0, 0, 0};
+  for (int q = 0; q < NQ; q++) acc[q] = v4{0, 0, 0, 0};
   for (int jb = t.job0; jb < t.job0 + t.njob; jb++) {
     const T* in = jobs[jb].in ? (const T*)jobs[jb].in : xbase;
-    const T* A = (const T*)jobs[jb].A + l16;
+    const T* A = (const T*)jobs[jb].A + 16 * q0 + l16;
     const T coef = (T)jobs[jb].coef;
 #pragma unroll 4
     for (int k0 = 0; k0 < mj; k0 += 4) {
       const T bop = in[fo + (int64_t)(k0 + l4) * fs] * coef;
       const T* Ak = A + (int64_t)(k0 + l4) * mj;
 #pragma unroll
-      for (int q = 0; q < NI; q++) acc[q] = mfma16(Ak[16 * q], bop, acc[q]);
+      for (int q = 0; q < NQ; q++) acc[q] = mfma16(Ak[16 * q], bop, acc[q]);
     }
   }
   T* out = (T*)t.out;
 #pragma unroll
-  for (int q = 0; q < NI; q++)
+  for (int q = 0; q < NQ; q++)
 #pragma unroll
     for (int i = 0; i < 4; i++) {
-      const int64_t ad = fo + (int64_t)(16 * q + drow<T>(l4, i)) * fs;
+      const int64_t ad = fo + (int64_t)(16 * (q0 + q) + drow<T>(l4, i)) * fs;
       if (t.accumulate) out[ad] += acc[q][i];
       else out[ad] = acc[q][i];
     }
@@ -2625,7 +2629,14 @@ hipError_t launch_mode(int dtype, int mj, bool mfma, const MPTask* tasks, const 
                        const int2* wus, int nwu, const void* xbase, hipStream_t s, bool nt) {
   if (nwu == 0) return hipSuccess;
   if (mfma && nt && mj <= 64) {
-#define MNT(T, NI) hipLaunchKernelGGL((k_mode_nt<T, NI>), dim3(nwu), dim3(256), 0, s, tasks, jobs, wus, (const T*)xbase); return hipGetLastError();
+// m_j = 32 or 64: the output rows of a tile are spread over 2 or 4 waves
+#define MNT(T, NI)                                                                                        \
+  {                                                                                                       \
+    constexpr int QS = NI == 4 ? 4 : (NI == 2 ? 2 : 1);                                                   \
+    hipLaunchKernelGGL((k_mode_nt<T, NI, QS>), dim3(nwu, QS), dim3(256), 0, s, tasks, jobs, wus,          \
+                       (const T*)xbase);                                                                  \
+    return hipGetLastError();                                                                             \
+  }
     if (dtype == 0) {
       switch (mj / 16) { case 1: MNT(double, 1) case 2: MNT(double, 2) case 3: MNT(double, 3) case 4: MNT(double, 4) }
     } else {
