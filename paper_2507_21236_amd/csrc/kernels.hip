@@ -2905,6 +2905,31 @@ hipError_t launch_reduce_list(int dtype_in, const RDTask* tasks, int ntask, int6
   return hipGetLastError();
 }
 
+// sticky[0] |= status of st (and a non-finite eigenvalue when with_theta);
+// sticky[1] counts the calls.  One thread: the state is a single struct.
+__global__ void k_status_accum(const KrylovState* __restrict__ st, int* __restrict__ sticky, int with_theta) {
+  if (threadIdx.x != 0) return;
+  int bad = st->status;
+  if (with_theta && !isfinite(st->scal[0])) bad |= 1;
+  sticky[0] |= bad;
+  sticky[1] += 1;
+}
+
+hipError_t launch_status_accum(const KrylovState* st, int* sticky, int with_theta, hipStream_t s) {
+  hipLaunchKernelGGL(k_status_accum, dim3(1), dim3(64), 0, s, st, sticky, with_theta);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_int(int* __restrict__ p, int n) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < n) p[e] = 0;
+}
+
+hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero, dim3(gridv(n)), dim3(256), 0, s, p, n);

@@ -54,6 +54,9 @@ hipError_t launch_batch_mode(int dtype, const MPTask* tasks, const MPJob* jobs, 
 hipError_t launch_transpose_list(int dtype, const TRTask* tasks, int ntask, int64_t maxM, hipStream_t s);
 hipError_t launch_reduce_list(int dtype_in, const RDTask* tasks, int ntask, int64_t maxM, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+// sticky[0] |= st->status (| 1 for a non-finite eigenvalue when with_theta); sticky[1]++
+hipError_t launch_status_accum(const KrylovState* st, int* sticky, int with_theta, hipStream_t s);
+hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 hipError_t prepare_kernel_attributes();
 
 // Davidson form.  op: 0 init, 1 start (arg = phase 0/1), 2 dots of W[k-1],

@@ -983,6 +983,11 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
     HIPCHK(launch_tiny(h->d_tjobs + n, 1, (int)Msz, kk, s));
     h->n_matvec += k;
     h->mv_flops += (double)k * h->M.mv[n].flops;
+    if (h->defer_status) {
+      HIPCHK(launch_status_accum(h->d_st, h->d_sticky, 1, s));
+      if (nmv) *nmv = k;
+      return std::nan("");
+    }
     KrylovState st;
     HIPCHK(hipMemcpyAsync(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1016,6 +1021,11 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
   HIPCHK(launch_ktridiag(J, 1, s));
   HIPCHK(launch_kritz(J, 1, s));
   HIPCHK(launch_kscale(J, 1, Msz, 1, s));
+  if (h->defer_status) {
+    HIPCHK(launch_status_accum(h->d_st, h->d_sticky, 1, s));
+    if (nmv) *nmv = k;
+    return std::nan("");
+  }
   KrylovState st;
   HIPCHK(hipMemcpyAsync(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -1290,6 +1300,7 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
     h->cv_cap = 6 + 2 * (int)std::max<size_t>(1, [&] { size_t mx = 0; for (int n = 0; n < nn; n++) mx = std::max(mx, h->M.mv[n].combines.size()); return mx; }());
     h->d_cvtasks = dev_alloc(h, (size_t)h->cv_cap * sizeof(CVTask));
     h->d_st = (KrylovState*)dev_alloc(h, sizeof(KrylovState));
+    h->d_sticky = (int*)dev_alloc(h, 2 * sizeof(int));
     // device plans
     h->mv.assign(nn, MVDev());
     h->comb_blocks.assign(nn, {});
@@ -1529,6 +1540,7 @@ attn_status attn_isometrize(attn_handle* h, int32_t from, int32_t to, void* stre
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipSetDevice(h->device));
     qr_node(h, from, leg, s);
+    if (h->defer_status) HIPCHK(launch_status_accum(h->d_st, h->d_sticky, 0, s));
     absorb(h, to, leg_toward(tr, to, from), s);
     h->iso[from] = leg;
     h->iso[to] = -1;
@@ -1865,16 +1877,44 @@ attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* 
   attn_solver_opts so;
   if (opts) so = opts->solver;
   else { std::memset(&so, 0, sizeof(so)); so.krylov_k = 20; }
+  // Lanczos sweeps check the per-node status on the device and read it (with
+  // the last eigenvalue) once per sweep, so the host never waits inside a
+  // sweep; the Davidson form steers its restarts from the host and keeps its
+  // own synchronisation.
+  const bool defer = so.solver == ATTN_SOLVER_LANCZOS && !h->dead && h->d_sticky;
   for (int sw = 0; sw < n_sweeps; sw++) {
     auto t0 = std::chrono::steady_clock::now();
     double th = 0;
+    if (defer) {
+      if (hipSetDevice(h->device) != hipSuccess || launch_zero_int(h->d_sticky, 2, nullptr) != hipSuccess) {
+        h->err = "status reset failed";
+        return ATTN_ERR_HIP;
+      }
+      h->defer_status = true;
+    }
     for (int n = 0; n < (int)tr.nodes.size(); n++) {
       attn_status st = attn_move_center(h, n, nullptr);
-      if (st) return st;
-      st = attn_eigsolve_node(h, n, &so, &th, nullptr, nullptr);
-      if (st) return st;
+      if (st == ATTN_OK) st = attn_eigsolve_node(h, n, &so, &th, nullptr, nullptr);
+      if (st) { h->defer_status = false; return st; }
     }
+    h->defer_status = false;
     if (hipDeviceSynchronize() != hipSuccess) { h->err = "device synchronisation failed"; return ATTN_ERR_HIP; }
+    if (defer) {
+      int sticky[2] = {0, 0};
+      KrylovState st;
+      if (hipMemcpy(sticky, h->d_sticky, sizeof(sticky), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) {
+        h->err = "status read failed";
+        h->dead = true;
+        return ATTN_ERR_HIP;
+      }
+      if (sticky[0] != 0) {
+        h->err = (sticky[0] & 2) ? "sweep: QR factorisation broke down" : "sweep: non-finite value in the eigensolver";
+        h->dead = true;
+        return ATTN_ERR_NUMERIC;
+      }
+      th = st.scal[0];
+    }
     auto t1 = std::chrono::steady_clock::now();
     if (energies) energies[sw] = th;
     if (seconds) seconds[sw] = std::chrono::duration<double>(t1 - t0).count();
