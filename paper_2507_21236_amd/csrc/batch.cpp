@@ -129,6 +129,17 @@ void add_sandwich(attn_batch* b, attn_handle* h, int n, const void* x, attn_batc
     for (const Combine& c : P.combines) { off.push_back(tot); tot += (int64_t)c.dim * c.dim; }
   }
   int64_t part_used = 0;
+  int nchs[3];
+  {
+    int64_t target[3];
+    for (int sp = 0; sp < 3; sp++) {
+      int ma, mb, ns;
+      int64_t sl, row;
+      slice_geom(sp, dm, ma, mb, ns, sl, row);
+      target[sp] = target_for(b, ma, mb);
+    }
+    mv_chunks(P, dm, target, nchs);
+  }
   for (int sp = 0; sp < 3; sp++) {
     std::vector<const Item2*> its;
     for (const Item2& it : P.items)
@@ -139,10 +150,7 @@ void add_sandwich(attn_batch* b, attn_handle* h, int n, const void* x, attn_batc
     slice_geom(sp, dm, ma, mb, ns, sl, row);
     if (shape && (shape->first != ma || shape->second != mb)) continue;
     const bool mf = sw_mfma(ma, mb) && mb <= 64;
-    const int64_t units = mf ? (int64_t)ns * ((ma / 16 + 3) / 4) : (int64_t)ns * ((ma * mb + 255) / 256);
-    int64_t c = target_for(b, ma, mb) / std::max<int64_t>(1, units);
-    c = std::max<int64_t>(1, std::min<int64_t>(c, (int64_t)its.size()));
-    const int nch = (int)std::min<int64_t>(c, chunk_cap(Msz));
+    const int nch = nchs[sp];
     for (int ci = 0; ci < nch; ci++) {
       const size_t i0 = its.size() * ci / nch, i1 = its.size() * (ci + 1) / nch;
       if (i1 == i0) continue;

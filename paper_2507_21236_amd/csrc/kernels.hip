@@ -60,6 +60,14 @@ __device__ __forceinline__ int bf_pinv(int a) {
 // Stage 2 consumes the stage-1 accumulators directly as the B operand by
 // walking K = p in the order {16 tp + drow(j, i) : j = 0..3} for fixed (tp, i),
 // which is exactly how the accumulator layout spreads p over lane groups.
+// Loads of operator blocks through the global address space: the blocks
+// arrive as generic pointers, and flat loads would make every wait for them
+// also wait for LDS traffic (full drains instead of counted partial waits).
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+
 // The rows of Y_s owned by this wave for items [i0, i1), written to y.
 template <typename T, int NB>
 __device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __restrict__ items, int i0, int i1,
@@ -86,7 +94,7 @@ __device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __r
       for (int q = 0; q < NB; q++) t1[q] = v4{0, 0, 0, 0};
       const T* Ap = A + arow;
       for (int k0 = 0; k0 < ma; k0 += 4) {
-        const T bop = Ap[(int64_t)(k0 + l4) * ma] * coef;
+        const T bop = gload(Ap + (int64_t)(k0 + l4) * ma) * coef;
         const T* xr = lds + (k0 + l4) * ld + l16;
 #pragma unroll
         for (int q = 0; q < NB; q++) t1[q] = mfma16(xr[16 * q], bop, t1[q]);
@@ -105,7 +113,7 @@ __device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __r
         for (int i = 0; i < 4; i++) {
           const T* Bp = B + (int64_t)(16 * tp + drow<T>(l4, i)) * mb + l16;
 #pragma unroll
-          for (int tq = 0; tq < NB; tq++) acc[tq] = mfma16(Bp[16 * tq], t1[tp][i], acc[tq]);
+          for (int tq = 0; tq < NB; tq++) acc[tq] = mfma16(gload(Bp + 16 * tq), t1[tp][i], acc[tq]);
         }
     } else {
 #pragma unroll

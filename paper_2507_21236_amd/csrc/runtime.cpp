@@ -203,12 +203,18 @@ void upload_mp(attn_handle* h, std::vector<MPGroup>& gs) {
   }
 }
 
-int chunks_for(size_t nitems, int64_t units_per_chunk, int64_t Msz) {
-  // aim at roughly 1024 workgroups for the whole launch
-  int64_t c = (int64_t)1024 / std::max<int64_t>(1, units_per_chunk);
-  c = std::max<int64_t>(1, std::min<int64_t>(c, (int64_t)nitems));
-  c = std::min<int64_t>(c, chunk_cap(Msz));
-  return (int)c;
+void mv_chunks(const MatvecPlan& P, const int* dm, const int64_t target[3], int out[3]) {
+  int64_t nit[3] = {0, 0, 0}, units[3] = {1, 1, 1};
+  int ma[3], mb[3];
+  for (const Item2& it : P.items) nit[it.spect]++;
+  for (int sp = 0; sp < 3; sp++) {
+    int ns;
+    int64_t sl, row;
+    slice_geom(sp, dm, ma[sp], mb[sp], ns, sl, row);
+    units[sp] = sw_mfma(ma[sp], mb[sp]) ? (int64_t)ns * ((ma[sp] / 16 + 3) / 4)
+                                        : (int64_t)ns * ((ma[sp] * mb[sp] + 255) / 256);
+  }
+  mv_chunk_counts(nit, ma, mb, units, (int64_t)dm[0] * dm[1] * dm[2], target, out);
 }
 
 // ------------------------------------------------------------------ plan construction
@@ -227,6 +233,9 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
   h->comb_blocks[n].clear();
   for (size_t i = 0; i < P.combines.size(); i++) h->comb_blocks[n].push_back({off[i], P.combines[i].dim});
   int64_t part_used = 0;
+  int nchs[3];
+  const int64_t target[3] = {1024, 1024, 1024};
+  mv_chunks(P, dm, target, nchs);
   // two-leg items and local operators, grouped by spectator
   for (int sp = 0; sp < 3; sp++) {
     std::vector<const Item2*> its;
@@ -236,9 +245,7 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
     int ma, mb, ns;
     int64_t sl, row;
     slice_geom(sp, dm, ma, mb, ns, sl, row);
-    const int64_t units = sw_mfma(ma, mb) ? (int64_t)ns * ((ma / 16 + 3) / 4)
-                                          : (int64_t)ns * ((ma * mb + 255) / 256);
-    const int nch = chunks_for(its.size(), units, Msz);
+    const int nch = nchs[sp];
     SWGroup& g = group_for(D.sw, ma, mb);
     for (int c = 0; c < nch; c++) {
       const size_t i0 = its.size() * c / nch, i1 = its.size() * (c + 1) / nch;
@@ -1233,17 +1240,10 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
       const int dm[3] = {nd.dims[0], nd.dims[1], nd.dims[2]};
       const int64_t Msz = (int64_t)dm[0] * dm[1] * dm[2];
       const MatvecPlan& P = h->M.mv[n];
-      int nparts = 0;
-      for (int sp = 0; sp < 3; sp++) {
-        size_t cnt = 0;
-        for (auto& it : P.items) cnt += it.spect == sp;
-        if (!cnt) continue;
-        int ma, mb, ns;
-        int64_t sl, row;
-        slice_geom(sp, dm, ma, mb, ns, sl, row);
-        const int64_t units = sw_mfma(ma, mb) ? (int64_t)ns * ((ma / 16 + 3) / 4) : (int64_t)ns * ((ma * mb + 255) / 256);
-        nparts += chunks_for(cnt, units, Msz);
-      }
+      int nparts = 0, nchs[3];
+      const int64_t target[3] = {1024, 1024, 1024};
+      mv_chunks(P, dm, target, nchs);
+      for (int sp = 0; sp < 3; sp++) nparts += nchs[sp];
       part_need = std::max(part_need, nparts * Msz);
       int64_t cn = 0;
       for (auto& ch : P.chains) cn += (int64_t)(ch.O1.size() + ch.O2.size());

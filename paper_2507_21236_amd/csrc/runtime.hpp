@@ -249,12 +249,34 @@ T* upload(attn_handle* h, const std::vector<T>& v) {
 }
 double* block_ptr(attn_handle* h, const BRef& b, double* comb_base, const std::vector<int64_t>& comb_off);
 void slice_geom(int spect, const int* dm, int& ma, int& mb, int& ns, int64_t& sl, int64_t& row);
+// item chunks per spectator of the matvec plan of a node with dims dm
+// (target workgroups per launch, per spectator's slice shape)
+void mv_chunks(const MatvecPlan& P, const int* dm, const int64_t target[3], int out[3]);
 bool sw_mfma(int ma, int mb);
 // Most item chunks (workgroup sets with their own partial output) of one
 // sandwich group of a matvec: small nodes get more, so that their few slices
 // still spread over the chip.
 inline int64_t chunk_cap(int64_t Msz) {
   return Msz >= 65536 ? 32 : std::min<int64_t>(128, std::max<int64_t>(32, ((int64_t)1 << 19) / Msz));
+}
+// Item chunks per spectator of a matvec plan.  Spectators whose slices have
+// the same shape share one launch; the launch gets about target / units item
+// chunks per spectator in total (units = workgroups per chunk), shared out in
+// proportion to the spectators' item counts so that every chunk of the launch
+// carries about the same number of items.  nitems[sp] = 0: no chunk.
+inline void mv_chunk_counts(const int64_t nitems[3], const int ma[3], const int mb[3], const int64_t units[3],
+                            int64_t Msz, const int64_t target[3], int out[3]) {
+  for (int sp = 0; sp < 3; sp++) {
+    out[sp] = 0;
+    if (nitems[sp] <= 0) continue;
+    int64_t tot = 0, nsp = 0;
+    for (int q = 0; q < 3; q++)
+      if (nitems[q] > 0 && ma[q] == ma[sp] && mb[q] == mb[sp]) { tot += nitems[q]; nsp++; }
+    const int64_t C = nsp * std::max<int64_t>(1, target[sp] / std::max<int64_t>(1, units[sp]));
+    int64_t c = (C * nitems[sp] + tot / 2) / tot;
+    c = std::max<int64_t>(1, std::min<int64_t>(c, std::min<int64_t>(nitems[sp], chunk_cap(Msz))));
+    out[sp] = (int)c;
+  }
 }
 void run_comb(CBPlan& P, hipStream_t s);
 void* to_mirror(attn_handle* h, const void* p, int fmt);
