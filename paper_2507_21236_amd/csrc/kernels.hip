@@ -930,6 +930,66 @@ __global__ __launch_bounds__(256) void k_gram_nt(const GRTask* __restrict__ task
   }
 }
 
+// Register-direct gram for m_j = 64 with the X block of each 16-wide step of
+// the free index staged once per workgroup in LDS (double buffered) and
+// shared by the four waves, instead of loaded by each wave: wave w owns output
+// column tile w (its Z fragment straight from memory, the next step's
+// prefetched) and the four row tiles.  Fewer registers than k_gram_nt<4>, so
+// more waves per SIMD hide the latency of Z.  Same products, same order.
+__global__ __launch_bounds__(256) void k_gram_x4(const GRTask* __restrict__ tasks) {
+  constexpr int mj = 64, LDX = 20;   // LDS row stride in doubles (32-byte aligned rows)
+  __shared__ __align__(16) double xs[2][mj * LDX];
+  const GRTask& t = tasks[blockIdx.x];
+  const int j = t.j, d1 = t.d1, d2 = t.d2;
+  const double* X = (const double*)t.X;
+  const double* Z = (const double*)t.Z;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int si = tid >> 2, sq = tid & 3;   // staging: row si, four f values from 4 sq
+  const int64_t F = (int64_t)t.d0 * d1 * d2 / mj;
+  auto addr = [&](int i, int64_t f) -> int64_t {
+    if (j == 0) return (int64_t)i * F + f;
+    const int64_t a = f / d2, c = f - a * d2;
+    return a * d1 * d2 + (int64_t)i * d2 + c;
+  };
+  d4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; q++) acc[q] = d4{0, 0, 0, 0};
+  d4 zr = d4{0, 0, 0, 0}, zn = d4{0, 0, 0, 0}, xg = d4{0, 0, 0, 0};
+  int64_t f0 = t.f0;
+  if (f0 < t.f1) {
+    xg = *(const d4*)(X + addr(si, f0 + 4 * sq));
+    zr = *(const d4*)(Z + addr(16 * wave + l16, f0 + 4 * l4));
+    *(d4*)(&xs[0][si * LDX + 4 * sq]) = xg;
+  }
+  __syncthreads();
+  int buf = 0;
+  for (; f0 < t.f1; f0 += 16) {
+    const bool more = f0 + 16 < t.f1;
+    if (more) {
+      xg = *(const d4*)(X + addr(si, f0 + 16 + 4 * sq));
+      zn = *(const d4*)(Z + addr(16 * wave + l16, f0 + 16 + 4 * l4));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const d4 xf = *(const d4*)(&xs[buf][(16 * q + l16) * LDX + 4 * l4]);
+#pragma unroll
+      for (int kk = 0; kk < 4; kk++) acc[q] = mfma16(xf[kk], zr[kk], acc[q]);
+    }
+    if (more) {
+      *(d4*)(&xs[buf ^ 1][si * LDX + 4 * sq]) = xg;
+      zr = zn;
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* P = (double*)t.partial;
+#pragma unroll
+  for (int q = 0; q < 4; q++)
+#pragma unroll
+    for (int i = 0; i < 4; i++) P[(int64_t)(16 * wave + l16) * mj + 16 * q + drow<double>(l4, i)] = acc[q][i];
+}
+
 // Generic gram: one thread per output element (j, j'), loop over the f range.
 __global__ __launch_bounds__(256) void k_gram_gen(const GRTask* __restrict__ tasks, int maxm) {
   const GRTask& t = tasks[blockIdx.y];
@@ -2692,7 +2752,7 @@ hipError_t launch_gram(int mj, bool mfma, const GRTask* tasks, int ntask, hipStr
       case 1: hipLaunchKernelGGL(k_gram_nt<1>, dim3(ntask), dim3(256), 0, s, tasks); return hipGetLastError();
       case 2: hipLaunchKernelGGL(k_gram_nt<2>, dim3(ntask), dim3(256), 0, s, tasks); return hipGetLastError();
       case 3: hipLaunchKernelGGL(k_gram_nt<3>, dim3(ntask), dim3(256), 0, s, tasks); return hipGetLastError();
-      case 4: hipLaunchKernelGGL(k_gram_nt<4>, dim3(ntask), dim3(256), 0, s, tasks); return hipGetLastError();
+      case 4: hipLaunchKernelGGL(k_gram_x4, dim3(ntask), dim3(256), 0, s, tasks); return hipGetLastError();
       default: break;
     }
   }
