@@ -578,66 +578,73 @@ __device__ __forceinline__ int64_t mode_addr(int j, int d0, int d1, int d2, int 
 
 // out (+)= sum_jobs coef * A x_j in.  wu = (task, f-tile of 64).  LDS holds the
 // input tile [i'][f]; wave w owns f in [16 w, +16) and every i.
-template <typename T, int NI>
+// workgroups per 64-wide free block of the LDS-staged mode product
+constexpr int mode_qs(int NI) { return NI == 4 ? 4 : (NI == 2 ? 2 : 1); }
+
+template <typename T, int NI, int QS = 1>
 __device__ __forceinline__ void mode_mfma(const MPTask& t, const MPJob* __restrict__ jobs,
                                           const int2 wu, const T* __restrict__ xbase,
                                           unsigned char* smem_raw) {
+  // QS > 1: the 64-wide free block of the work unit is split over blockIdx.y
+  // into QS parts, and the four waves take (4 / QS) tiles of 16 free indices
+  // times QS groups of output rows; every output entry keeps its summation order
   typedef typename V4<T>::type v4;
-  constexpr int mj = 16 * NI;
+  constexpr int mj = 16 * NI, NQ = NI / QS, FW = 64 / QS;   // rows per wave, free width per WG
   constexpr int ld = 64 + 2;
   T* lds = reinterpret_cast<T*>(smem_raw);
   const int j = t.j, d0 = t.d0, d1 = t.d1, d2 = t.d2;
-  const int64_t f0 = (int64_t)wu.y * 64;
+  const int64_t f0 = (int64_t)wu.y * 64 + (QS > 1 ? FW * (int64_t)blockIdx.y : 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, l4 = lane >> 4;
-  v4 acc[NI];
+  const int tile = wave / QS, q0 = (wave % QS) * NQ;
+  v4 acc[NQ];
 #pragma unroll
-  for (int q = 0; q < NI; q++) acc[q] = v4{0, 0, 0, 0};
+  for (int q = 0; q < NQ; q++) acc[q] = v4{0, 0, 0, 0};
   for (int jb = t.job0; jb < t.job0 + t.njob; jb++) {
     const T* in = jobs[jb].in ? (const T*)jobs[jb].in : xbase;
     const T* A = (const T*)jobs[jb].A;
     const T coef = (T)jobs[jb].coef;
     __syncthreads();
     if (j == 2) {
-      for (int e = threadIdx.x; e < 64 * mj; e += 256) {
+      for (int e = threadIdx.x; e < FW * mj; e += 256) {
         const int fl = e / mj, i = e - fl * mj;
         lds[i * ld + fl] = in[mode_addr(j, d0, d1, d2, i, f0 + fl)];
       }
     } else {
-      for (int e = threadIdx.x; e < 64 * mj; e += 256) {
-        const int i = e >> 6, fl = e & 63;
+      for (int e = threadIdx.x; e < FW * mj; e += 256) {
+        const int i = e / FW, fl = e - i * FW;
         lds[i * ld + fl] = in[mode_addr(j, d0, d1, d2, i, f0 + fl)];
       }
     }
     __syncthreads();
-    const T* Ap = A + l16;
+    const T* Ap = A + 16 * q0 + l16;
     for (int k0 = 0; k0 < mj; k0 += 4) {
-      const T bop = lds[(k0 + l4) * ld + 16 * wave + l16] * coef;
+      const T bop = lds[(k0 + l4) * ld + 16 * tile + l16] * coef;
       const T* Ak = Ap + (int64_t)(k0 + l4) * mj;
 #pragma unroll
-      for (int q = 0; q < NI; q++) acc[q] = mfma16(Ak[16 * q], bop, acc[q]);
+      for (int q = 0; q < NQ; q++) acc[q] = mfma16(Ak[16 * q], bop, acc[q]);
     }
   }
   T* out = (T*)t.out;
-  const int64_t f = f0 + 16 * wave + l16;
+  const int64_t f = f0 + 16 * tile + l16;
 #pragma unroll
-  for (int q = 0; q < NI; q++)
+  for (int q = 0; q < NQ; q++)
 #pragma unroll
     for (int i = 0; i < 4; i++) {
-      const int64_t ad = mode_addr(j, d0, d1, d2, 16 * q + drow<T>(l4, i), f);
+      const int64_t ad = mode_addr(j, d0, d1, d2, 16 * (q0 + q) + drow<T>(l4, i), f);
       if (t.accumulate) out[ad] += acc[q][i];
       else out[ad] = acc[q][i];
     }
 }
 
-template <typename T, int NI>
+template <typename T, int NI, int QS>
 __global__ __launch_bounds__(256) void k_mode(const MPTask* __restrict__ tasks,
                                               const MPJob* __restrict__ jobs,
                                               const int2* __restrict__ wus,
                                               const T* __restrict__ xbase) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int2 wu = wus[blockIdx.x];
-  mode_mfma<T, NI>(tasks[wu.x], jobs, wu, xbase, smem_raw);
+  mode_mfma<T, NI, QS>(tasks[wu.x], jobs, wu, xbase, smem_raw);
 }
 
 // Mode product for contracted leg j = 0 or 1 with 16 | d2: a 16-wide tile of
@@ -2687,8 +2694,11 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
 template <typename T, int NI>
 static hipError_t mode_launch(const MPTask* tasks, const MPJob* jobs, const int2* wus, int nwu,
                               const void* xbase, hipStream_t s) {
+  // m_j = 32 or 64: the output rows of a work unit are spread over 2 or 4
+  // workgroups (each stages a quarter or half of the free block)
+  constexpr int QS = mode_qs(NI);
   const size_t lds = (size_t)16 * NI * 66 * sizeof(T);
-  hipLaunchKernelGGL((k_mode<T, NI>), dim3(nwu), dim3(256), lds, s, tasks, jobs, wus,
+  hipLaunchKernelGGL((k_mode<T, NI, QS>), dim3(nwu, QS), dim3(256), lds, s, tasks, jobs, wus,
                      (const T*)xbase);
   return hipGetLastError();
 }
@@ -3022,12 +3032,14 @@ hipError_t prepare_kernel_attributes() {
       (const void*)k_sandwich_bf2w<2, 2>, (const void*)k_sandwich_bf2w<2, 4>,
       (const void*)k_sandwich_bf2w<4, 2>, (const void*)k_sandwich_bf2w<4, 4>,
       (const void*)k_sandwich_bf2<6>, (const void*)k_sandwich_bf2<8>,
-      (const void*)k_mode<double, 1>, (const void*)k_mode<double, 2>, (const void*)k_mode<double, 3>,
-      (const void*)k_mode<double, 4>, (const void*)k_mode<double, 5>, (const void*)k_mode<double, 6>,
-      (const void*)k_mode<double, 7>, (const void*)k_mode<double, 8>,
-      (const void*)k_mode<float, 1>, (const void*)k_mode<float, 2>, (const void*)k_mode<float, 3>,
-      (const void*)k_mode<float, 4>, (const void*)k_mode<float, 5>, (const void*)k_mode<float, 6>,
-      (const void*)k_mode<float, 7>, (const void*)k_mode<float, 8>, (const void*)k_mlp_grad};
+      (const void*)k_mode<double, 1, mode_qs(1)>, (const void*)k_mode<double, 2, mode_qs(2)>,
+      (const void*)k_mode<double, 3, mode_qs(3)>, (const void*)k_mode<double, 4, mode_qs(4)>,
+      (const void*)k_mode<double, 5, mode_qs(5)>, (const void*)k_mode<double, 6, mode_qs(6)>,
+      (const void*)k_mode<double, 7, mode_qs(7)>, (const void*)k_mode<double, 8, mode_qs(8)>,
+      (const void*)k_mode<float, 1, mode_qs(1)>, (const void*)k_mode<float, 2, mode_qs(2)>,
+      (const void*)k_mode<float, 3, mode_qs(3)>, (const void*)k_mode<float, 4, mode_qs(4)>,
+      (const void*)k_mode<float, 5, mode_qs(5)>, (const void*)k_mode<float, 6, mode_qs(6)>,
+      (const void*)k_mode<float, 7, mode_qs(7)>, (const void*)k_mode<float, 8, mode_qs(8)>, (const void*)k_mlp_grad};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
