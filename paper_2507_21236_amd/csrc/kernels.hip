@@ -69,6 +69,15 @@ __device__ __forceinline__ T gload(const T* p) {
 }
 
 // The rows of Y_s owned by this wave for items [i0, i1), written to y.
+// Column order of a 16-wide tile as the products see it: tile row m of both
+// MFMA stages stands for column colperm(m).  FP64: the accumulator rows of a
+// lane, l/16 + 4 i, become the columns 2 (l/16) + {0, 1, 8, 9}, so that each
+// lane ends up with two pairs of adjacent columns and stores them as 16-byte
+// writes; FP32 lanes already hold 4 adjacent columns.
+template <typename T> __device__ __forceinline__ int colperm(int m);
+template <> __device__ __forceinline__ int colperm<double>(int m) { return 2 * (m & 3) + ((m >> 2) & 1) + 8 * (m >> 3); }
+template <> __device__ __forceinline__ int colperm<float>(int m) { return m; }
+
 template <typename T, int NB>
 __device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __restrict__ items, int i0, int i1,
                                               void* y, int accumulate, int s, int strip0, const T* lds) {
@@ -81,6 +90,10 @@ __device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __r
   if (strip * 16 >= ma) return;
   const int l16 = lane & 15, l4 = lane >> 4;
   const int arow = strip * 16 + l16;
+  const int pc = colperm<T>(l16);   // column read by this lane for an A operand
+  int pk[4];                        // column of the contraction index of item i
+#pragma unroll
+  for (int i = 0; i < 4; i++) pk[i] = colperm<T>(drow<T>(l4, i));
   v4 acc[NB];
 #pragma unroll
   for (int q = 0; q < NB; q++) acc[q] = v4{0, 0, 0, 0};
@@ -95,7 +108,7 @@ __device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __r
       const T* Ap = A + arow;
       for (int k0 = 0; k0 < ma; k0 += 4) {
         const T bop = gload(Ap + (int64_t)(k0 + l4) * ma) * coef;
-        const T* xr = lds + (k0 + l4) * ld + l16;
+        const T* xr = lds + (k0 + l4) * ld + pc;
 #pragma unroll
         for (int q = 0; q < NB; q++) t1[q] = mfma16(xr[16 * q], bop, t1[q]);
       }
@@ -104,14 +117,14 @@ __device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __r
 #pragma unroll
       for (int q = 0; q < NB; q++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) t1[q][i] = xr[16 * q + drow<T>(l4, i)] * coef;
+        for (int i = 0; i < 4; i++) t1[q][i] = xr[16 * q + pk[i]] * coef;
     }
     if (B) {
 #pragma unroll
       for (int tp = 0; tp < NB; tp++)
 #pragma unroll
         for (int i = 0; i < 4; i++) {
-          const T* Bp = B + (int64_t)(16 * tp + drow<T>(l4, i)) * mb + l16;
+          const T* Bp = B + (int64_t)(16 * tp + pk[i]) * mb + pc;
 #pragma unroll
           for (int tq = 0; tq < NB; tq++) acc[tq] = mfma16(gload(Bp + 16 * tq), t1[tp][i], acc[tq]);
         }
@@ -121,14 +134,31 @@ __device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __r
     }
   }
   T* Y = (T*)y + (int64_t)s * t.ys_slice + (int64_t)arow * t.ys_row;
+  if constexpr (sizeof(T) == 8) {
 #pragma unroll
-  for (int q = 0; q < NB; q++)
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int c = 16 * q + drow<T>(l4, i);
-      if (accumulate) Y[c] += acc[q][i];
-      else Y[c] = acc[q][i];
+    for (int q = 0; q < NB; q++) {
+      double2* p0 = (double2*)(Y + 16 * q + 2 * l4);
+      double2* p1 = (double2*)(Y + 16 * q + 8 + 2 * l4);
+      double2 v0 = make_double2(acc[q][0], acc[q][1]), v1 = make_double2(acc[q][2], acc[q][3]);
+      if (accumulate) {
+        const double2 o0 = *p0, o1 = *p1;
+        v0.x += o0.x; v0.y += o0.y; v1.x += o1.x; v1.y += o1.y;
+      }
+      *p0 = v0;
+      *p1 = v1;
     }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NB; q++) {
+      float4* p0 = (float4*)(Y + 16 * q + 4 * l4);
+      float4 v = make_float4(acc[q][0], acc[q][1], acc[q][2], acc[q][3]);
+      if (accumulate) {
+        const float4 o = *p0;
+        v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
+      }
+      *p0 = v;
+    }
+  }
 }
 
 
