@@ -55,7 +55,7 @@ struct attn_batch {
     std::vector<CVTask> cv;
     int64_t cv_max = 0;
     std::vector<TJob> tj;
-    int tj_maxM = 0;
+    int tj_minM = 1 << 30, tj_maxM = 0;
     std::vector<KJob> kj;
     int64_t kj_max = 0;
     std::vector<int> kj_inst;   // instance of each eigensolve job
@@ -261,6 +261,7 @@ void build_step(attn_batch* b, int t) {
     S.flops += (double)h->M.mv[n].flops;
     if (D.d_tiny) {
       S.tj.push_back(h->h_tjobs[n]);
+      S.tj_minM = std::min(S.tj_minM, (int)Msz);
       S.tj_maxM = std::max(S.tj_maxM, (int)Msz);
       continue;
     }
@@ -342,7 +343,7 @@ void enqueue_step(attn_batch* b, int t, hipStream_t s0) {
     HIPCHK(launch_combine(S.d_cb_tasks, S.d_cb_terms, (int)S.cb_tasks.size(), S.cb_maxn, s0));
   if (!S.cv.empty()) HIPCHK(launch_convert(1, S.d_cv, (int)S.cv.size(), S.cv_max, s0));
   const int kk = std::min(b->krylov_k, 64);
-  if (!S.tj.empty()) HIPCHK(launch_tiny(S.d_tj, (int)S.tj.size(), S.tj_maxM, kk, s0));
+  if (!S.tj.empty()) HIPCHK(launch_tiny(S.d_tj, (int)S.tj.size(), S.tj_minM, S.tj_maxM, kk, s0));
   if (S.kj.empty()) return;
   const int nj = (int)S.kj.size();
   const KJob* J = S.d_kj;

@@ -1357,95 +1357,140 @@ __global__ __launch_bounds__(256) void k_kbeta(const KJob* __restrict__ jobs, in
   }
 }
 
-// Lowest eigenpair of the keff x keff symmetric tridiagonal matrix
-// T = tridiag(beta, alpha, beta), one thread:
-//  * eigenvalue by bisection on Sturm counts (number of negative pivots of the
-//    LDL^T factorisation of T - x I) inside the Gershgorin interval, down to
-//    adjacent floating-point numbers;
-//  * eigenvector by inverse iteration with T - theta I (Gaussian elimination
-//    with partial pivoting on the tridiagonal system, three iterations);
-//  * normalised, sign fixed as described at the end of the kernel.
-constexpr int kTriLds = 11 * 64;
-constexpr size_t kTinyLdsMax = 144 * 1024;   // dynamic LDS of the tiny-node Lanczos kernel
-
-// Number of eigenvalues of the symmetric tridiagonal (a, b) below x, from the
-// signs of the leading principal minors p_i = (a_i - x) p_{i-1} - b_{i-1}^2
-// p_{i-2} (a Sturm sequence): every negative ratio p_i / p_{i-1} counts one
-// eigenvalue, and a zero minor takes the sign of the one before it.  There is
-// no division and no branch on data, so a step costs one dependent FMA.  The
-// caller scales a, b and x by a power of two (exact) so that |a_i - x| <= 2
-// and b_i^2 <= 1: the minors then grow by less than 2^2 per step, and every
-// eighth step the pair (p_{i-1}, p_i) is brought back into [2^-200, 2^200]
-// by a power of two, which changes no sign and no ratio.  b2 holds b_i^2.
-__device__ int sturm_count(const double* a, const double* b2, int k, double x) {
-  double pm = 1.0, pc = a[0] - x;
-  int neg = pc < 0.0;   // sign carried by the last nonzero minor
-  int cnt = neg;
-  for (int i = 1; i < k; i++) {
-    const double pn = (a[i] - x) * pc - b2[i - 1] * pm;
-    const int nn = pn < 0.0, nz = pn != 0.0;
-    cnt += nz & (nn ^ neg);
-    neg = nz ? nn : neg;
-    pm = pc;
-    pc = pn;
-    if ((i & 7) == 0) {
-      const double m = fmax(fabs(pm), fabs(pc));
-      const double sc = m > 0x1p200 ? 0x1p-200 : (m < 0x1p-200 ? 0x1p200 : 1.0);
-      pm *= sc;
-      pc *= sc;
-    }
-  }
-  return cnt;
+// ---- wavefront-wide reductions.  Every step combines a lane with a partner
+// holding the same partial (the operations are commutative), and the result
+// is read from lane 0, so every lane gets the same bits.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+template <typename Op>
+__device__ __forceinline__ double wave_reduce(double v, Op op) {
+  v = op(v, dpp_d<0xB1>(v));    // quad_perm(1, 0, 3, 2)
+  v = op(v, dpp_d<0x4E>(v));    // quad_perm(2, 3, 0, 1)
+  v = op(v, dpp_d<0x141>(v));   // row_half_mirror
+  v = op(v, dpp_d<0x140>(v));   // row_mirror
+  v = op(v, __shfl_xor(v, 16, 64));
+  v = op(v, __shfl_xor(v, 32, 64));
+  return readlane_d(v, 0);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  return wave_reduce(v, [](double x, double y) { return x + y; });
+}
+__device__ __forceinline__ double wave_max(double v) {
+  return wave_reduce(v, [](double x, double y) { return fmax(x, y); });
+}
+__device__ __forceinline__ double wave_min(double v) {
+  return wave_reduce(v, [](double x, double y) { return fmin(x, y); });
 }
 
-// Lowest eigenpair of the keff x keff Lanczos tridiagonal in st, run by one
-// full wavefront (64 lanes); lds must hold kTriLds doubles.  The eigenvalue by
-// multisection (64 Sturm counts per round) and bisection to the last bit, the
-// eigenvector by three rounds of inverse iteration on one LU factorisation
-// (partial pivoting) of T - theta I.
-__device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restrict__ lds) {
-  const int lane = threadIdx.x & 63;
-  const int k = st->keff;
-  double* a = lds;
-  double* b = lds + 64;
-  double* b2 = lds + 128;
-  double* y = lds + 192;
-  double* d = lds + 256;
-  double* du = lds + 320;
-  double* du2 = lds + 384;
-  double* f = lds + 448;
-  double* rd = lds + 512;
-  double* sw = lds + 576;
-  double* as = lds + 640;   // a scaled for the Sturm counts
-  if (lane < k) a[lane] = st->alpha[lane];
-  if (lane + 1 < k) b[lane] = st->beta[lane];
-  wave_sync();
-  double lo = a[0], hi = a[0], nrm = 0;
-  for (int i = 0; i < k; i++) {
-    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < k ? fabs(b[i]) : 0.0);
-    lo = fmin(lo, a[i] - r);
-    hi = fmax(hi, a[i] + r);
-    nrm = fmax(nrm, fabs(a[i]) + r);
+// Lowest eigenpair of the keff x keff symmetric tridiagonal matrix
+// T = tridiag(beta, alpha, beta) of a Lanczos run, by one full wavefront:
+//  * eigenvalue by multisection on Sturm counts (64 points per round, one per
+//    lane) inside the Gershgorin interval, then bisection down to adjacent
+//    floating-point numbers;
+//  * eigenvector by three rounds of inverse iteration with one LU
+//    factorisation (partial pivoting) of T - theta I;
+//  * normalised, sign fixed as described at the end.
+// lds must hold kTriLds doubles.
+constexpr int kTriLds = 768;
+constexpr size_t kTinyLdsMax = 144 * 1024;   // dynamic LDS of the tiny-node Lanczos kernels
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with
+// diagonal as[] and squared off-diagonal bs2[] (bs2[i] couples rows i - 1 and
+// i; bs2[0] = 0): the number of sign changes along the leading principal
+// minors p_i = (as_i - x) p_{i-1} - bs2_i p_{i-2} (a Sturm sequence, starting
+// from p_{-1} = 1, p_{-2} = 0), read off the sign bits.  A zero minor inside
+// the sequence is followed by one of the sign opposite to its predecessor, so
+// its own sign bit does not change the count; a zero last minor (x an
+// eigenvalue of the computed sequence) counts by its sign bit, which puts x on
+// one side of that eigenvalue.  No division and no branch: a step is one
+// dependent FMA and three integer operations.  The caller scales the matrix
+// and x by a power of two (exact) so that |as_i - x| <= 2 and bs2_i <= 1: the
+// minors grow by less than 2^2 per step, and after every 8 steps the pair
+// (p_{i-1}, p_i) is brought back into [2^-200, 2^200] by a power of two, which
+// changes no sign.  The arrays hold kp (a multiple of 8) entries; entries past
+// the matrix have as = 2^60 and bs2 = 0, steps that multiply the last minor by
+// a positive factor and count nothing.
+__device__ __forceinline__ int sturm_count(const double* __restrict__ as, const double* __restrict__ bs2, int kp,
+                                           double x) {
+  double pm = 0.0, pc = 1.0;
+  unsigned cnt = 0;
+  for (int c = 0; c < kp; c += 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) { av[u] = as[c + u]; bv[u] = bs2[c + u]; }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const double pn = (av[u] - x) * pc - bv[u] * pm;
+      cnt += ((unsigned)__double2hiint(pn) ^ (unsigned)__double2hiint(pc)) >> 31;
+      pm = pc;
+      pc = pn;
+    }
+    const double m = fmax(fabs(pm), fabs(pc));
+    const double sc = m > 0x1p200 ? 0x1p-200 : (m < 0x1p-200 ? 0x1p200 : 1.0);
+    pm *= sc;
+    pc *= sc;
   }
+  return (int)cnt;
+}
+
+__device__ __forceinline__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restrict__ lds) {
+  const int lane = threadIdx.x & 63;
+  const int k = __builtin_amdgcn_readfirstlane(st->keff);   // 1 <= k <= 64
+  const int kp = (k + 7) & ~7;
+  double* a = lds;           // alpha [64]
+  double* b = lds + 64;      // beta, zero from index k - 1 on [72]
+  double* as = lds + 136;    // alpha scaled for the Sturm counts, padded [72]
+  double* bs2 = lds + 208;   // (scaled beta_{i-1})^2, padded [72]
+  double* d = lds + 280;     // U = P L^-1 (T - theta I): diagonal [64]
+  double* du = lds + 344;    //   first superdiagonal [64]
+  double* du2 = lds + 408;   //   second superdiagonal [64]
+  double* f = lds + 472;     // multipliers of L [64]
+  double* sw = lds + 536;    // 1 where rows i and i + 1 were swapped [64]
+  double* rd = lds + 600;    // 1 / d [64]
+  double* y = lds + 664;     // eigenvector [72]
+  const bool on = lane < k;
+  const double al = on ? st->alpha[lane] : 0.0;
+  const double bl = lane + 1 < k ? st->beta[lane] : 0.0;
+  a[lane] = al;
+  b[lane] = bl;
+  y[lane] = 1.0;
+  if (lane < 8) { b[64 + lane] = 0.0; y[64 + lane] = 0.0; }
+  wave_sync();
+  // Gershgorin interval and a bound of ||T||, one row per lane
+  const double bp = lane > 0 ? b[lane - 1] : 0.0;
+  const double r = fabs(bp) + fabs(bl);
+  double lo = wave_min(on ? al - r : __builtin_huge_val());
+  double hi = wave_max(on ? al + r : -__builtin_huge_val());
+  const double nrm = wave_max(on ? fabs(al) + r : 0.0);
   // power-of-two scale sg with nrm * sg <= 1 for the Sturm counts (exact)
   int ex = 0;
   (void)frexp(nrm, &ex);
   const double sg = (nrm > 0.0 && isfinite(nrm)) ? ldexp(1.0, -ex) : 1.0;
-  if (lane < k) as[lane] = a[lane] * sg;
-  if (lane + 1 < k) {
-    const double bs = b[lane] * sg;
-    b2[lane] = bs * bs;
-  }
+  as[lane] = on ? al * sg : 0x1p60;
+  const double bsc = bp * sg;
+  bs2[lane] = on ? bsc * bsc : 0.0;
+  if (lane < 8) { as[64 + lane] = 0x1p60; bs2[64 + lane] = 0.0; }
   wave_sync();
-  // multisection: 64 Sturm counts per step, bracket [lo, hi] keeps lambda_min
+  // multisection: lane l probes lo + (hi - lo) (l + 1) / 65; the bracket
+  // [lo, hi] keeps the lowest eigenvalue
+  const double frac = (double)(lane + 1) / 65.0;
   for (int it = 0; it < 40; it++) {
     const double w = hi - lo;
-    const double x = lo + w * (double)(lane + 1) / 65.0;
-    const bool has = (x > lo && x < hi) ? sturm_count(as, b2, k, x * sg) >= 1 : (x >= hi);
+    const double x = lo + w * frac;
+    const bool has = (x > lo && x < hi) ? sturm_count(as, bs2, kp, x * sg) >= 1 : (x >= hi);
     const unsigned long long m = __ballot(has);
     const int first = m ? __ffsll((long long)m) - 1 : 64;
-    const double nhi = first < 64 ? lo + w * (double)(first + 1) / 65.0 : hi;
-    const double nlo = first > 0 ? lo + w * (double)first / 65.0 : lo;
+    const double xf = readlane_d(x, first & 63), xb = readlane_d(x, (first - 1) & 63);
+    const double nhi = first < 64 ? xf : hi;
+    const double nlo = first > 0 ? xb : lo;
     if (!(nhi < hi || nlo > lo)) break;
     hi = fmin(hi, nhi);
     lo = fmax(lo, nlo);
@@ -1455,81 +1500,103 @@ __device__ void tridiag_solve_wave(KrylovState* __restrict__ st, double* __restr
   for (int it = 0; it < 64; it++) {
     const double mid = 0.5 * (lo + hi);
     if (mid <= lo || mid >= hi) break;
-    if (sturm_count(as, b2, k, mid * sg) >= 1) hi = mid;
+    if (sturm_count(as, bs2, kp, mid * sg) >= 1) hi = mid;
     else lo = mid;
   }
   const double theta = hi;
   const double tiny = 1e-300 + 2.2e-16 * nrm * 1e-3;
   if (lane == 0) {
-    // T - theta I = P L U: U with diagonal d and superdiagonals du, du2,
-    // multipliers f, row swaps sw
-    for (int i = 0; i < k; i++) {
-      d[i] = a[i] - theta;
-      du[i] = (i + 1 < k) ? b[i] : 0.0;
-      du2[i] = 0.0;
-    }
-    for (int i = 0; i + 1 < k; i++) {
-      const double li = b[i];
-      if (fabs(d[i]) >= fabs(li)) {
-        if (d[i] == 0.0) d[i] = tiny;
-        const double fi = li / d[i];
+    // T - theta I = P L U, row by row; cd and cu carry the diagonal and
+    // superdiagonal entries of the current row as updated so far.  Both
+    // pivoting choices are evaluated and the taken one selected (no branch);
+    // entries past row k - 2 are written but never read.
+    double cd = a[0] - theta, cu = b[0];
+    for (int c = 0; c + 1 < k; c += 8) {
+      double av[8], bv[9];
+#pragma unroll
+      for (int u = 0; u < 8; u++) av[u] = a[c + 1 + u];
+#pragma unroll
+      for (int u = 0; u < 9; u++) bv[u] = b[c + u];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const int i = c + u;
+        const double li = bv[u], an = av[u] - theta, bn = bv[u + 1];
+        const bool swp = !(fabs(cd) >= fabs(li));   // rows i and i + 1 swapped
+        const double piv = (!swp && cd == 0.0) ? tiny : cd;
+        const double fi = (swp ? piv : li) / (swp ? li : piv);
         f[i] = fi;
-        sw[i] = 0.0;
-        d[i + 1] -= fi * du[i];
-      } else {
-        const double fi = d[i] / li;
-        f[i] = fi;
-        sw[i] = 1.0;
-        d[i] = li;
-        const double t1 = d[i + 1];
-        d[i + 1] = du[i] - fi * t1;
-        du[i] = t1;
-        if (i + 2 < k) {
-          du2[i] = du[i + 1];
-          du[i + 1] = -fi * du2[i];
-        }
+        sw[i] = swp ? 1.0 : 0.0;
+        d[i] = swp ? li : piv;
+        du[i] = swp ? an : cu;
+        du2[i] = swp ? bn : 0.0;
+        const double ncd = swp ? cu - fi * an : an - fi * cu;
+        const double ncu = swp ? -fi * bn : bn;
+        const bool live = i + 1 < k;
+        cd = live ? ncd : cd;
+        cu = live ? ncu : cu;
       }
     }
-    if (d[k - 1] == 0.0) d[k - 1] = tiny;
+    if (cd == 0.0) cd = tiny;
+    d[k - 1] = cd;
+    du[k - 1] = 0.0;
+    du2[k - 1] = 0.0;
   }
   wave_sync();
-  if (lane < k) rd[lane] = 1.0 / d[lane];
+  if (on) rd[lane] = 1.0 / d[lane];
   wave_sync();
+  double sc = 1.0;   // y is held unnormalised; sc is its pending scale
   if (lane == 0) {
-    for (int i = 0; i < k; i++) y[i] = 1.0;
     for (int rep = 0; rep < 3; rep++) {
-      // forward: y <- L^{-1} P y, in place
-      double cur = y[0];
-      for (int i = 0; i + 1 < k; i++) {
-        const double nx = y[i + 1];
-        if (sw[i] == 0.0) {
-          y[i] = cur;
-          cur = nx - f[i] * cur;
-        } else {
-          y[i] = nx;
-          cur = cur - f[i] * nx;
+      // forward: y <- L^{-1} P (sc y), in place (writes past row k - 1 are
+      // overwritten or never read)
+      double cur = y[0] * sc;
+      for (int c = 0; c + 1 < k; c += 8) {
+        double yv[8], fv[8], sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) { yv[u] = y[c + 1 + u]; fv[u] = f[c + u]; sv[u] = sw[c + u]; }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          // no swap: y_i = cur, cur' = nx - f cur; swap: y_i = nx, cur' = cur - f nx
+          const double nx = yv[u] * sc;
+          const bool swp = sv[u] != 0.0;
+          const double first = swp ? nx : cur, second = swp ? cur : nx;
+          y[c + u] = first;
+          const double ncur = second - fv[u] * first;
+          cur = c + u + 1 < k ? ncur : cur;
         }
       }
       y[k - 1] = cur;
-      // backward: y <- U^{-1} y
+      // backward: y <- U^{-1} y, from the last row up
       double y1 = 0.0, y2 = 0.0, n2 = 0.0;
-      for (int i = k - 1; i >= 0; i--) {
-        const double v = (y[i] - du[i] * y1 - du2[i] * y2) * rd[i];
-        y[i] = v;
-        n2 += v * v;
-        y2 = y1;
-        y1 = v;
+      for (int c = kp - 8; c >= 0; c -= 8) {
+        double yv[8], uv[8], u2v[8], rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) { yv[u] = y[c + u]; uv[u] = du[c + u]; u2v[u] = du2[c + u]; rv[u] = rd[c + u]; }
+#pragma unroll
+        for (int u = 7; u >= 0; u--) {
+          const double v = (yv[u] - uv[u] * y1 - u2v[u] * y2) * rv[u];
+          if (c + u < k) {
+            y[c + u] = v;
+            n2 += v * v;
+            y2 = y1;
+            y1 = v;
+          }
+        }
       }
-      const double inv = 1.0 / sqrt(n2);
-      for (int i = 0; i < k; i++) y[i] *= inv;
+      sc = 1.0 / sqrt(n2);
     }
-    // sign (a gauge): first component with magnitude >= 1e-8 of the largest one positive
-    double ymax = 0;
-    for (int i = 0; i < k; i++) ymax = fmax(ymax, fabs(y[i]));
-    int first = 0;
-    while (first < k - 1 && fabs(y[first]) < 1e-8 * ymax) first++;
-    const double sg = y[first] < 0 ? -1.0 : 1.0;
-    for (int i = 0; i < k; i++) st->y[i] = sg * y[i];
+  }
+  wave_sync();
+  sc = readlane_d(sc, 0);
+  // sign (a gauge): the first component with magnitude >= 1e-8 of the largest
+  // one is made positive
+  const double yl = on ? y[lane] * sc : 0.0;
+  const double ymax = wave_max(fabs(yl));
+  const unsigned long long big = __ballot(on && fabs(yl) >= 1e-8 * ymax);
+  const int first = big ? min(__ffsll((long long)big) - 1, k - 1) : k - 1;
+  const double sgn = readlane_d(yl, first) < 0 ? -1.0 : 1.0;
+  if (on) st->y[lane] = sgn * yl;
+  if (lane == 0) {
     st->scal[0] = theta;
     if (!isfinite(theta)) st->status = 1;
   }
@@ -1581,106 +1648,229 @@ __global__ __launch_bounds__(256) void k_tiny_assemble(const TJob* __restrict__ 
   H[e] = acc;
 }
 
-// Tiny-node Lanczos: one workgroup per job, one thread per vector entry
-// (M <= blockDim.x <= 1024).  The dense matvec splits the columns over
-// S = min(M, 1024 / M) slices whose partial sums are added in a fixed order;
-// every Gram-Schmidt dot product is taken by one wavefront.  Block sums add
-// the per-wave partials in wave order, and waves past M contribute zeros, so
-// the results do not depend on the workgroup size.
-// Dynamic LDS: partial sums [1024], then V [k][M] and w [M] when they fit in
-// the vcap bytes that follow (else V and w stay in the job's global buffers;
-// the arithmetic is the same either way).
-__device__ __forceinline__ double block_sum_waves(double v, double* red, int nw) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0;
-  for (int i = 0; i < nw; i++) s += red[i];
-  return s;
-}
+// Tiny-node Lanczos, the same steps in both kernels below:
+//   u = H V_j;  alpha_j = V_j . u;
+//   w = u - sum_{i<=j} (V_i . u) V_i;  w -= sum_{i<=j} (V_i . w) V_i
+//   (classical Gram-Schmidt twice, against the whole basis; in exact
+//   arithmetic the first pass removes alpha_j V_j and beta_{j-1} V_{j-1});
+//   beta_j = ||w||;  V_{j+1} = w / beta_j;
+// then the tridiagonal eigenpair and the Ritz vector.  Which kernel runs a
+// job, and every summation order, depend only on the job's M, so a job gives
+// the same bits alone or in a batch.
+constexpr int kTinyWaveM = 64;   // largest M of the one-wavefront kernel
+constexpr int64_t kTinyWaveLds = (64 * 64 + 64 * 65) * (int64_t)sizeof(double);
 
-__global__ __launch_bounds__(1024) void k_tiny_lanczos_lds(const TJob* __restrict__ jobs, int kreq,
-                                                           int64_t vcap) {
+// M <= 64: one wavefront per job, no barriers.  H and the basis in LDS (basis
+// rows padded to an odd stride); lane t owns vector entry t; lane i takes
+// the dot product with basis vector i.
+__global__ __launch_bounds__(64) void k_tiny_lanczos_wave(const TJob* __restrict__ jobs, int kreq) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[16];
-  __shared__ double hs[64];
+  __shared__ double ub[64], wb[64], hs[64], hs2[64];
   __shared__ double tri_lds[kTriLds];
   const TJob& J = jobs[blockIdx.x];
+  const int M = J.M;
+  if (M > kTinyWaveM) return;   // run by k_tiny_lanczos_block
   const double* __restrict__ H = J.H;
   double* __restrict__ T = J.T;
   KrylovState* __restrict__ st = J.st;
-  const int M = J.M, k = kreq < M ? kreq : M;
-  double* part = reinterpret_cast<double*>(smem_raw);
-  const bool in_lds = (int64_t)(k + 1) * M * (int64_t)sizeof(double) <= vcap;
-  double* V = in_lds ? part + 1024 : J.V;
-  double* w = in_lds ? V + (int64_t)k * M : J.w;
-  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int nthr = blockDim.x, nw = nthr >> 6;   // M <= nthr
-  const int S = max(1, min(M, 1024 / M));
+  const int k = kreq < M ? kreq : M;
+  const int t = threadIdx.x;
+  const int ldv = M | 1;
+  double* Hs = reinterpret_cast<double*>(smem_raw);   // [M][M], column c at c * M
+  double* V = Hs + 64 * 64;                            // [k][ldv]
+  for (int e = t; e < M * M; e += 64) Hs[e] = H[e];
   const bool mine = t < M;
   if (t == 0) { st->kmax = k; st->keff = 1; st->stop = 0; st->status = 0; }
   const double t0 = mine ? T[t] : 0.0;
-  const double nrm = sqrt(block_sum_waves(t0 * t0, red, nw));
+  const double nrm = sqrt(wave_sum(t0 * t0));
   if (mine) V[t] = t0 / nrm;
-  __syncthreads();
-  double beta_prev = 0, amax = 0;
+  wave_sync();
+  double amax = 0;
   int keff = 1;
   for (int j = 0; j < k; j++) {
-    const double* x = V + (int64_t)j * M;
-    for (int q = t; q < S * M; q += nthr) {   // w = H x, slice sl of the columns
-      const int r = q % M, sl = q / M;
-      double acc = 0;
-      int c = sl;
-      for (; c + 7 * S < M; c += 8 * S) {   // eight loads in flight
-        double hv[8];
-#pragma unroll
-        for (int u = 0; u < 8; u++) hv[u] = H[(int64_t)(c + u * S) * M + r];
-#pragma unroll
-        for (int u = 0; u < 8; u++) acc += hv[u] * x[c + u * S];
-      }
-      for (; c < M; c += S) acc += H[(int64_t)c * M + r] * x[c];
-      part[sl * M + r] = acc;
-    }
-    __syncthreads();
-    double wv = 0, xv = 0;
+    const double* x = V + j * ldv;
+    double u = 0;
     if (mine) {
-      for (int sl = 0; sl < S; sl++) wv += part[sl * M + t];
-      xv = x[t];
+#pragma unroll 8
+      for (int c = 0; c < M; c++) u += Hs[c * M + t] * x[c];
+      ub[t] = u;
     }
-    const double a = block_sum_waves(xv * wv, red, nw);
+    wave_sync();
+    if (t <= j) {
+      const double* vi = V + t * ldv;
+      double d = 0;
+#pragma unroll 8
+      for (int e = 0; e < M; e++) d += vi[e] * ub[e];
+      hs[t] = d;
+    }
+    wave_sync();
+    const double a = hs[j];
     if (t == 0) st->alpha[j] = a;
     amax = fmax(amax, fabs(a));
     if (j == k - 1) break;
+    double w = u;
     if (mine) {
-      wv -= a * xv;
-      if (j > 0) wv -= beta_prev * V[(int64_t)(j - 1) * M + t];
+      for (int i = 0; i <= j; i++) w -= hs[i] * V[i * ldv + t];
+      wb[t] = w;
+    }
+    wave_sync();
+    if (t <= j) {
+      const double* vi = V + t * ldv;
+      double d = 0;
+#pragma unroll 8
+      for (int e = 0; e < M; e++) d += vi[e] * wb[e];
+      hs2[t] = d;
+    }
+    wave_sync();
+    if (mine) {
+      for (int i = 0; i <= j; i++) w -= hs2[i] * V[i * ldv + t];
+      wb[t] = w;
+    }
+    wave_sync();
+    double n2 = 0;
+#pragma unroll 8
+    for (int e = 0; e < M; e++) n2 += wb[e] * wb[e];
+    const double b = sqrt(n2);
+    if (!(b > 1e-14 * amax)) break;
+    if (t == 0) st->beta[j] = b;
+    keff = j + 2;
+    if (mine) V[(j + 1) * ldv + t] = w / b;
+    wave_sync();
+  }
+  if (t == 0) st->keff = keff;
+  wave_sync();
+  tridiag_solve_wave(st, tri_lds);
+  wave_sync();
+  if (t < keff) hs[t] = st->y[t];
+  wave_sync();
+  double u = 0;
+  if (mine)
+    for (int i = 0; i < keff; i++) u += hs[i] * V[i * ldv + t];
+  const double nr = sqrt(wave_sum(u * u));
+  if (mine) T[t] = u / nr;
+  if (t == 0 && !(nr > 0 && isfinite(nr))) st->status = 1;
+}
+
+// Sum over the first nwm wavefronts of v (one value per thread, zeros past the
+// vector), in wave order; a barrier must separate two calls.
+__device__ __forceinline__ double block_sum_nw(double v, double* red, int nwm) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0;
+  for (int i = 0; i < nwm; i++) s += red[i];
+  return s;
+}
+
+// 64 < M <= 1024: one workgroup of 1024 threads per job; thread t owns vector
+// entry t.  The dense matvec splits the columns over S = min(M, 1024 / M)
+// slices (thread S-slice sl, row r), 16 loads of H in flight per thread; the
+// slices' partial sums are added in a fixed order.  Each Gram-Schmidt dot
+// product is taken by one wavefront.  The product of step j + 1 runs on the
+// unnormalised w of step j and is scaled by 1 / beta_j afterwards, so the new
+// basis vector needs no barrier of its own.
+// Dynamic LDS: partial sums [1024], H x [1024], then (VL) the basis [k][M] and
+// w [M]; without VL the basis and w stay in the job's global buffers.
+__host__ __device__ __forceinline__ int64_t tiny_basis_bytes(int M, int kreq) {
+  const int64_t k = kreq < M ? kreq : M;
+  return (k + 1) * M * (int64_t)sizeof(double);
+}
+constexpr int64_t kTinyBlockFixed = 2048 * (int64_t)sizeof(double);
+
+template <bool VL>
+__global__ __launch_bounds__(1024) void k_tiny_lanczos_block(const TJob* __restrict__ jobs, int kreq) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[16];
+  __shared__ double hs[64], hs2[64];
+  __shared__ double tri_lds[kTriLds];
+  const TJob& J = jobs[blockIdx.x];
+  const int M = J.M;
+  if (M <= kTinyWaveM) return;   // run by k_tiny_lanczos_wave
+  if ((tiny_basis_bytes(M, kreq) <= (int64_t)kTinyLdsMax - kTinyBlockFixed) != VL) return;   // other form
+  const __attribute__((address_space(1))) double* __restrict__ H =
+      (const __attribute__((address_space(1))) double*)J.H;
+  double* __restrict__ T = J.T;
+  KrylovState* __restrict__ st = J.st;
+  const int k = kreq < M ? kreq : M;
+  double* part = reinterpret_cast<double*>(smem_raw);
+  double* ub = part + 1024;
+  double* V = VL ? ub + 1024 : J.V;
+  double* w = VL ? V + (int64_t)k * M : J.w;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int S = max(1, min(M, 1024 / M));
+  const int nwm = (M + 63) >> 6;
+  const bool mine = t < M;
+  if (t == 0) { st->kmax = k; st->keff = 1; st->stop = 0; st->status = 0; }
+  const double t0 = mine ? T[t] : 0.0;
+  const double nrm = sqrt(block_sum_nw(t0 * t0, red, nwm));
+  if (mine) V[t] = t0 / nrm;
+  __syncthreads();
+  const double* xp = V;   // vector multiplied by H in this step ...
+  double xs = 1.0;        // ... and the scale applied to the product
+  double amax = 0;
+  int keff = 1;
+  double wv = 0;
+  for (int j = 0; j < k; j++) {
+    if (t < S * M) {
+      const int r = t % M, sl = t / M;
+      const __attribute__((address_space(1))) double* hp = H + r;
+      double acc = 0;
+      int c = sl;
+      for (; c + 15 * S < M; c += 16 * S) {
+        double hv[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) hv[u] = hp[(int64_t)(c + u * S) * M];
+#pragma unroll
+        for (int u = 0; u < 16; u++) acc += hv[u] * xp[c + u * S];
+      }
+      for (; c < M; c += S) acc += hp[(int64_t)c * M] * xp[c];
+      part[sl * M + r] = acc;
+    }
+    __syncthreads();
+    double u = 0;
+    if (mine) {
+      for (int sl = 0; sl < S; sl++) u += part[sl * M + t];
+      u *= xs;
+      ub[t] = u;
+      if (j > 0) V[(int64_t)j * M + t] = wv * xs;
+    }
+    __syncthreads();
+    for (int i = wave; i <= j; i += 16) {   // V_i . u
+      const double* vi = V + (int64_t)i * M;
+      double d = 0;
+      for (int e = lane; e < M; e += 64) d += vi[e] * ub[e];
+      d = wave_sum(d);
+      if (lane == 0) hs[i] = d;
+    }
+    __syncthreads();
+    const double a = hs[j];
+    if (t == 0) st->alpha[j] = a;
+    amax = fmax(amax, fabs(a));
+    if (j == k - 1) break;
+    wv = u;
+    if (mine) {
+      for (int i = 0; i <= j; i++) wv -= hs[i] * V[(int64_t)i * M + t];
       w[t] = wv;
     }
     __syncthreads();
-    for (int pass = 0; pass < 2; pass++) {
-      for (int i = wave; i <= j; i += nw) {   // hs[i] = V_i . w
-        double d = 0;
-        for (int e = lane; e < M; e += 64) d += V[(int64_t)i * M + e] * w[e];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
-        if (lane == 0) hs[i] = d;
-      }
-      __syncthreads();
-      if (mine) {
-        for (int i = 0; i <= j; i++) wv -= hs[i] * V[(int64_t)i * M + t];
-        w[t] = wv;
-      }
-      __syncthreads();
+    for (int i = wave; i <= j; i += 16) {   // V_i . w
+      const double* vi = V + (int64_t)i * M;
+      double d = 0;
+      for (int e = lane; e < M; e += 64) d += vi[e] * w[e];
+      d = wave_sum(d);
+      if (lane == 0) hs2[i] = d;
     }
-    const double b = sqrt(block_sum_waves(wv * wv, red, nw));
+    __syncthreads();
+    if (mine) {
+      for (int i = 0; i <= j; i++) wv -= hs2[i] * V[(int64_t)i * M + t];
+      w[t] = wv;
+    }
+    const double b = sqrt(block_sum_nw(wv * wv, red, nwm));
     if (!(b > 1e-14 * amax)) break;
     if (t == 0) st->beta[j] = b;
-    beta_prev = b;
     keff = j + 2;
-    if (mine) V[(int64_t)(j + 1) * M + t] = wv / b;
-    __syncthreads();
+    xp = w;
+    xs = 1.0 / b;
   }
   if (t == 0) st->keff = keff;
   __syncthreads();
@@ -1691,17 +1881,9 @@ __global__ __launch_bounds__(1024) void k_tiny_lanczos_lds(const TJob* __restric
   double u = 0;
   if (mine)
     for (int i = 0; i < keff; i++) u += hs[i] * V[(int64_t)i * M + t];
-  const double nr = sqrt(block_sum_waves(u * u, red, nw));
+  const double nr = sqrt(block_sum_nw(u * u, red, nwm));
   if (mine) T[t] = u / nr;
   if (t == 0 && !(nr > 0 && isfinite(nr))) st->status = 1;
-}
-
-// bytes for V and w of the largest job, capped
-int64_t tiny_vcap(int maxM, int kreq) {
-  const int64_t k = kreq < maxM ? kreq : maxM;
-  const int64_t need = (k + 1) * maxM * (int64_t)sizeof(double);
-  const int64_t cap = (int64_t)kTinyLdsMax - 1024 * (int64_t)sizeof(double);
-  return need < cap ? need : cap;
 }
 
 // out = sum_i y_i V_i with partial ||out||^2
@@ -2935,16 +3117,21 @@ hipError_t launch_kritz(const KJob* jobs, int nj, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tiny(const TJob* jobs, int nj, int maxM, int kreq, hipStream_t s) {
+hipError_t launch_tiny(const TJob* jobs, int nj, int minM, int maxM, int kreq, hipStream_t s) {
+  if (maxM > 1024 || minM < 1 || minM > maxM) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_tiny_assemble, dim3((unsigned)(((int64_t)maxM * maxM + 255) / 256), nj), dim3(256),
                      0, s, jobs);
-  if (maxM > 1024) return hipErrorInvalidValue;
-  const int64_t vcap = tiny_vcap(maxM, kreq);
-  // enough threads for one per entry and for the matvec's S x M partial sums
-  const int pairs = std::min(maxM * maxM, 1024);
-  const int nthr = std::max(64, std::min(1024, (std::max(pairs, maxM) + 63) / 64 * 64));
-  hipLaunchKernelGGL(k_tiny_lanczos_lds, dim3(nj), dim3(nthr), (size_t)(vcap + 1024 * sizeof(double)), s, jobs,
-                     kreq, vcap);
+  if (minM <= kTinyWaveM)
+    hipLaunchKernelGGL(k_tiny_lanczos_wave, dim3(nj), dim3(64), (size_t)kTinyWaveLds, s, jobs, kreq);
+  if (maxM > kTinyWaveM) {
+    // jobs whose basis fits in LDS run in the first form, the others in the second
+    const int64_t cap = (int64_t)kTinyLdsMax - kTinyBlockFixed;
+    const int64_t need = tiny_basis_bytes(maxM, kreq);
+    hipLaunchKernelGGL(k_tiny_lanczos_block<true>, dim3(nj), dim3(1024),
+                       (size_t)(kTinyBlockFixed + (need < cap ? need : cap)), s, jobs, kreq);
+    if (need > cap)
+      hipLaunchKernelGGL(k_tiny_lanczos_block<false>, dim3(nj), dim3(1024), (size_t)kTinyBlockFixed, s, jobs, kreq);
+  }
   return hipGetLastError();
 }
 
@@ -3074,7 +3261,10 @@ hipError_t prepare_kernel_attributes() {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
   }
-  return hipFuncSetAttribute((const void*)k_tiny_lanczos_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+  hipError_t e = hipFuncSetAttribute((const void*)k_tiny_lanczos_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kTinyWaveLds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_tiny_lanczos_block<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)kTinyLdsMax);
 }
 

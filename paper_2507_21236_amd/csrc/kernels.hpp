@@ -158,7 +158,7 @@ struct KJob {
 
 // ---------------------------------------------------------------- tiny nodes
 // Whole matvec plan of a node whose contractions all use the generic kernels,
-// executed inside one workgroup (see k_tiny_lanczos_lds).
+// executed inside one workgroup (the tiny-node Lanczos kernels).
 // Three-operator product item (one operator per leg) of a three-leg term.
 struct Item3 {
   const void* op[3];

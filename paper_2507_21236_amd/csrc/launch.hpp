@@ -43,7 +43,7 @@ hipError_t launch_kortho(const KJob* jobs, int nj, int j, int pin, int norm_only
 hipError_t launch_kbeta(const KJob* jobs, int nj, int j, int64_t nmax, hipStream_t s);
 hipError_t launch_ktridiag(const KJob* jobs, int nj, hipStream_t s);
 hipError_t launch_kritz(const KJob* jobs, int nj, hipStream_t s);
-hipError_t launch_tiny(const TJob* jobs, int nj, int maxM, int kreq, hipStream_t s);
+hipError_t launch_tiny(const TJob* jobs, int nj, int minM, int maxM, int kreq, hipStream_t s);
 
 // Mixed-shape launches over the tasks of several nodes / problem instances
 // (LDS in bytes: the largest any unit of the launch needs).

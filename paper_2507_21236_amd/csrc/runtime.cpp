@@ -987,7 +987,7 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
   run_comb(D.comb, s);
   // tiny nodes (dense H_eff, negligible work) stay in FP64 for every form
   if (D.d_tiny) {
-    HIPCHK(launch_tiny(h->d_tjobs + n, 1, (int)Msz, kk, s));
+    HIPCHK(launch_tiny(h->d_tjobs + n, 1, (int)Msz, (int)Msz, kk, s));
     h->n_matvec += k;
     h->mv_flops += (double)k * h->M.mv[n].flops;
     if (h->defer_status) {
