@@ -35,6 +35,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// A failure status of the eigensolver / QR state, also collected in the
+// sticky word that sweeps read once at their end.
+__device__ __forceinline__ void fail_status(KrylovState* st, int v) {
+  st->status = v;
+  atomicOr(&st->sticky, v);
+}
+
 // accumulator row of item i in lane group g = lane / 16
 template <typename T> __device__ __forceinline__ int drow(int g, int i);
 template <> __device__ __forceinline__ int drow<double>(int g, int i) { return g + 4 * i; }
@@ -1183,7 +1190,7 @@ __global__ __launch_bounds__(256) void k_kscale(const KJob* __restrict__ jobs, i
   __shared__ double red[4];
   const KJob& J = jobs[blockIdx.y];
   const double nr = sqrt(sum_partials(parea(J, 0), red));
-  if (blockIdx.x == 0 && threadIdx.x == 0 && !(nr > 0 && isfinite(nr))) J.st->status = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !(nr > 0 && isfinite(nr))) fail_status(J.st, 1);
   const double inv = 1.0 / nr;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)gridDim.x * 256) {
     const double v = J.T[e] * inv;
@@ -1213,7 +1220,7 @@ __global__ __launch_bounds__(256) void k_kalpha(const KJob* __restrict__ jobs, i
   const double a = sum_partials(parea(J, 0), red);
   if (threadIdx.x == 0) {
     J.st->alpha[j] = a;
-    if (!isfinite(a)) J.st->status = 1;
+    if (!isfinite(a)) fail_status(J.st, 1);
   }
 }
 
@@ -1273,37 +1280,22 @@ __device__ __forceinline__ void sums_of_partials(const double* __restrict__ p, i
   __syncthreads();
 }
 
-// alpha_j = sum P0; w -= alpha_j v_j + beta_{j-1} v_{j-1}; P1 = partial dots V[0..j] . w
-__global__ __launch_bounds__(256) void k_kupdate(const KJob* __restrict__ jobs, int j) {
-  __shared__ double red[4];
+// P1 = partial dots V[0..j] . w of the product w = H v_j.  The two classical
+// Gram-Schmidt passes that follow run against the whole basis, so the first
+// one also removes alpha_j v_j and beta_{j-1} v_{j-1} (alpha_j = v_j . w is the
+// partial sum of dot j, the same bits as a separate dot product).
+__global__ __launch_bounds__(256) void k_kdots(const KJob* __restrict__ jobs, int j) {
   const KJob& J = jobs[blockIdx.y];
-  KrylovState* st = J.st;
-  if (st->stop) return;
-  const int64_t n = J.n;
-  double* w = J.w;
-  const double a = sum_partials(parea(J, 0), red);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->alpha[j] = a;
-    if (!isfinite(a)) st->status = 1;
-  }
-  const int b = blockIdx.x;
-  const double bb = j > 0 ? st->beta[j - 1] : 0.0;
-  const double* vj = J.V + (int64_t)j * n;
-  const double* vm = j > 0 ? J.V + (int64_t)(j - 1) * n : J.V;
-  for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
-    double x = w[e] - a * vj[e];
-    if (j > 0) x -= bb * vm[e];
-    w[e] = x;
-  }
-  // the same thread touches the same elements below: no barrier needed for w
+  if (J.st->stop) return;
   __shared__ double red8[4 * kDotChunk];
-  block_dots(J, w, j + 1, parea(J, 1), red8);
+  block_dots(J, J.w, j + 1, parea(J, 1), red8);
 }
 
 // classical Gram-Schmidt pass against V[0..j]: h = sums of P(pin); w -= sum h_i V_i;
-// then P(pin + 1) = partial dots V[0..j] . w, or ||w||^2 when norm_only
+// then P(pin + 1) = partial dots V[0..j] . w, or ||w||^2 when norm_only.
+// set_alpha (first pass): alpha_j = h_j.
 __global__ __launch_bounds__(256) void k_kortho(const KJob* __restrict__ jobs, int j, int pin,
-                                                int norm_only) {
+                                                int norm_only, int set_alpha) {
   __shared__ double red[4];
   __shared__ double hs[128];
   const KJob& J = jobs[blockIdx.y];
@@ -1313,6 +1305,10 @@ __global__ __launch_bounds__(256) void k_kortho(const KJob* __restrict__ jobs, i
   double* w = J.w;
   __shared__ double red8[4 * kDotChunk];
   sums_of_partials(parea(J, pin), nv, hs, red8);
+  if (set_alpha && blockIdx.x == 0 && threadIdx.x == 0) {
+    J.st->alpha[j] = hs[j];
+    if (!isfinite(hs[j])) fail_status(J.st, 1);
+  }
   const int b = blockIdx.x;
   for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
     double x = w[e];
@@ -1343,7 +1339,7 @@ __global__ __launch_bounds__(256) void k_kbeta(const KJob* __restrict__ jobs, in
   const bool brk = !(b > 1e-14 * amax);
   __syncthreads();   // every block has read the state before block 0 updates it
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (!isfinite(b)) st->status = 1;
+    if (!isfinite(b)) fail_status(st, 1);
     if (brk) st->stop = 1;
     else { st->beta[j] = b; st->keff = j + 2; }
   }
@@ -1598,7 +1594,7 @@ __device__ __forceinline__ void tridiag_solve_wave(KrylovState* __restrict__ st,
   if (on) st->y[lane] = sgn * yl;
   if (lane == 0) {
     st->scal[0] = theta;
-    if (!isfinite(theta)) st->status = 1;
+    if (!isfinite(theta)) fail_status(st, 1);
   }
 }
 
@@ -1748,7 +1744,7 @@ __global__ __launch_bounds__(64) void k_tiny_lanczos_wave(const TJob* __restrict
     for (int i = 0; i < keff; i++) u += hs[i] * V[i * ldv + t];
   const double nr = sqrt(wave_sum(u * u));
   if (mine) T[t] = u / nr;
-  if (t == 0 && !(nr > 0 && isfinite(nr))) st->status = 1;
+  if (t == 0 && !(nr > 0 && isfinite(nr))) fail_status(st, 1);
 }
 
 // Sum over the first nwm wavefronts of v (one value per thread, zeros past the
@@ -1883,7 +1879,7 @@ __global__ __launch_bounds__(1024) void k_tiny_lanczos_block(const TJob* __restr
     for (int i = 0; i < keff; i++) u += hs[i] * V[(int64_t)i * M + t];
   const double nr = sqrt(block_sum_nw(u * u, red, nwm));
   if (mine) T[t] = u / nr;
-  if (t == 0 && !(nr > 0 && isfinite(nr))) st->status = 1;
+  if (t == 0 && !(nr > 0 && isfinite(nr))) fail_status(st, 1);
 }
 
 // out = sum_i y_i V_i with partial ||out||^2
@@ -2649,7 +2645,7 @@ __global__ __launch_bounds__(64) void k_chol_inv_reg(const double* __restrict__ 
   for (int i = 0; i < N; i++) x[i] = (i == lane) ? 1.0 : 0.0;
   rowbuf[0][lane] = x[0];
   trinv_steps<N, 0>(x, Lc, rowbuf, RinvRow, lane, own);
-  if (lane == 0 && bad && st) st->status = 2;
+  if (lane == 0 && bad && st) fail_status(st, 2);
 }
 
 // (b) other n (<= 128): LDS-resident packed triangles, rank-1 updates over a
@@ -2709,7 +2705,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, 
       R[(int64_t)j * n + i] = (i <= j) ? L[tri(j, i)] : 0.0;
       RinvRow[(int64_t)i * n + j] = (i <= j) ? X[tri(j, i)] : 0.0;
     }
-  if (t == 0 && bad && st) st->status = 2;
+  if (t == 0 && bad && st) fail_status(st, 2);
 }
 
 // Householder QR of a small matricisation in one workgroup (rows * n <= 16384,
@@ -2802,7 +2798,7 @@ __global__ __launch_bounds__(256) void k_qr_small(double* __restrict__ T, int d0
     const int64_t f = e - (int64_t)c * rows;
     T[mode_addr(j, d0, d1, d2, c, f)] = A[e] * sgn[c];
   }
-  if (t == 0 && st && !isfinite(tau[0])) st->status = 2;
+  if (t == 0 && st && !isfinite(tau[0])) fail_status(st, 2);
 }
 
 // C = A B for n x n column-major matrices, one thread per output element
@@ -3092,13 +3088,13 @@ hipError_t launch_kalpha(const KJob* jobs, int nj, int j, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_kupdate(const KJob* jobs, int nj, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_kupdate, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs, j);
+hipError_t launch_kdots(const KJob* jobs, int nj, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_kdots, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs, j);
   return hipGetLastError();
 }
 
-hipError_t launch_kortho(const KJob* jobs, int nj, int j, int pin, int norm_only, hipStream_t s) {
-  hipLaunchKernelGGL(k_kortho, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs, j, pin, norm_only);
+hipError_t launch_kortho(const KJob* jobs, int nj, int j, int pin, int norm_only, int set_alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_kortho, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs, j, pin, norm_only, set_alpha);
   return hipGetLastError();
 }
 
@@ -3197,21 +3193,6 @@ hipError_t launch_reduce_list(int dtype_in, const RDTask* tasks, int ntask, int6
     hipLaunchKernelGGL((k_reduce_list<double, double>), dim3(gridv(maxM), ntask), dim3(256), 0, s, tasks);
   else
     hipLaunchKernelGGL((k_reduce_list<float, double>), dim3(gridv(maxM), ntask), dim3(256), 0, s, tasks);
-  return hipGetLastError();
-}
-
-// sticky[0] |= status of st (and a non-finite eigenvalue when with_theta);
-// sticky[1] counts the calls.  One thread: the state is a single struct.
-__global__ void k_status_accum(const KrylovState* __restrict__ st, int* __restrict__ sticky, int with_theta) {
-  if (threadIdx.x != 0) return;
-  int bad = st->status;
-  if (with_theta && !isfinite(st->scal[0])) bad |= 1;
-  sticky[0] |= bad;
-  sticky[1] += 1;
-}
-
-hipError_t launch_status_accum(const KrylovState* st, int* sticky, int with_theta, hipStream_t s) {
-  hipLaunchKernelGGL(k_status_accum, dim3(1), dim3(64), 0, s, st, sticky, with_theta);
   return hipGetLastError();
 }
 

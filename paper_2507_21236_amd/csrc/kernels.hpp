@@ -142,6 +142,8 @@ struct KrylovState {
   int32_t keff;       // number of Lanczos vectors kept
   int32_t stop;       // breakdown reached
   int32_t status;     // 0 ok, 1 non-finite, 2 factorisation breakdown
+  int32_t sticky;     // OR of every nonzero status set since it was last cleared
+  int32_t pad;
 };
 
 // One Lanczos eigensolve (one node of one problem instance).

@@ -38,8 +38,8 @@ hipError_t launch_knorm(const KJob* jobs, int nj, hipStream_t s);
 hipError_t launch_kscale(const KJob* jobs, int nj, int64_t nmax, int mode, hipStream_t s);
 hipError_t launch_kdot(const KJob* jobs, int nj, int j, hipStream_t s);
 hipError_t launch_kalpha(const KJob* jobs, int nj, int j, hipStream_t s);
-hipError_t launch_kupdate(const KJob* jobs, int nj, int j, hipStream_t s);
-hipError_t launch_kortho(const KJob* jobs, int nj, int j, int pin, int norm_only, hipStream_t s);
+hipError_t launch_kdots(const KJob* jobs, int nj, int j, hipStream_t s);
+hipError_t launch_kortho(const KJob* jobs, int nj, int j, int pin, int norm_only, int set_alpha, hipStream_t s);
 hipError_t launch_kbeta(const KJob* jobs, int nj, int j, int64_t nmax, hipStream_t s);
 hipError_t launch_ktridiag(const KJob* jobs, int nj, hipStream_t s);
 hipError_t launch_kritz(const KJob* jobs, int nj, hipStream_t s);
@@ -54,8 +54,6 @@ hipError_t launch_batch_mode(int dtype, const MPTask* tasks, const MPJob* jobs, 
 hipError_t launch_transpose_list(int dtype, const TRTask* tasks, int ntask, int64_t maxM, hipStream_t s);
 hipError_t launch_reduce_list(int dtype_in, const RDTask* tasks, int ntask, int64_t maxM, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
-// sticky[0] |= st->status (| 1 for a non-finite eigenvalue when with_theta); sticky[1]++
-hipError_t launch_status_accum(const KrylovState* st, int* sticky, int with_theta, hipStream_t s);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 hipError_t prepare_kernel_attributes();
 

@@ -991,7 +991,6 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
     h->n_matvec += k;
     h->mv_flops += (double)k * h->M.mv[n].flops;
     if (h->defer_status) {
-      HIPCHK(launch_status_accum(h->d_st, h->d_sticky, 1, s));
       if (nmv) *nmv = k;
       return std::nan("");
     }
@@ -1015,21 +1014,20 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
   for (int j = 0; j < k; j++) {
     if (precision == ATTN_F64) matvec_f64(h, n, V + (int64_t)j * Msz, h->d_w, s);
     else matvec_lowp(h, n, precision, h->d_x32, h->d_w, 0, s);
-    HIPCHK(launch_kdot(J, 1, j, s));
-    if (j == k - 1) {
+    if (j == k - 1) {   // last step: only alpha_j
+      HIPCHK(launch_kdot(J, 1, j, s));
       HIPCHK(launch_kalpha(J, 1, j, s));
       break;
     }
-    HIPCHK(launch_kupdate(J, 1, j, s));
-    HIPCHK(launch_kortho(J, 1, j, 1, 0, s));
-    HIPCHK(launch_kortho(J, 1, j, 2, 1, s));
+    HIPCHK(launch_kdots(J, 1, j, s));
+    HIPCHK(launch_kortho(J, 1, j, 1, 0, 1, s));
+    HIPCHK(launch_kortho(J, 1, j, 2, 1, 0, s));
     HIPCHK(launch_kbeta(J, 1, j, Msz, s));
   }
   HIPCHK(launch_ktridiag(J, 1, s));
   HIPCHK(launch_kritz(J, 1, s));
   HIPCHK(launch_kscale(J, 1, Msz, 1, s));
   if (h->defer_status) {
-    HIPCHK(launch_status_accum(h->d_st, h->d_sticky, 1, s));
     if (nmv) *nmv = k;
     return std::nan("");
   }
@@ -1300,7 +1298,6 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
     h->cv_cap = 6 + 2 * (int)std::max<size_t>(1, [&] { size_t mx = 0; for (int n = 0; n < nn; n++) mx = std::max(mx, h->M.mv[n].combines.size()); return mx; }());
     h->d_cvtasks = dev_alloc(h, (size_t)h->cv_cap * sizeof(CVTask));
     h->d_st = (KrylovState*)dev_alloc(h, sizeof(KrylovState));
-    h->d_sticky = (int*)dev_alloc(h, 2 * sizeof(int));
     // device plans
     h->mv.assign(nn, MVDev());
     h->comb_blocks.assign(nn, {});
@@ -1540,7 +1537,6 @@ attn_status attn_isometrize(attn_handle* h, int32_t from, int32_t to, void* stre
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(hipSetDevice(h->device));
     qr_node(h, from, leg, s);
-    if (h->defer_status) HIPCHK(launch_status_accum(h->d_st, h->d_sticky, 0, s));
     absorb(h, to, leg_toward(tr, to, from), s);
     h->iso[from] = leg;
     h->iso[to] = -1;
@@ -1881,12 +1877,12 @@ attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* 
   // the last eigenvalue) once per sweep, so the host never waits inside a
   // sweep; the Davidson form steers its restarts from the host and keeps its
   // own synchronisation.
-  const bool defer = so.solver == ATTN_SOLVER_LANCZOS && !h->dead && h->d_sticky;
+  const bool defer = so.solver == ATTN_SOLVER_LANCZOS && !h->dead && h->d_st;
   for (int sw = 0; sw < n_sweeps; sw++) {
     auto t0 = std::chrono::steady_clock::now();
     double th = 0;
     if (defer) {
-      if (hipSetDevice(h->device) != hipSuccess || launch_zero_int(h->d_sticky, 2, nullptr) != hipSuccess) {
+      if (hipSetDevice(h->device) != hipSuccess || launch_zero_int(&h->d_st->sticky, 1, nullptr) != hipSuccess) {
         h->err = "status reset failed";
         return ATTN_ERR_HIP;
       }
@@ -1900,16 +1896,14 @@ attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* 
     h->defer_status = false;
     if (hipDeviceSynchronize() != hipSuccess) { h->err = "device synchronisation failed"; return ATTN_ERR_HIP; }
     if (defer) {
-      int sticky[2] = {0, 0};
       KrylovState st;
-      if (hipMemcpy(sticky, h->d_sticky, sizeof(sticky), hipMemcpyDeviceToHost) != hipSuccess ||
-          hipMemcpy(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) {
+      if (hipMemcpy(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) {
         h->err = "status read failed";
         h->dead = true;
         return ATTN_ERR_HIP;
       }
-      if (sticky[0] != 0) {
-        h->err = (sticky[0] & 2) ? "sweep: QR factorisation broke down" : "sweep: non-finite value in the eigensolver";
+      if (st.sticky != 0) {
+        h->err = (st.sticky & 2) ? "sweep: QR factorisation broke down" : "sweep: non-finite value in the eigensolver";
         h->dead = true;
         return ATTN_ERR_NUMERIC;
       }

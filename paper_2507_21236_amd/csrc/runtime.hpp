@@ -193,9 +193,8 @@ struct attn_handle {
   int cv_cap = 0;
   int mmax = 1;
   KrylovState* d_st = nullptr;
-  // sweeps: per-node status checks run on the device (no host round trip per
-  // node); d_sticky[0] collects every status, d_sticky[1] counts the checks
-  int* d_sticky = nullptr;
+  // sweeps: per-node status checks stay on the device (no host round trip per
+  // node); every failure status also lands in d_st->sticky, read once per sweep
   bool defer_status = false;
   KJob* d_kjobs64 = nullptr;  // per node: eigensolve descriptors (FP64 / with FP32 copy)
   KJob* d_kjobs32 = nullptr;
