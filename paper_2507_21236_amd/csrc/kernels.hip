@@ -2529,127 +2529,178 @@ __global__ __launch_bounds__(256) void k_harvest_write(const double* __restrict_
 
 // ============================================================================ QR helpers
 // Cholesky of G + shift*I = L L^T (R = L^T upper with positive diagonal) and
-// the inverse of R, one workgroup.  L and X = L^{-1} are kept in LDS as packed
-// lower triangles (n (n + 1) doubles in total, n <= 128).  G is column-major.
-// Outputs: R column-major, RinvRow = R^{-1} row-major (= X^T column-major).
+// the inverse of R, one workgroup.  G is column-major.  Outputs: R
+// column-major, RinvRow = R^{-1} row-major (= X = L^{-1} column-major).
 // shift_mode 1: shift = 11 (rows n + n (n + 1)) u trace(G) (shifted CholeskyQR
 // of Fukaya et al.), making the factorisation safe for ill-conditioned input.
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// (a) n = 16, 32, 48 or 64: one wavefront.  Lane j keeps column j of the
-//     symmetric trailing matrix in registers (both triangles, so that row k,
-//     the broadcast operand of step k, is held one entry per lane); row k is
-//     published in LDS by the update of step k - 1 and read back as
-//     broadcasts.  Steps go in blocks of 16 with a rolled loop inside each
-//     block (a fully unrolled factorisation does not fit the instruction
-//     cache); the update of a block's steps covers every row from the block
-//     start on, so the broadcast reads of a step are issued together (rows
-//     already eliminated receive updates that are never read).  L is kept
-//     column-major in LDS; X = L^{-1} column j is formed in lane j by forward
-//     substitution with the columns of L broadcast, each finished entry stored
-//     as it is produced.
-template <int N, int I0>
-__device__ __forceinline__ void bcast_axpy(double (&v)[N], const double* __restrict__ src, double a) {
-  // v[i] -= src[i] * a for i in [I0, N), reads issued in chunks of 16
-#pragma unroll
-  for (int i0 = I0; i0 < N; i0 += 16) {
-    double t[16];
-#pragma unroll
-    for (int u = 0; u < 16; u++)
-      if (i0 + u < N) t[u] = src[i0 + u];
-#pragma unroll
-    for (int u = 0; u < 16; u++)
-      if (i0 + u < N) v[i0 + u] = fma(-t[u], a, v[i0 + u]);
-  }
-}
+// (a) n = 16, 32, 48 or 64, blocked, one wavefront; A (the trailing matrix,
+//      then L) and X = L^{-1} column-major in LDS with an odd stride.
+//      Cholesky by panels of 16 columns: a panel is factorised with one lane
+//      per row (the row's 16 panel entries in registers; the pivot and the
+//      panel column broadcast by readlane), then the trailing matrix takes the
+//      rank-16 update A_IJ -= L_I L_J^T on the matrix cores, one 16 x 16 tile
+//      (I >= J) at a time.  The inverse: the diagonal blocks X_bb = L_bb^{-1}
+//      by forward substitution (lane group b of 16 lanes, one lane per
+//      column), then the blocks below the diagonal block row by block row,
+//      X_IJ = -X_II (sum_{J <= K < I} L_IK X_KJ), on the matrix cores: the
+//      accumulator item s of T = sum L X holds rows 4 s + lane / 16 of T,
+//      exactly the B operand of K-slice s of X_II T.
+constexpr int kCholLd = 65;
 
-template <int N, int KB>
-__device__ __forceinline__ void chol_steps(double (&c)[N], double* Lc, double (*rowbuf)[64], double* sb,
-                                           int lane, bool own, int& bad) {
-  constexpr int LD = N + 1;
-#pragma unroll 1
-  for (int k = 16 * KB; k < 16 * KB + 16; k++) {
-    const int cur = k & 1;
-    const double rk = rowbuf[cur][lane];                  // A(k, lane)
-    const double d = rowbuf[cur][k];
+template <int NB, int KB>
+__device__ __forceinline__ void chol_panel(double* A, int lane, int& bad) {
+  constexpr int c0 = 16 * KB;
+  double p[16];
+#pragma unroll
+  for (int u = 0; u < 16; u++) p[u] = A[(c0 + u) * kCholLd + lane];
+#pragma unroll
+  for (int u = 0; u < 16; u++) {
+    const int k = c0 + u;
+    const double d = readlane_d(p[u], k);
     if (!(d > 0.0) || !isfinite(d)) bad = 1;
-    const double piv = sqrt(fmax(d, 1e-300));
-    const double inv = 1.0 / piv;
-    const double rks = rk * inv;                          // L(lane, k) for lane > k
-    const double ljk = (own && lane > k) ? rks : 0.0;
-    sb[lane] = rks;
-    if (own) Lc[k * LD + lane] = lane == k ? piv : ljk;   // column k of L (zero above the diagonal)
-    wave_sync();
-    bcast_axpy<N, 16 * KB + 1>(c, sb, ljk);
+    // 1 / sqrt(d) from the hardware estimate and two Newton steps; the
+    // pivot is d times it
+    const double dd = fmax(d, 1e-300);
+    double inv = __builtin_amdgcn_rsq(dd);
+    inv = inv * fma(-0.5 * dd * inv, inv, 1.5);
+    inv = inv * fma(-0.5 * dd * inv, inv, 1.5);
+    const double piv = dd * inv;
+    const double l = lane > k ? p[u] * inv : (lane == k ? piv : 0.0);   // L(lane, k)
+    p[u] = l;
 #pragma unroll
-    for (int i = 16 * KB + 1; i < 16 * KB + 17 && i < N; i++)
-      if (i == k + 1) rowbuf[cur ^ 1][lane] = c[i];
-    wave_sync();
+    for (int v = u + 1; v < 16; v++) p[v] = fma(-l, readlane_d(l, c0 + v), p[v]);
   }
-  if constexpr (16 * KB + 16 < N) chol_steps<N, KB + 1>(c, Lc, rowbuf, sb, lane, own, bad);
+#pragma unroll
+  for (int u = 0; u < 16; u++) A[(c0 + u) * kCholLd + lane] = p[u];
 }
 
-template <int N, int PB>
-__device__ __forceinline__ void trinv_steps(double (&x)[N], const double* Lc, double (*xbuf)[64],
-                                            double* __restrict__ RinvRow, int lane, bool own) {
-  constexpr int LD = N + 1;
-#pragma unroll 1
-  for (int p = 16 * PB; p < 16 * PB + 16; p++) {
-    const int cur = p & 1;
-    const double* col = Lc + p * LD;
-    const double xp = xbuf[cur][lane] / col[p];           // X(p, lane)
-    if (own) RinvRow[(int64_t)lane * N + p] = xp;
-    bcast_axpy<N, 16 * PB + 1>(x, col, xp);
+template <int NB, int KB>
+__device__ __forceinline__ void chol_trailing(double* A, int lane) {
+  const int l16 = lane & 15, l4 = lane >> 4;
+  constexpr int c0 = 16 * KB;
 #pragma unroll
-    for (int i = 16 * PB + 1; i < 16 * PB + 17 && i < N; i++)
-      if (i == p + 1) xbuf[cur ^ 1][lane] = x[i];
+  for (int J = KB + 1; J < NB; J++)
+#pragma unroll
+    for (int I = J; I < NB; I++) {
+      double* tile = A + (16 * J + l16) * kCholLd + 16 * I + l4;   // D[l4 + 4 i][l16] = A(16 I + l4 + 4 i, 16 J + l16)
+      d4 acc;
+#pragma unroll
+      for (int i = 0; i < 4; i++) acc[i] = tile[4 * i];
+#pragma unroll
+      for (int s = 0; s < 4; s++) {
+        const double* col = A + (c0 + 4 * s + l4) * kCholLd;
+        acc = mfma16(-col[16 * I + l16], col[16 * J + l16], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; i++) tile[4 * i] = acc[i];
+    }
+}
+
+template <int NB, int KB>
+__device__ __forceinline__ void chol_blocks(double* A, int lane, int& bad) {
+  chol_panel<NB, KB>(A, lane, bad);
+  wave_sync();
+  if constexpr (KB + 1 < NB) {
+    chol_trailing<NB, KB>(A, lane);
+    wave_sync();
+    chol_blocks<NB, KB + 1>(A, lane, bad);
   }
-  if constexpr (16 * PB + 16 < N) trinv_steps<N, PB + 1>(x, Lc, xbuf, RinvRow, lane, own);
+}
+
+template <int NB, int I>
+__device__ __forceinline__ void trinv_blocks(const double* A, double* X, int lane) {
+  const int l16 = lane & 15, l4 = lane >> 4;
+#pragma unroll
+  for (int Jb = 0; Jb < I; Jb++) {
+    d4 T = {0, 0, 0, 0};
+#pragma unroll
+    for (int K = Jb; K < I; K++)
+#pragma unroll
+      for (int s = 0; s < 4; s++)
+        T = mfma16(A[(16 * K + 4 * s + l4) * kCholLd + 16 * I + l16],    // L(16 I + l16, 16 K + 4 s + l4)
+                   X[(16 * Jb + l16) * kCholLd + 16 * K + 4 * s + l4],   // X(16 K + 4 s + l4, 16 Jb + l16)
+                   T);
+    d4 Rt = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; s++) Rt = mfma16(-X[(16 * I + 4 * s + l4) * kCholLd + 16 * I + l16], T[s], Rt);
+    double* tile = X + (16 * Jb + l16) * kCholLd + 16 * I + l4;
+#pragma unroll
+    for (int i = 0; i < 4; i++) tile[4 * i] = Rt[i];
+  }
+  if constexpr (I + 1 < NB) {
+    wave_sync();
+    trinv_blocks<NB, I + 1>(A, X, lane);
+  }
 }
 
 template <int N>
-__global__ __launch_bounds__(64) void k_chol_inv_reg(const double* __restrict__ G,
-                                                     double* __restrict__ R,
-                                                     double* __restrict__ RinvRow, int shift_mode,
-                                                     int64_t rows, KrylovState* __restrict__ st) {
-  static_assert(N % 16 == 0 && N <= 64, "one lane per column, blocks of 16 steps");
-  constexpr int LD = N + 1;           // odd stride: strided reads of Lc are free of bank conflicts
-  __shared__ double Lc[N * LD];       // Lc[k * LD + j] = L(j, k)
-  __shared__ double rowbuf[2][64];    // row k of the trailing matrix (double buffered)
-  __shared__ double sb[64];           // scaled row k = column k of L
+__global__ __launch_bounds__(64) void k_chol_inv_blk(const double* __restrict__ G, double* __restrict__ R,
+                                                     double* __restrict__ RinvRow, int shift_mode, int64_t rows,
+                                                     KrylovState* __restrict__ st) {
+  static_assert(N % 16 == 0 && N <= 64, "blocks of 16, one lane per row");
+  constexpr int NB = N / 16;
+  __shared__ double A[64 * kCholLd];   // A(i, j) at j * kCholLd + i
+  __shared__ double X[64 * kCholLd];
   const int lane = threadIdx.x;
   const bool own = lane < N;
-  double tr = own ? G[(int64_t)lane * N + lane] : 0.0;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) tr += __shfl_xor(tr, off, 64);
+  const double tr = wave_sum(own ? G[(int64_t)lane * N + lane] : 0.0);
   const double shift =
       shift_mode ? 11.0 * ((double)rows * N + (double)N * (N + 1)) * 1.1102230246251565e-16 * tr : 0.0;
-  // c[i] = A(i, lane) from the lower triangle of G (column-major)
-  double c[N];
+  // A = G + shift I, column by column (coalesced); only the lower triangle
+  // takes part in the factorisation: an entry above the diagonal only ever
+  // meets a zero multiplier or is overwritten
+  {
+    double g[N];   // all loads in flight at once
 #pragma unroll
-  for (int i = 0; i < N; i++)
-    c[i] = own ? (i >= lane ? G[(int64_t)lane * N + i] : G[(int64_t)i * N + lane]) + (i == lane ? shift : 0.0)
-               : 0.0;
-  rowbuf[0][lane] = c[0];
+    for (int j = 0; j < N; j++) g[j] = own ? G[(int64_t)j * N + lane] : 0.0;
+#pragma unroll
+    for (int j = 0; j < N; j++) A[j * kCholLd + lane] = g[j] + (lane == j ? shift : 0.0);
+  }
   wave_sync();
   int bad = 0;
-  chol_steps<N, 0>(c, Lc, rowbuf, sb, lane, own, bad);
-  // R = L^T column-major: R(lane, j) = L(j, lane)
-  if (own)
-    for (int j = 0; j < N; j++) R[(int64_t)j * N + lane] = Lc[lane * LD + j];
-  // X = L^{-1}, column lane: x(i) = (delta(i, lane) - sum_{p < i} L(i, p) x(p)) / L(i, i),
-  // the sum taken in increasing p.  RinvRow = R^{-1} row-major = X^T, so row
-  // lane of RinvRow is column lane of X.
-  double x[N];
+  chol_blocks<NB, 0>(A, lane, bad);
+  // diagonal blocks of X: lane group b, column 16 b + (lane % 16)
+  {
+    const int b = lane >> 4, j = lane & 15;
+    if (b < NB) {
+      const double* Lb = A + 16 * b * kCholLd + 16 * b;   // L_bb(r, p) at p * kCholLd + r
+      double x[16];
 #pragma unroll
-  for (int i = 0; i < N; i++) x[i] = (i == lane) ? 1.0 : 0.0;
-  rowbuf[0][lane] = x[0];
-  trinv_steps<N, 0>(x, Lc, rowbuf, RinvRow, lane, own);
+      for (int r = 0; r < 16; r++) {
+        double acc = r == j ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < r; q++) acc = fma(-Lb[q * kCholLd + r], x[q], acc);
+        x[r] = acc / Lb[r * kCholLd + r];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; r++) X[(16 * b + j) * kCholLd + 16 * b + r] = x[r];
+    }
+  }
+  wave_sync();
+  if constexpr (NB > 1) {
+    trinv_blocks<NB, 1>(A, X, lane);
+    wave_sync();
+  }
+  // R = L^T column-major: R(i, j) = L(j, i); RinvRow = R^{-1} row-major = X column-major;
+  // blocks above the diagonal are zero
+  if (own) {
+    double r[N];
+#pragma unroll
+    for (int j = 0; j < N; j++) r[j] = (j >> 4) >= (lane >> 4) ? A[lane * kCholLd + j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < N; j++) R[(int64_t)j * N + lane] = r[j];
+#pragma unroll
+    for (int j = 0; j < N; j++) r[j] = (j >> 4) <= (lane >> 4) ? X[j * kCholLd + lane] : 0.0;
+#pragma unroll
+    for (int j = 0; j < N; j++) RinvRow[(int64_t)j * N + lane] = r[j];
+  }
   if (lane == 0 && bad && st) fail_status(st, 2);
 }
 
-// (b) other n (<= 128): LDS-resident packed triangles, rank-1 updates over a
-//     16 x 16 thread grid.
+// (b) other n (<= 128): L and X = L^{-1} as packed lower triangles in LDS
+//     (n (n + 1) doubles), rank-1 updates over a 16 x 16 thread grid.
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, int n,
                                                   double* __restrict__ R,
                                                   double* __restrict__ RinvRow, int shift_mode,
@@ -3134,10 +3185,10 @@ hipError_t launch_tiny(const TJob* jobs, int nj, int minM, int maxM, int kreq, h
 hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, int shift_mode,
                            int64_t rows, KrylovState* st, hipStream_t s) {
   switch (n) {
-    case 16: hipLaunchKernelGGL(k_chol_inv_reg<16>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
-    case 32: hipLaunchKernelGGL(k_chol_inv_reg<32>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
-    case 48: hipLaunchKernelGGL(k_chol_inv_reg<48>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
-    case 64: hipLaunchKernelGGL(k_chol_inv_reg<64>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
+    case 16: hipLaunchKernelGGL(k_chol_inv_blk<16>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
+    case 32: hipLaunchKernelGGL(k_chol_inv_blk<32>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
+    case 48: hipLaunchKernelGGL(k_chol_inv_blk<48>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
+    case 64: hipLaunchKernelGGL(k_chol_inv_blk<64>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
     default: break;
   }
   hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), (size_t)n * (n + 1) * sizeof(double), s, G,
