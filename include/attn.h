@@ -125,7 +125,11 @@ typedef struct attn_solver_opts {
 
 typedef struct attn_sweep_opts {
   attn_solver_opts solver;
-  int32_t use_graphs;  /* reserved, 0 */
+  int32_t use_graphs;  /* 1: FP64 Lanczos sweeps run from HIP graphs on a stream of
+                          the handle: the first sweep from a given host state
+                          (centre, isometries, valid effective operators) is
+                          captured, later sweeps from the same state replay it
+                          (two graphs kept); same results as without graphs */
 } attn_sweep_opts;
 
 /*

@@ -73,8 +73,8 @@ class AttnHandle:
     def eigsolve(self, node, opts=None, stream=None):
         return _lib.attn_eigsolve_node(self.h, node, opts, stream)
 
-    def sweep(self, n_sweeps, opts=None):
-        return _lib.attn_sweep(self.h, n_sweeps, opts)
+    def sweep(self, n_sweeps, opts=None, use_graphs=False):
+        return _lib.attn_sweep(self.h, n_sweeps, opts, use_graphs)
 
     def set_precond_weights(self, params):
         _lib.attn_precond_set_weights(self.h, params)

@@ -233,10 +233,10 @@ def attn_isometrize(h, frm, to, stream=None):
     _check(_lib.attn_isometrize(h, frm, to, stream), h)
 
 
-def attn_sweep(h, n_sweeps, opts=None):
+def attn_sweep(h, n_sweeps, opts=None, use_graphs=False):
     e = np.zeros(n_sweeps)
     s = np.zeros(n_sweeps)
-    so = attn_sweep_opts(opts if opts is not None else solver_opts(), 0)
+    so = attn_sweep_opts(opts if opts is not None else solver_opts(), int(use_graphs))
     _check(_lib.attn_sweep(h, n_sweeps, ctypes.byref(so), e.ctypes.data_as(_f64p),
                            s.ctypes.data_as(_f64p)), h)
     return e, s

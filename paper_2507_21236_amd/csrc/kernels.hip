@@ -845,6 +845,12 @@ __global__ __launch_bounds__(256) void k_zero(double* __restrict__ p, int64_t n)
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) p[e] = 0.0;
 }
 
+// dst = src (a kernel rather than a copy command, so that captured sweeps
+// hold kernel nodes only)
+__global__ __launch_bounds__(256) void k_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) dst[e] = src[e];
+}
+
 // ============================================================================ gram
 // partial[j][j'] (column-major) = sum_{f in [f0, f1)} X[f][j] Z[f][j'].
 template <int NI>
@@ -3260,6 +3266,12 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s) {
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero, dim3(gridv(n)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(gridv(n)), dim3(256), 0, s, dst, src, n);
   return hipGetLastError();
 }
 

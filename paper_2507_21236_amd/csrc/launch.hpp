@@ -54,6 +54,8 @@ hipError_t launch_batch_mode(int dtype, const MPTask* tasks, const MPJob* jobs, 
 hipError_t launch_transpose_list(int dtype, const TRTask* tasks, int ntask, int64_t maxM, hipStream_t s);
 hipError_t launch_reduce_list(int dtype_in, const RDTask* tasks, int ntask, int64_t maxM, hipStream_t s);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
+// dst = src (n doubles; the ranges do not overlap)
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 hipError_t prepare_kernel_attributes();
 

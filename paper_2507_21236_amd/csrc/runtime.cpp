@@ -844,9 +844,11 @@ void build_qr_dev(attn_handle* h, int n, int leg, QRDev& Q) {
   else for (int64_t e = 0; e < Msz; e += 256) wus.push_back(make_int2(0, (int)e));
   Q.nwus = (int)wus.size();
   Q.d_wus = upload(h, wus);
+  // the passes rotate through T -> tmp -> tmp2 -> T, so Q lands in T
+  double* const bufs[4] = {T, h->d_tmp, h->d_tmp2, T};
   for (int pass = 0; pass < 3; pass++) {
-    double* src = (pass % 2 == 0) ? T : h->d_tmp;
-    double* dst = (pass % 2 == 0) ? h->d_tmp : T;
+    double* src = bufs[pass];
+    double* dst = bufs[pass + 1];
     std::vector<GRTask> gt(Q.nfc);
     for (int c = 0; c < Q.nfc; c++) {
       gt[c].X = src; gt[c].Z = src; gt[c].partial = h->d_grpart + (int64_t)c * mj * mj;
@@ -918,15 +920,13 @@ void qr_node(attn_handle* h, int n, int leg, hipStream_t s) {
   double* R[3] = {G + nn, G + 2 * nn, G + 3 * nn};
   double* Rinv = G + 4 * nn;
   double* Rt = G + 5 * nn;
-  double* T = h->d_T + h->T_off[n];
+  // the passes rotate T -> tmp -> tmp2 -> T (plans built that way): Q ends in T
   for (int pass = 0; pass < 3; pass++) {
     HIPCHK(launch_gram(mj, Q.gmf, Q.d_gt[pass], Q.nfc, s, Q.gnt));
     HIPCHK(launch_gram_reduce(Q.d_gr, 1, mj, s));
     HIPCHK(launch_chol_inv(G, mj, R[pass], Rinv, pass == 0 ? 1 : 0, Q.rows, h->d_st, s));
     HIPCHK(launch_mode(0, mj, Q.mmf, Q.d_mt[pass], Q.d_mj[pass], Q.d_wus, Q.nwus, nullptr, s, Q.mnt));
   }
-  // passes write tmp, T, tmp: the result is in tmp
-  HIPCHK(hipMemcpyAsync(T, h->d_tmp, Q.Msz * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(launch_small_matmul(R[1], R[0], Rt, mj, s));
   HIPCHK(launch_small_matmul(R[2], Rt, h->d_qrR, mj, s));
   h->n_qr++;
@@ -937,7 +937,7 @@ void absorb(attn_handle* h, int q, int leg, hipStream_t s) {
   ABDev& A = h->ab[leg][q];
   if (!A.present) throw StatusFail{ATTN_ERR_STATE, "internal: no absorb plan for this leg"};
   HIPCHK(launch_mode(0, A.mj, A.mmf, A.d_mt, A.d_mj, A.d_wus, A.nwus, nullptr, s, A.mnt));
-  HIPCHK(hipMemcpyAsync(h->d_T + h->T_off[q], h->d_tmp2, A.Msz * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_copy(h->d_T + h->T_off[q], h->d_tmp2, A.Msz, s));
 }
 
 attn_status guard(attn_handle* h, const std::function<attn_status()>& f) {
@@ -1362,6 +1362,8 @@ attn_status attn_destroy(attn_handle* h) {
     (void)hipDeviceSynchronize();
     for (void* p : h->owned) (void)hipFree(p);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    for (auto& g : h->sgraphs) (void)hipGraphExecDestroy(g.exec);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
   }
   delete h;
   return ATTN_OK;
@@ -1878,23 +1880,104 @@ attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* 
   // sweep; the Davidson form steers its restarts from the host and keeps its
   // own synchronisation.
   const bool defer = so.solver == ATTN_SOLVER_LANCZOS && !h->dead && h->d_st;
+  // with use_graphs, FP64 Lanczos sweeps run from HIP graphs on a stream of
+  // the handle (not while the matvec launches are being timed)
+  const bool graphs = defer && opts && opts->use_graphs && so.precision == ATTN_F64 && so.krylov_k >= 1 &&
+                      !h->host_only && !h->dryrun;
+  auto state = [&]() {
+    attn_handle::SweepState st;
+    st.center = h->center;
+    st.iso = h->iso;
+    st.valid0 = h->valid[0];
+    st.valid1 = h->valid[1];
+    return st;
+  };
+  double th = 0;   // energy of the sweep: the last node's eigenvalue
+  auto node_loop = [&](void* stream) -> attn_status {
+    for (int n = 0; n < (int)tr.nodes.size(); n++) {
+      attn_status st = attn_move_center(h, n, stream);
+      if (st == ATTN_OK) st = attn_eigsolve_node(h, n, &so, &th, nullptr, stream);
+      if (st) return st;
+    }
+    return ATTN_OK;
+  };
   for (int sw = 0; sw < n_sweeps; sw++) {
     auto t0 = std::chrono::steady_clock::now();
-    double th = 0;
+    th = 0;
+    const bool use_graph = graphs && !h->prof;
+    if (use_graph && !h->gstream) {
+      if (hipSetDevice(h->device) != hipSuccess || hipStreamCreate(&h->gstream) != hipSuccess) {
+        h->err = "stream creation failed";
+        return ATTN_ERR_HIP;
+      }
+    }
+    hipStream_t s = use_graph ? h->gstream : nullptr;
     if (defer) {
-      if (hipSetDevice(h->device) != hipSuccess || launch_zero_int(&h->d_st->sticky, 1, nullptr) != hipSuccess) {
+      if (hipSetDevice(h->device) != hipSuccess || launch_zero_int(&h->d_st->sticky, 1, s) != hipSuccess) {
         h->err = "status reset failed";
         return ATTN_ERR_HIP;
       }
       h->defer_status = true;
     }
-    for (int n = 0; n < (int)tr.nodes.size(); n++) {
-      attn_status st = attn_move_center(h, n, nullptr);
-      if (st == ATTN_OK) st = attn_eigsolve_node(h, n, &so, &th, nullptr, nullptr);
+    if (use_graph) {
+      const attn_handle::SweepState pre = state();
+      attn_handle::SweepGraph* G = nullptr;
+      for (auto& g : h->sgraphs)
+        if (g.krylov_k == so.krylov_k && g.pre == pre) G = &g;
+      if (!G) {
+        // capture this sweep's launches (nothing runs yet), then launch them
+        attn_handle::SweepGraph ng;
+        ng.krylov_k = so.krylov_k;
+        ng.pre = pre;
+        const int64_t m0 = h->n_matvec, e0 = h->n_env, q0 = h->n_qr;
+        const double f0 = h->mv_flops;
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+          h->defer_status = false;
+          h->err = "graph capture failed to start";
+          return ATTN_ERR_HIP;
+        }
+        const attn_status st = node_loop((void*)s);
+        const hipError_t ec = hipStreamEndCapture(s, &g);
+        h->defer_status = false;
+        if (st || ec != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          if (!st) { h->err = "graph capture failed"; h->dead = true; }
+          return st ? st : ATTN_ERR_HIP;
+        }
+        const hipError_t ei = hipGraphInstantiate(&ng.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) { h->err = "graph instantiation failed"; h->dead = true; return ATTN_ERR_HIP; }
+        ng.post = state();
+        ng.d_matvec = h->n_matvec - m0; ng.d_env = h->n_env - e0; ng.d_qr = h->n_qr - q0;
+        ng.d_flops = h->mv_flops - f0;
+        if (h->sgraphs.size() >= 2) {
+          (void)hipGraphExecDestroy(h->sgraphs.front().exec);
+          h->sgraphs.erase(h->sgraphs.begin());
+        }
+        h->sgraphs.push_back(ng);
+        G = &h->sgraphs.back();
+        if (hipGraphLaunch(G->exec, s) != hipSuccess) { h->err = "graph launch failed"; h->dead = true; return ATTN_ERR_HIP; }
+      } else {
+        if (hipGraphLaunch(G->exec, s) != hipSuccess) { h->err = "graph launch failed"; h->dead = true; return ATTN_ERR_HIP; }
+        // the host bookkeeping of the replayed sweep
+        h->center = G->post.center;
+        h->iso = G->post.iso;
+        h->valid[0] = G->post.valid0;
+        h->valid[1] = G->post.valid1;
+        h->n_matvec += G->d_matvec; h->n_env += G->d_env; h->n_qr += G->d_qr;
+        h->mv_flops += G->d_flops;
+      }
+    } else {
+      const attn_status st = node_loop(nullptr);
       if (st) { h->defer_status = false; return st; }
     }
     h->defer_status = false;
-    if (hipDeviceSynchronize() != hipSuccess) { h->err = "device synchronisation failed"; return ATTN_ERR_HIP; }
+    if ((s ? hipStreamSynchronize(s) : hipDeviceSynchronize()) != hipSuccess) {
+      h->err = "device synchronisation failed";
+      h->dead = true;
+      return ATTN_ERR_HIP;
+    }
     if (defer) {
       KrylovState st;
       if (hipMemcpy(&st, h->d_st, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) {

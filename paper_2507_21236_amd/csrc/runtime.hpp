@@ -224,6 +224,27 @@ struct attn_handle {
   std::vector<EnvDev> env_up, env_down[2];
   std::vector<QRDev> qr[3];   // per leg, per node
   std::vector<ABDev> ab[3];   // absorb into node along leg
+  // FP64 Lanczos sweeps captured as HIP graphs (attn_sweep_opts.use_graphs):
+  // a graph replays the launches of one whole sweep from the host state it was
+  // captured in (centre, isometry legs, valid stores) and leaves the state it
+  // left then, so it is replayed only from an identical start state
+  struct SweepState {
+    int center = -1;
+    std::vector<int> iso;
+    std::vector<char> valid0, valid1;
+    bool operator==(const SweepState& o) const {
+      return center == o.center && iso == o.iso && valid0 == o.valid0 && valid1 == o.valid1;
+    }
+  };
+  struct SweepGraph {
+    hipGraphExec_t exec = nullptr;
+    int krylov_k = 0;
+    SweepState pre, post;
+    int64_t d_matvec = 0, d_env = 0, d_qr = 0;
+    double d_flops = 0;
+  };
+  hipStream_t gstream = nullptr;
+  std::vector<SweepGraph> sgraphs;   // at most two (the first sweep from a fresh state, then the steady one)
   // counters
   int64_t n_matvec = 0, n_env = 0, n_qr = 0;
   double mv_flops = 0;
