@@ -353,11 +353,11 @@ void enqueue_step(attn_batch* b, int t, hipStream_t s0) {
   for (int j = 0; j < kk; j++) {
     run_matvec(b, S.mv, s0);
     if (j == kk - 1) {   // last step: only alpha_j
-      HIPCHK(launch_kdot(J, nj, j, s0));
+      HIPCHK(launch_kdots(J, nj, j, 1, 0, s0));
       HIPCHK(launch_kalpha(J, nj, j, s0));
       break;
     }
-    HIPCHK(launch_kdots(J, nj, j, s0));
+    HIPCHK(launch_kdots(J, nj, 0, j + 1, 1, s0));
     HIPCHK(launch_kortho(J, nj, j, 1, 0, 1, s0));
     HIPCHK(launch_kortho(J, nj, j, 2, 1, 0, s0));
     HIPCHK(launch_kbeta(J, nj, j, S.kj_max, s0));

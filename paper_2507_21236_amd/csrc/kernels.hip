@@ -1205,18 +1205,6 @@ __global__ __launch_bounds__(256) void k_kscale(const KJob* __restrict__ jobs, i
   }
 }
 
-// P0 = partial sums of v_j . w
-__global__ __launch_bounds__(256) void k_kdot(const KJob* __restrict__ jobs, int j) {
-  __shared__ double red[4];
-  const KJob& J = jobs[blockIdx.y];
-  if (J.st->stop) return;
-  const double* v = J.V + (int64_t)j * J.n;
-  double acc = 0;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < J.n; e += (int64_t)kRedBlocks * 256)
-    acc += v[e] * J.w[e];
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) parea(J, 0)[blockIdx.x] = s;
-}
 
 // alpha_j = sum P0 (last step, no update follows)
 __global__ __launch_bounds__(256) void k_kalpha(const KJob* __restrict__ jobs, int j) {
@@ -1286,15 +1274,90 @@ __device__ __forceinline__ void sums_of_partials(const double* __restrict__ p, i
   __syncthreads();
 }
 
-// P1 = partial dots V[0..j] . w of the product w = H v_j.  The two classical
-// Gram-Schmidt passes that follow run against the whole basis, so the first
-// one also removes alpha_j v_j and beta_{j-1} v_{j-1} (alpha_j = v_j . w is the
-// partial sum of dot j, the same bits as a separate dot product).
-__global__ __launch_bounds__(256) void k_kdots(const KJob* __restrict__ jobs, int j) {
+// Dot products of basis vectors with the product w = H v_j, right after the
+// product.  Blocks of kDotThreads = 1024 threads, kRedBlocks of them: element
+// e belongs to thread e % 1024 of block (e / 1024) % kRedBlocks, whose
+// partial sum is written to out[(i - i0) * kRedBlocks + block] (the layout
+// every later step reads).  A step j < k - 1 takes the dots of V[0..j] into
+// P1 (the two classical Gram-Schmidt passes that follow run against the whole
+// basis, so the first also removes alpha_j v_j and beta_{j-1} v_{j-1}, and
+// alpha_j is the sum of dot j); the last step takes v_j . w into P0.
+constexpr int kDotThreads = 1024;
+
+// block sums of C per-thread values at once over 16 wavefronts (shuffle tree
+// per wave, then the waves in order); the sum of value q is returned in
+// thread q.  red holds 16 C doubles.
+template <int C>
+__device__ __forceinline__ double block_sums_1k(double (&v)[C], double* red) {
+#pragma unroll
+  for (int q = 0; q < C; q++)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < C; q++) red[wave * C + q] = v[q];
+  __syncthreads();
+  const int q = threadIdx.x < C ? threadIdx.x : 0;
+  double s = 0;
+#pragma unroll
+  for (int w = 0; w < kDotThreads / 64; w++) s += red[w * C + q];
+  return s;
+}
+
+__device__ __forceinline__ void block_dots_1k(const KJob& J, const double* __restrict__ w, int i0, int nv,
+                                              double* out, double* red) {
+  const int64_t n = J.n;
+  const int b = blockIdx.x;
+  for (int c0 = 0; c0 < nv; c0 += kDotChunk) {
+    double acc[kDotChunk];
+#pragma unroll
+    for (int q = 0; q < kDotChunk; q++) acc[q] = 0.0;
+    for (int64_t e = (int64_t)b * kDotThreads + threadIdx.x; e < n; e += (int64_t)kRedBlocks * kDotThreads) {
+      const double we = w[e];
+#pragma unroll
+      for (int q = 0; q < kDotChunk; q++)
+        if (c0 + q < nv) acc[q] += J.V[(int64_t)(i0 + c0 + q) * n + e] * we;
+    }
+    const double s = block_sums_1k<kDotChunk>(acc, red);
+    if (threadIdx.x < kDotChunk && c0 + (int)threadIdx.x < nv) out[(c0 + threadIdx.x) * kRedBlocks + b] = s;
+  }
+}
+
+// partial dots of V[i0, i0 + nv) with w into area pin (w as the product left it)
+__global__ __launch_bounds__(1024) void k_kdots(const KJob* __restrict__ jobs, int i0, int nv, int pin) {
   const KJob& J = jobs[blockIdx.y];
   if (J.st->stop) return;
-  __shared__ double red8[4 * kDotChunk];
-  block_dots(J, J.w, j + 1, parea(J, 1), red8);
+  __shared__ double red[16 * kDotChunk];
+  block_dots_1k(J, J.w, i0, nv, parea(J, pin), red);
+}
+
+// w = the sum of the product's partial outputs (per element in the order of
+// k_reduce_out), then the partial dots of k_kdots: one launch instead of two
+// (single job; the same bits as k_reduce_out followed by k_kdots)
+__global__ __launch_bounds__(1024) void k_reduce_dots(const RDSrc* __restrict__ srcs, int nsrc,
+                                                      const KJob* __restrict__ jobs, int ml, int mr, int mp,
+                                                      int i0, int nv, int pin) {
+  const KJob& J = jobs[0];
+  const int64_t M = (int64_t)ml * mr * mp;
+  double* w = J.w;
+  for (int64_t e = (int64_t)blockIdx.x * kDotThreads + threadIdx.x; e < M; e += (int64_t)kRedBlocks * kDotThreads) {
+    const int64_t l = e / ((int64_t)mr * mp);
+    const int64_t rem = e - l * mr * mp;
+    const int64_t r = rem / mp, p = rem - r * mp;
+    const int64_t et = p * ml * mr + l * mr + r;
+    double acc = 0;
+#pragma unroll 8
+    for (int k = 0; k < nsrc; k++) {
+      const double* src = (const double*)srcs[k].p;
+      acc += srcs[k].layout ? src[et] : src[e];
+    }
+    w[e] = acc;
+  }
+  if (J.st->stop) return;
+  __shared__ double red[16 * kDotChunk];
+  block_dots_1k(J, w, i0, nv, parea(J, pin), red);
 }
 
 // classical Gram-Schmidt pass against V[0..j]: h = sums of P(pin); w -= sum h_i V_i;
@@ -3135,18 +3198,21 @@ hipError_t launch_kscale(const KJob* jobs, int nj, int64_t nmax, int mode, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_kdot(const KJob* jobs, int nj, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_kdot, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs, j);
-  return hipGetLastError();
-}
 
 hipError_t launch_kalpha(const KJob* jobs, int nj, int j, hipStream_t s) {
   hipLaunchKernelGGL(k_kalpha, dim3(1, nj), dim3(256), 0, s, jobs, j);
   return hipGetLastError();
 }
 
-hipError_t launch_kdots(const KJob* jobs, int nj, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_kdots, dim3(kRedBlocks, nj), dim3(256), 0, s, jobs, j);
+hipError_t launch_kdots(const KJob* jobs, int nj, int i0, int nv, int pin, hipStream_t s) {
+  hipLaunchKernelGGL(k_kdots, dim3(kRedBlocks, nj), dim3(kDotThreads), 0, s, jobs, i0, nv, pin);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_dots(const RDSrc* srcs, int nsrc, const KJob* job, int ml, int mr, int mp, int i0,
+                              int nv, int pin, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_dots, dim3(kRedBlocks), dim3(kDotThreads), 0, s, srcs, nsrc, job, ml, mr, mp, i0,
+                     nv, pin);
   return hipGetLastError();
 }
 

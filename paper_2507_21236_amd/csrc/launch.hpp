@@ -36,9 +36,12 @@ hipError_t launch_cast(const void* src, int src_dtype, void* dst, int dst_dtype,
 hipError_t launch_kinit(const KJob* jobs, int nj, int kmax, hipStream_t s);
 hipError_t launch_knorm(const KJob* jobs, int nj, hipStream_t s);
 hipError_t launch_kscale(const KJob* jobs, int nj, int64_t nmax, int mode, hipStream_t s);
-hipError_t launch_kdot(const KJob* jobs, int nj, int j, hipStream_t s);
 hipError_t launch_kalpha(const KJob* jobs, int nj, int j, hipStream_t s);
-hipError_t launch_kdots(const KJob* jobs, int nj, int j, hipStream_t s);
+// partial dots of basis vectors [i0, i0 + nv) with w into partial-sum area pin
+hipError_t launch_kdots(const KJob* jobs, int nj, int i0, int nv, int pin, hipStream_t s);
+// w = sum of a product's partial outputs, then launch_kdots' partial dots (one job)
+hipError_t launch_reduce_dots(const RDSrc* srcs, int nsrc, const KJob* job, int ml, int mr, int mp, int i0,
+                              int nv, int pin, hipStream_t s);
 hipError_t launch_kortho(const KJob* jobs, int nj, int j, int pin, int norm_only, int set_alpha, hipStream_t s);
 hipError_t launch_kbeta(const KJob* jobs, int nj, int j, int64_t nmax, hipStream_t s);
 hipError_t launch_ktridiag(const KJob* jobs, int nj, hipStream_t s);

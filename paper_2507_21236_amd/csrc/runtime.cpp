@@ -613,8 +613,11 @@ void run_mp(std::vector<MPGroup>& gs, int dtype, const void* xbase, hipStream_t 
     HIPCHK(launch_mode(dtype, g.mj, g.mfma, g.d_tasks, g.d_jobs, g.d_wus, (int)g.wus.size(), xbase, s, g.nt));
 }
 
-// y <- H_eff(n) x (FP64), combines must be current
-void matvec_f64(attn_handle* h, int n, const double* x, double* y, hipStream_t s) {
+// y <- H_eff(n) x (FP64), combines must be current.  With a Krylov job J
+// (y = J's w), the partial dots of basis vectors [i0, i0 + nv) with y go to
+// area pin in the same launch as the sum of the partial outputs.
+void matvec_f64(attn_handle* h, int n, const double* x, double* y, hipStream_t s, const KJob* J = nullptr,
+                int i0 = 0, int nv = 0, int pin = 0) {
   MVDev& D = h->mv[n];
   if (D.need_xt) HIPCHK(launch_transpose_plr(0, x, h->d_xt, D.dims[0], D.dims[1], D.dims[2], s));
   run_mp(D.chainA, 0, x, s);
@@ -623,6 +626,9 @@ void matvec_f64(attn_handle* h, int n, const double* x, double* y, hipStream_t s
   run_sw_mv(h, D.sw, 0, x, s);
   if (D.srcs.empty()) {
     HIPCHK(launch_zero(y, (int64_t)D.dims[0] * D.dims[1] * D.dims[2], s));
+    if (J) HIPCHK(launch_kdots(J, 1, i0, nv, pin, s));
+  } else if (J) {
+    HIPCHK(launch_reduce_dots(D.d_srcs, (int)D.srcs.size(), J, D.dims[0], D.dims[1], D.dims[2], i0, nv, pin, s));
   } else {
     HIPCHK(launch_reduce_out(0, D.d_srcs, (int)D.srcs.size(), y, 0, D.dims[0], D.dims[1], D.dims[2], s));
   }
@@ -1012,14 +1018,20 @@ double lanczos(attn_handle* h, int n, int kreq, int precision, int* nmv, hipStre
   HIPCHK(launch_knorm(J, 1, s));
   HIPCHK(launch_kscale(J, 1, Msz, 0, s));
   for (int j = 0; j < k; j++) {
-    if (precision == ATTN_F64) matvec_f64(h, n, V + (int64_t)j * Msz, h->d_w, s);
-    else matvec_lowp(h, n, precision, h->d_x32, h->d_w, 0, s);
-    if (j == k - 1) {   // last step: only alpha_j
-      HIPCHK(launch_kdot(J, 1, j, s));
+    // dots after the product: V[0..j] . w into P1, or at the last step only
+    // v_j . w (alpha_j) into P0
+    const bool last = j == k - 1;
+    const int i0 = last ? j : 0, nv = last ? 1 : j + 1, pin = last ? 0 : 1;
+    if (precision == ATTN_F64) {
+      matvec_f64(h, n, V + (int64_t)j * Msz, h->d_w, s, J, i0, nv, pin);
+    } else {
+      matvec_lowp(h, n, precision, h->d_x32, h->d_w, 0, s);
+      HIPCHK(launch_kdots(J, 1, i0, nv, pin, s));
+    }
+    if (last) {
       HIPCHK(launch_kalpha(J, 1, j, s));
       break;
     }
-    HIPCHK(launch_kdots(J, 1, j, s));
     HIPCHK(launch_kortho(J, 1, j, 1, 0, 1, s));
     HIPCHK(launch_kortho(J, 1, j, 2, 1, 0, s));
     HIPCHK(launch_kbeta(J, 1, j, Msz, s));
