@@ -53,7 +53,7 @@ KERNELS = {"f64": "k_sandwich<double,4>", "f32": "k_sandwich<float,4>",
 # (profiles/k_sandwich_f64_legs64_hbm_traffic.md).  The writes are the
 # kernel's partial outputs (one per item chunk); the reads are X and the
 # operator blocks.  Valid for the kernel as measured: None once it changes.
-TRAFFIC_F64 = {"read": 116.6e6, "write": 97.9e6}
+TRAFFIC_F64 = {"read": 116.4e6, "write": 97.9e6}
 
 
 def cpu_baseline(problem, sample_matvecs=3):

@@ -1218,30 +1218,49 @@ __global__ __launch_bounds__(256) void k_kalpha(const KJob* __restrict__ jobs, i
   }
 }
 
-// Block sums of C per-thread values at once, each in block_sum's order (wave
-// shuffle tree, then the four waves in order); the sum of value q is returned
-// in thread q.  red holds 4 C doubles.
-template <int C>
-__device__ __forceinline__ double block_sums(double (&v)[C], double* red) {
+// Wave sums of eight per-lane values at once by recursive halving: at each of
+// the first three levels a lane keeps half of its values and adds its
+// partner's copy of them (partner lane ^ 32, ^ 16, ^ 8), so that lane l ends
+// with value l >> 3 summed over eight lanes; three more exchanges (^ 4, ^ 2,
+// ^ 1) complete the sum over the wavefront.  Ten exchanges instead of 48 for
+// eight separate trees; the eight lanes holding a value agree bit for bit.
+__device__ __forceinline__ double wave_sums8(const double (&v)[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8;
+  double a[4];
 #pragma unroll
-  for (int q = 0; q < C; q++)
+  for (int u = 0; u < 4; u++) a[u] = (h5 ? v[u + 4] : v[u]) + __shfl_xor(h5 ? v[u] : v[u + 4], 32, 64);
+  double b2[2];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+  for (int u = 0; u < 2; u++) b2[u] = (h4 ? a[u + 2] : a[u]) + __shfl_xor(h4 ? a[u] : a[u + 2], 16, 64);
+  double c = (h3 ? b2[1] : b2[0]) + __shfl_xor(h3 ? b2[0] : b2[1], 8, 64);
+  c += __shfl_xor(c, 4, 64);
+  c += __shfl_xor(c, 2, 64);
+  c += __shfl_xor(c, 1, 64);
+  return c;
+}
+
+// Block sums of 8 per-thread values at once (wave sums above, then the waves
+// in order); the sum of value q is returned in thread q.  red holds 8 doubles
+// per wavefront of the block.
+template <int NW>
+__device__ __forceinline__ double block_sums8(const double (&v)[8], double* red) {
+  const double c = wave_sums8(v);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int q = 0; q < C; q++) red[wave * C + q] = v[q];
+  if ((lane & 7) == 0) red[wave * 8 + (lane >> 3)] = c;
   __syncthreads();
-  const int q = threadIdx.x < C ? threadIdx.x : 0;
-  return red[q] + red[C + q] + red[2 * C + q] + red[3 * C + q];
+  const int q = threadIdx.x & 7;
+  double s = 0;
+#pragma unroll
+  for (int w = 0; w < NW; w++) s += red[w * 8 + q];
+  return s;
 }
 
 constexpr int kDotChunk = 8;
 
 // out[i * kRedBlocks + b] = this block's partial dot V_i . w for i < nv, eight
-// vectors per pass over the block's elements (same per-thread order as one
-// vector at a time).
+// vectors per pass over the block's elements.
 __device__ __forceinline__ void block_dots(const KJob& J, const double* __restrict__ w, int nv, double* out,
                                            double* red) {
   const int64_t n = J.n;
@@ -1256,7 +1275,7 @@ __device__ __forceinline__ void block_dots(const KJob& J, const double* __restri
       for (int q = 0; q < kDotChunk; q++)
         if (i0 + q < nv) acc[q] += J.V[(int64_t)(i0 + q) * n + e] * we;
     }
-    const double s = block_sums<kDotChunk>(acc, red);
+    const double s = block_sums8<4>(acc, red);
     if (threadIdx.x < kDotChunk && i0 + (int)threadIdx.x < nv) out[(i0 + threadIdx.x) * kRedBlocks + b] = s;
   }
 }
@@ -1268,7 +1287,7 @@ __device__ __forceinline__ void sums_of_partials(const double* __restrict__ p, i
     double v[kDotChunk];
 #pragma unroll
     for (int q = 0; q < kDotChunk; q++) v[q] = i0 + q < nv ? p[(i0 + q) * kRedBlocks + threadIdx.x] : 0.0;
-    const double s = block_sums<kDotChunk>(v, red);
+    const double s = block_sums8<4>(v, red);
     if (threadIdx.x < kDotChunk && i0 + (int)threadIdx.x < nv) hs[i0 + threadIdx.x] = s;
   }
   __syncthreads();
@@ -1284,28 +1303,6 @@ __device__ __forceinline__ void sums_of_partials(const double* __restrict__ p, i
 // alpha_j is the sum of dot j); the last step takes v_j . w into P0.
 constexpr int kDotThreads = 1024;
 
-// block sums of C per-thread values at once over 16 wavefronts (shuffle tree
-// per wave, then the waves in order); the sum of value q is returned in
-// thread q.  red holds 16 C doubles.
-template <int C>
-__device__ __forceinline__ double block_sums_1k(double (&v)[C], double* red) {
-#pragma unroll
-  for (int q = 0; q < C; q++)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int q = 0; q < C; q++) red[wave * C + q] = v[q];
-  __syncthreads();
-  const int q = threadIdx.x < C ? threadIdx.x : 0;
-  double s = 0;
-#pragma unroll
-  for (int w = 0; w < kDotThreads / 64; w++) s += red[w * C + q];
-  return s;
-}
-
 __device__ __forceinline__ void block_dots_1k(const KJob& J, const double* __restrict__ w, int i0, int nv,
                                               double* out, double* red) {
   const int64_t n = J.n;
@@ -1320,7 +1317,7 @@ __device__ __forceinline__ void block_dots_1k(const KJob& J, const double* __res
       for (int q = 0; q < kDotChunk; q++)
         if (c0 + q < nv) acc[q] += J.V[(int64_t)(i0 + c0 + q) * n + e] * we;
     }
-    const double s = block_sums_1k<kDotChunk>(acc, red);
+    const double s = block_sums8<kDotThreads / 64>(acc, red);
     if (threadIdx.x < kDotChunk && c0 + (int)threadIdx.x < nv) out[(c0 + threadIdx.x) * kRedBlocks + b] = s;
   }
 }
