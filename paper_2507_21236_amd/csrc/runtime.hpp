@@ -280,22 +280,43 @@ inline int64_t chunk_cap(int64_t Msz) {
   return Msz >= 65536 ? 32 : std::min<int64_t>(128, std::max<int64_t>(32, ((int64_t)1 << 19) / Msz));
 }
 // Item chunks per spectator of a matvec plan.  Spectators whose slices have
-// the same shape share one launch; the launch gets about target / units item
-// chunks per spectator in total (units = workgroups per chunk), shared out in
-// proportion to the spectators' item counts so that every chunk of the launch
-// carries about the same number of items.  nitems[sp] = 0: no chunk.
+// the same shape share one launch; the launch gets C = (number of such
+// spectators) x target / units item chunks in total (units = workgroups per
+// chunk), shared out in proportion to the spectators' item counts by largest
+// remainders, so that every chunk carries about the same number of items and
+// the chunks add up to exactly C (a launch of C x units workgroups: with the
+// default target, whole rounds of the chip's workgroup slots, and no round
+// that starts only a few of them).  nitems[sp] = 0: no chunk.
 inline void mv_chunk_counts(const int64_t nitems[3], const int ma[3], const int mb[3], const int64_t units[3],
                             int64_t Msz, const int64_t target[3], int out[3]) {
+  for (int sp = 0; sp < 3; sp++) out[sp] = 0;
+  bool done[3] = {false, false, false};
   for (int sp = 0; sp < 3; sp++) {
-    out[sp] = 0;
-    if (nitems[sp] <= 0) continue;
-    int64_t tot = 0, nsp = 0;
+    if (nitems[sp] <= 0 || done[sp]) continue;
+    int grp[3], ng = 0;
+    int64_t tot = 0;
     for (int q = 0; q < 3; q++)
-      if (nitems[q] > 0 && ma[q] == ma[sp] && mb[q] == mb[sp]) { tot += nitems[q]; nsp++; }
-    const int64_t C = nsp * std::max<int64_t>(1, target[sp] / std::max<int64_t>(1, units[sp]));
-    int64_t c = (C * nitems[sp] + tot / 2) / tot;
-    c = std::max<int64_t>(1, std::min<int64_t>(c, std::min<int64_t>(nitems[sp], chunk_cap(Msz))));
-    out[sp] = (int)c;
+      if (nitems[q] > 0 && ma[q] == ma[sp] && mb[q] == mb[sp]) { grp[ng++] = q; tot += nitems[q]; done[q] = true; }
+    const int64_t C = ng * std::max<int64_t>(1, target[sp] / std::max<int64_t>(1, units[sp]));
+    int64_t c[3], rem[3], sum = 0;
+    for (int g = 0; g < ng; g++) {
+      const int q = grp[g];
+      c[g] = C * nitems[q] / tot;
+      rem[g] = C * nitems[q] - c[g] * tot;   // remainder of the exact share, in units of 1 / tot
+      sum += c[g];
+    }
+    while (sum < C) {   // the largest remainders get one more chunk (lowest spectator first on ties)
+      int best = 0;
+      for (int g = 1; g < ng; g++)
+        if (rem[g] > rem[best]) best = g;
+      c[best]++;
+      rem[best] -= tot;
+      sum++;
+    }
+    for (int g = 0; g < ng; g++) {
+      const int q = grp[g];
+      out[q] = (int)std::max<int64_t>(1, std::min<int64_t>(c[g], std::min<int64_t>(nitems[q], chunk_cap(Msz))));
+    }
   }
 }
 void run_comb(CBPlan& P, hipStream_t s);
