@@ -405,6 +405,9 @@ EnvGeom env_geom(const Model& M, const EnvPlan& P) {
   return g;
 }
 
+// Workgroups an effective-operator update's sandwich launch aims at.
+constexpr int64_t kEnvWorkgroups = 2048;
+
 // Pieces per output: on the matrix cores an output whose item count exceeds
 // the balanced share of one task is split into pieces (separate partial Z
 // tensors, summed by the gram reduction) so that no task dominates the launch.
@@ -414,7 +417,7 @@ std::vector<int> env_pieces(const Model& M, const EnvPlan& P, int& cap_out) {
   int64_t W = 0;
   for (size_t o = 0; o < P.outs.size(); o++) W += (int64_t)P.outs[o].items.size();
   const int64_t strips = std::max(1, (g.ma / 16 + 3) / 4);
-  const int64_t ntask = std::max<int64_t>(1, (2048 + g.ns * strips - 1) / (g.ns * strips));
+  const int64_t ntask = std::max<int64_t>(1, (kEnvWorkgroups + g.ns * strips - 1) / (g.ns * strips));
   const int cap = sw_mfma(g.ma, g.mb) ? (int)std::max<int64_t>(4, (W + ntask - 1) / ntask) : 1 << 30;
   for (size_t o = 0; o < P.outs.size(); o++) {
     const int w = (int)P.outs[o].items.size();
@@ -509,7 +512,7 @@ void build_env_dev(attn_handle* h, const EnvPlan& P, EnvDev& D) {
     std::vector<std::vector<size_t>> packs;
     if (multi && !vouts.empty()) {
       const int64_t ntask = std::max<int64_t>(1, std::min<int64_t>((int64_t)vouts.size(),
-                                                                   (2048 + ns * strips - 1) / (ns * strips)));
+                                                                   (kEnvWorkgroups + ns * strips - 1) / (ns * strips)));
       std::vector<size_t> byw(vouts.size());
       for (size_t v = 0; v < vouts.size(); v++) byw[v] = v;
       std::stable_sort(byw.begin(), byw.end(), [&](size_t a, size_t b) { return vouts[a].ni > vouts[b].ni; });
