@@ -303,6 +303,7 @@ inline void mv_chunk_counts(const int64_t nitems[3], const int ma[3], const int 
       const int q = grp[g];
       c[g] = C * nitems[q] / tot;
       rem[g] = C * nitems[q] - c[g] * tot;   // remainder of the exact share, in units of 1 / tot
+      if (c[g] == 0) { c[g] = 1; rem[g] -= tot; }   // every spectator with items gets a chunk
       sum += c[g];
     }
     while (sum < C) {   // the largest remainders get one more chunk (lowest spectator first on ties)
@@ -312,6 +313,15 @@ inline void mv_chunk_counts(const int64_t nitems[3], const int ma[3], const int 
       c[best]++;
       rem[best] -= tot;
       sum++;
+    }
+    while (sum > C) {   // the smallest remainders among spectators with two chunks or more give one back
+      int worst = -1;
+      for (int g = 0; g < ng; g++)
+        if (c[g] > 1 && (worst < 0 || rem[g] < rem[worst])) worst = g;
+      if (worst < 0) break;
+      c[worst]--;
+      rem[worst] += tot;
+      sum--;
     }
     for (int g = 0; g < ng; g++) {
       const int q = grp[g];
