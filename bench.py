@@ -46,14 +46,14 @@ KERNELS = {"f64": "k_sandwich<double,4>", "f32": "k_sandwich<float,4>",
            "bf16x2": "k_sandwich_bf2w<4,4>"}
 # HBM bytes per launch of the FP64 contraction kernel at legs of dimension 64,
 # averaged like the live timing over the 620 matvec launches of a sweep of
-# this workload (300 launches of 3072 workgroups, 200 of 3136, 100 of 3008, 20
+# this workload (600 launches of 3072 workgroups at the (64,64,64) nodes, 20
 # at the root):
 # rocprofv3 --pmc FETCH_SIZE (x 2) and WRITE_SIZE (x 1) on
 # `bench.py --traffic-probe`, the factors read off a plain 1 GiB device copy
 # (profiles/k_sandwich_f64_legs64_hbm_traffic.md).  The writes are the
 # kernel's partial outputs (one per item chunk); the reads are X and the
 # operator blocks.  Valid for the kernel as measured: None once it changes.
-TRAFFIC_F64 = {"read": 116.4e6, "write": 97.9e6}
+TRAFFIC_F64 = {"read": 110.7e6, "write": 97.5e6}
 
 
 def cpu_baseline(problem, sample_matvecs=3):
