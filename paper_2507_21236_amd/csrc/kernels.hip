@@ -1673,41 +1673,67 @@ __global__ __launch_bounds__(64) void k_ktridiag(const KJob* __restrict__ jobs) 
 // (the same operator as the factorised matvec: every item's Kronecker product
 // written out entry by entry), then the Lanczos steps run in one workgroup
 // with a dense matvec.
+// O[ip][i] (column ip of the m x m block), or the identity when O is null.  The
+// load is unconditional (from a valid dummy when O is null), so that the
+// loads of consecutive items can be in flight together.
+__device__ const double g_one = 1.0;
 __device__ __forceinline__ double blk(const double* O, int m, int i, int ip) {
-  return O ? O[(int64_t)ip * m + i] : (i == ip ? 1.0 : 0.0);
+  const double x = *(O ? O + (int64_t)ip * m + i : &g_one);
+  return O ? x : (i == ip ? 1.0 : 0.0);
 }
 
-// H^T[j][i] = H[i][j] (H is symmetric), one thread per entry; job blockIdx.y
+// Items per entry are split over S threads (part q takes items q, q + S, ...)
+// whose sums are added in part order; S depends only on the node size, so a
+// job assembles the same bits alone or in a batch.
+__host__ __device__ __forceinline__ int tiny_assemble_parts(int M) { return (int64_t)M * M >= 65536 ? 4 : 8; }
+
+// H^T[j][i] = H[i][j] (H is symmetric); a block of 256 threads takes 256 / S
+// entries with S parts each; job blockIdx.y
 __global__ __launch_bounds__(256) void k_tiny_assemble(const TJob* __restrict__ jobs) {
+  __shared__ double part[256];
   const TJob& J = jobs[blockIdx.y];
   const TinyPlan P = *J.plan;
   double* __restrict__ H = J.H;
   const int d0 = P.d0, d1 = P.d1, d2 = P.d2;
   const int M = d0 * d1 * d2;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)M * M) return;
-  const int col = (int)(e / M), row = (int)(e - (int64_t)col * M);
-  const int l1 = row / (d1 * d2), r1 = (row / d2) % d1, p1 = row % d2;
-  const int l2 = col / (d1 * d2), r2 = (col / d2) % d1, p2 = col % d2;
+  const int S = tiny_assemble_parts(M), per = 256 / S;
+  const int q = threadIdx.x / per, le = threadIdx.x - q * per;
+  const int64_t e = (int64_t)blockIdx.x * per + le;
+  const bool on = e < (int64_t)M * M;
   double acc = 0;
-  if (l1 == l2)
-    for (int it = P.item0[0]; it < P.item0[0] + P.nitem[0]; it++)
-      acc += P.items[it].coef * blk((const double*)P.items[it].A, d1, r1, r2) *
-             blk((const double*)P.items[it].B, d2, p1, p2);
-  if (r1 == r2)
-    for (int it = P.item0[1]; it < P.item0[1] + P.nitem[1]; it++)
-      acc += P.items[it].coef * blk((const double*)P.items[it].A, d0, l1, l2) *
-             blk((const double*)P.items[it].B, d2, p1, p2);
-  if (p1 == p2)
-    for (int it = P.item0[2]; it < P.item0[2] + P.nitem[2]; it++)
-      acc += P.items[it].coef * blk((const double*)P.items[it].A, d0, l1, l2) *
-             blk((const double*)P.items[it].B, d1, r1, r2);
-  for (int it = 0; it < P.n3; it++) {
-    const Item3& q = P.items3[it];
-    acc += q.coef * blk((const double*)q.op[0], d0, l1, l2) * blk((const double*)q.op[1], d1, r1, r2) *
-           blk((const double*)q.op[2], d2, p1, p2);
+  if (on) {
+    const int col = (int)(e / M), row = (int)(e - (int64_t)col * M);
+    const int l1 = row / (d1 * d2), r1 = (row / d2) % d1, p1 = row % d2;
+    const int l2 = col / (d1 * d2), r2 = (col / d2) % d1, p2 = col % d2;
+    if (l1 == l2)
+#pragma unroll 2
+      for (int it = P.item0[0] + q; it < P.item0[0] + P.nitem[0]; it += S)
+        acc += P.items[it].coef * blk((const double*)P.items[it].A, d1, r1, r2) *
+               blk((const double*)P.items[it].B, d2, p1, p2);
+    if (r1 == r2)
+#pragma unroll 2
+      for (int it = P.item0[1] + q; it < P.item0[1] + P.nitem[1]; it += S)
+        acc += P.items[it].coef * blk((const double*)P.items[it].A, d0, l1, l2) *
+               blk((const double*)P.items[it].B, d2, p1, p2);
+    if (p1 == p2)
+#pragma unroll 2
+      for (int it = P.item0[2] + q; it < P.item0[2] + P.nitem[2]; it += S)
+        acc += P.items[it].coef * blk((const double*)P.items[it].A, d0, l1, l2) *
+               blk((const double*)P.items[it].B, d1, r1, r2);
+#pragma unroll 2
+    for (int it = q; it < P.n3; it += S) {
+      const Item3& t3 = P.items3[it];
+      acc += t3.coef * blk((const double*)t3.op[0], d0, l1, l2) * blk((const double*)t3.op[1], d1, r1, r2) *
+             blk((const double*)t3.op[2], d2, p1, p2);
+    }
   }
-  H[e] = acc;
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (q == 0 && on) {
+    double h = 0;
+    for (int r = 0; r < S; r++) h += part[r * per + le];
+    H[e] = h;
+  }
 }
 
 // Tiny-node Lanczos, the same steps in both kernels below:
@@ -3235,8 +3261,11 @@ hipError_t launch_kritz(const KJob* jobs, int nj, hipStream_t s) {
 
 hipError_t launch_tiny(const TJob* jobs, int nj, int minM, int maxM, int kreq, hipStream_t s) {
   if (maxM > 1024 || minM < 1 || minM > maxM) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_tiny_assemble, dim3((unsigned)(((int64_t)maxM * maxM + 255) / 256), nj), dim3(256),
-                     0, s, jobs);
+  // blocks for the most entries x parts of any job size in [minM, maxM]
+  int64_t ablocks = 0;
+  for (int64_t m : {(int64_t)minM, (int64_t)maxM, std::min<int64_t>(maxM, 255)})
+    if (m >= minM && m <= maxM) ablocks = std::max<int64_t>(ablocks, (m * m * tiny_assemble_parts((int)m) + 255) / 256);
+  hipLaunchKernelGGL(k_tiny_assemble, dim3((unsigned)ablocks, nj), dim3(256), 0, s, jobs);
   if (minM <= kTinyWaveM)
     hipLaunchKernelGGL(k_tiny_lanczos_wave, dim3(nj), dim3(64), (size_t)kTinyWaveLds, s, jobs, kreq);
   if (maxM > kTinyWaveM) {
