@@ -16,6 +16,7 @@
 namespace attn {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double dv2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
@@ -1851,19 +1852,20 @@ __device__ __forceinline__ double block_sum_nw(double v, double* red, int nwm) {
 }
 
 // 64 < M <= 1024: one workgroup of 1024 threads per job; thread t owns vector
-// entry t.  The dense matvec splits the columns over S = min(M, 1024 / M)
-// slices (thread S-slice sl, row r), 16 loads of H in flight per thread; the
-// slices' partial sums are added in a fixed order.  Each Gram-Schmidt dot
+// entry t.  The dense matvec splits the columns over S slices, 16 loads of H
+// in flight per thread: for even M a thread takes two adjacent rows with
+// 16-byte loads (S = min(M, 2048 / M)), for odd M one row (S = min(M,
+// 1024 / M)); the slices' partial sums are added in a fixed order.  Each Gram-Schmidt dot
 // product is taken by one wavefront.  The product of step j + 1 runs on the
 // unnormalised w of step j and is scaled by 1 / beta_j afterwards, so the new
 // basis vector needs no barrier of its own.
-// Dynamic LDS: partial sums [1024], H x [1024], then (VL) the basis [k][M] and
+// Dynamic LDS: partial sums [2048], H x [1024], then (VL) the basis [k][M] and
 // w [M]; without VL the basis and w stay in the job's global buffers.
 __host__ __device__ __forceinline__ int64_t tiny_basis_bytes(int M, int kreq) {
   const int64_t k = kreq < M ? kreq : M;
   return (k + 1) * M * (int64_t)sizeof(double);
 }
-constexpr int64_t kTinyBlockFixed = 2048 * (int64_t)sizeof(double);
+constexpr int64_t kTinyBlockFixed = 3072 * (int64_t)sizeof(double);
 
 template <bool VL>
 __global__ __launch_bounds__(1024) void k_tiny_lanczos_block(const TJob* __restrict__ jobs, int kreq) {
@@ -1880,12 +1882,16 @@ __global__ __launch_bounds__(1024) void k_tiny_lanczos_block(const TJob* __restr
   double* __restrict__ T = J.T;
   KrylovState* __restrict__ st = J.st;
   const int k = kreq < M ? kreq : M;
-  double* part = reinterpret_cast<double*>(smem_raw);
-  double* ub = part + 1024;
+  double* part = reinterpret_cast<double*>(smem_raw);   // [S][M] <= 2048
+  double* ub = part + 2048;
   double* V = VL ? ub + 1024 : J.V;
   double* w = VL ? V + (int64_t)k * M : J.w;
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int S = max(1, min(M, 1024 / M));
+  // column slices of the product: M even, S x (M / 2) threads on row pairs;
+  // M odd, S x M threads on single rows
+  const bool even = (M & 1) == 0;
+  const int P2 = M / 2;
+  const int S = even ? max(1, min(M, 1024 / P2)) : max(1, min(M, 1024 / M));
   const int nwm = (M + 63) >> 6;
   const bool mine = t < M;
   if (t == 0) { st->kmax = k; st->keff = 1; st->stop = 0; st->status = 0; }
@@ -1899,7 +1905,34 @@ __global__ __launch_bounds__(1024) void k_tiny_lanczos_block(const TJob* __restr
   int keff = 1;
   double wv = 0;
   for (int j = 0; j < k; j++) {
-    if (t < S * M) {
+    if (even) {
+      // rows 2 rp and 2 rp + 1 of each column in one 16-byte load (the
+      // product is bound by load instructions, not bytes)
+      if (t < S * P2) {
+        const int rp = t % P2, sl = t / P2;
+        const __attribute__((address_space(1))) dv2* hp = (const __attribute__((address_space(1))) dv2*)(H + 2 * rp);
+        double a0 = 0, a1 = 0;
+        int c = sl;
+        for (; c + 15 * S < M; c += 16 * S) {
+          dv2 hv[16];
+#pragma unroll
+          for (int u = 0; u < 16; u++) hv[u] = hp[(int64_t)(c + u * S) * P2];
+#pragma unroll
+          for (int u = 0; u < 16; u++) {
+            const double xv = xp[c + u * S];
+            a0 += hv[u].x * xv;
+            a1 += hv[u].y * xv;
+          }
+        }
+        for (; c < M; c += S) {
+          const dv2 hv = hp[(int64_t)c * P2];
+          a0 += hv.x * xp[c];
+          a1 += hv.y * xp[c];
+        }
+        part[sl * M + 2 * rp] = a0;
+        part[sl * M + 2 * rp + 1] = a1;
+      }
+    } else if (t < S * M) {
       const int r = t % M, sl = t / M;
       const __attribute__((address_space(1))) double* hp = H + r;
       double acc = 0;
