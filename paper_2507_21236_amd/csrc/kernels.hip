@@ -1377,12 +1377,51 @@ __global__ __launch_bounds__(256) void k_kortho(const KJob* __restrict__ jobs, i
     if (!isfinite(hs[j])) fail_status(J.st, 1);
   }
   const int b = blockIdx.x;
+  double* po = parea(J, pin + 1);
+  if ((n & 1) == 0) {
+    // even n: element pairs (2 e, 2 e + 1) per thread, 16-byte loads
+    const int64_t np = n / 2;
+    dv2* w2 = reinterpret_cast<dv2*>(w);
+    for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < np; e += (int64_t)kRedBlocks * 256) {
+      dv2 x = w2[e];
+      for (int i = 0; i < nv; i++) x -= hs[i] * reinterpret_cast<const dv2*>(J.V + (int64_t)i * n)[e];
+      w2[e] = x;
+    }
+    if (norm_only) {
+      double acc = 0;
+      for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < np; e += (int64_t)kRedBlocks * 256) {
+        const dv2 x = w2[e];
+        acc += x.x * x.x;
+        acc += x.y * x.y;
+      }
+      const double s = block_sum(acc, red);
+      if (threadIdx.x == 0) po[b] = s;
+      return;
+    }
+    for (int i0 = 0; i0 < nv; i0 += kDotChunk) {
+      double acc[kDotChunk];
+#pragma unroll
+      for (int q = 0; q < kDotChunk; q++) acc[q] = 0.0;
+      for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < np; e += (int64_t)kRedBlocks * 256) {
+        const dv2 we = w2[e];
+#pragma unroll
+        for (int q = 0; q < kDotChunk; q++)
+          if (i0 + q < nv) {
+            const dv2 v = reinterpret_cast<const dv2*>(J.V + (int64_t)(i0 + q) * n)[e];
+            acc[q] += v.x * we.x;
+            acc[q] += v.y * we.y;
+          }
+      }
+      const double s = block_sums8<4>(acc, red8);
+      if (threadIdx.x < kDotChunk && i0 + (int)threadIdx.x < nv) po[(i0 + threadIdx.x) * kRedBlocks + b] = s;
+    }
+    return;
+  }
   for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256) {
     double x = w[e];
     for (int i = 0; i < nv; i++) x -= hs[i] * J.V[(int64_t)i * n + e];
     w[e] = x;
   }
-  double* po = parea(J, pin + 1);
   if (norm_only) {
     double acc = 0;
     for (int64_t e = (int64_t)b * 256 + threadIdx.x; e < n; e += (int64_t)kRedBlocks * 256)
