@@ -97,3 +97,38 @@ def test_lowp_sweeps_8x8_m16_track_fp64():
         d = np.abs(np.asarray(e) - np.asarray(e64)).max() / p.n_sites
         print(f"{name}: sweep energies {list(e)} vs fp64 {list(e64)}; max |dE|/N {d:.2e}")
         assert d < 10 * TOL[name], (name, d)
+
+
+
+def test_sweeps_8x8_m32_against_oracle_golden():
+    # 8 x 8 Ising, h = 3.05, m = 32, 16 gates, 8 sweeps, against the FP64
+    # oracle's energies (tests/golden, written by make_reference.py from the
+    # oracle only).  FP64 follows the oracle's trajectory to rounding.  The
+    # FP32 and split BF16 forms keep the Krylov recurrences, the Rayleigh
+    # quotient, the projected eigenproblem and QR in FP64, so the energy they
+    # report is the FP64 energy of the state they produced (checked against
+    # the FP64 Rayleigh quotient at the centre); their trajectories separate
+    # from the FP64 one by rounding amplification, bounded as in the test above.
+    import json
+    import os
+    from paper_2507_21236_amd import AttnHandle, solver_opts, ATTN_F64
+    from tests.gpu_util import gpu_matvec
+    p = config_problem("ising8_m32")
+    with open(os.path.join(os.path.dirname(__file__), "golden", "ising8_m32_oracle.json")) as f:
+        gold = np.asarray(json.load(f)["energies"])
+    assert len(gold) == 8
+    for name, dt in [("f64", ATTN_F64)] + _forms():
+        a = AttnHandle(p)
+        a.init_state()
+        e, _ = a.sweep(8, solver_opts(krylov_k=20, precision=dt))
+        r = np.abs(np.asarray(e) - gold) / np.abs(gold)
+        n = a.center
+        t = a.get_tensor(n)
+        rq = float(np.vdot(t, gpu_matvec(a, n, t)) / np.vdot(t, t))
+        print(f"{name}: relative energy difference to the oracle per sweep",
+              " ".join(f"{x:.1e}" for x in r), f"; reported vs FP64 Rayleigh quotient {abs(e[-1] - rq) / abs(rq):.1e}")
+        assert abs(e[-1] - rq) <= 1e-12 * abs(rq), (name, e[-1], rq)
+        if name == "f64":
+            assert r.max() <= 1e-12, r
+        else:
+            assert r.max() <= 10 * TOL[name], (name, r)
