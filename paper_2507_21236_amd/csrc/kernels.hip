@@ -2863,14 +2863,18 @@ __global__ __launch_bounds__(64) void k_chol_inv_blk(const double* __restrict__ 
   if (lane == 0 && bad && st) fail_status(st, 2);
 }
 
-// (b) other n (<= 128): L and X = L^{-1} as packed lower triangles in LDS
-//     (n (n + 1) doubles), rank-1 updates over a 16 x 16 thread grid.
+// (b) other n: L and X = L^{-1} as packed lower triangles (n (n + 1)
+//     doubles), rank-1 updates over a 16 x 16 thread grid; in LDS for
+//     n <= 128, else in the device workspace ws (the one workgroup's own
+//     writes, ordered by its barriers; the triangles stay in L2).
+template <bool WS>
 __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ G, int n,
                                                   double* __restrict__ R,
                                                   double* __restrict__ RinvRow, int shift_mode,
-                                                  int64_t rows, KrylovState* __restrict__ st) {
+                                                  int64_t rows, KrylovState* __restrict__ st,
+                                                  double* __restrict__ ws) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* L = reinterpret_cast<double*>(smem_raw);
+  double* L = WS ? ws : reinterpret_cast<double*>(smem_raw);
   double* X = L + n * (n + 1) / 2;
   __shared__ double shift;
   __shared__ int bad;
@@ -3353,7 +3357,7 @@ hipError_t launch_tiny(const TJob* jobs, int nj, int minM, int maxM, int kreq, h
 }
 
 hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, int shift_mode,
-                           int64_t rows, KrylovState* st, hipStream_t s) {
+                           int64_t rows, KrylovState* st, double* ws, hipStream_t s) {
   switch (n) {
     case 16: hipLaunchKernelGGL(k_chol_inv_blk<16>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
     case 32: hipLaunchKernelGGL(k_chol_inv_blk<32>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
@@ -3361,8 +3365,13 @@ hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, i
     case 64: hipLaunchKernelGGL(k_chol_inv_blk<64>, dim3(1), dim3(64), 0, s, G, R, RinvRow, shift_mode, rows, st); return hipGetLastError();
     default: break;
   }
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), (size_t)n * (n + 1) * sizeof(double), s, G,
-                     n, R, RinvRow, shift_mode, rows, st);
+  if (n <= 128) {
+    hipLaunchKernelGGL(k_chol_inv<false>, dim3(1), dim3(256), (size_t)n * (n + 1) * sizeof(double), s, G,
+                       n, R, RinvRow, shift_mode, rows, st, nullptr);
+    return hipGetLastError();
+  }
+  if (!ws) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chol_inv<true>, dim3(1), dim3(256), 0, s, G, n, R, RinvRow, shift_mode, rows, st, ws);
   return hipGetLastError();
 }
 

@@ -84,9 +84,10 @@ hipError_t launch_axpby(double alpha, const double* x, double beta, double* y, i
 hipError_t launch_harvest_write(const double* diag, const double* r, const double* x, double theta, double sc,
                                 double rinf, float* feats, float* targets, int64_t n, hipStream_t s);
 
-// QR helpers
+// QR helpers.  ws: n (n + 1) doubles of device workspace, used (and required)
+// when n > 128
 hipError_t launch_chol_inv(const double* G, int n, double* R, double* RinvRow, int shift_mode,
-                           int64_t rows, KrylovState* st, hipStream_t s);
+                           int64_t rows, KrylovState* st, double* ws, hipStream_t s);
 hipError_t launch_qr_small(double* T, int d0, int d1, int d2, int j, double* Rout, KrylovState* st,
                            hipStream_t s);
 hipError_t launch_small_matmul(const double* A, const double* B, double* C, int n, hipStream_t s);

@@ -929,11 +929,12 @@ void qr_node(attn_handle* h, int n, int leg, hipStream_t s) {
   double* R[3] = {G + nn, G + 2 * nn, G + 3 * nn};
   double* Rinv = G + 4 * nn;
   double* Rt = G + 5 * nn;
+  double* ws = G + 6 * nn;   // Cholesky workspace for links wider than 128
   // the passes rotate T -> tmp -> tmp2 -> T (plans built that way): Q ends in T
   for (int pass = 0; pass < 3; pass++) {
     HIPCHK(launch_gram(mj, Q.gmf, Q.d_gt[pass], Q.nfc, s, Q.gnt));
     HIPCHK(launch_gram_reduce(Q.d_gr, 1, mj, s));
-    HIPCHK(launch_chol_inv(G, mj, R[pass], Rinv, pass == 0 ? 1 : 0, Q.rows, h->d_st, s));
+    HIPCHK(launch_chol_inv(G, mj, R[pass], Rinv, pass == 0 ? 1 : 0, Q.rows, h->d_st, ws, s));
     HIPCHK(launch_mode(0, mj, Q.mmf, Q.d_mt[pass], Q.d_mj[pass], Q.d_wus, Q.nwus, nullptr, s, Q.mnt));
   }
   HIPCHK(launch_small_matmul(R[1], R[0], Rt, mj, s));
@@ -1308,7 +1309,7 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
     h->d_red = alloc((int64_t)4 * 64 * kRedBlocks);
     for (int n = 0; n < nn; n++)
       for (int l = 0; l < 3; l++) h->mmax = std::max(h->mmax, tr.nodes[n].dims[l]);
-    h->d_qrmat = alloc(6 * (int64_t)h->mmax * h->mmax);
+    h->d_qrmat = alloc(qrmat_doubles(h->mmax));
     h->d_qrR = alloc((int64_t)h->mmax * h->mmax);
     h->cv_cap = 6 + 2 * (int)std::max<size_t>(1, [&] { size_t mx = 0; for (int n = 0; n < nn; n++) mx = std::max(mx, h->M.mv[n].combines.size()); return mx; }());
     h->d_cvtasks = dev_alloc(h, (size_t)h->cv_cap * sizeof(CVTask));
@@ -2180,7 +2181,7 @@ extern "C" attn_status attn_validate(const attn_handle* h) {
           c.mp(Q.h_mp[pass], 0, 8);
         }
         c.red(Q.h_gr);
-        c.span(h->d_qrmat, 6 * (int64_t)h->mmax * h->mmax * 8, "qr matrices");
+        c.span(h->d_qrmat, qrmat_doubles(h->mmax) * 8, "qr matrices");
       }
       const ABDev& A = h->ab[l][n];
       if (A.present) c.mp(A.h_mp, 0, 8);

@@ -187,7 +187,7 @@ struct attn_handle {
   double* d_Z = nullptr;
   double* d_grpart = nullptr;
   double* d_red = nullptr;    // 128 x kRedBlocks
-  double* d_qrmat = nullptr;  // G, R0, R1, R2, Rinv, Rt (mmax^2 each)
+  double* d_qrmat = nullptr;  // G, R0, R1, R2, Rinv, Rt (mmax^2 each), Cholesky workspace
   double* d_qrR = nullptr;    // R of the last QR (absorbed into the neighbour)
   void* d_cvtasks = nullptr;  // conversion work list (low-precision forms)
   int cv_cap = 0;
@@ -273,6 +273,10 @@ void slice_geom(int spect, const int* dm, int& ma, int& mb, int& ns, int64_t& sl
 // (target workgroups per launch, per spectator's slice shape)
 void mv_chunks(const MatvecPlan& P, const int* dm, const int64_t target[3], int out[3]);
 bool sw_mfma(int ma, int mb);
+// Doubles of the QR matrices of a handle whose widest link is mmax: G, R0, R1,
+// R2, R^-1, R products (mmax^2 each) and the Cholesky workspace of links wider
+// than 128 (two packed triangles, mmax (mmax + 1)).
+inline int64_t qrmat_doubles(int64_t mmax) { return 6 * mmax * mmax + mmax * (mmax + 1); }
 // Most item chunks (workgroup sets with their own partial output) of one
 // sandwich group of a matvec: small nodes get more, so that their few slices
 // still spread over the chip.

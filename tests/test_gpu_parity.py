@@ -5,7 +5,7 @@ energies per site to 1e-10."""
 import numpy as np
 import pytest
 
-from problems import config_problem, make_chain_problem, batch_instances
+from problems import config_problem, make_chain_problem, make_problem, batch_instances
 from tests.gpu_util import make_pair, move_both, gpu_matvec, rel
 
 pytestmark = pytest.mark.gpu
@@ -163,3 +163,29 @@ def test_sweeps_16x16_track_oracle_golden():
     for s, (x, y) in enumerate(zip(e, ref)):
         print(f"sweep {s}: GPU {x:.10f} oracle {y:.10f} |dE|/N {abs(x - y) / p.n_sites:.2e}")
         assert abs(x - y) / p.n_sites < 1e-5, (s, x, y)
+
+
+def test_sweeps_4x4_against_exact_diagonalisation():
+    # The rotated Hamiltonian has the spectrum of the lattice one (the gates
+    # are orthogonal), whose ground energy comes from exact diagonalisation of
+    # the 2^16-dimensional space.  At m = 8 every sweep energy is a Rayleigh
+    # quotient of a state in the variational class: it stays above E_0 and
+    # never rises.  At m = 256 no bond of the 16-leaf tree is truncated (the
+    # top link needs 2^8; no gates are placed then), so the sweeps reach E_0.
+    from oracle.ed import ground_energy
+    from paper_2507_21236_amd import AttnHandle
+    p = config_problem("ising4_m8")
+    E0 = ground_energy(p.terms, p.n_sites)
+    a = AttnHandle(p)
+    a.init_state()
+    e, _ = a.sweep(5)
+    print("m = 8: relative error to ED per sweep", " ".join(f"{(x - E0) / abs(E0):.2e}" for x in e))
+    assert np.all(e >= E0 - 1e-12 * abs(E0))
+    assert np.all(np.diff(e) <= 1e-12 * abs(E0))
+    q = make_problem("ising4_m256", 4, "ising", 256, 1, 4, h=3.0)
+    b = AttnHandle(q)
+    b.init_state()
+    e, _ = b.sweep(12)
+    print("m = 256: relative error to ED per sweep", " ".join(f"{(x - E0) / abs(E0):.2e}" for x in e))
+    assert np.all(e >= E0 - 1e-12 * abs(E0))
+    assert abs(e[-1] - E0) <= 1e-10 * abs(E0)
