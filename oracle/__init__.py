@@ -13,8 +13,10 @@ Modules and the parts of the paper they follow:
                 D(u)|psi_TTN> (eq. 1) as a 2^N vector.
 * ``tree``   -- binary tree tensor network structure (Sec. 3.1).
 * ``terms``  -- disentangler layer contracted into every term, h' = U^T h U
-                (Sec. 4.2, algorithm "Contract disentangler layer"; ordering of
-                the rotation as read in the design doc), and operator-Schmidt splits.
+                (Sec. 4.2, algorithm "Contract disentangler layer"; the state is
+                D|psi_TTN>, so the rotated Hamiltonian is D^T H D and every term
+                becomes U^T h U -- the paper also writes D H D^dagger, which spans
+                the same variational class), and operator-Schmidt splits.
 * ``davidson`` -- an eigensolver form that is not from the paper: the H_eff
                 diagonal, Davidson's method with Jacobi or learned pointwise
                 corrections, the exact Jacobi-Davidson correction, the MLP

@@ -11,8 +11,9 @@ Follows the paper step by step, in float64, with no fusion:
 * Sec. 4.3.2: the generalised matvec contracts every item into the tensor in
   turn (``matvec``).
 * Sec. 4 (steps 2-3): a DMRG sweep of single-tensor updates with the Lanczos
-  eigensolver (``eigsolve``; the paper names Lanczos without details -- k = 20
-  vectors, full reorthogonalisation, no restart, as read in the design doc).
+  eigensolver (``eigsolve``; the paper names Lanczos without details, read
+  here as k = min(20, M) vectors from the current tensor, full
+  reorthogonalisation, stop when beta_j <= 1e-14 max|alpha|, no restart).
 
 Effective operators are kept per directed link and recomputed only for the
 link the centre has just crossed.  For every link the oracle stores, besides
