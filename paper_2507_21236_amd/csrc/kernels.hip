@@ -152,8 +152,12 @@ __device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __r
         const double2 o0 = *p0, o1 = *p1;
         v0.x += o0.x; v0.y += o0.y; v1.x += o1.x; v1.y += o1.y;
       }
-      *p0 = v0;
-      *p1 = v1;
+      // streaming stores: each output (a partial sum, a Z tensor) is read once
+      // by the next kernel, and not allocating it in L2 keeps the operator
+      // blocks there (matvec launches -2 %, effective-operator launches -5 %;
+      // the reduction of the partials reads them from HBM, +4 us)
+      __builtin_nontemporal_store(dv2{v0.x, v0.y}, (dv2*)p0);
+      __builtin_nontemporal_store(dv2{v1.x, v1.y}, (dv2*)p1);
     }
   } else {
 #pragma unroll
