@@ -7,11 +7,12 @@
  *   |psi_aTTN> = D(u) |psi_TTN>, D(u) = prod_k u_k two-site unitaries on the
  *   bottom of a binary TTN (Sec. 2, eq. 1).  The ground-state sweep maps the
  *   Hamiltonian (a sum of local terms stored term by term as a TPO, Sec. 3.3)
- *   to H' with the disentangler layer contracted into every term (Sec. 4.2,
+ *   to H' with the disentangler layer contracted into every term (Sec. 4.3,
  *   algorithm "Contract disentangler layer"), then runs a DMRG sweep of
  *   single-tensor updates on the TTN (Sec. 4, step 3): QR isometrisation
  *   (Sec. 3.1), effective operators kept term by term (Sec. 3.3.2), and the
- *   generalised matvec inside the Lanczos eigensolver (Sec. 4.3.2).
+ *   generalised matvec (Sec. 3.3.2, cost in Sec. 4.4.2) inside the Lanczos
+ *   eigensolver (Sec. 4.4.2).
  *
  * Conventions shared by every call:
  *   - Every call returns attn_status: 0 = ATTN_OK, negative = error.  No C++
@@ -54,6 +55,8 @@ typedef int32_t attn_status;
 #define ATTN_ERR_SHAPE          -9   /* buffer length does not match the tensor size */
 #define ATTN_ERR_NUMERIC       -10   /* NaN / Inf, or a factorisation broke down */
 #define ATTN_ERR_UNSUPPORTED   -11   /* valid input outside what this build implements */
+#define ATTN_ERR_IO            -12   /* a file cannot be opened, read or written, or is corrupt */
+#define ATTN_ERR_MISMATCH      -13   /* a checkpoint belongs to another problem */
 
 /* attn_problem.flags */
 #define ATTN_DE_STRICT     1u  /* enforce both placement restrictions of Sec. 6.1.1 */
@@ -105,7 +108,7 @@ typedef struct attn_problem {
 
 typedef struct attn_handle attn_handle;
 
-/* Local eigensolver options (Sec. 4.3.2: Lanczos inside the sweep). */
+/* Local eigensolver options (Sec. 4.4.2: Lanczos inside the sweep). */
 #define ATTN_SOLVER_LANCZOS  0
 #define ATTN_SOLVER_DAVIDSON 1
 #define ATTN_PRECOND_NONE    0
@@ -133,7 +136,7 @@ typedef struct attn_sweep_opts {
 } attn_sweep_opts;
 
 /*
- * a1. Rotated TPO build (Sec. 4.2, algorithm "Contract disentangler layer"):
+ * a1. Rotated TPO build (Sec. 4.3, algorithm "Contract disentangler layer"):
  * validates the problem, builds the tree and bond dimensions, contracts the
  * disentanglers touching each term into it (h' = U^T h U on the extended
  * support), factorises every rotated term across each tree link it crosses
@@ -154,7 +157,10 @@ attn_status attn_destroy(attn_handle* h);
  * With h == NULL: the last error of a failed attn_build_tpo in this thread. */
 const char* attn_last_error(const attn_handle* h);
 
-/* Structure of node `node`: dims[3] = (m_l, m_r, m_p); *n_cross = number of
+/* Structure of node `node` and the cost of its matvec (Sec. 4.4.2: each TPO
+ * term of the effective operators is contracted into the tensor in turn, so
+ * the cost is set by the bond dimensions, the TPO bonds t and the number of
+ * terms): dims[3] = (m_l, m_r, m_p); *n_cross = number of
  * crossing terms; *flops = algorithmic flops of one matvec (summed local legs
  * 2 m_j M, two-leg terms 2 M t (m_a + m_b), three-leg terms the cheapest chain
  * 2 M (t_a m_a + t_a t_c m_b + t_c m_c); M = m_l m_r m_p, t = minimal bonds).
@@ -198,7 +204,7 @@ attn_status attn_get_center(const attn_handle* h, int32_t* node);
 attn_status attn_update_env(attn_handle* h, int32_t node, int32_t leg, void* stream);
 
 /*
- * a3. H_eff matvec (Sec. 3.3.2 and 4.3.2): y <- H_eff(node) x, with
+ * a3. H_eff matvec (Sec. 3.3.2; its cost, Sec. 4.4.2): y <- H_eff(node) x, with
  * H_eff = E_l x 1 x 1 + 1 x E_r x 1 + 1 x 1 x E_p + sum over crossing terms of
  * their leg blocks contracted into x over the TPO bonds.  x and y are device
  * pointers of M = m_l m_r m_p elements, row-major [l][r][p]: double for
@@ -211,7 +217,9 @@ attn_status attn_heff_apply(attn_handle* h, int32_t node, int32_t dtype, const v
                             void* y, void* stream);
 
 /*
- * a4. Local eigensolve: lowest eigenpair of H_eff(node), warm-started from
+ * a4. Local eigensolve (Sec. 4: the variational sweep minimises the energy
+ * of one tensor at a time; Sec. 4.4.2: with the Lanczos algorithm, one matvec
+ * per iteration): lowest eigenpair of H_eff(node), warm-started from
  * T_node.  Lanczos: k = min(opts->krylov_k, M) matvecs, three-term recurrence
  * plus two passes of classical Gram-Schmidt in FP64, stop when
  * beta_j <= 1e-14 max|alpha|; lowest eigenpair of the tridiagonal matrix; the
@@ -359,6 +367,44 @@ attn_status attn_batch_info(const attn_batch* b, int32_t* n_steps, int64_t* n_la
 const char* attn_batch_last_error(const attn_batch* b);
 
 attn_status attn_batch_destroy(attn_batch* b);
+
+/*
+ * Checkpoint and restore of the variational state (the sweep is an iteration,
+ * Sec. 4: the state after any number of sweeps is the starting point of the
+ * next, so it can be saved and resumed).
+ *
+ * attn_checkpoint writes `path` (through `path`.tmp and a rename): a hash of
+ * the problem the handle was built from (sizes, leaf order, terms,
+ * disentangler sites, strict flag), the disentangler matrices, every tensor
+ * T_n, the isometry centre and the isometry direction of every node, and the
+ * energies of every sweep run so far through attn_sweep; the file ends with a
+ * checksum.  Synchronises the device.  Errors: ARG (NULL path), STATE (no
+ * state: attn_init_state not called; host-only handle), IO, HIP.
+ *
+ * attn_restore loads such a file into a handle built from the same problem
+ * (same hash) with the same disentanglers: tensors, centre, isometry
+ * directions and sweep history are replaced, and every effective operator
+ * pointing toward the centre is recomputed from the restored tensors, so the
+ * handle continues exactly as the saved one would have (sweeps after a
+ * restore repeat those of the uninterrupted run bit for bit).  Synchronises
+ * the device.  Errors: ARG, IO (unreadable, truncated or corrupt file,
+ * directions that do not point to the centre), MISMATCH (another problem or
+ * other disentanglers), STATE (host-only), HIP.
+ */
+attn_status attn_checkpoint(attn_handle* h, const char* path);
+attn_status attn_restore(attn_handle* h, const char* path);
+
+/* Header of a checkpoint file, read and checksum-verified on the host (no
+ * handle or GPU needed).  Any output pointer may be NULL.  Errors: ARG, IO. */
+attn_status attn_checkpoint_info(const char* path, uint64_t* problem_hash, int32_t* n_nodes,
+                                 int32_t* center, int64_t* n_sweeps);
+
+/* Problem hash of the handle (the value a checkpoint records). */
+attn_status attn_problem_hash(const attn_handle* h, uint64_t* hash);
+
+/* Energies of every sweep run on the handle (including those restored from a
+ * checkpoint): *n_sweeps = count, energies[0 .. min(cap, count)) written. */
+attn_status attn_sweep_history(const attn_handle* h, int64_t* n_sweeps, double* energies, int64_t cap);
 
 /* Checks on the host that every work unit of every device work list of the
  * handle reads and writes only inside the buffer it was built for.  Meant for

@@ -13,7 +13,7 @@ Modules and the parts of the paper they follow:
                 D(u)|psi_TTN> (eq. 1) as a 2^N vector.
 * ``tree``   -- binary tree tensor network structure (Sec. 3.1).
 * ``terms``  -- disentangler layer contracted into every term, h' = U^T h U
-                (Sec. 4.2, algorithm "Contract disentangler layer"; the state is
+                (Sec. 4.3, algorithm "Contract disentangler layer"; the state is
                 D|psi_TTN>, so the rotated Hamiltonian is D^T H D and every term
                 becomes U^T h U -- the paper also writes D H D^dagger, which spans
                 the same variational class), and operator-Schmidt splits.
@@ -23,7 +23,7 @@ Modules and the parts of the paper they follow:
                 model, its gradient and Adam updates (published methods cited
                 in the module).
 * ``ttn``    -- isometric TTN, effective operators kept term by term
-                (Sec. 3.3.2), the generalised matvec (Sec. 4.3.2), Lanczos,
+                (Sec. 3.3.2), the generalised matvec (Sec. 4.4.2), Lanczos,
                 QR isometrisation (Sec. 3.1) and the sweep (Sec. 4).
 
 Pins: every function is checked in ``tests/test_oracle_*.py`` against exact

@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
-The paper solves the local eigenproblem with the Lanczos method (Sec. 4.3.2
-and the cost analysis of Sec. 5); this module defines an alternative eigensolver
+The paper solves the local eigenproblem with the Lanczos method (Sec. 4.4.2,
+the cost analysis of the ground-state search); this module defines an alternative eigensolver
 form that is not from the paper, written from the published methods it uses:
 
 * ``heff_diagonal`` -- the diagonal of H_eff(n).  H_eff(n) is a sum of

@@ -2,7 +2,7 @@
 
 The aTTN state is D|psi_TTN> with D the product of the two-site gates
 (paper Sec. 2, eq. 1), so its energy is <psi_TTN| D^T H D |psi_TTN>.  The
-mapped Hamiltonian H' = D^T H D is built term by term (Sec. 4.2, algorithm
+mapped Hamiltonian H' = D^T H D is built term by term (Sec. 4.3, algorithm
 "Contract disentangler layer"): a term h is conjugated only by the gates that
 touch its support -- gates away from it cancel by unitarity (Sec. 4.1,
 figure on the energy split).  A gate lying fully on the term keeps it n-body

@@ -8,7 +8,7 @@ Follows the paper step by step, in float64, with no fusion:
 * Sec. 3.3.2: effective operators are built term by term; a term whose support
   lies inside one region of the centre is summed into that leg's operator, the
   others stay separate items passed to the matvec.
-* Sec. 4.3.2: the generalised matvec contracts every item into the tensor in
+* Sec. 3.3.2 and 4.4.2: the generalised matvec contracts every item into the tensor in
   turn (``matvec``).
 * Sec. 4 (steps 2-3): a DMRG sweep of single-tensor updates with the Lanczos
   eigensolver (``eigsolve``; the paper names Lanczos without details, read

@@ -100,6 +100,18 @@ class AttnHandle:
     def validate(self):
         _lib.attn_validate(self.h)
 
+    def checkpoint(self, path):
+        _lib.attn_checkpoint(self.h, path)
+
+    def restore(self, path):
+        _lib.attn_restore(self.h, path)
+
+    def problem_hash(self):
+        return _lib.attn_problem_hash(self.h)
+
+    def sweep_history(self):
+        return _lib.attn_sweep_history(self.h)
+
     def counters(self):
         return _lib.attn_counters(self.h)
 

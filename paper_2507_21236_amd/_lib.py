@@ -36,7 +36,7 @@ ERRORS = {
     -1: "ATTN_ERR_ARG", -2: "ATTN_ERR_NOT_UNITARY", -3: "ATTN_ERR_NOT_HERMITIAN",
     -4: "ATTN_ERR_DE_OVERLAP", -5: "ATTN_ERR_DE_RESTRICTION", -6: "ATTN_ERR_OOM",
     -7: "ATTN_ERR_HIP", -8: "ATTN_ERR_STATE", -9: "ATTN_ERR_SHAPE", -10: "ATTN_ERR_NUMERIC",
-    -11: "ATTN_ERR_UNSUPPORTED",
+    -11: "ATTN_ERR_UNSUPPORTED", -12: "ATTN_ERR_IO", -13: "ATTN_ERR_MISMATCH",
 }
 ATTN_DE_STRICT = 1
 ATTN_HOST_ONLY = 2
@@ -120,6 +120,12 @@ _proto = {
                                          ctypes.c_int32]),
     "attn_batch_last_error": (ctypes.c_char_p, [_H]),
     "attn_batch_destroy": (ctypes.c_int32, [_H]),
+    "attn_checkpoint": (ctypes.c_int32, [_H, ctypes.c_char_p]),
+    "attn_restore": (ctypes.c_int32, [_H, ctypes.c_char_p]),
+    "attn_checkpoint_info": (ctypes.c_int32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint64), _i32p,
+                                              _i32p, ctypes.POINTER(ctypes.c_int64)]),
+    "attn_problem_hash": (ctypes.c_int32, [_H, ctypes.POINTER(ctypes.c_uint64)]),
+    "attn_sweep_history": (ctypes.c_int32, [_H, ctypes.POINTER(ctypes.c_int64), _f64p, ctypes.c_int64]),
 }
 for _name, (_res, _args) in _proto.items():
     _f = getattr(_lib, _name)
@@ -340,3 +346,37 @@ def attn_mlp_eval(params, feats_ptr, out_ptr, n, stream=None):
 
 def attn_move_center(h, target, stream=None):
     _check(_lib.attn_move_center(h, target, stream), h)
+
+
+def attn_checkpoint(h, path):
+    _check(_lib.attn_checkpoint(h, os.fsencode(path)), h)
+
+
+def attn_restore(h, path):
+    _check(_lib.attn_restore(h, os.fsencode(path)), h)
+
+
+def attn_checkpoint_info(path):
+    """(problem hash, n_nodes, centre, n_sweeps) of a checkpoint file."""
+    hs = ctypes.c_uint64()
+    nn, c = ctypes.c_int32(), ctypes.c_int32()
+    ns = ctypes.c_int64()
+    code = _lib.attn_checkpoint_info(os.fsencode(path), ctypes.byref(hs), ctypes.byref(nn),
+                                     ctypes.byref(c), ctypes.byref(ns))
+    if code != ATTN_OK:
+        raise AttnError(code, f"attn_checkpoint_info({path})")
+    return hs.value, nn.value, c.value, ns.value
+
+
+def attn_problem_hash(h):
+    v = ctypes.c_uint64()
+    _check(_lib.attn_problem_hash(h, ctypes.byref(v)), h)
+    return v.value
+
+
+def attn_sweep_history(h):
+    n = ctypes.c_int64()
+    _check(_lib.attn_sweep_history(h, ctypes.byref(n), None, 0), h)
+    e = np.zeros(n.value)
+    _check(_lib.attn_sweep_history(h, ctypes.byref(n), e.ctypes.data_as(_f64p), e.size), h)
+    return e

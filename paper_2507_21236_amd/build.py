@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libattn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["model.cpp", "runtime.cpp", "batch.cpp", "kernels.hip"]
+SOURCES = ["model.cpp", "runtime.cpp", "state.cpp", "batch.cpp", "kernels.hip"]
 
 # packed FP32 instructions are kept out of the generated code
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
@@ -25,7 +25,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
 
 
 def build_library(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     objs = []
+    cmds = []
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
     for src in SOURCES:
@@ -36,8 +38,14 @@ def build_library(verbose: bool = False) -> str:
                                       os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    # every source is compiled on every call, several at a time
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for r in ex.map(lambda c: subprocess.run(c, check=False), cmds):
+            if r.returncode != 0:
+                raise subprocess.CalledProcessError(r.returncode, r.args)
     tmp = LIB + ".tmp"
     cmd = [HIPCC] + DEVICE_FLAGS + ["-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -1,8 +1,8 @@
 // Host build of an aTTN problem (no GPU work): validation, the binary tree,
-// the disentangler layer contracted into every term (paper Sec. 4.2),
+// the disentangler layer contracted into every term (paper Sec. 4.3, algorithm "Contract disentangler layer"),
 // operator-Schmidt factorisation of every rotated term across each tree link it
 // crosses (minimal TPO bonds), block slots per link, and per-node plans for the
-// matvec (Sec. 4.3.2) and the effective-operator updates (Sec. 3.3.2).
+// matvec (Sec. 3.3.2, cost in Sec. 4.4.2) and the effective-operator updates (Sec. 3.3.2).
 #include "model.hpp"
 
 #include <algorithm>

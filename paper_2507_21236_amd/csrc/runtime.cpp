@@ -1196,6 +1196,14 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
     delete h;
     return st;
   }
+  try {
+    h->prob.assign(p);
+  } catch (const std::bad_alloc&) {
+    g_build_error = "host allocation failed";
+    delete h;
+    return ATTN_ERR_OOM;
+  }
+  h->problem_hash = h->prob.hash();
   h->host_only = (p->flags & ATTN_HOST_ONLY) != 0;
   h->dryrun = (p->flags & ATTN_DRYRUN) != 0;
   h->device = p->device;
@@ -2009,6 +2017,7 @@ attn_status attn_sweep(attn_handle* h, int32_t n_sweeps, const attn_sweep_opts* 
       th = st.scal[0];
     }
     auto t1 = std::chrono::steady_clock::now();
+    h->sweep_energies.push_back(th);
     if (energies) energies[sw] = th;
     if (seconds) seconds[sw] = std::chrono::duration<double>(t1 - t0).count();
   }

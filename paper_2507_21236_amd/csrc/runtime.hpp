@@ -148,8 +148,28 @@ inline bool gram_mfma_ok(int mj, int64_t M) { return mj % 16 == 0 && mj <= 128 &
 using namespace attn;   // internal header: the runtime sources use both namespaces
 using namespace rt;
 
+// Host copy of the problem a handle was built from (every array deep-copied),
+// kept for the problem hash of checkpoints and for rebuilding the rotated
+// terms when the disentanglers change.
+struct ProblemCopy {
+  int32_t n_sites = 0, d = 0, m = 0;
+  std::vector<int32_t> leaf_order, term_nsites, term_sites, de_sites;
+  std::vector<double> term_ops, term_coef, de_u;
+  uint32_t flags = 0;
+  int32_t device = 0;
+  void assign(const attn_problem* p);
+  attn_problem view() const;
+  // FNV-1a over everything that fixes the tree and the Hamiltonian: sizes,
+  // leaf order, terms, disentangler sites and the strict flag (not the
+  // disentangler matrices, which the optimisation changes, and not the device)
+  uint64_t hash() const;
+};
+
 struct attn_handle {
   Model M;
+  ProblemCopy prob;
+  uint64_t problem_hash = 0;
+  std::vector<double> sweep_energies;   // theta at the last node of every attn_sweep sweep
   std::string err;
   bool host_only = false;
   bool dryrun = false;
@@ -341,4 +361,13 @@ int leg_toward(const Tree& tr, int a, int b);
 void run_env(attn_handle* h, EnvDev& D, hipStream_t s);
 void qr_node(attn_handle* h, int n, int leg, hipStream_t s);
 void absorb(attn_handle* h, int q, int leg, hipStream_t s);
+attn_status guard(attn_handle* h, const std::function<attn_status()>& f);
+attn_status need_device(attn_handle* h);
+void check_state(attn_handle* h, hipStream_t s, const char* where);
+void reset_state(attn_handle* h, int kmax, hipStream_t s);
+// Mark every effective-operator store stale, then recompute every store that
+// points toward the current centre (children before parents off the centre's
+// path, then down the path from the root).  Requires every node other than the
+// centre to be isometric toward the centre.
+void rebuild_envs(attn_handle* h, hipStream_t s);
 }  // namespace rt

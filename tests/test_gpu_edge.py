@@ -6,8 +6,8 @@ product basis with a two-fold ground state of energy -(number of bonds); with
 identity disentanglers the rotated Hamiltonian (Sec. 3.2) is the same, a
 product state is exact at any bond dimension, and once the sweeps have found
 it every centre tensor is an eigenvector of its H_eff (the projected
-Hamiltonian of Sec. 3.1) to rounding, so the local Krylov recursion of the
-eigensolver (Sec. 4) has nothing to add after its first vector."""
+Hamiltonian of Sec. 3.3.2) to rounding, so the local Krylov recursion of the
+eigensolver (Sec. 4.4.2) has nothing to add after its first vector."""
 import numpy as np
 import pytest
 

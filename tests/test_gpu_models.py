@@ -1,4 +1,4 @@
-"""The triangular-lattice Heisenberg model J sum S_i.S_j (Sec. 5's second
+"""The triangular-lattice Heisenberg model J sum S_i.S_j (Sec. 6.2.2's
 model family: XX, YY and ZZ parts on horizontal, vertical and diagonal bonds)
 through the C interface.
 

@@ -116,22 +116,32 @@ def test_uneven_instance_matvec():
             assert rel(gpu_matvec(a, n, x), o.matvec(n, x)) < 1e-12, (n, o.tree.dims[n])
 
 
-def test_sweep_prefix_16x16_node_by_node():
-    # the first 31 node visits of a sweep of the 16 x 16, m = 64 workload
-    # (every node shape, including three (64, 64, 64) nodes): eigenvalues and
-    # tensors stay within rounding of the oracle.  Over a whole random-start
-    # sweep the single-site updates amplify rounding through ill-conditioned
-    # centre matricisations, so whole-sweep energies are compared on the
-    # smaller instances only.
+@pytest.mark.timeout(1500)
+def test_sweep_16x16_every_node_with_resync():
+    # every one of the 255 node visits of a sweep of the 16 x 16, m = 64
+    # workload from the seeded start.  At each visit: the matvec on a seeded
+    # input (1e-12 relative) and the Lanczos eigenvalue (1e-11 relative); then
+    # the GPU centre is set to the oracle's Ritz vector, so both sides go on
+    # from the same tensor and rounding differences cannot compound over the
+    # sweep (the isometries left behind differ by one QR's rounding only).
     p = config_problem("ising16_m64")
     a, o = make_pair(p)
-    for n in range(31):
+    rng = np.random.default_rng(11)
+    worst_mv, worst_th = (0.0, -1), (0.0, -1)
+    for n in range(o.tree.n_nodes):
         move_both(a, o, n)
+        x = rng.standard_normal(o.T[n].shape)
+        e_mv = rel(gpu_matvec(a, n, x), o.matvec(n, x))
         th_o = o.eigsolve(n)
         th_a, _ = a.eigsolve(n)
-        assert abs(th_a - th_o) <= 1e-11 * abs(th_o), (n, th_a, th_o)
-        ta, to = a.get_tensor(n), o.T[n]
-        assert min(np.abs(ta - to).max(), np.abs(ta + to).max()) < 1e-8, n
+        e_th = abs(th_a - th_o) / abs(th_o)
+        worst_mv = max(worst_mv, (e_mv, n))
+        worst_th = max(worst_th, (e_th, n))
+        assert e_mv < 1e-12, (n, o.tree.dims[n], e_mv)
+        assert e_th <= 1e-11, (n, o.tree.dims[n], th_a, th_o)
+        a.set_tensor(n, o.T[n])
+    print(f"255 node visits: worst matvec rel err {worst_mv[0]:.2e} (node {worst_mv[1]}), "
+          f"worst eigenvalue rel err {worst_th[0]:.2e} (node {worst_th[1]})")
 
 
 def test_matvec_heaviest_node_16x16():
