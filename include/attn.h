@@ -312,6 +312,19 @@ attn_status attn_precond_harvest(attn_handle* h, int32_t node, int32_t n_pairs, 
 attn_status attn_mlp_train(const float* feats, const float* targets, int64_t n, int32_t steps,
                            int32_t batch, float lr, float* params, float* loss, void* stream);
 
+/* attn_mlp_train without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, work and results as
+ * attn_mlp_train; its working memory (parameters, Adam moments, gradient,
+ * per-workgroup partial sums, per-step losses: 9.25 MB) is a fixed device
+ * array of the library, one per device, held until the process ends, on the
+ * device current at the call.  Limits: batch <= 16384 and steps <= 65536,
+ * else UNSUPPORTED.  Every call on a device shares that device's array:
+ * calls that overlap on one device (other host threads, other streams) race,
+ * so serialise them.  Synchronises `stream`.  Errors: ARG, UNSUPPORTED, HIP. */
+attn_status attn_mlp_train_noalloc(const float* feats, const float* targets, int64_t n, int32_t steps,
+                                   int32_t batch, float lr, float* params, float* loss, void* stream);
+
 /* Model outputs o for n feature triples (device in/out) with the FP16-rounded
  * parameters (host FP32).  Synchronises `stream`. */
 attn_status attn_mlp_eval(const float* params, const float* feats, float* out, int64_t n,

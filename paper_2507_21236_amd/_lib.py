@@ -120,6 +120,10 @@ _proto = {
                                          ctypes.c_int32]),
     "attn_batch_last_error": (ctypes.c_char_p, [_H]),
     "attn_batch_destroy": (ctypes.c_int32, [_H]),
+    "attn_mlp_train_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                                ctypes.POINTER(ctypes.c_float),
+                                                ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]),
     "attn_checkpoint": (ctypes.c_int32, [_H, ctypes.c_char_p]),
     "attn_restore": (ctypes.c_int32, [_H, ctypes.c_char_p]),
     "attn_checkpoint_info": (ctypes.c_int32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint64), _i32p,
@@ -380,3 +384,13 @@ def attn_sweep_history(h):
     e = np.zeros(n.value)
     _check(_lib.attn_sweep_history(h, ctypes.byref(n), e.ctypes.data_as(_f64p), e.size), h)
     return e
+
+
+def attn_mlp_train_noalloc(feats_ptr, targets_ptr, n, steps, batch, lr, params, stream=None):
+    p = np.array(params, dtype=np.float32, copy=True)
+    loss = np.zeros(steps, dtype=np.float32)
+    code = _lib.attn_mlp_train_noalloc(feats_ptr, targets_ptr, n, steps, batch, lr, p.ctypes.data_as(_f32p),
+                                       loss.ctypes.data_as(_f32p), stream)
+    if code != ATTN_OK:
+        raise AttnError(code, "attn_mlp_train_noalloc failed")
+    return p, loss

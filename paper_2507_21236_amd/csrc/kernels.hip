@@ -3556,3 +3556,73 @@ hipError_t launch_harvest_write(const double* diag, const double* r, const doubl
 }
 
 }  // namespace attn
+
+// ---------------------------------------------------------------- allocation-free model training
+// attn_mlp_train_noalloc: attn_mlp_train with its working memory (parameters,
+// Adam moments, gradient, per-workgroup gradient partial sums, per-step
+// losses) in a fixed file-scope device array instead of hipMalloc'ed buffers.
+// Each device the library runs on holds its own copy of the array until the
+// process ends; the host takes the array's device address once per device
+// with hipGetSymbolAddress and uses only that address afterwards.
+#include <mutex>
+
+#include "attn.h"
+
+namespace {
+constexpr size_t kNaAlign = 256;
+constexpr size_t na_round(size_t b) { return (b + kNaAlign - 1) / kNaAlign * kNaAlign; }
+constexpr int kNaMaxBatch = 16384;    // points per Adam step
+constexpr int kNaMaxSteps = 65536;    // Adam steps per call
+constexpr size_t kNaParamBytes = na_round((size_t)attn::kMlpParams * sizeof(float));
+constexpr size_t kNaGradBytes = na_round((size_t)(attn::kMlpParams + 1) * sizeof(float));
+constexpr size_t kNaPartBytes = na_round((size_t)(kNaMaxBatch / 64) * (attn::kMlpParams + 1) * sizeof(float));
+constexpr size_t kNaLossBytes = na_round((size_t)kNaMaxSteps * sizeof(float));
+// w, m, v, grad, gpart, loss
+constexpr size_t kNaScratchBytes = 3 * kNaParamBytes + kNaGradBytes + kNaPartBytes + kNaLossBytes;
+constexpr int kNaMaxDevices = 64;
+
+std::mutex g_na_mu;
+void* g_na_ptr[kNaMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaScratchBytes];
+
+extern "C" attn_status attn_mlp_train_noalloc(const float* feats, const float* targets, int64_t n, int32_t steps,
+                                              int32_t batch, float lr, float* params, float* loss, void* stream) {
+  using namespace attn;
+  if (!feats || !targets || !params || steps < 1 || batch < 64 || batch % 64 || n < batch) return ATTN_ERR_ARG;
+  if (batch > kNaMaxBatch || steps > kNaMaxSteps) return ATTN_ERR_UNSUPPORTED;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return ATTN_ERR_HIP;
+  if (dev < 0 || dev >= kNaMaxDevices) return ATTN_ERR_UNSUPPORTED;
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ATTN_ERR_HIP;
+      g_na_ptr[dev] = p;
+    }
+    base = (unsigned char*)g_na_ptr[dev];
+  }
+  float* w = (float*)base;
+  float* m = (float*)(base + kNaParamBytes);
+  float* v = (float*)(base + 2 * kNaParamBytes);
+  float* grad = (float*)(base + 3 * kNaParamBytes);
+  float* gpart = (float*)(base + 3 * kNaParamBytes + kNaGradBytes);
+  float* dl = (float*)(base + 3 * kNaParamBytes + kNaGradBytes + kNaPartBytes);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = prepare_kernel_attributes();
+  // the array keeps the previous call's contents: the moments start at zero
+  if (e == hipSuccess) e = hipMemcpyAsync(w, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(m, 0, 2 * kNaParamBytes, s);
+  const int64_t nb = n / batch;
+  for (int st = 1; st <= steps && e == hipSuccess; st++) {
+    const int64_t off = ((st - 1) % nb) * batch;
+    e = launch_mlp_train_step(w, feats, targets, off, batch, gpart, grad, m, v, st, lr, dl, s);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(params, w, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && loss) e = hipMemcpyAsync(loss, dl, steps * sizeof(float), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e == hipSuccess ? ATTN_OK : ATTN_ERR_HIP;
+}
