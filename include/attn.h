@@ -63,6 +63,10 @@ typedef int32_t attn_status;
 #define ATTN_HOST_ONLY     2u  /* build host-side structures only, touch no GPU */
 #define ATTN_DRYRUN        4u  /* build every device work list against a fake address
                                   space without touching the GPU (for attn_validate) */
+#define ATTN_COMPRESS_TERMS 8u /* sum the terms that act on the same set of sites into
+                                  one term before the factorisation (Sec. 6.2.2, closing
+                                  paragraph: fewer TPO terms, one bond <= d^2 per cut
+                                  for a two-site sum under one disentangler) */
 
 typedef enum attn_dtype {
   ATTN_F64 = 0,     /* FP64 operands, FP64 accumulation */
@@ -88,7 +92,8 @@ typedef enum attn_dtype {
  *   de_sites          [n_de][2] site pairs (no site in two pairs).
  *   de_u              [n_de][d*d][d*d] row-major real orthogonal matrices acting on
  *                     |s_a s_b> with the first listed site the major index.
- *   flags             ATTN_DE_STRICT, ATTN_HOST_ONLY.
+ *   flags             ATTN_DE_STRICT, ATTN_HOST_ONLY, ATTN_DRYRUN,
+ *                     ATTN_COMPRESS_TERMS.
  *   device            HIP device ordinal for all device memory of the handle.
  */
 typedef struct attn_problem {

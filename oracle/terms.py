@@ -120,3 +120,27 @@ def op_rank(h, S, group_a, group_b, d=2, rel_tol=1e-12):
     """Operator-Schmidt rank of h across the bipartition (group_a | group_b)."""
     mat = realign(h, S, [list(group_a), list(group_b)], d)
     return len(schmidt(mat, rel_tol)[0])
+
+
+def compress_terms(terms, rterms):
+    """Sum the rotated terms whose original supports are the same set of sites
+    (Sec. 6.2.2, closing paragraph: the terms acting on the same sites, e.g.
+    XX, YY and ZZ on one bond, become one term; after the disentangler layer
+    it has one bond of at most d^2 across any cut instead of one such bond per
+    term).  Terms with the same support meet the same disentanglers, so their
+    rotated supports coincide as sets; each rotated operator is re-expressed
+    on the sorted support before the sum.  Order: first occurrence."""
+    groups = {}
+    order = []
+    for (sites, _, _), (S, h) in zip(terms, rterms):
+        key = frozenset(sites)
+        Sc = tuple(sorted(S))
+        hc = embed(h, list(S), list(Sc), int(round(h.shape[0] ** (1.0 / len(S)))))
+        if key in groups:
+            S0, h0 = groups[key]
+            assert S0 == Sc
+            groups[key] = (S0, h0 + hc)
+        else:
+            groups[key] = (Sc, hc)
+            order.append(key)
+    return [groups[k] for k in order]

@@ -30,7 +30,7 @@ import itertools
 import numpy as np
 
 from .tree import Tree
-from .terms import rotate_all, realign, schmidt
+from .terms import rotate_all, compress_terms, realign, schmidt
 
 
 def mode(A, x, j):
@@ -84,12 +84,14 @@ class Link:
 
 class OracleTTN:
     def __init__(self, n_sites, d, m, leaf_order, terms, de_sites, de_u, raw_tensors,
-                 krylov_k=20, structure_only=False):
+                 krylov_k=20, structure_only=False, compress=False):
         self.tree = tr = Tree(leaf_order, m, d)
         assert tr.N == n_sites
         self.d = d
         self.krylov_k = krylov_k
         self.rterms = rotate_all(terms, de_sites, de_u, d)
+        if compress:
+            self.rterms = compress_terms(terms, self.rterms)
         self.supports = [frozenset(S) for S, _ in self.rterms]
         self.all_sites = frozenset(range(n_sites))
         self._needed = {}

@@ -472,6 +472,29 @@ attn_status build_model(const attn_problem* p, Model& M, std::string& err) {
     M.terms[t].S = S;
     M.terms[t].h = std::move(H);
   }
+  // ---- compression of terms acting on the same sites (Sec. 6.2.2, closing
+  //      paragraph): terms with the same support meet the same disentanglers,
+  //      so their rotated operators live on the same extended support and are
+  //      summed into one term before the factorisation, which then finds the
+  //      minimal bonds of the sum (e.g. XX + YY + ZZ on a bond: one term of
+  //      bond <= d^2 across any cut instead of three)
+  if (p->flags & ATTN_COMPRESS_TERMS) {
+    std::map<std::vector<int>, int> first;
+    std::vector<RTerm> merged;
+    for (int t = 0; t < p->n_terms; t++) {
+      std::vector<int> key = tsites[t];
+      std::sort(key.begin(), key.end());
+      auto it = first.find(key);
+      if (it == first.end()) {
+        first[key] = (int)merged.size();
+        merged.push_back(std::move(M.terms[t]));
+      } else {
+        RTerm& R = merged[it->second];
+        for (size_t i = 0; i < R.h.size(); i++) R.h[i] += M.terms[t].h[i];
+      }
+    }
+    M.terms.swap(merged);
+  }
   // ---- crossing terms per edge, slots
   const int NE = tr.n_edges();
   M.cross.assign(NE, {});
@@ -486,7 +509,7 @@ attn_status build_model(const attn_problem* p, Model& M, std::string& err) {
     }
     return mk;
   };
-  for (int t = 0; t < p->n_terms; t++) {
+  for (int t = 0; t < (int)M.terms.size(); t++) {
     RTerm& T = M.terms[t];
     uint32_t full = (1u << T.S.size()) - 1;
     std::set<int> edges;
@@ -518,7 +541,7 @@ attn_status build_model(const attn_problem* p, Model& M, std::string& err) {
   for (int s0 = 0; s0 < N; s0++) {
     std::vector<double>& B = M.site_blocks[s0];
     B.assign((size_t)(1 + M.n_slots[s0]) * dd, 0.0);
-    for (int t = 0; t < p->n_terms; t++) {
+    for (int t = 0; t < (int)M.terms.size(); t++) {
       const RTerm& T = M.terms[t];
       if (T.S.size() == 1 && T.S[0] == s0) {
         for (int o = 0; o < d; o++)
