@@ -34,7 +34,19 @@ from .terms import rotate_all, compress_terms, realign, schmidt
 
 
 def mode(A, x, j):
-    """Mode-j product: (A x_j x)[.., i, ..] = sum_k A[i, k] x[.., k, ..]."""
+    """Mode-j product: (A x_j x)[.., i, ..] = sum_k A[i, k] x[.., k, ..].
+
+    Written as one matrix product on a reshaped view of x (leg j first: A
+    times x as a k x (rest) matrix; leg j last: x as a (rest) x k matrix times
+    A^T; leg 1 of a 3-leg tensor: A times every x[a] slice), which is the same
+    sum without transposed copies of x."""
+    x = np.ascontiguousarray(x)
+    if j == 0:
+        return (A @ x.reshape(x.shape[0], -1)).reshape((A.shape[0],) + x.shape[1:])
+    if j == x.ndim - 1:
+        return (x.reshape(-1, x.shape[-1]) @ A.T).reshape(x.shape[:-1] + (A.shape[0],))
+    if x.ndim == 3 and j == 1:
+        return np.matmul(A, x)
     return np.moveaxis(np.tensordot(A, x, axes=(1, j)), 0, j)
 
 
@@ -115,6 +127,31 @@ class OracleTTN:
             self._compute_link(('up', ('s', s)))
         for n in range(tr.n_nodes):
             self._compute_link(('up', ('n', n)))
+
+    def set_disentanglers(self, terms, de_sites, de_u, compress=False):
+        """Replace the disentangler layer (Sec. 4, step 2 of each sweep): the
+        rotated terms are rebuilt from the original ones, the tree tensors stay,
+        and every link pointing toward the current centre is recomputed."""
+        tr = self.tree
+        self.rterms = rotate_all(terms, de_sites, de_u, self.d)
+        if compress:
+            self.rterms = compress_terms(terms, self.rterms)
+        self.supports = [frozenset(S) for S, _ in self.rterms]
+        self._needed = {}
+        self.links = {}
+        path = []
+        x = self.center
+        while x != -1:
+            path.append(x)
+            x = tr.parent[x]
+        on_path = set(path)
+        for s_ in range(tr.N):
+            self._compute_link(('up', ('s', s_)))
+        for n in range(tr.n_nodes):
+            if n not in on_path:
+                self._compute_link(('up', ('n', n)))
+        for x in reversed(path[:-1]):
+            self._compute_link(('down', x))
 
     # ------------------------------------------------------------ link bookkeeping
     def side(self, key):
@@ -359,7 +396,7 @@ class OracleTTN:
                     V = mode(Ar, V, 1)
                 if Al is not None:
                     V = mode(Al, V, 0)
-                y = y + (wc * c) * V
+                y += (wc * c) * V
         self.n_matvec += 1
         return y
 
