@@ -424,6 +424,38 @@ attn_status attn_problem_hash(const attn_handle* h, uint64_t* hash);
  * checkpoint): *n_sweeps = count, energies[0 .. min(cap, count)) written. */
 attn_status attn_sweep_history(const attn_handle* h, int64_t* n_sweeps, double* energies, int64_t cap);
 
+/*
+ * Observables (Sec. 5).  Every call moves the isometry centre to the root
+ * first (attn_move_center; the state is unchanged, only its gauge) and
+ * synchronises the device.  Operators are d x d row-major real matrices,
+ * element [i][k] = <i|A|k>.
+ *
+ * attn_expect_products: out[p] = <psi_TTN| prod_i A_(p,i) |psi_TTN> for n_prod
+ * products of one-site operators on distinct sites (the TTN alone, no
+ * disentanglers; Sec. 5.1: only the subtree holding the operators is
+ * contracted).  nsites[p] sites per product; sites and ops concatenated over
+ * the products (d*d values per site).  Errors: ARG, STATE, HIP.
+ *
+ * attn_measure: out[o] = <psi_aTTN| coef_o prod_i A_(o,i) |psi_aTTN> for n_obs
+ * observables on 1..4 distinct sites each: the disentanglers touching an
+ * observable are contracted into it, o' = U^T o U (Sec. 5.2, eq. 6, read with
+ * the state D|psi_TTN> as for the Hamiltonian), and o' is measured on the TTN
+ * as a sum of products of one-site operators (nested operator-Schmidt
+ * decompositions).  coef may be NULL (all 1).  Errors: ARG, STATE, UNSUPPORTED
+ * (rotated support beyond 6 sites), HIP.
+ *
+ * attn_correlation: the two-body correlation matrix of eq. 7 (Sec. 5.3),
+ * C[i * N + j] = <psi_aTTN| o^a_i o^b_j |psi_aTTN> for all sites i, j (N x N,
+ * row-major, caller-owned), the diagonal being the one-site product
+ * o^a o^b; every entry is the rotated pair measured as above, the rotated
+ * one-site factors shared between entries.  Errors: ARG, STATE, HIP.
+ */
+attn_status attn_expect_products(attn_handle* h, int32_t n_prod, const int32_t* nsites, const int32_t* sites,
+                                 const double* ops, double* out);
+attn_status attn_measure(attn_handle* h, int32_t n_obs, const int32_t* nsites, const int32_t* sites,
+                         const double* ops, const double* coef, double* out);
+attn_status attn_correlation(attn_handle* h, const double* oa, const double* ob, double* C);
+
 /* Checks on the host that every work unit of every device work list of the
  * handle reads and writes only inside the buffer it was built for.  Meant for
  * ATTN_DRYRUN handles (no GPU needed).  Errors: STATE (message names the first

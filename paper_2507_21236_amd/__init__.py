@@ -100,6 +100,18 @@ class AttnHandle:
     def validate(self):
         _lib.attn_validate(self.h)
 
+    def expect_products(self, items):
+        """<psi_TTN| prod A |psi_TTN> for products given as [(site, op), ...]"""
+        return _lib.attn_expect_products(self.h, items)
+
+    def measure(self, items, coef=None):
+        """<psi_aTTN| coef prod A |psi_aTTN> (disentanglers contracted in)"""
+        return _lib.attn_measure(self.h, items, coef)
+
+    def correlation(self, oa, ob):
+        """N x N matrix <o^a_i o^b_j> of the augmented state"""
+        return _lib.attn_correlation(self.h, oa, ob, self.problem.n_sites)
+
     def checkpoint(self, path):
         _lib.attn_checkpoint(self.h, path)
 

@@ -124,6 +124,9 @@ _proto = {
                                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
                                                 ctypes.POINTER(ctypes.c_float),
                                                 ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]),
+    "attn_expect_products": (ctypes.c_int32, [_H, ctypes.c_int32, _i32p, _i32p, _f64p, _f64p]),
+    "attn_measure": (ctypes.c_int32, [_H, ctypes.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p]),
+    "attn_correlation": (ctypes.c_int32, [_H, _f64p, _f64p, _f64p]),
     "attn_checkpoint": (ctypes.c_int32, [_H, ctypes.c_char_p]),
     "attn_restore": (ctypes.c_int32, [_H, ctypes.c_char_p]),
     "attn_checkpoint_info": (ctypes.c_int32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint64), _i32p,
@@ -394,3 +397,38 @@ def attn_mlp_train_noalloc(feats_ptr, targets_ptr, n, steps, batch, lr, params, 
     if code != ATTN_OK:
         raise AttnError(code, "attn_mlp_train_noalloc failed")
     return p, loss
+
+
+def _flat_products(items, d=2):
+    """items: list of [(site, d x d op), ...] -> (nsites, sites, ops) arrays."""
+    ns = np.array([len(it) for it in items], dtype=np.int32)
+    st = np.array([s for it in items for s, _ in it], dtype=np.int32)
+    ops = np.concatenate([np.asarray(o, dtype=np.float64).reshape(-1) for it in items for _, o in it]) \
+        if len(st) else np.zeros(0)
+    return ns, st, _arr(ops, np.float64)
+
+
+def attn_expect_products(h, items):
+    ns, st, ops = _flat_products(items)
+    out = np.zeros(len(items))
+    _check(_lib.attn_expect_products(h, len(items), ns.ctypes.data_as(_i32p), st.ctypes.data_as(_i32p),
+                                     ops.ctypes.data_as(_f64p), out.ctypes.data_as(_f64p)), h)
+    return out
+
+
+def attn_measure(h, items, coef=None):
+    ns, st, ops = _flat_products(items)
+    c = None if coef is None else _arr(coef, np.float64)
+    out = np.zeros(len(items))
+    _check(_lib.attn_measure(h, len(items), ns.ctypes.data_as(_i32p), st.ctypes.data_as(_i32p),
+                             ops.ctypes.data_as(_f64p), None if c is None else c.ctypes.data_as(_f64p),
+                             out.ctypes.data_as(_f64p)), h)
+    return out
+
+
+def attn_correlation(h, oa, ob, n_sites):
+    a = _arr(oa, np.float64)
+    b = _arr(ob, np.float64)
+    C = np.zeros((n_sites, n_sites))
+    _check(_lib.attn_correlation(h, a.ctypes.data_as(_f64p), b.ctypes.data_as(_f64p), C.ctypes.data_as(_f64p)), h)
+    return C

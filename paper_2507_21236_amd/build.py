@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libattn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["model.cpp", "runtime.cpp", "state.cpp", "batch.cpp", "kernels.hip"]
+SOURCES = ["model.cpp", "runtime.cpp", "state.cpp", "measure.cpp", "batch.cpp", "kernels.hip",
+           "measure_kernels.hip"]
 
 # packed FP32 instructions are kept out of the generated code
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

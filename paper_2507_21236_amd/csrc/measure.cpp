@@ -1,0 +1,670 @@
+// Observables of the augmented state (Sec. 5) and the MERA-like optimisation
+// of the disentangler layer (Sec. 4.1.1, 4.2), both built on one device
+// engine: expectation values <psi_TTN| prod_s A_s |psi_TTN> of many products
+// of one-site operators, with the isometry centre at the root.
+//
+// Engine (all FP64, launches of measure_kernels.hip):
+//  * image of the factors below a link: at the link above node q,
+//    R = T_q^T (R_l (x) R_r) T_q with R_l / R_r the images on q's child links
+//    (a site link carries the operator itself, a factor-free side the
+//    identity); images are shared between products by content and computed
+//    level by level from the leaves up;
+//  * Gram matrix of every link from above, G_child = sum T G_p T^T over the
+//    other two legs, from the root (G = 1 above it) down;
+//  * at the lowest node n holding all factors of a product, with the left
+//    image R_l and right image R_r: <P> = <R_l^T x_l T_n, R_r x_r (G_p x_p T_n)>,
+//    all pairs of a node's left and right images in one product of the two
+//    stacked lists (split over the summed index, partials summed in order).
+#include <array>
+#include <map>
+
+#include "measure.hpp"
+#include "runtime.hpp"
+
+using namespace attn;
+using namespace rt;
+
+namespace {
+
+struct Buf {
+  std::vector<void*> ptrs;
+  double* get(int64_t n) {
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, std::max<int64_t>(n, 1) * sizeof(double)));
+    ptrs.push_back(p);
+    return (double*)p;
+  }
+  ~Buf() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+template <typename T>
+T* upload_tmp(Buf& b, const std::vector<T>& v) {
+  double* p = b.get((int64_t)((v.size() * sizeof(T) + 7) / 8));
+  HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return (T*)p;
+}
+
+// GEMM jobs of one launch and their work units
+struct GemmList {
+  std::vector<GMJob> jobs;
+  std::vector<int4> wus;
+  void add(const GMJob& j, int batch) {
+    const int id = (int)jobs.size();
+    jobs.push_back(j);
+    const int tm = (j.M + 63) / 64, tn = (j.N + 63) / 64;
+    for (int b = 0; b < batch; b++)
+      for (int x = 0; x < tm; x++)
+        for (int y = 0; y < tn; y++) wus.push_back(int4{id, b, x, y});
+  }
+  void run(Buf& buf, hipStream_t s) {
+    if (jobs.empty()) return;
+    GMJob* dj = upload_tmp(buf, jobs);
+    int4* dw = upload_tmp(buf, wus);
+    HIPCHK(launch_gemm_jobs(dj, dw, (int)wus.size(), s));
+    jobs.clear();
+    wus.clear();
+  }
+};
+
+GMJob gm(const double* A, const double* B, double* C, int M, int N, int K, int lda, int ldb, int ldc, int ta = 0,
+         int tb = 0, int64_t sa = 0, int64_t sb = 0, int64_t sc = 0) {
+  GMJob j;
+  j.A = A; j.B = B; j.C = C;
+  j.sa = sa; j.sb = sb; j.sc = sc;
+  j.M = M; j.N = N; j.K = K;
+  j.lda = lda; j.ldb = ldb; j.ldc = ldc;
+  j.ta = ta; j.tb = tb;
+  j.accumulate = 0; j.pad = 0;
+  return j;
+}
+
+}  // namespace
+
+namespace rt {
+
+// A product of one-site operators: (site, operator id), sites distinct.
+struct XProd {
+  std::vector<std::pair<int, int>> f;
+};
+
+struct XEngine {
+  attn_handle* h;
+  int d;
+  std::vector<double> ops;   // d x d row-major per operator id
+  std::map<std::vector<double>, int> op_ids;
+
+  explicit XEngine(attn_handle* hh) : h(hh), d(hh->M.tree.d) {}
+
+  int op_id(const double* m) {
+    std::vector<double> key(m, m + d * d);
+    auto it = op_ids.find(key);
+    if (it != op_ids.end()) return it->second;
+    const int id = (int)(ops.size() / (d * d));
+    ops.insert(ops.end(), key.begin(), key.end());
+    op_ids.emplace(std::move(key), id);
+    return id;
+  }
+
+  struct Img {
+    int edge, node, opid, left, right, dim;
+    double* dev;
+  };
+
+  void run(const std::vector<XProd>& prods, std::vector<double>& out, hipStream_t s);
+};
+
+void XEngine::run(const std::vector<XProd>& prods, std::vector<double>& out, hipStream_t s) {
+  const Tree& tr = h->M.tree;
+  const int nn = (int)tr.nodes.size();
+  const int dd = d * d;
+  out.assign(prods.size(), 0.0);
+  if (prods.empty()) return;
+  Buf buf;
+  double* d_ops = upload_tmp(buf, ops.empty() ? std::vector<double>(1, 0.0) : ops);
+  auto Tptr = [&](int n) { return h->d_T + h->T_off[n]; };
+
+  // ---- images (content-keyed) and, per product, its lowest common node
+  std::vector<Img> imgs;
+  std::map<std::pair<int, std::vector<std::pair<int, int>>>, int> memo;
+  std::function<int(int, const std::vector<std::pair<int, int>>&)> image =
+      [&](int edge, const std::vector<std::pair<int, int>>& fs) -> int {
+    auto key = std::make_pair(edge, fs);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+    Img im;
+    im.edge = edge;
+    im.dev = nullptr;
+    if (tr.edge_is_site(edge)) {
+      if (fs.size() != 1) throw StatusFail{ATTN_ERR_ARG, "internal: several factors on one site"};
+      im.node = -1;
+      im.opid = fs[0].second;
+      im.left = im.right = -1;
+      im.dim = d;
+    } else {
+      const int q = edge - tr.N;
+      const Node& nd = tr.nodes[q];
+      std::vector<std::pair<int, int>> fl, fr;
+      for (auto& x : fs) (tr.pos[x.first] < nd.mid ? fl : fr).push_back(x);
+      im.node = q;
+      im.opid = -1;
+      im.left = fl.empty() ? -1 : image(tr.edge_of_child(q, 0), fl);
+      im.right = fr.empty() ? -1 : image(tr.edge_of_child(q, 1), fr);
+      im.dim = nd.dims[2];
+    }
+    const int id = (int)imgs.size();
+    imgs.push_back(im);
+    memo.emplace(std::move(key), id);
+    return id;
+  };
+  struct Eval {
+    std::vector<int> L, R;   // distinct image ids (-1 = identity)
+    std::map<int, int> li, ri;
+  };
+  std::map<int, Eval> evals;
+  std::vector<std::array<int, 3>> where(prods.size());   // (node, left index, right index)
+  for (size_t p = 0; p < prods.size(); p++) {
+    std::vector<std::pair<int, int>> fs = prods[p].f;
+    if (fs.empty()) throw StatusFail{ATTN_ERR_ARG, "empty product"};
+    std::sort(fs.begin(), fs.end());
+    for (size_t i = 1; i < fs.size(); i++)
+      if (fs[i].first == fs[i - 1].first) throw StatusFail{ATTN_ERR_ARG, "repeated site in a product"};
+    int n = tr.root;
+    while (true) {
+      const Node& nd = tr.nodes[n];
+      bool all_l = true, all_r = true;
+      for (auto& x : fs) {
+        if (tr.pos[x.first] < nd.mid) all_r = false;
+        else all_l = false;
+      }
+      if (all_l && nd.child[0] >= 0) { n = nd.child[0]; continue; }
+      if (all_r && nd.child[1] >= 0) { n = nd.child[1]; continue; }
+      break;
+    }
+    const Node& nd = tr.nodes[n];
+    std::vector<std::pair<int, int>> fl, fr;
+    for (auto& x : fs) (tr.pos[x.first] < nd.mid ? fl : fr).push_back(x);
+    const int il = fl.empty() ? -1 : image(tr.edge_of_child(n, 0), fl);
+    const int ir = fr.empty() ? -1 : image(tr.edge_of_child(n, 1), fr);
+    Eval& ev = evals[n];
+    if (!ev.li.count(il)) { ev.li[il] = (int)ev.L.size(); ev.L.push_back(il); }
+    if (!ev.ri.count(ir)) { ev.ri[ir] = (int)ev.R.size(); ev.R.push_back(ir); }
+    where[p] = {n, ev.li[il], ev.ri[ir]};
+  }
+
+  // ---- image storage; site images point into the operator table
+  {
+    int64_t tot = 0;
+    for (auto& im : imgs)
+      if (im.node >= 0) tot += (int64_t)im.dim * im.dim;
+    double* store = buf.get(tot);
+    int64_t off = 0;
+    for (auto& im : imgs) {
+      if (im.node >= 0) { im.dev = store + off; off += (int64_t)im.dim * im.dim; }
+      else im.dev = d_ops + (int64_t)im.opid * dd;
+    }
+  }
+  // node heights (a node above two sites has height 1)
+  std::vector<int> height(nn, 0), depth(nn, 0);
+  int hmax = 0, dmax = 0;
+  for (int n = 0; n < nn; n++) {   // post-order: children first
+    int hh = 0;
+    for (int sd = 0; sd < 2; sd++)
+      if (tr.nodes[n].child[sd] >= 0) hh = std::max(hh, height[tr.nodes[n].child[sd]]);
+    height[n] = hh + 1;
+    hmax = std::max(hmax, height[n]);
+  }
+  for (int n = nn - 1; n >= 0; n--) {   // reverse post-order: parents first
+    const int p = tr.nodes[n].parent;
+    depth[n] = p < 0 ? 0 : depth[p] + 1;
+    dmax = std::max(dmax, depth[n]);
+  }
+  const int64_t kScratch = (int64_t)1 << 25;   // doubles of intermediate tensors per launch group
+  // ---- images, level by level from the leaves
+  for (int lev = 1; lev <= hmax; lev++) {
+    std::vector<int> todo;
+    for (int i = 0; i < (int)imgs.size(); i++)
+      if (imgs[i].node >= 0 && height[imgs[i].node] == lev) todo.push_back(i);
+    size_t k = 0;
+    while (k < todo.size()) {
+      std::vector<int> chunk;
+      int64_t need = 0;
+      while (k < todo.size()) {
+        const Node& nd = tr.nodes[imgs[todo[k]].node];
+        const int64_t M = (int64_t)nd.dims[0] * nd.dims[1] * nd.dims[2];
+        if (!chunk.empty() && need + 2 * M > kScratch) break;
+        need += 2 * M;
+        chunk.push_back(todo[k++]);
+      }
+      Buf lb;   // freed (after the device has finished with it) at the end of the chunk
+      double* z = lb.get(need);
+      GemmList ga, gb, gc;
+      int64_t off = 0;
+      for (int i : chunk) {
+        const Img& im = imgs[i];
+        const Node& nd = tr.nodes[im.node];
+        const int dl = nd.dims[0], dr = nd.dims[1], dp = nd.dims[2];
+        const int64_t M = (int64_t)dl * dr * dp;
+        double* z1 = z + off;
+        double* z2 = z + off + M;
+        off += 2 * M;
+        const double* T = Tptr(im.node);
+        const double* cur = T;
+        if (im.right >= 0) {
+          ga.add(gm(imgs[im.right].dev, T, z1, dr, dp, dr, dr, dp, dp, 0, 0, 0, (int64_t)dr * dp, (int64_t)dr * dp), dl);
+          cur = z1;
+        }
+        if (im.left >= 0) {
+          gb.add(gm(imgs[im.left].dev, cur, z2, dl, dr * dp, dl, dl, dr * dp, dr * dp), 1);
+          cur = z2;
+        }
+        gc.add(gm(T, cur, im.dev, dp, dp, dl * dr, dp, dp, dp, 1, 0), 1);
+      }
+      ga.run(lb, s);
+      gb.run(lb, s);
+      gc.run(lb, s);
+    }
+  }
+  // ---- Gram matrices of the parent links, from the root down
+  std::vector<double*> G(nn, nullptr);
+  std::vector<double*> W(nn, nullptr);   // T_n x_p G_p, kept for the closing products
+  {
+    int64_t gtot = 0;
+    for (int n = 0; n < nn; n++) gtot += (int64_t)tr.nodes[n].dims[2] * tr.nodes[n].dims[2];
+    double* gs = buf.get(gtot);
+    int64_t off = 0;
+    for (int n = 0; n < nn; n++) { G[n] = gs + off; off += (int64_t)tr.nodes[n].dims[2] * tr.nodes[n].dims[2]; }
+    const double one = 1.0;
+    HIPCHK(hipMemcpy(G[tr.root], &one, sizeof(double), hipMemcpyHostToDevice));
+  }
+  for (int dep = 0; dep <= dmax; dep++) {
+    std::vector<int> lvl;
+    for (int n = 0; n < nn; n++)
+      if (depth[n] == dep) lvl.push_back(n);
+    GemmList gw, gg;
+    std::vector<PMJob> pm;
+    int64_t maxM = 0;
+    Buf lb;
+    for (int n : lvl) {
+      const Node& nd = tr.nodes[n];
+      const int dl = nd.dims[0], dr = nd.dims[1], dp = nd.dims[2];
+      const int64_t M = (int64_t)dl * dr * dp;
+      const bool need_down = nd.child[0] >= 0 || nd.child[1] >= 0;
+      if (!need_down && !evals.count(n)) continue;
+      W[n] = buf.get(M);
+      gw.add(gm(Tptr(n), G[n], W[n], dl * dr, dp, dp, dp, dp, dp, 0, 1), 1);
+      if (nd.child[0] >= 0) gg.add(gm(Tptr(n), W[n], G[nd.child[0]], dl, dl, dr * dp, dr * dp, dr * dp, dl, 0, 1), 1);
+      if (nd.child[1] >= 0) {
+        double* tp = lb.get(M);
+        double* wp = lb.get(M);
+        pm.push_back(PMJob{Tptr(n), tp, dl, dr, dp, 0});
+        pm.push_back(PMJob{W[n], wp, dl, dr, dp, 0});
+        maxM = std::max(maxM, M);
+        gg.add(gm(tp, wp, G[nd.child[1]], dr, dr, dl * dp, dl * dp, dl * dp, dr, 0, 1), 1);
+      }
+    }
+    gw.run(lb, s);
+    if (!pm.empty()) {
+      PMJob* dpm = upload_tmp(lb, pm);
+      HIPCHK(launch_permute_jobs(dpm, (int)pm.size(), maxM, s));
+    }
+    gg.run(lb, s);
+  }
+  // ---- closing products at every lowest common node.  The needed (left,
+  // right) pairs of a node are evaluated either as all pairs of two stacked
+  // lists (one matrix product, when most pairs are needed) or pair by pair
+  // (when the images are specific to single products); the stacked images
+  // are formed in groups that fit kUVBudget doubles.
+  const int64_t kUVBudget = (int64_t)1 << 28;
+  std::map<int, std::map<std::pair<int, int>, double>> vals;
+  std::map<int, std::vector<std::pair<int, int>>> needed;
+  for (size_t p = 0; p < prods.size(); p++) needed[where[p][0]].push_back({where[p][1], where[p][2]});
+  for (auto& kv : needed) {
+    std::sort(kv.second.begin(), kv.second.end());
+    kv.second.erase(std::unique(kv.second.begin(), kv.second.end()), kv.second.end());
+  }
+  for (auto& kv : evals) {
+    const int n = kv.first;
+    const Eval& ev = kv.second;
+    const Node& nd = tr.nodes[n];
+    const int dl = nd.dims[0], dr = nd.dims[1], dp = nd.dims[2];
+    const int64_t M = (int64_t)dl * dr * dp;
+    const int nl = (int)ev.L.size(), nr = (int)ev.R.size();
+    const std::vector<std::pair<int, int>>& pairs = needed[n];
+    std::map<std::pair<int, int>, double>& out_n = vals[n];
+    Buf nb;   // this node's stacked images and partials
+    // U_i = R_l^T x_l T (or T), V_j = R_r x_r W (or W), written at given addresses
+    auto make_u = [&](GemmList& g, int i, double* dst) {
+      if (ev.L[i] < 0) HIPCHK(launch_copy(dst, Tptr(n), M, s));
+      else g.add(gm(imgs[ev.L[i]].dev, Tptr(n), dst, dl, dr * dp, dl, dl, dr * dp, dr * dp, 1, 0), 1);
+    };
+    auto make_v = [&](GemmList& g, int j, double* dst) {
+      if (ev.R[j] < 0) HIPCHK(launch_copy(dst, W[n], M, s));
+      else
+        g.add(gm(imgs[ev.R[j]].dev, W[n], dst, dr, dp, dr, dr, dp, dp, 0, 0, 0, (int64_t)dr * dp, (int64_t)dr * dp),
+              dl);
+    };
+    const int64_t cap = std::max<int64_t>(2, kUVBudget / M);   // stacked vectors held at once
+    if ((int64_t)nl * nr <= 4 * (int64_t)pairs.size()) {
+      // all pairs: C (nl x nr) block by block
+      const int cl = (int)std::max<int64_t>(1, std::min<int64_t>(nl, cap / 2));
+      const int cr = (int)std::max<int64_t>(1, std::min<int64_t>(nr, cap - cl));
+      double* U = nb.get((int64_t)cl * M);
+      double* V = nb.get((int64_t)cr * M);
+      std::vector<double> Cn((size_t)nl * nr);
+      for (int i0 = 0; i0 < nl; i0 += cl) {
+        const int ml = std::min(cl, nl - i0);
+        GemmList gu;
+        for (int i = 0; i < ml; i++) make_u(gu, i0 + i, U + (int64_t)i * M);
+        gu.run(nb, s);
+        for (int j0 = 0; j0 < nr; j0 += cr) {
+          const int mr = std::min(cr, nr - j0);
+          GemmList gv;
+          for (int j = 0; j < mr; j++) make_v(gv, j0 + j, V + (int64_t)j * M);
+          gv.run(nb, s);
+          const int64_t tiles = (int64_t)((ml + 63) / 64) * ((mr + 63) / 64);
+          int nq = (int)std::max<int64_t>(1, std::min<int64_t>({256, M / 2048, std::max<int64_t>(1, 1024 / tiles)}));
+          const int64_t kc = (M + nq - 1) / nq;
+          nq = (int)((M + kc - 1) / kc);
+          double* part = nb.get((int64_t)nq * ml * mr);
+          double* Cb = nb.get((int64_t)ml * mr);
+          GemmList gp;
+          for (int q = 0; q < nq; q++) {
+            const int64_t k0 = (int64_t)q * kc;
+            const int K = (int)std::min<int64_t>(kc, M - k0);
+            gp.add(gm(U + k0, V + k0, part + (int64_t)q * ml * mr, ml, mr, K, (int)M, (int)M, mr, 0, 1), 1);
+          }
+          gp.run(nb, s);
+          std::vector<SPJob> sp(1, SPJob{part, Cb, (int64_t)ml * mr, (int64_t)ml * mr, nq, 0});
+          SPJob* dsp = upload_tmp(nb, sp);
+          HIPCHK(launch_sum_parts(dsp, 1, (int64_t)ml * mr, s));
+          std::vector<double> hb((size_t)ml * mr);
+          HIPCHK(hipMemcpyAsync(hb.data(), Cb, hb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+          for (int i = 0; i < ml; i++)
+            for (int j = 0; j < mr; j++) Cn[(size_t)(i0 + i) * nr + j0 + j] = hb[(size_t)i * mr + j];
+        }
+      }
+      for (auto& pr : pairs) out_n[pr] = Cn[(size_t)pr.first * nr + pr.second];
+    } else {
+      // pair by pair, in groups whose distinct images fit the budget
+      size_t k = 0;
+      double* UV = nb.get(cap * M);
+      while (k < pairs.size()) {
+        std::map<int, int> su, sv;
+        std::vector<int2> pl;
+        size_t k1 = k;
+        while (k1 < pairs.size()) {
+          const int nu = (int)su.size() + (su.count(pairs[k1].first) ? 0 : 1);
+          const int nv = (int)sv.size() + (sv.count(pairs[k1].second) ? 0 : 1);
+          if (nu + nv > cap && k1 > k) break;
+          if (!su.count(pairs[k1].first)) { const int id = (int)su.size(); su[pairs[k1].first] = id; }
+          if (!sv.count(pairs[k1].second)) { const int id = (int)sv.size(); sv[pairs[k1].second] = id; }
+          k1++;
+        }
+        const int nu = (int)su.size();
+        GemmList gu;
+        for (auto& x : su) make_u(gu, x.first, UV + (int64_t)x.second * M);
+        for (auto& x : sv) make_v(gu, x.first, UV + (int64_t)(nu + x.second) * M);
+        gu.run(nb, s);
+        for (size_t q = k; q < k1; q++) pl.push_back(int2{su[pairs[q].first], nu + sv[pairs[q].second]});
+        int2* dpl = upload_tmp(nb, pl);
+        double* res = nb.get((int64_t)pl.size());
+        HIPCHK(launch_pair_dots(UV, dpl, (int)pl.size(), M, res, s));
+        std::vector<double> hr(pl.size());
+        HIPCHK(hipMemcpyAsync(hr.data(), res, hr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t q = k; q < k1; q++) out_n[pairs[q]] = hr[q - k];
+        k = k1;
+      }
+    }
+  }
+  for (size_t p = 0; p < prods.size(); p++) {
+    const auto& w = where[p];
+    out[p] = vals[w[0]].at({w[1], w[2]});
+  }
+}
+
+}  // namespace rt
+
+// ====================================================================== host helpers
+namespace {
+
+// Products of one-site operators whose sum is the dense operator H on the
+// sorted sites S (first site most significant): nested operator-Schmidt
+// decompositions, one site split off at a time (singular values above 1e-13
+// of the largest kept).
+struct HostProd {
+  double coef;
+  std::vector<std::pair<int, std::vector<double>>> f;
+};
+
+void decompose(const std::vector<int>& S, const std::vector<double>& H, int d, double coef, HostProd prefix,
+               std::vector<HostProd>& out) {
+  const int s = (int)S.size();
+  if (s == 1) {
+    prefix.coef *= coef;
+    prefix.f.push_back({S[0], H});
+    out.push_back(prefix);
+    return;
+  }
+  int Dr = 1;
+  for (int i = 1; i < s; i++) Dr *= d;
+  const int D = d * Dr;
+  // rows (o0, i0), columns (o_rest, i_rest)
+  std::vector<double> A((size_t)d * d * Dr * Dr);
+  for (int o = 0; o < D; o++)
+    for (int i = 0; i < D; i++) {
+      const int o0 = o / Dr, orr = o % Dr, i0 = i / Dr, ir = i % Dr;
+      A[(size_t)(o0 * d + i0) * (Dr * Dr) + (size_t)orr * Dr + ir] = H[(size_t)o * D + i];
+    }
+  std::vector<double> U, sv, V;
+  svd_jacobi(A, d * d, Dr * Dr, U, sv, V);
+  const int k = (int)sv.size();
+  const std::vector<int> rest(S.begin() + 1, S.end());
+  for (int t = 0; t < k; t++) {
+    if (!(sv[t] > 1e-13 * sv[0])) break;
+    std::vector<double> X((size_t)d * d), Y((size_t)Dr * Dr);
+    for (int e = 0; e < d * d; e++) X[e] = U[(size_t)e * k + t];
+    for (int e = 0; e < Dr * Dr; e++) Y[e] = V[(size_t)e * k + t];
+    HostProd p = prefix;
+    p.f.push_back({S[0], X});
+    decompose(rest, Y, d, coef * sv[t], p, out);
+  }
+}
+
+// rotated dense operator of coef * prod ops on sites (Sec. 5.2): o' = U^T o U
+void rotate_obs(attn_handle* h, const std::vector<int>& sites, const std::vector<const double*>& ops, double coef,
+                std::vector<int>& S, std::vector<double>& H) {
+  const ProblemCopy& P = h->prob;
+  const int d = P.d;
+  std::vector<int> de_of(P.n_sites, -1);
+  for (size_t k = 0; k < P.de_sites.size() / 2; k++) de_of[P.de_sites[2 * k]] = de_of[P.de_sites[2 * k + 1]] = (int)k;
+  std::vector<double> t(1, coef);
+  int cur = 1;
+  for (const double* o : ops) {
+    std::vector<double> nt((size_t)cur * d * cur * d);
+    for (int a = 0; a < cur; a++)
+      for (int b = 0; b < cur; b++)
+        for (int x = 0; x < d; x++)
+          for (int y = 0; y < d; y++) nt[(size_t)(a * d + x) * (cur * d) + (b * d + y)] = t[(size_t)a * cur + b] * o[x * d + y];
+    t.swap(nt);
+    cur *= d;
+  }
+  std::string err;
+  if (attn_status st = rotate_term_dense(sites, t, d, de_of, P.de_sites.data(), P.de_u.data(), S, H, err))
+    throw StatusFail{st, err};
+}
+
+void to_engine(XEngine& E, const std::vector<HostProd>& hp, std::vector<XProd>& prods, std::vector<double>& coefs) {
+  for (const HostProd& p : hp) {
+    XProd x;
+    for (auto& f : p.f) x.f.push_back({f.first, E.op_id(f.second.data())});
+    prods.push_back(x);
+    coefs.push_back(p.coef);
+  }
+}
+
+attn_status need_root(attn_handle* h) {
+  if (!h->state_ready) { h->err = "no state (attn_init_state not called)"; return ATTN_ERR_STATE; }
+  const int root = h->M.tree.root;
+  if (h->center != root) {
+    attn_status st = attn_move_center(h, root, nullptr);
+    if (st) return st;
+  }
+  return ATTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+attn_status attn_expect_products(attn_handle* h, int32_t n_prod, const int32_t* nsites, const int32_t* sites,
+                                 const double* ops, double* out) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (n_prod < 0 || (n_prod > 0 && (!nsites || !sites || !ops || !out))) { h->err = "bad arguments"; return ATTN_ERR_ARG; }
+    HIPCHK(hipSetDevice(h->device));
+    if (attn_status e = need_root(h)) return e;
+    const Tree& tr = h->M.tree;
+    const int d = tr.d;
+    XEngine E(h);
+    std::vector<XProd> prods(n_prod);
+    int64_t off = 0;
+    for (int p = 0; p < n_prod; p++) {
+      if (nsites[p] < 1 || nsites[p] > tr.N) { h->err = "product size out of range"; return ATTN_ERR_ARG; }
+      for (int i = 0; i < nsites[p]; i++, off++) {
+        const int s = sites[off];
+        if (s < 0 || s >= tr.N) { h->err = "site out of range"; return ATTN_ERR_ARG; }
+        prods[p].f.push_back({s, E.op_id(ops + off * d * d)});
+      }
+    }
+    std::vector<double> v;
+    E.run(prods, v, nullptr);
+    for (int p = 0; p < n_prod; p++) out[p] = v[p];
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_measure(attn_handle* h, int32_t n_obs, const int32_t* nsites, const int32_t* sites,
+                         const double* ops, const double* coef, double* out) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (n_obs < 0 || (n_obs > 0 && (!nsites || !sites || !ops || !out))) { h->err = "bad arguments"; return ATTN_ERR_ARG; }
+    HIPCHK(hipSetDevice(h->device));
+    if (attn_status e = need_root(h)) return e;
+    const Tree& tr = h->M.tree;
+    const int d = tr.d;
+    XEngine E(h);
+    std::vector<XProd> prods;
+    std::vector<double> coefs;
+    std::vector<int> owner;
+    int64_t off = 0;
+    for (int o = 0; o < n_obs; o++) {
+      if (nsites[o] < 1 || nsites[o] > 4) { h->err = "observables act on 1..4 sites"; return ATTN_ERR_ARG; }
+      std::vector<int> st;
+      std::vector<const double*> op;
+      for (int i = 0; i < nsites[o]; i++, off++) {
+        const int s = sites[off];
+        if (s < 0 || s >= tr.N || std::find(st.begin(), st.end(), s) != st.end()) { h->err = "bad observable site"; return ATTN_ERR_ARG; }
+        st.push_back(s);
+        op.push_back(ops + off * d * d);
+      }
+      std::vector<int> S;
+      std::vector<double> H;
+      rotate_obs(h, st, op, coef ? coef[o] : 1.0, S, H);
+      std::vector<HostProd> hp;
+      decompose(S, H, d, 1.0, HostProd{1.0, {}}, hp);
+      const size_t before = prods.size();
+      to_engine(E, hp, prods, coefs);
+      owner.resize(prods.size(), o);
+      (void)before;
+    }
+    std::vector<double> v;
+    E.run(prods, v, nullptr);
+    for (int o = 0; o < n_obs; o++) out[o] = 0.0;
+    for (size_t p = 0; p < prods.size(); p++) out[owner[p]] += coefs[p] * v[p];
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_correlation(attn_handle* h, const double* oa, const double* ob, double* C) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (!oa || !ob || !C) { h->err = "NULL argument"; return ATTN_ERR_ARG; }
+    HIPCHK(hipSetDevice(h->device));
+    if (attn_status e = need_root(h)) return e;
+    const Tree& tr = h->M.tree;
+    const int N = tr.N, d = tr.d;
+    const ProblemCopy& P = h->prob;
+    std::vector<int> de_of(N, -1);
+    for (size_t k = 0; k < P.de_sites.size() / 2; k++) de_of[P.de_sites[2 * k]] = de_of[P.de_sites[2 * k + 1]] = (int)k;
+    std::vector<double> ab((size_t)d * d, 0.0);
+    for (int i = 0; i < d; i++)
+      for (int j = 0; j < d; j++)
+        for (int k = 0; k < d; k++) ab[(size_t)i * d + j] += oa[i * d + k] * ob[k * d + j];
+    // decompositions of the rotated one-site observables o' (shared by every pair)
+    auto one = [&](int i, const double* o) {
+      std::vector<int> S;
+      std::vector<double> H;
+      rotate_obs(h, {i}, {o}, 1.0, S, H);
+      std::vector<HostProd> hp;
+      decompose(S, H, d, 1.0, HostProd{1.0, {}}, hp);
+      return hp;
+    };
+    std::vector<std::vector<HostProd>> da(N), db(N);
+    for (int i = 0; i < N; i++) { da[i] = one(i, oa); db[i] = one(i, ob); }
+    XEngine E(h);
+    // operator ids of the shared factors
+    auto ids = [&](const std::vector<HostProd>& hp) {
+      std::vector<std::vector<std::pair<int, int>>> r;
+      for (const HostProd& p : hp) {
+        std::vector<std::pair<int, int>> f;
+        for (auto& x : p.f) f.push_back({x.first, E.op_id(x.second.data())});
+        r.push_back(f);
+      }
+      return r;
+    };
+    std::vector<std::vector<std::vector<std::pair<int, int>>>> ia(N), ib(N);
+    for (int i = 0; i < N; i++) { ia[i] = ids(da[i]); ib[i] = ids(db[i]); }
+    std::vector<XProd> prods;
+    std::vector<double> coefs;
+    std::vector<int64_t> owner;
+    for (int i = 0; i < N; i++)
+      for (int j = 0; j < N; j++) {
+        const int64_t e = (int64_t)i * N + j;
+        const bool same = i == j || (de_of[i] >= 0 && de_of[i] == de_of[j]);
+        if (same) {
+          // the pair acts on one gate's sites (or one site): rotate it as a whole
+          std::vector<int> S;
+          std::vector<double> H;
+          if (i == j) rotate_obs(h, {i}, {ab.data()}, 1.0, S, H);
+          else rotate_obs(h, {i, j}, {oa, ob}, 1.0, S, H);
+          std::vector<HostProd> hp;
+          decompose(S, H, d, 1.0, HostProd{1.0, {}}, hp);
+          const size_t b0 = prods.size();
+          to_engine(E, hp, prods, coefs);
+          owner.resize(prods.size(), e);
+          (void)b0;
+          continue;
+        }
+        for (size_t k = 0; k < da[i].size(); k++)
+          for (size_t l = 0; l < db[j].size(); l++) {
+            XProd x;
+            x.f = ia[i][k];
+            x.f.insert(x.f.end(), ib[j][l].begin(), ib[j][l].end());
+            prods.push_back(x);
+            coefs.push_back(da[i][k].coef * db[j][l].coef);
+            owner.push_back(e);
+          }
+      }
+    std::vector<double> v;
+    E.run(prods, v, nullptr);
+    for (int64_t e = 0; e < (int64_t)N * N; e++) C[e] = 0.0;
+    for (size_t p = 0; p < prods.size(); p++) C[owner[p]] += coefs[p] * v[p];
+    return ATTN_OK;
+  });
+}
+
+}  // extern "C"

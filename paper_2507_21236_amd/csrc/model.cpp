@@ -250,6 +250,89 @@ double max_abs(const std::vector<double>& v) {
 
 }  // namespace
 
+// Disentanglers contracted into one term (Sec. 4.3, algorithm "Contract
+// disentangler layer"): S = the term's sites plus the partner sites of every
+// gate that touches them (sorted), H = U^T (h (x) 1) U on S with U the product
+// of those gates; tdense is the term's dense operator on its own site order.
+attn_status rotate_term_dense(const std::vector<int>& tsites_t, const std::vector<double>& tdense_t, int d,
+                              const std::vector<int>& de_of, const int32_t* de_sites, const double* de_u,
+                              std::vector<int>& S_out, std::vector<double>& H_out, std::string& err) {
+  const int dd = d * d;
+    std::vector<int> S = tsites_t;
+    std::vector<int> touch;
+    for (int s : tsites_t)
+      if (de_of[s] >= 0 && std::find(touch.begin(), touch.end(), de_of[s]) == touch.end()) touch.push_back(de_of[s]);
+    for (int k : touch)
+      for (int q = 0; q < 2; q++) {
+        int x = de_sites[2 * k + q];
+        if (std::find(S.begin(), S.end(), x) == S.end()) S.push_back(x);
+      }
+    if (S.size() > 6) { err = "rotated term support beyond 6 sites"; return ATTN_ERR_UNSUPPORTED; }
+    std::sort(S.begin(), S.end());
+    int s = (int)S.size();
+    int D = ipow(d, s);
+    // the original term embedded on S
+    int k0 = (int)tsites_t.size();
+    int D0 = ipow(d, k0);
+    std::vector<int> tpos(k0);
+    for (int i = 0; i < k0; i++) tpos[i] = (int)(std::find(S.begin(), S.end(), tsites_t[i]) - S.begin());
+    auto digits = [&](int x, int* dg) { for (int q = s - 1; q >= 0; q--) { dg[q] = x % d; x /= d; } };
+    std::vector<double> H((size_t)D * D, 0.0);
+    int od[8], id[8];
+    for (int o = 0; o < D; o++) {
+      digits(o, od);
+      for (int i = 0; i < D; i++) {
+        digits(i, id);
+        bool ok = true;
+        for (int q = 0; q < s && ok; q++)
+          if (std::find(tpos.begin(), tpos.end(), q) == tpos.end() && od[q] != id[q]) ok = false;
+        if (!ok) continue;
+        int ro = 0, ri = 0;
+        for (int q = 0; q < k0; q++) { ro = ro * d + od[tpos[q]]; ri = ri * d + id[tpos[q]]; }
+        H[(size_t)o * D + i] = tdense_t[(size_t)ro * D0 + ri];
+      }
+    }
+    // U = product of the touching gates embedded on S; h' = U^T H U
+    for (int k : touch) {
+      int a = (int)(std::find(S.begin(), S.end(), de_sites[2 * k]) - S.begin());
+      int b = (int)(std::find(S.begin(), S.end(), de_sites[2 * k + 1]) - S.begin());
+      const double* u = de_u + (size_t)k * dd * dd;
+      // G = embed(u): G[o][i] = u[(o_a o_b)][(i_a i_b)] prod_{q != a, b} delta(o_q, i_q)
+      auto apply_right = [&](std::vector<double>& X) {   // X <- X G
+        std::vector<double> Y((size_t)D * D, 0.0);
+        for (int i = 0; i < D; i++) {
+          digits(i, id);
+          for (int xa = 0; xa < d; xa++)
+            for (int xb = 0; xb < d; xb++) {
+              int o2[8];
+              for (int q = 0; q < s; q++) o2[q] = id[q];
+              o2[a] = xa; o2[b] = xb;
+              int o = 0;
+              for (int q = 0; q < s; q++) o = o * d + o2[q];
+              double g = u[(xa * d + xb) * dd + (id[a] * d + id[b])];
+              if (g == 0.0) continue;
+              for (int r = 0; r < D; r++) Y[(size_t)r * D + i] += X[(size_t)r * D + o] * g;
+            }
+        }
+        X.swap(Y);
+      };
+      apply_right(H);                  // H G
+      // G^T (H G): transpose, right-multiply by G, transpose back
+      std::vector<double> Ht((size_t)D * D);
+      for (int i = 0; i < D; i++) for (int j = 0; j < D; j++) Ht[(size_t)j * D + i] = H[(size_t)i * D + j];
+      apply_right(Ht);
+      for (int i = 0; i < D; i++) for (int j = 0; j < D; j++) H[(size_t)j * D + i] = Ht[(size_t)i * D + j];
+    }
+  S_out = S;
+  H_out = std::move(H);
+  return ATTN_OK;
+}
+
+void svd_jacobi(const std::vector<double>& A, int r, int c, std::vector<double>& U, std::vector<double>& s,
+                std::vector<double>& V) {
+  svd(A, r, c, U, s, V);
+}
+
 // ====================================================================== build
 attn_status build_model(const attn_problem* p, Model& M, std::string& err) {
   if (!p) { err = "problem is NULL"; return ATTN_ERR_ARG; }
@@ -404,71 +487,10 @@ attn_status build_model(const attn_problem* p, Model& M, std::string& err) {
   //      partner sites of the disentanglers that touch the term
   M.terms.assign(p->n_terms, RTerm());
   for (int t = 0; t < p->n_terms; t++) {
-    std::vector<int> S = tsites[t];
-    std::vector<int> touch;
-    for (int s : tsites[t])
-      if (de_of[s] >= 0 && std::find(touch.begin(), touch.end(), de_of[s]) == touch.end()) touch.push_back(de_of[s]);
-    for (int k : touch)
-      for (int q = 0; q < 2; q++) {
-        int x = p->de_sites[2 * k + q];
-        if (std::find(S.begin(), S.end(), x) == S.end()) S.push_back(x);
-      }
-    if (S.size() > 6) { err = "rotated term support beyond 6 sites"; return ATTN_ERR_UNSUPPORTED; }
-    std::sort(S.begin(), S.end());
-    int s = (int)S.size();
-    int D = ipow(d, s);
-    // the original term embedded on S
-    int k0 = (int)tsites[t].size();
-    int D0 = ipow(d, k0);
-    std::vector<int> tpos(k0);
-    for (int i = 0; i < k0; i++) tpos[i] = (int)(std::find(S.begin(), S.end(), tsites[t][i]) - S.begin());
-    auto digits = [&](int x, int* dg) { for (int q = s - 1; q >= 0; q--) { dg[q] = x % d; x /= d; } };
-    std::vector<double> H((size_t)D * D, 0.0);
-    int od[8], id[8];
-    for (int o = 0; o < D; o++) {
-      digits(o, od);
-      for (int i = 0; i < D; i++) {
-        digits(i, id);
-        bool ok = true;
-        for (int q = 0; q < s && ok; q++)
-          if (std::find(tpos.begin(), tpos.end(), q) == tpos.end() && od[q] != id[q]) ok = false;
-        if (!ok) continue;
-        int ro = 0, ri = 0;
-        for (int q = 0; q < k0; q++) { ro = ro * d + od[tpos[q]]; ri = ri * d + id[tpos[q]]; }
-        H[(size_t)o * D + i] = tdense[t][(size_t)ro * D0 + ri];
-      }
-    }
-    // U = product of the touching gates embedded on S; h' = U^T H U
-    for (int k : touch) {
-      int a = (int)(std::find(S.begin(), S.end(), p->de_sites[2 * k]) - S.begin());
-      int b = (int)(std::find(S.begin(), S.end(), p->de_sites[2 * k + 1]) - S.begin());
-      const double* u = p->de_u + (size_t)k * dd * dd;
-      // G = embed(u): G[o][i] = u[(o_a o_b)][(i_a i_b)] prod_{q != a, b} delta(o_q, i_q)
-      auto apply_right = [&](std::vector<double>& X) {   // X <- X G
-        std::vector<double> Y((size_t)D * D, 0.0);
-        for (int i = 0; i < D; i++) {
-          digits(i, id);
-          for (int xa = 0; xa < d; xa++)
-            for (int xb = 0; xb < d; xb++) {
-              int o2[8];
-              for (int q = 0; q < s; q++) o2[q] = id[q];
-              o2[a] = xa; o2[b] = xb;
-              int o = 0;
-              for (int q = 0; q < s; q++) o = o * d + o2[q];
-              double g = u[(xa * d + xb) * dd + (id[a] * d + id[b])];
-              if (g == 0.0) continue;
-              for (int r = 0; r < D; r++) Y[(size_t)r * D + i] += X[(size_t)r * D + o] * g;
-            }
-        }
-        X.swap(Y);
-      };
-      apply_right(H);                  // H G
-      // G^T (H G): transpose, right-multiply by G, transpose back
-      std::vector<double> Ht((size_t)D * D);
-      for (int i = 0; i < D; i++) for (int j = 0; j < D; j++) Ht[(size_t)j * D + i] = H[(size_t)i * D + j];
-      apply_right(Ht);
-      for (int i = 0; i < D; i++) for (int j = 0; j < D; j++) H[(size_t)j * D + i] = Ht[(size_t)i * D + j];
-    }
+    std::vector<int> S;
+    std::vector<double> H;
+    if (attn_status st = rotate_term_dense(tsites[t], tdense[t], d, de_of, p->de_sites, p->de_u, S, H, err))
+      return st;
     M.terms[t].S = S;
     M.terms[t].h = std::move(H);
   }

@@ -144,4 +144,18 @@ attn_status build_model(const attn_problem* p, Model& M, std::string& err);
 // helpers shared with tests of the host build
 int mask_popcount(uint32_t m);
 
+// The disentanglers touching a term contracted into it (Sec. 4.3): S = the
+// term's sites plus the partner sites of every gate touching them (sorted),
+// H = U^T (h (x) 1) U, d^|S| x d^|S| row-major with S[0] most significant;
+// tdense = the term's own dense operator on tsites (in that order); de_of[site]
+// = index of its gate or -1.  Errors: UNSUPPORTED (support beyond 6 sites).
+attn_status rotate_term_dense(const std::vector<int>& tsites, const std::vector<double>& tdense, int d,
+                              const std::vector<int>& de_of, const int32_t* de_sites, const double* de_u,
+                              std::vector<int>& S, std::vector<double>& H, std::string& err);
+
+// One-sided Jacobi SVD of the r x c row-major A: A = U diag(s) V^T (U r x k,
+// V c x k row-major, k = min(r, c), singular values descending).
+void svd_jacobi(const std::vector<double>& A, int r, int c, std::vector<double>& U, std::vector<double>& s,
+                std::vector<double>& V);
+
 }  // namespace attn
