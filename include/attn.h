@@ -456,6 +456,59 @@ attn_status attn_measure(attn_handle* h, int32_t n_obs, const int32_t* nsites, c
                          const double* ops, const double* coef, double* out);
 attn_status attn_correlation(attn_handle* h, const double* oa, const double* ob, double* C);
 
+/*
+ * Disentangler optimisation (Sec. 4.1, MERA-like variant of Sec. 4.1.1) and
+ * the aTTN ground-state recipe of Sec. 4 (each sweep: optimise the layer,
+ * contract it into the Hamiltonian, sweep the TTN).  Needs the placement
+ * restriction of Sec. 4.1 (no term acts on two disentanglers: problems built
+ * with ATTN_DE_STRICT placements), else DE_RESTRICTION.
+ *
+ * attn_optimize_disentanglers: for every gate k, the energy of the terms on
+ * its sites with the bra copy of u_k fixed at u~ is Tr(u_k Gamma_k) (eq. 4);
+ * Gamma_k is built from expectation values of the current TTN state (the
+ * environment, computed once on the GPU with the centre moved to the root);
+ * u_k <- -V U^T for Gamma_k = U sigma V^T (eq. 5), repeated with the new u as
+ * u~ until the gate's energy changes by <= rel_tol * max(1, |E|) or max_iter
+ * steps.  With shift = 1 the gate's terms are shifted by an upper bound of
+ * their largest eigenvalue (sum of |coef| prod ||op||_2) first: the energy is
+ * then a concave function of u_k, its linearisation an upper bound, and no
+ * step raises the energy (the paper does not fix a safeguard; shift = 0 is
+ * the plain linearisation).  Gates are independent under the restriction, so
+ * all are optimised from the same state.  Writes the new matrices
+ * (de_u_out, [n_de][d^2][d^2] row-major, the layout of attn_problem.de_u),
+ * and per gate the energy of its terms before and after and the number of
+ * steps (any output may be NULL).  The handle keeps its disentanglers: apply
+ * the result with attn_set_disentanglers.  opts may be NULL (20 steps,
+ * rel_tol 1e-12, shift on).  Errors: ARG, STATE, DE_RESTRICTION, HIP.
+ *
+ * attn_set_disentanglers: replaces the disentangler matrices (same sites):
+ * the rotated TPO is rebuilt (attn_build_tpo on the stored problem), the TTN
+ * tensors, centre and sweep history are kept, and every effective operator
+ * toward the centre is recomputed.  Batches that borrow the handle become
+ * invalid.  Errors: ARG, NOT_UNITARY, OOM, HIP.
+ *
+ * attn_sweep_attn: n_sweeps sweeps; from sweep s_ttn on (counted in this
+ * call), each sweep is preceded by attn_optimize_disentanglers and
+ * attn_set_disentanglers (Sec. 6.3: the first S_TTN sweeps run on the TTN
+ * with the given layer, e.g. the identity, S_TTN = 1 being the paper's best
+ * schedule).  energies[s] / seconds[s] as attn_sweep (seconds include the
+ * layer update).  Errors: as the calls it makes.
+ *
+ * attn_get_disentanglers: the current matrices (len = n_de d^4 values).
+ */
+typedef struct attn_de_opts {
+  int32_t max_iter;   /* self-consistent steps per gate (20) */
+  double rel_tol;     /* stop at |dE| <= rel_tol * max(1, |E|) (1e-12) */
+  int32_t shift;      /* 1: shifted terms (monotone steps); 0: plain linearisation */
+} attn_de_opts;
+
+attn_status attn_optimize_disentanglers(attn_handle* h, const attn_de_opts* opts, double* de_u_out,
+                                        double* e_before, double* e_after, int32_t* iters);
+attn_status attn_set_disentanglers(attn_handle* h, const double* de_u);
+attn_status attn_sweep_attn(attn_handle* h, int32_t n_sweeps, int32_t s_ttn, const attn_sweep_opts* sopts,
+                            const attn_de_opts* dopts, double* energies, double* seconds);
+attn_status attn_get_disentanglers(const attn_handle* h, double* de_u, int64_t len);
+
 /* Checks on the host that every work unit of every device work list of the
  * handle reads and writes only inside the buffer it was built for.  Meant for
  * ATTN_DRYRUN handles (no GPU needed).  Errors: STATE (message names the first

@@ -13,7 +13,7 @@ import numpy as np
 from . import _lib
 from ._lib import (ATTN_F64, ATTN_F32, ATTN_BF16X2, ATTN_DE_STRICT, ATTN_HOST_ONLY, ATTN_DRYRUN,
                    ATTN_SOLVER_LANCZOS, ATTN_SOLVER_DAVIDSON, ATTN_PRECOND_JACOBI,
-                   ATTN_PRECOND_LEARNED, ATTN_MLP_PARAMS, AttnError, solver_opts)
+                   ATTN_PRECOND_LEARNED, ATTN_MLP_PARAMS, AttnError, solver_opts, de_opts)
 
 
 class AttnHandle:
@@ -111,6 +111,20 @@ class AttnHandle:
     def correlation(self, oa, ob):
         """N x N matrix <o^a_i o^b_j> of the augmented state"""
         return _lib.attn_correlation(self.h, oa, ob, self.problem.n_sites)
+
+    def optimize_disentanglers(self, opts=None):
+        """(new matrices, gate energies before, after, steps) from the current state"""
+        return _lib.attn_optimize_disentanglers(self.h, len(self.problem.de_sites), self.problem.d, opts)
+
+    def set_disentanglers(self, de_u):
+        _lib.attn_set_disentanglers(self.h, de_u)
+
+    def get_disentanglers(self):
+        return _lib.attn_get_disentanglers(self.h, len(self.problem.de_sites), self.problem.d)
+
+    def sweep_attn(self, n_sweeps, s_ttn=1, opts=None, dopts=None, use_graphs=False):
+        """aTTN sweeps: from sweep s_ttn on, the layer is optimised before each sweep"""
+        return _lib.attn_sweep_attn(self.h, n_sweeps, s_ttn, opts, dopts, use_graphs)
 
     def checkpoint(self, path):
         _lib.attn_checkpoint(self.h, path)

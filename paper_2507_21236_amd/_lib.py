@@ -70,6 +70,10 @@ class attn_sweep_opts(ctypes.Structure):
     _fields_ = [("solver", attn_solver_opts), ("use_graphs", ctypes.c_int32)]
 
 
+class attn_de_opts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("rel_tol", ctypes.c_double), ("shift", ctypes.c_int32)]
+
+
 class attn_batch_opts(ctypes.Structure):
     _fields_ = [("krylov_k", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("use_graphs", ctypes.c_int32), ("autotune", ctypes.c_int32)]
@@ -127,6 +131,12 @@ _proto = {
     "attn_expect_products": (ctypes.c_int32, [_H, ctypes.c_int32, _i32p, _i32p, _f64p, _f64p]),
     "attn_measure": (ctypes.c_int32, [_H, ctypes.c_int32, _i32p, _i32p, _f64p, _f64p, _f64p]),
     "attn_correlation": (ctypes.c_int32, [_H, _f64p, _f64p, _f64p]),
+    "attn_optimize_disentanglers": (ctypes.c_int32, [_H, ctypes.POINTER(attn_de_opts), _f64p, _f64p, _f64p,
+                                                     _i32p]),
+    "attn_set_disentanglers": (ctypes.c_int32, [_H, _f64p]),
+    "attn_sweep_attn": (ctypes.c_int32, [_H, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(attn_sweep_opts),
+                                         ctypes.POINTER(attn_de_opts), _f64p, _f64p]),
+    "attn_get_disentanglers": (ctypes.c_int32, [_H, _f64p, ctypes.c_int64]),
     "attn_checkpoint": (ctypes.c_int32, [_H, ctypes.c_char_p]),
     "attn_restore": (ctypes.c_int32, [_H, ctypes.c_char_p]),
     "attn_checkpoint_info": (ctypes.c_int32, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint64), _i32p,
@@ -432,3 +442,39 @@ def attn_correlation(h, oa, ob, n_sites):
     C = np.zeros((n_sites, n_sites))
     _check(_lib.attn_correlation(h, a.ctypes.data_as(_f64p), b.ctypes.data_as(_f64p), C.ctypes.data_as(_f64p)), h)
     return C
+
+
+def de_opts(max_iter=20, rel_tol=1e-12, shift=True):
+    return attn_de_opts(max_iter, rel_tol, int(shift))
+
+
+def attn_optimize_disentanglers(h, n_de, d=2, opts=None):
+    """(new matrices [n_de, d^2, d^2], energies before, after, steps) per gate."""
+    u = np.zeros((n_de, d * d, d * d))
+    eb, ea = np.zeros(n_de), np.zeros(n_de)
+    it = np.zeros(n_de, dtype=np.int32)
+    o = opts if opts is not None else de_opts()
+    _check(_lib.attn_optimize_disentanglers(h, ctypes.byref(o), u.ctypes.data_as(_f64p), eb.ctypes.data_as(_f64p),
+                                            ea.ctypes.data_as(_f64p), it.ctypes.data_as(_i32p)), h)
+    return u, eb, ea, it
+
+
+def attn_set_disentanglers(h, de_u):
+    u = _arr(de_u, np.float64)
+    _check(_lib.attn_set_disentanglers(h, u.ctypes.data_as(_f64p)), h)
+
+
+def attn_get_disentanglers(h, n_de, d=2):
+    u = np.zeros((n_de, d * d, d * d))
+    _check(_lib.attn_get_disentanglers(h, u.ctypes.data_as(_f64p), u.size), h)
+    return u
+
+
+def attn_sweep_attn(h, n_sweeps, s_ttn=1, opts=None, dopts=None, use_graphs=False):
+    e = np.zeros(n_sweeps)
+    s = np.zeros(n_sweeps)
+    so = attn_sweep_opts(opts if opts is not None else solver_opts(), int(use_graphs))
+    o = dopts if dopts is not None else de_opts()
+    _check(_lib.attn_sweep_attn(h, n_sweeps, s_ttn, ctypes.byref(so), ctypes.byref(o), e.ctypes.data_as(_f64p),
+                                s.ctypes.data_as(_f64p)), h)
+    return e, s

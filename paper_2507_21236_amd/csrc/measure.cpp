@@ -668,3 +668,269 @@ attn_status attn_correlation(attn_handle* h, const double* oa, const double* ob,
 }
 
 }  // extern "C"
+
+// ====================================================================== disentangler optimisation
+namespace {
+
+struct DeTerm {
+  double coef;
+  std::vector<std::pair<int, std::vector<double>>> rest;   // the term's operators off the gate
+  std::vector<double> Q;                                    // its operators on the gate's sites, (a b), a major
+};
+
+// Terms acting on the sites of every gate; ATTN_ERR_DE_RESTRICTION when a term
+// acts on two gates (the optimisation of Sec. 4.1 needs that restriction).
+attn_status gate_terms(const ProblemCopy& P, std::vector<std::vector<DeTerm>>& out, std::string& err) {
+  const int d = P.d, dd = d * d;
+  const int nde = (int)P.de_sites.size() / 2;
+  std::vector<int> de_of(P.n_sites, -1);
+  for (int k = 0; k < nde; k++) de_of[P.de_sites[2 * k]] = de_of[P.de_sites[2 * k + 1]] = k;
+  out.assign(nde, {});
+  int64_t off = 0;
+  for (size_t t = 0; t < P.term_nsites.size(); t++) {
+    const int ns = P.term_nsites[t];
+    int k = -1;
+    for (int i = 0; i < ns; i++) {
+      const int g = de_of[P.term_sites[off + i]];
+      if (g < 0) continue;
+      if (k >= 0 && g != k) {
+        err = "a term acts on two disentanglers (the optimisation needs ATTN_DE_STRICT placements)";
+        return ATTN_ERR_DE_RESTRICTION;
+      }
+      k = g;
+    }
+    if (k >= 0) {
+      const int a = P.de_sites[2 * k], b = P.de_sites[2 * k + 1];
+      DeTerm dt;
+      dt.coef = P.term_coef[t];
+      std::vector<double> A(dd, 0.0), B(dd, 0.0);   // one-site factors on a and b (identity if absent)
+      for (int x = 0; x < d; x++) A[x * d + x] = B[x * d + x] = 1.0;
+      for (int i = 0; i < ns; i++) {
+        const int s = P.term_sites[off + i];
+        const double* o = P.term_ops.data() + (off + i) * dd;
+        if (s == a) A.assign(o, o + dd);
+        else if (s == b) B.assign(o, o + dd);
+        else dt.rest.push_back({s, std::vector<double>(o, o + dd)});
+      }
+      dt.Q.assign((size_t)dd * dd, 0.0);
+      for (int xa = 0; xa < d; xa++)
+        for (int xb = 0; xb < d; xb++)
+          for (int ya = 0; ya < d; ya++)
+            for (int yb = 0; yb < d; yb++) dt.Q[(size_t)(xa * d + xb) * dd + ya * d + yb] = A[xa * d + ya] * B[xb * d + yb];
+      out[k].push_back(std::move(dt));
+    }
+    off += ns;
+  }
+  return ATTN_OK;
+}
+
+void matmul(const double* A, const double* B, double* C, int n) {   // C = A B, n x n row-major
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) {
+      double acc = 0;
+      for (int k = 0; k < n; k++) acc += A[i * n + k] * B[k * n + j];
+      C[i * n + j] = acc;
+    }
+}
+
+void transpose(const double* A, double* At, int n) {
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) At[j * n + i] = A[i * n + j];
+}
+
+}  // namespace
+
+extern "C" {
+
+attn_status attn_optimize_disentanglers(attn_handle* h, const attn_de_opts* opts, double* de_u_out, double* e_before,
+                                        double* e_after, int32_t* iters) {
+  return guard(h, [&]() -> attn_status {
+    const ProblemCopy& P = h->prob;
+    const int d = P.d, dd = d * d;
+    const int nde = (int)P.de_sites.size() / 2;
+    attn_de_opts o;
+    if (opts) o = *opts;
+    else { o.max_iter = 20; o.rel_tol = 1e-12; o.shift = 1; }
+    if (o.max_iter < 0) { h->err = "max_iter < 0"; return ATTN_ERR_ARG; }
+    std::vector<std::vector<DeTerm>> gt;
+    if (attn_status e = gate_terms(P, gt, h->err)) return e;
+    if (attn_status e = need_device(h)) return e;
+    HIPCHK(hipSetDevice(h->device));
+    if (attn_status e = need_root(h)) return e;
+    // products: for every gate, the d^2 x d^2 units |y><x| on (a, b) times each
+    // term's operators off the gate, and alone (rho_ab)
+    XEngine E(h);
+    std::vector<int> unit_a(dd * dd), unit_b(dd * dd);
+    std::vector<std::vector<double>> units(dd, std::vector<double>(dd, 0.0));
+    for (int o2 = 0; o2 < d; o2++)
+      for (int i2 = 0; i2 < d; i2++) units[o2 * d + i2][o2 * d + i2] = 1.0;
+    std::vector<XProd> prods;
+    for (int k = 0; k < nde; k++) {
+      const int a = P.de_sites[2 * k], b = P.de_sites[2 * k + 1];
+      for (int t = -1; t < (int)gt[k].size(); t++)
+        for (int x = 0; x < dd; x++)
+          for (int y = 0; y < dd; y++) {
+            const int ya = y / d, yb = y % d, xa = x / d, xb = x % d;
+            XProd pr;
+            pr.f.push_back({a, E.op_id(units[ya * d + xa].data())});
+            pr.f.push_back({b, E.op_id(units[yb * d + xb].data())});
+            if (t >= 0)
+              for (auto& r : gt[k][t].rest) pr.f.push_back({r.first, E.op_id(r.second.data())});
+            prods.push_back(pr);
+          }
+    }
+    std::vector<double> v;
+    E.run(prods, v, nullptr);
+    // the self-consistent iteration of every gate on the host (d^2 x d^2 algebra)
+    size_t pi = 0;
+    for (int k = 0; k < nde; k++) {
+      std::vector<double> rho(v.begin() + pi, v.begin() + pi + dd * dd);
+      pi += dd * dd;
+      const int nt = (int)gt[k].size();
+      std::vector<std::vector<double>> sig(nt);
+      double c = 0.0;
+      for (int t = 0; t < nt; t++) {
+        sig[t].assign(v.begin() + pi, v.begin() + pi + dd * dd);
+        for (double& z : sig[t]) z *= gt[k][t].coef;
+        pi += dd * dd;
+        if (o.shift) {
+          // |coef| prod ||op||_2 over the term's operators (spectral norms by SVD)
+          double nrm = std::fabs(gt[k][t].coef);
+          std::vector<std::vector<double>> fs;
+          for (auto& r : gt[k][t].rest) fs.push_back(r.second);
+          std::vector<double> U, s, V;
+          svd_jacobi(gt[k][t].Q, dd, dd, U, s, V);
+          nrm *= s.empty() ? 0.0 : s[0];
+          for (auto& f : fs) { svd_jacobi(f, d, d, U, s, V); nrm *= s.empty() ? 0.0 : s[0]; }
+          c += nrm;
+        }
+      }
+      std::vector<double> u(P.de_u.begin() + (size_t)k * dd * dd, P.de_u.begin() + (size_t)(k + 1) * dd * dd);
+      // energy of the gate's terms: sum_t Tr(u sigma_t u^T Q_t)
+      auto energy = [&](const std::vector<double>& uu) {
+        std::vector<double> ut(dd * dd), t1(dd * dd), t2(dd * dd), t3(dd * dd);
+        transpose(uu.data(), ut.data(), dd);
+        double e = 0;
+        for (int t = 0; t < nt; t++) {
+          matmul(uu.data(), sig[t].data(), t1.data(), dd);
+          matmul(t1.data(), ut.data(), t2.data(), dd);
+          matmul(t2.data(), gt[k][t].Q.data(), t3.data(), dd);
+          for (int i = 0; i < dd; i++) e += t3[i * dd + i];
+        }
+        return e;
+      };
+      double e0 = energy(u), e_prev = e0;
+      int it = 0;
+      for (; it < o.max_iter; it++) {
+        // Gamma = sum_t sigma_t u^T Q_t - c rho u^T  (eq. 4, bra copy fixed)
+        std::vector<double> ut(dd * dd), G(dd * dd, 0.0), t1(dd * dd), t2(dd * dd);
+        transpose(u.data(), ut.data(), dd);
+        for (int t = 0; t < nt; t++) {
+          matmul(sig[t].data(), ut.data(), t1.data(), dd);
+          matmul(t1.data(), gt[k][t].Q.data(), t2.data(), dd);
+          for (int i = 0; i < dd * dd; i++) G[i] += t2[i];
+        }
+        matmul(rho.data(), ut.data(), t1.data(), dd);
+        for (int i = 0; i < dd * dd; i++) G[i] -= c * t1[i];
+        // u = -V U^T for Gamma = U s V^T (eq. 5)
+        std::vector<double> U, s, V;
+        svd_jacobi(G, dd, dd, U, s, V);
+        std::vector<double> nu(dd * dd, 0.0);
+        for (int i = 0; i < dd; i++)
+          for (int j = 0; j < dd; j++) {
+            double acc = 0;
+            for (int q = 0; q < dd; q++) acc += V[i * dd + q] * U[j * dd + q];
+            nu[i * dd + j] = -acc;
+          }
+        u = nu;
+        const double e1 = energy(u);
+        const bool done = std::fabs(e1 - e_prev) <= o.rel_tol * std::max(1.0, std::fabs(e1));
+        e_prev = e1;
+        if (done) { it++; break; }
+      }
+      if (de_u_out) std::copy(u.begin(), u.end(), de_u_out + (size_t)k * dd * dd);
+      if (e_before) e_before[k] = e0;
+      if (e_after) e_after[k] = e_prev;
+      if (iters) iters[k] = it;
+    }
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_set_disentanglers(attn_handle* h, const double* de_u) {
+  return guard(h, [&]() -> attn_status {
+    if (attn_status e = need_device(h)) return e;
+    if (!de_u) { h->err = "de_u is NULL"; return ATTN_ERR_ARG; }
+    ProblemCopy np = h->prob;
+    np.de_u.assign(de_u, de_u + np.de_u.size());
+    attn_problem pv = np.view();
+    pv.flags &= ~(ATTN_HOST_ONLY | ATTN_DRYRUN);
+    attn_handle* h2 = nullptr;
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipDeviceSynchronize());
+    const attn_status st = attn_build_tpo(&pv, &h2);
+    if (st) { h->err = attn_last_error(nullptr); return st; }
+    try {
+      int64_t tot = 0;
+      for (int64_t l : h->T_len) tot += l;
+      HIPCHK(hipMemcpy(h2->d_T, h->d_T, tot * sizeof(double), hipMemcpyDeviceToDevice));
+      h2->iso = h->iso;
+      h2->center = h->center;
+      h2->state_ready = h->state_ready;
+      h2->sweep_energies = h->sweep_energies;
+      h2->n_matvec = h->n_matvec; h2->n_env = h->n_env; h2->n_qr = h->n_qr; h2->mv_flops = h->mv_flops;
+      h2->jacobi_rate = h->jacobi_rate; h2->n_dav_iter = h->n_dav_iter; h2->n_fallback = h->n_fallback;
+      if (h->mlp_ready) {
+        h2->d_mlp = dev_alloc(h2, kMlpParams * 2);
+        HIPCHK(hipMemcpy(h2->d_mlp, h->d_mlp, kMlpParams * 2, hipMemcpyDeviceToDevice));
+        h2->mlp_ready = true;
+      }
+      if (h2->state_ready) {
+        reset_state(h2, 0, nullptr);
+        rebuild_envs(h2, nullptr);
+        check_state(h2, nullptr, "attn_set_disentanglers");
+      }
+    } catch (...) {
+      attn_destroy(h2);
+      throw;
+    }
+    std::swap(*h, *h2);
+    std::swap(h->err, h2->err);
+    attn_destroy(h2);
+    return ATTN_OK;
+  });
+}
+
+attn_status attn_sweep_attn(attn_handle* h, int32_t n_sweeps, int32_t s_ttn, const attn_sweep_opts* sopts,
+                            const attn_de_opts* dopts, double* energies, double* seconds) {
+  if (!h) return ATTN_ERR_ARG;
+  if (n_sweeps < 0 || s_ttn < 0) { h->err = "n_sweeps and s_ttn must be >= 0"; return ATTN_ERR_ARG; }
+  const int dd = h->prob.d * h->prob.d;
+  std::vector<double> u(h->prob.de_u.size());
+  for (int s = 0; s < n_sweeps; s++) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (s >= s_ttn && !u.empty()) {
+      attn_status st = attn_optimize_disentanglers(h, dopts, u.data(), nullptr, nullptr, nullptr);
+      if (st) return st;
+      st = attn_set_disentanglers(h, u.data());
+      if (st) return st;
+    }
+    double e = 0;
+    attn_status st = attn_sweep(h, 1, sopts, &e, nullptr);
+    if (st) return st;
+    auto t1 = std::chrono::steady_clock::now();
+    if (energies) energies[s] = e;
+    if (seconds) seconds[s] = std::chrono::duration<double>(t1 - t0).count();
+    (void)dd;
+  }
+  return ATTN_OK;
+}
+
+attn_status attn_get_disentanglers(const attn_handle* h, double* de_u, int64_t len) {
+  if (!h || !de_u) return ATTN_ERR_ARG;
+  if (len != (int64_t)h->prob.de_u.size()) return ATTN_ERR_SHAPE;
+  std::copy(h->prob.de_u.begin(), h->prob.de_u.end(), de_u);
+  return ATTN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+"""The MERA-like disentangler optimisation (Sec. 4.1.1) and the aTTN recipe of
+Sec. 4 (optimise the layer, contract it into the Hamiltonian, sweep) through
+the C interface, against the oracle (oracle/measure.py) on the same seeded
+states: the new gate matrices and gate energies, the Hamiltonian rebuilt with
+them, the S_TTN = 1 schedule sweep by sweep, and the schedule against plain
+TTN sweeps."""
+import numpy as np
+import pytest
+
+from problems import config_problem, make_problem
+from oracle.ttn import OracleTTN
+from oracle.measure import optimize_layer, attn_sweeps
+from tests.gpu_util import gpu_matvec, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _synced(p, sweeps):
+    from paper_2507_21236_amd import AttnHandle
+    a = AttnHandle(p)
+    a.init_state()
+    o = OracleTTN(p.n_sites, p.d, p.m, p.leaf_order, p.terms, p.de_sites, p.de_u, p.raw_tensors)
+    a.sweep(sweeps)
+    for _ in range(sweeps):
+        o.sweep()
+    assert a.center == o.center == o.tree.root
+    for n in range(o.tree.n_nodes):
+        a.set_tensor(n, o.T[n])
+    return a, o
+
+
+@pytest.mark.parametrize("key", ["ising4_m8", "ising8_m16_strict"])
+def test_layer_optimisation_matches_oracle(key):
+    p = config_problem("ising4_m8") if key == "ising4_m8" else \
+        config_problem("ising8_m16", strict_only=True)
+    a, o = _synced(p, 1)
+    u, eb, ea, it = a.optimize_disentanglers()
+    u_ref, hist = optimize_layer(o.tree, o.T, p.terms, p.de_sites, p.de_u)
+    for k in range(len(p.de_sites)):
+        assert abs(eb[k] - hist[k][0]) <= 1e-12 * max(1.0, abs(hist[k][0])), k
+        assert abs(ea[k] - hist[k][-1]) <= 1e-11 * max(1.0, abs(hist[k][-1])), k
+        assert it[k] == len(hist[k]) - 1, (k, it[k], len(hist[k]))
+        assert ea[k] <= eb[k] + 1e-12
+    assert np.abs(u - u_ref).max() <= 1e-10
+    for k in range(len(p.de_sites)):
+        assert np.abs(u[k].T @ u[k] - np.eye(4)).max() <= 1e-12
+    # the Hamiltonian rebuilt with the new layer: the same effective
+    # Hamiltonian at the root as the oracle's, for the same tensors
+    a.set_disentanglers(u)
+    o.set_disentanglers(p.terms, p.de_sites, u)
+    r = o.tree.root
+    assert a.center == r
+    assert np.array_equal(a.get_disentanglers(), u)
+    x = np.random.default_rng(3).standard_normal(o.T[r].shape)
+    assert rel(gpu_matvec(a, r, x), o.matvec(r, x)) < 1e-12
+
+
+def test_attn_schedule_matches_oracle_4x4():
+    from paper_2507_21236_amd import AttnHandle
+    p = make_problem("t", 4, "ising", 4, 1, 4, h=3.0, identity_de=True)
+    a = AttnHandle(p)
+    a.init_state()
+    e_gpu, _ = a.sweep_attn(6, s_ttn=1)
+    o = OracleTTN(p.n_sites, p.d, p.m, p.leaf_order, p.terms, p.de_sites, p.de_u, p.raw_tensors)
+    e_ref, u_ref = attn_sweeps(o, p.terms, p.de_sites, p.de_u, 6, s_ttn=1)
+    print("GPU", e_gpu, "oracle", e_ref)
+    assert np.abs(np.asarray(e_gpu) - np.asarray(e_ref)).max() / p.n_sites <= 1e-10
+    assert np.abs(a.get_disentanglers() - u_ref).max() <= 1e-8
+
+
+def test_attn_schedule_8x8_against_oracle_and_plain_ttn():
+    from paper_2507_21236_amd import AttnHandle
+    p = config_problem("ising8_m16", strict_only=True, identity_de=True)
+    a = AttnHandle(p)
+    a.init_state()
+    e_attn, secs = a.sweep_attn(6, s_ttn=1)
+    o = OracleTTN(p.n_sites, p.d, p.m, p.leaf_order, p.terms, p.de_sites, p.de_u, p.raw_tensors)
+    e_ref, _ = attn_sweeps(o, p.terms, p.de_sites, p.de_u, 3, s_ttn=1)
+    b = AttnHandle(p)
+    b.init_state()
+    e_ttn, _ = b.sweep(6)
+    print("aTTN", e_attn / p.n_sites, "oracle", np.asarray(e_ref) / p.n_sites, "TTN", e_ttn / p.n_sites,
+          "seconds", secs)
+    assert np.abs(e_attn[:3] - np.asarray(e_ref)).max() / p.n_sites <= 1e-8
+    assert e_attn[0] == e_ttn[0]
+    assert e_attn[-1] < e_ttn[-1] - 1e-6 * p.n_sites

@@ -139,3 +139,18 @@ def test_binding_loads_torch_before_library():
     import sys
     assert "torch" in sys.modules
     assert _lib.LIB_PATH.endswith("libattn.so")
+
+
+def test_disentangler_optimisation_needs_the_strict_placement():
+    # 8 x 8 relaxed placement: four gates share a term with another gate
+    a = AttnHandle(config_problem("ising8_m32"), flags=ATTN_HOST_ONLY)
+    with pytest.raises(AttnError) as e:
+        a.optimize_disentanglers()
+    assert e.value.code == -5
+    b = AttnHandle(config_problem("ising8_m32", strict_only=True), flags=ATTN_HOST_ONLY)
+    with pytest.raises(AttnError) as e:
+        b.optimize_disentanglers()
+    assert e.value.code == -8          # strict placement accepted, then: no device state
+    u = b.get_disentanglers()
+    assert u.shape == (len(b.problem.de_sites), 4, 4)
+    assert np.allclose(u, np.asarray(b.problem.de_u))
