@@ -478,8 +478,8 @@ attn_status attn_correlation(attn_handle* h, const double* oa, const double* ob,
  * (de_u_out, [n_de][d^2][d^2] row-major, the layout of attn_problem.de_u),
  * and per gate the energy of its terms before and after and the number of
  * steps (any output may be NULL).  The handle keeps its disentanglers: apply
- * the result with attn_set_disentanglers.  opts may be NULL (20 steps,
- * rel_tol 1e-12, shift on).  Errors: ARG, STATE, DE_RESTRICTION, HIP.
+ * the result with attn_set_disentanglers.  opts may be NULL (MERA-like,
+ * 20 steps, rel_tol 1e-12, shift on).  Errors: ARG, STATE, DE_RESTRICTION, HIP.
  *
  * attn_set_disentanglers: replaces the disentangler matrices (same sites):
  * the rotated TPO is rebuilt (attn_build_tpo on the stored problem), the TTN
@@ -497,10 +497,22 @@ attn_status attn_correlation(attn_handle* h, const double* oa, const double* ob,
  * attn_get_disentanglers: the current matrices (len = n_de d^4 values).
  */
 typedef struct attn_de_opts {
-  int32_t max_iter;   /* self-consistent steps per gate (20) */
+  int32_t max_iter;   /* steps per gate (20) */
   double rel_tol;     /* stop at |dE| <= rel_tol * max(1, |E|) (1e-12) */
-  int32_t shift;      /* 1: shifted terms (monotone steps); 0: plain linearisation */
+  int32_t shift;      /* MERA-like: 1 shifted terms (monotone steps); 0 plain linearisation */
+  int32_t method;     /* ATTN_DE_MERA (default) or ATTN_DE_RCG */
 } attn_de_opts;
+
+/* attn_de_opts.method.  ATTN_DE_RCG: gradient optimisation of Sec. 4.1.2, both
+ * copies of u_k varied together, as Riemannian conjugate gradient on the
+ * orthogonal group (the paper names Riemannian nonlinear CG): skew directions
+ * in the frame of u, Polak-Ribiere+ coefficient, steps u <- u cay(t D) with
+ * cay(X) = (I - X/2)^-1 (I + X/2) and t halved from 1 until the Armijo
+ * condition E_new <= E + 1e-4 t <g, D> holds, restart along -g when D is not
+ * a descent direction; the energy never rises.  Real orthogonal gates only:
+ * every tensor of this library is real. */
+#define ATTN_DE_MERA 0
+#define ATTN_DE_RCG  1
 
 attn_status attn_optimize_disentanglers(attn_handle* h, const attn_de_opts* opts, double* de_u_out,
                                         double* e_before, double* e_after, int32_t* iters);

@@ -207,16 +207,21 @@ def term_norm_bound(terms):
     return float(sum(abs(c) * np.prod([np.linalg.norm(o, 2) for o in ops]) for _, ops, c in terms))
 
 
-def optimize_layer(tree, T, terms, de_sites, de_u, max_iter=20, rel_tol=1e-12, use_shift=True, d=2):
+def optimize_layer(tree, T, terms, de_sites, de_u, max_iter=20, rel_tol=1e-12, use_shift=True, d=2,
+                   method="mera"):
     """Every disentangler of the layer optimised with the others fixed (they
     act on other terms only, Sec. 4.1), from the TTN state T (centre at the
-    root).  Returns (new de_u, per-gate energy histories)."""
+    root), by the MERA-like update ("mera", Sec. 4.1.1) or Riemannian CG
+    ("rcg", Sec. 4.1.2).  Returns (new de_u, per-gate energy histories)."""
     new_u = np.array(de_u, dtype=float, copy=True)
     hist = []
     for k in range(len(de_sites)):
         parts, rho = de_environment_parts(tree, T, terms, de_sites, k, d)
-        c = term_norm_bound(de_terms(terms, de_sites, k)) if use_shift else 0.0
-        u, es = optimize_disentangler(parts, rho, de_u[k], c, max_iter, rel_tol)
+        if method == "rcg":
+            u, es = optimize_disentangler_rcg(parts, de_u[k], max_iter, rel_tol)
+        else:
+            c = term_norm_bound(de_terms(terms, de_sites, k)) if use_shift else 0.0
+            u, es = optimize_disentangler(parts, rho, de_u[k], c, max_iter, rel_tol)
         new_u[k] = u
         hist.append(es)
     return new_u, hist
@@ -239,3 +244,67 @@ def attn_sweeps(o, terms, de_sites, de_u0, n_sweeps, s_ttn=1, max_iter=20, rel_t
             o.set_disentanglers(terms, de_sites, de_u, compress)
         es.append(o.sweep())
     return es, de_u
+
+
+# ---------------------------------------------------------------- gradient-based optimisation (Sec. 4.1.2)
+def de_euclid_grad(parts, u):
+    """Gradient of E(u) = sum Tr(u sigma u^T Q) in both copies of u at once:
+    dE = Tr(G^T du) with G = sum (Q^T u sigma^T + Q u sigma)."""
+    return sum(Q.T @ u @ s.T + Q @ u @ s for s, Q in parts)
+
+
+def de_riem_grad(parts, u):
+    """Riemannian gradient on the orthogonal group, written in the frame of u:
+    the tangent vector is u Omega with Omega = skew(u^T G)."""
+    A = u.T @ de_euclid_grad(parts, u)
+    return 0.5 * (A - A.T)
+
+
+def cayley(X):
+    """(I - X/2)^-1 (I + X/2): orthogonal for skew-symmetric X (the Cayley
+    retraction of the orthogonal group)."""
+    n = X.shape[0]
+    return np.linalg.solve(np.eye(n) - 0.5 * X, np.eye(n) + 0.5 * X)
+
+
+def optimize_disentangler_rcg(parts, u0, max_iter=50, rel_tol=1e-12):
+    """Riemannian conjugate gradient on O(d^2) (Sec. 4.1.2: both copies of
+    u_k are varied together and the constraint u^T u = 1 is kept by the
+    geometry; the paper points to Riemannian nonlinear CG).  Directions are
+    skew matrices Omega (tangent vectors u Omega, carried between points by
+    the group translation); Polak-Ribiere+ coefficient; steps u <- u
+    cay(t D) with t halved from 1 until the Armijo condition
+    E(new) <= E + 1e-4 t <g, D> holds; restart along -g when D is not a
+    descent direction.  Stops when the energy changes by at most
+    rel_tol max(1, |E|).  Returns (u, energies)."""
+    u = np.asarray(u0, dtype=float)
+    E = de_energy(parts, u)
+    es = [E]
+    g = de_riem_grad(parts, u)
+    D = -g
+    for _ in range(max_iter):
+        gg = float(np.sum(g * g))
+        if gg == 0.0:
+            break
+        slope = float(np.sum(g * D))
+        if slope >= 0.0:
+            D = -g
+            slope = -gg
+        t = 1.0
+        while True:
+            un = u @ cayley(t * D)
+            En = de_energy(parts, un)
+            if En <= E + 1e-4 * t * slope or t < 1e-12:
+                break
+            t *= 0.5
+        if En > E:
+            break
+        gn = de_riem_grad(parts, un)
+        beta = max(0.0, float(np.sum(gn * (gn - g))) / gg)
+        D = -gn + beta * D
+        done = abs(En - E) <= rel_tol * max(1.0, abs(En))
+        u, E, g = un, En, gn
+        es.append(E)
+        if done:
+            break
+    return u, es

@@ -71,7 +71,11 @@ class attn_sweep_opts(ctypes.Structure):
 
 
 class attn_de_opts(ctypes.Structure):
-    _fields_ = [("max_iter", ctypes.c_int32), ("rel_tol", ctypes.c_double), ("shift", ctypes.c_int32)]
+    _fields_ = [("max_iter", ctypes.c_int32), ("rel_tol", ctypes.c_double), ("shift", ctypes.c_int32),
+                ("method", ctypes.c_int32)]
+
+
+ATTN_DE_MERA, ATTN_DE_RCG = 0, 1
 
 
 class attn_batch_opts(ctypes.Structure):
@@ -444,8 +448,8 @@ def attn_correlation(h, oa, ob, n_sites):
     return C
 
 
-def de_opts(max_iter=20, rel_tol=1e-12, shift=True):
-    return attn_de_opts(max_iter, rel_tol, int(shift))
+def de_opts(max_iter=20, rel_tol=1e-12, shift=True, method=ATTN_DE_MERA):
+    return attn_de_opts(max_iter, rel_tol, int(shift), method)
 
 
 def attn_optimize_disentanglers(h, n_de, d=2, opts=None):

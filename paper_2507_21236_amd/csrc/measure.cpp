@@ -750,8 +750,9 @@ attn_status attn_optimize_disentanglers(attn_handle* h, const attn_de_opts* opts
     const int nde = (int)P.de_sites.size() / 2;
     attn_de_opts o;
     if (opts) o = *opts;
-    else { o.max_iter = 20; o.rel_tol = 1e-12; o.shift = 1; }
+    else { o.max_iter = 20; o.rel_tol = 1e-12; o.shift = 1; o.method = ATTN_DE_MERA; }
     if (o.max_iter < 0) { h->err = "max_iter < 0"; return ATTN_ERR_ARG; }
+    if (o.method != ATTN_DE_MERA && o.method != ATTN_DE_RCG) { h->err = "unknown method"; return ATTN_ERR_ARG; }
     std::vector<std::vector<DeTerm>> gt;
     if (attn_status e = gate_terms(P, gt, h->err)) return e;
     if (attn_status e = need_device(h)) return e;
@@ -821,7 +822,98 @@ attn_status attn_optimize_disentanglers(attn_handle* h, const attn_de_opts* opts
       };
       double e0 = energy(u), e_prev = e0;
       int it = 0;
-      for (; it < o.max_iter; it++) {
+      if (o.method == ATTN_DE_RCG) {
+        // Riemannian gradient in the frame of u: Omega = skew(u^T G), with the
+        // gradient of E in both copies G = sum_t (Q_t^T u sigma_t^T + Q_t u sigma_t)
+        auto rgrad = [&](const std::vector<double>& uu) {
+          std::vector<double> G(dd * dd, 0.0), t1(dd * dd), t2(dd * dd), qt(dd * dd), st(dd * dd);
+          for (int t = 0; t < nt; t++) {
+            transpose(gt[k][t].Q.data(), qt.data(), dd);
+            transpose(sig[t].data(), st.data(), dd);
+            matmul(qt.data(), uu.data(), t1.data(), dd);
+            matmul(t1.data(), st.data(), t2.data(), dd);
+            for (int i = 0; i < dd * dd; i++) G[i] += t2[i];
+            matmul(gt[k][t].Q.data(), uu.data(), t1.data(), dd);
+            matmul(t1.data(), sig[t].data(), t2.data(), dd);
+            for (int i = 0; i < dd * dd; i++) G[i] += t2[i];
+          }
+          std::vector<double> ut(dd * dd), A(dd * dd), W(dd * dd);
+          transpose(uu.data(), ut.data(), dd);
+          matmul(ut.data(), G.data(), A.data(), dd);
+          for (int i = 0; i < dd; i++)
+            for (int j = 0; j < dd; j++) W[i * dd + j] = 0.5 * (A[i * dd + j] - A[j * dd + i]);
+          return W;
+        };
+        // u cay(X), cay(X) = (I - X/2)^-1 (I + X/2) by Gaussian elimination with partial pivoting
+        auto retract = [&](const std::vector<double>& uu, const std::vector<double>& X) {
+          std::vector<double> L(dd * dd), R(dd * dd);
+          for (int i = 0; i < dd; i++)
+            for (int j = 0; j < dd; j++) {
+              L[i * dd + j] = (i == j ? 1.0 : 0.0) - 0.5 * X[i * dd + j];
+              R[i * dd + j] = (i == j ? 1.0 : 0.0) + 0.5 * X[i * dd + j];
+            }
+          for (int c = 0; c < dd; c++) {
+            int pv = c;
+            for (int r = c + 1; r < dd; r++)
+              if (std::fabs(L[r * dd + c]) > std::fabs(L[pv * dd + c])) pv = r;
+            if (pv != c)
+              for (int j = 0; j < dd; j++) { std::swap(L[c * dd + j], L[pv * dd + j]); std::swap(R[c * dd + j], R[pv * dd + j]); }
+            for (int r = c + 1; r < dd; r++) {
+              const double f = L[r * dd + c] / L[c * dd + c];
+              for (int j = 0; j < dd; j++) { L[r * dd + j] -= f * L[c * dd + j]; R[r * dd + j] -= f * R[c * dd + j]; }
+            }
+          }
+          std::vector<double> C(dd * dd);
+          for (int j = 0; j < dd; j++)
+            for (int r = dd - 1; r >= 0; r--) {
+              double acc = R[r * dd + j];
+              for (int q = r + 1; q < dd; q++) acc -= L[r * dd + q] * C[q * dd + j];
+              C[r * dd + j] = acc / L[r * dd + r];
+            }
+          std::vector<double> out(dd * dd);
+          matmul(uu.data(), C.data(), out.data(), dd);
+          return out;
+        };
+        auto dot = [&](const std::vector<double>& a, const std::vector<double>& b) {
+          double acc = 0;
+          for (int i = 0; i < dd * dd; i++) acc += a[i] * b[i];
+          return acc;
+        };
+        std::vector<double> g = rgrad(u), D(dd * dd);
+        for (int i = 0; i < dd * dd; i++) D[i] = -g[i];
+        double E = e0;
+        for (; it < o.max_iter; it++) {
+          const double gg = dot(g, g);
+          if (gg == 0.0) break;
+          double slope = dot(g, D);
+          if (slope >= 0.0) {
+            for (int i = 0; i < dd * dd; i++) D[i] = -g[i];
+            slope = -gg;
+          }
+          double t = 1.0, En;
+          std::vector<double> un, X(dd * dd);
+          while (true) {
+            for (int i = 0; i < dd * dd; i++) X[i] = t * D[i];
+            un = retract(u, X);
+            En = energy(un);
+            if (En <= E + 1e-4 * t * slope || t < 1e-12) break;
+            t *= 0.5;
+          }
+          if (En > E) break;
+          std::vector<double> gn = rgrad(un);
+          double num = 0;
+          for (int i = 0; i < dd * dd; i++) num += gn[i] * (gn[i] - g[i]);
+          const double beta = std::max(0.0, num / gg);
+          for (int i = 0; i < dd * dd; i++) D[i] = -gn[i] + beta * D[i];
+          const bool done = std::fabs(En - E) <= o.rel_tol * std::max(1.0, std::fabs(En));
+          u = un;
+          E = En;
+          g = gn;
+          if (done) { it++; break; }
+        }
+        e_prev = E;
+      }
+      for (; o.method == ATTN_DE_MERA && it < o.max_iter; it++) {
         // Gamma = sum_t sigma_t u^T Q_t - c rho u^T  (eq. 4, bra copy fixed)
         std::vector<double> ut(dd * dd), G(dd * dd, 0.0), t1(dd * dd), t2(dd * dd);
         transpose(u.data(), ut.data(), dd);

@@ -84,3 +84,19 @@ def test_attn_schedule_8x8_against_oracle_and_plain_ttn():
     assert np.abs(e_attn[:3] - np.asarray(e_ref)).max() / p.n_sites <= 1e-8
     assert e_attn[0] == e_ttn[0]
     assert e_attn[-1] < e_ttn[-1] - 1e-6 * p.n_sites
+
+
+def test_riemannian_cg_matches_oracle():
+    # the gradient variant of Sec. 4.1.2 (Riemannian CG on the orthogonal group)
+    from paper_2507_21236_amd import de_opts
+    from paper_2507_21236_amd._lib import ATTN_DE_RCG
+    p = config_problem("ising8_m16", strict_only=True)
+    a, o = _synced(p, 1)
+    u, eb, ea, it = a.optimize_disentanglers(de_opts(max_iter=40, method=ATTN_DE_RCG))
+    u_ref, hist = optimize_layer(o.tree, o.T, p.terms, p.de_sites, p.de_u, max_iter=40, method="rcg")
+    for k in range(len(p.de_sites)):
+        assert abs(eb[k] - hist[k][0]) <= 1e-12 * max(1.0, abs(hist[k][0])), k
+        assert abs(ea[k] - hist[k][-1]) <= 1e-10 * max(1.0, abs(hist[k][-1])), k
+        assert ea[k] <= eb[k] + 1e-12
+    assert np.abs(u - u_ref).max() <= 1e-8
+    print("gate energy changes", ea - eb, "steps", it)

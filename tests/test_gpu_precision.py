@@ -100,35 +100,44 @@ def test_lowp_sweeps_8x8_m16_track_fp64():
 
 
 
-def test_sweeps_8x8_m32_against_oracle_golden():
-    # 8 x 8 Ising, h = 3.05, m = 32, 16 gates, 8 sweeps, against the FP64
-    # oracle's energies (tests/golden, written by make_reference.py from the
-    # oracle only).  FP64 follows the oracle's trajectory to rounding.  The
-    # FP32 and split BF16 forms keep the Krylov recurrences, the Rayleigh
-    # quotient, the projected eigenproblem and QR in FP64, so the energy they
-    # report is the FP64 energy of the state they produced (checked against
-    # the FP64 Rayleigh quotient at the centre); their trajectories separate
-    # from the FP64 one by rounding amplification, bounded as in the test above.
+def test_sweeps_8x8_m32_converged_against_oracle():
+    # 8 x 8 Ising, h = 3.05, m = 32, 16 gates, swept from the seeded start as
+    # long as the oracle needed to settle (consecutive changes below 1e-10 per
+    # site after 71 sweeps; tests/golden, written by make_reference.py from
+    # the oracle only), each form from the same start:
+    # * FP64 follows the oracle's trajectory: every sweep within 1e-12 relative;
+    # * FP32 operands (the form this workload states a bound for): the
+    #   converged energy within 1e-6 relative of the oracle's;
+    # * split BF16 settles in another stationary point of the single-tensor
+    #   sweep (FP64 sweeps started from its state stop at once, moving the
+    #   energy by 1e-10 relative): its converged energy is only held to 1e-4.
+    # Every form keeps the Krylov recurrences, the Rayleigh quotient, the
+    # projected eigenproblem and QR in FP64, so the energy it reports is the
+    # FP64 energy of the state it produced (checked at the centre).
     import json
     import os
     from paper_2507_21236_amd import AttnHandle, solver_opts, ATTN_F64
     from tests.gpu_util import gpu_matvec
     p = config_problem("ising8_m32")
-    with open(os.path.join(os.path.dirname(__file__), "golden", "ising8_m32_oracle.json")) as f:
-        gold = np.asarray(json.load(f)["energies"])
-    assert len(gold) == 8
+    with open(os.path.join(os.path.dirname(__file__), "golden", "ising8_m32_oracle_converged.json")) as f:
+        rec = json.load(f)
+    gold = np.asarray(rec["energies"])
+    assert rec["stop"].startswith("consecutive") and len(gold) == 71
+    e_inf = gold[-1]
+    bound = {"f32": 1e-6, "bf16x2": 1e-4}
     for name, dt in [("f64", ATTN_F64)] + _forms():
         a = AttnHandle(p)
         a.init_state()
-        e, _ = a.sweep(8, solver_opts(krylov_k=20, precision=dt))
-        r = np.abs(np.asarray(e) - gold) / np.abs(gold)
+        e, _ = a.sweep(len(gold), solver_opts(krylov_k=20, precision=dt))
         n = a.center
         t = a.get_tensor(n)
         rq = float(np.vdot(t, gpu_matvec(a, n, t)) / np.vdot(t, t))
-        print(f"{name}: relative energy difference to the oracle per sweep",
-              " ".join(f"{x:.1e}" for x in r), f"; reported vs FP64 Rayleigh quotient {abs(e[-1] - rq) / abs(rq):.1e}")
+        r_inf = (e[-1] - e_inf) / abs(e_inf)
+        print(f"{name}: converged energy {e[-1]:.12f}, relative to the oracle's {r_inf:.2e}; "
+              f"reported vs FP64 Rayleigh quotient {abs(e[-1] - rq) / abs(rq):.1e}")
         assert abs(e[-1] - rq) <= 1e-12 * abs(rq), (name, e[-1], rq)
         if name == "f64":
+            r = np.abs(np.asarray(e) - gold) / np.abs(gold)
             assert r.max() <= 1e-12, r
         else:
-            assert r.max() <= 10 * TOL[name], (name, r)
+            assert abs(r_inf) <= bound[name], (name, r_inf)

@@ -163,3 +163,41 @@ def test_attn_schedule_beats_plain_ttn():
     assert e_attn[-1] < e_ttn[-1] - 1e-6
     from oracle.ed import ground_energy
     assert e_attn[-1] >= ground_energy(p.terms, 16) - 1e-10
+
+
+def test_riemannian_gradient_matches_finite_differences():
+    from oracle.measure import de_riem_grad, cayley
+    p = config_problem("ising4_m8")
+    o = _oracle(p)
+    parts, _ = de_environment_parts(o.tree, o.T, p.terms, p.de_sites, 0)
+    rng = np.random.default_rng(7)
+    u = haar_orthogonal(rng, 4)
+    g = de_riem_grad(parts, u)
+    assert np.abs(g + g.T).max() <= 1e-15
+    for _ in range(5):
+        X = rng.standard_normal((4, 4))
+        X = X - X.T
+        h = 1e-6
+        fd = (de_energy(parts, u @ cayley(h * X)) - de_energy(parts, u @ cayley(-h * X))) / (2 * h)
+        assert abs(fd - float(np.sum(g * X))) <= 1e-7 * max(1.0, abs(fd))
+        assert np.abs(cayley(X).T @ cayley(X) - np.eye(4)).max() <= 1e-13
+
+
+def test_rcg_reaches_a_stationary_point_without_raising_the_energy():
+    from oracle.measure import optimize_disentangler_rcg, de_riem_grad
+    p = config_problem("ising4_m8")
+    o = _oracle(p)
+    for k in range(len(p.de_sites)):
+        parts, rho = de_environment_parts(o.tree, o.T, p.terms, p.de_sites, k)
+        u, es = optimize_disentangler_rcg(parts, p.de_u[k], max_iter=200, rel_tol=1e-15)
+        assert np.all(np.diff(es) <= 1e-13 * max(1.0, abs(es[0]))), k
+        assert np.abs(u.T @ u - np.eye(4)).max() <= 1e-12
+        g = de_riem_grad(parts, u)
+        assert np.abs(g).max() <= 1e-5 * max(1.0, abs(es[-1])), (k, np.abs(g).max())
+        # a local minimum: no small rotation lowers the energy
+        rng = np.random.default_rng(k)
+        from oracle.measure import cayley
+        for _ in range(20):
+            X = rng.standard_normal((4, 4))
+            X = 1e-3 * (X - X.T)
+            assert de_energy(parts, u @ cayley(X)) >= es[-1] - 1e-10
