@@ -404,6 +404,8 @@ def main():
                     help="only apply H_eff once at every node with two legs of dimension 64 (the "
                          "launches of the dominant kernel in a sweep), on a stream of its own, "
                          "for HBM counter runs")
+    ap.add_argument("--probe-precision", default="f64", choices=["f64", "f32", "bf16x2"],
+                    help="operand precision of the --traffic-probe matvecs")
     ap.add_argument("--node-reps", type=int, default=100,
                     help="timed H_eff applications per full node after the sweeps (0 to skip)")
     ap.add_argument("--learned-tol", type=float, default=1e-5,
@@ -451,14 +453,19 @@ def main():
         side = torch.cuda.Stream()
         gen = torch.Generator(device="cuda").manual_seed(0)
         nodes = [n for n in range(a.n_nodes) if tuple(a.node_info(n)[0][:2]) == (64, 64)]
+        pdt = prec[args.probe_precision]
+        tdt = torch.float64 if pdt == ATTN_F64 else torch.float32
         for n in nodes:
             a.move_center(n)
             dims = a.node_info(n)[0]
-            x = torch.randn(int(dims[0]) * int(dims[1]) * int(dims[2]), dtype=torch.float64,
+            x = torch.randn(int(dims[0]) * int(dims[1]) * int(dims[2]), dtype=tdt,
                             device="cuda", generator=gen)
             y = torch.empty_like(x)
             torch.cuda.synchronize()
-            a.heff_apply(n, x, y, stream=side.cuda_stream)
+            if pdt != ATTN_F64:   # first call converts the operator mirrors (not part of the probe)
+                a.heff_apply(n, x, y, dtype=pdt)
+                torch.cuda.synchronize()
+            a.heff_apply(n, x, y, dtype=pdt, stream=side.cuda_stream)
             torch.cuda.synchronize()
         print(f"[bench] traffic probe: H_eff applied once at {len(nodes)} nodes {nodes}",
               file=sys.stderr, flush=True)

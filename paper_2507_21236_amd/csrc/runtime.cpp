@@ -664,6 +664,94 @@ void* to_mirror(attn_handle* h, const void* p, int fmt) {
   throw StatusFail{ATTN_ERR_STATE, "internal: block outside every store"};
 }
 
+// The wave-per-slice split-BF16 kernel keeps two workgroups resident per CU
+// (its LDS double buffer), so a launch takes ceil(W / 512) rounds of W
+// workgroups.  Its tasks (copied from the FP64 plan, W = tasks x slices / 4)
+// are re-cut into fewer, longer item ranges so that W is a multiple of 512:
+// per class of tasks with the same slice geometry, the items are shared out
+// over fewer tasks in proportion to the class's item count, each new task
+// writing the partial output of one of the class's old tasks; the outputs
+// left unwritten are added to `dropped`.
+void rechunk_bf2w(SWGroup& g, std::vector<int>& ns_of, std::vector<RDSrc>& srcs, std::vector<const void*>& dropped) {
+  (void)srcs;
+  const int nt = (int)g.tasks.size();
+  if (nt == 0) return;
+  for (const SWTask& t : g.tasks)
+    if (t.pad) return;
+  int64_t W = 0;
+  for (int t = 0; t < nt; t++) W += (ns_of[t] + 3) / 4;
+  const int64_t kRound = 512;
+  if (W <= kRound || W % kRound == 0) return;
+  const int64_t Wt = kRound * (W / kRound);
+  // classes of tasks with one slice geometry (consecutive in task order)
+  std::vector<std::vector<int>> cls;
+  for (int t = 0; t < nt; t++) {
+    const SWTask& a = g.tasks[t];
+    bool found = false;
+    for (auto& c : cls) {
+      const SWTask& b = g.tasks[c[0]];
+      if (a.x == b.x && a.xs_slice == b.xs_slice && a.xs_row == b.xs_row && a.ys_slice == b.ys_slice &&
+          a.ys_row == b.ys_row && ns_of[t] == ns_of[c[0]] && a.accumulate == b.accumulate) {
+        c.push_back(t);
+        found = true;
+        break;
+      }
+    }
+    if (!found) cls.push_back({t});
+  }
+  const int nc = (int)cls.size();
+  std::vector<int64_t> items(nc, 0), units(nc, 0);
+  int64_t tot_items = 0;
+  for (int c = 0; c < nc; c++) {
+    for (int t : cls[c]) items[c] += g.tasks[t].nitem;
+    units[c] = (ns_of[cls[c][0]] + 3) / 4;
+    tot_items += items[c];
+  }
+  // tasks per class: the workgroup target in proportion to item counts
+  std::vector<int> keep(nc, 1);
+  int64_t used = 0;
+  for (int c = 0; c < nc; c++) used += units[c];
+  for (int c = 0; c < nc; c++) {
+    const int64_t want = Wt * items[c] / std::max<int64_t>(1, tot_items) / units[c];
+    keep[c] = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cls[c].size(), want));
+  }
+  int64_t w = 0;
+  for (int c = 0; c < nc; c++) w += keep[c] * units[c];
+  for (int guard = 0; w < Wt && guard < 4096; guard++) {   // top up the classes with the most items per task
+    int best = -1;
+    for (int c = 0; c < nc; c++)
+      if (keep[c] < (int)cls[c].size() && w + units[c] <= Wt &&
+          (best < 0 || items[c] * keep[best] > items[best] * keep[c]))
+        best = c;
+    if (best < 0) break;
+    keep[best]++;
+    w += units[best];
+  }
+  if (w % kRound != 0) return;   // no exact cut: keep the plan as it is
+  std::vector<SWTask> tasks;
+  std::vector<SWItem> its;
+  std::vector<int> nns;
+  for (int c = 0; c < nc; c++) {
+    std::vector<SWItem> ci;
+    for (int t : cls[c])
+      for (int i = g.tasks[t].item0; i < g.tasks[t].item0 + g.tasks[t].nitem; i++) ci.push_back(g.items[i]);
+    const int k = keep[c];
+    for (int j = 0; j < k; j++) {
+      SWTask t = g.tasks[cls[c][j]];
+      const size_t i0 = ci.size() * j / k, i1 = ci.size() * (j + 1) / k;
+      t.item0 = (int)its.size();
+      t.nitem = (int)(i1 - i0);
+      its.insert(its.end(), ci.begin() + i0, ci.begin() + i1);
+      tasks.push_back(t);
+      nns.push_back(ns_of[cls[c][j]]);
+    }
+    for (size_t j = k; j < cls[c].size(); j++) dropped.push_back(g.tasks[cls[c][j]].y);
+  }
+  g.tasks.swap(tasks);
+  g.items.swap(its);
+  ns_of.swap(nns);
+}
+
 // Build the mirrors and the work lists of precision form `dtype` (1 = FP32,
 // 2 = split BF16; the latter runs its mode products and the sandwich groups
 // whose legs are not multiples of 32 in FP32).
@@ -688,6 +776,8 @@ void ensure_lowp(attn_handle* h, int dtype) {
     L.need_xt = D.need_xt;
     std::copy(D.dims, D.dims + 3, L.dims);
     L.sw = D.sw;
+    L.srcs = D.srcs;
+    std::vector<const void*> dropped;   // partial outputs no task of this form writes
     for (auto& g : L.sw) {
       bool bf = dtype == 2 && sw_bf16(g.ma, g.mb);
       if (bf)
@@ -700,6 +790,7 @@ void ensure_lowp(attn_handle* h, int dtype) {
         // one slice per wave: units of up to four consecutive slices of a task
         std::vector<int> ns_of(g.tasks.size(), 0);
         for (const int4& wu : g.wus) ns_of[wu.x] = std::max(ns_of[wu.x], wu.y + 1);
+        rechunk_bf2w(g, ns_of, L.srcs, dropped);
         std::vector<int4> w2;
         for (size_t ti = 0; ti < g.tasks.size(); ti++)
           for (int s0 = 0; s0 < ns_of[ti]; s0 += 4) w2.push_back(make_int4((int)ti, s0, 0, std::min(4, ns_of[ti] - s0)));
@@ -714,7 +805,12 @@ void ensure_lowp(attn_handle* h, int dtype) {
       for (auto& g : *dst[k])
         for (auto& jb : g.jobs) jb.A = to_mirror(h, jb.A, 1);
     }
-    L.srcs = D.srcs;
+    if (!dropped.empty()) {
+      std::vector<RDSrc> keep;
+      for (const RDSrc& r : L.srcs)
+        if (std::find(dropped.begin(), dropped.end(), r.p) == dropped.end()) keep.push_back(r);
+      L.srcs.swap(keep);
+    }
     upload_sw(h, L.sw, true);
     upload_mp(h, L.chainA);
     upload_mp(h, L.chainB);

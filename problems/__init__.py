@@ -95,6 +95,9 @@ CONFIGS = {
     "heis16_m96": dict(L=16, model="heisenberg_tri", h=0.0, m=96, seed=4, n_de=64, sweeps=6),
     # 32x32 Ising, h = 3.05, m = 128, 256 disentanglers, seed 5
     "ising32_m128": dict(L=32, model="ising", h=3.05, m=128, seed=5, n_de=256, sweeps=3),
+    # 16x16 Ising at m = 128: the (128, 128, 128) node shape of the 32x32 workload
+    # on a lattice the oracle can hold in memory
+    "ising16_m128": dict(L=16, model="ising", h=3.0, m=128, seed=16, n_de=64, sweeps=3),
 }
 
 
