@@ -171,24 +171,38 @@ def test_matvec_heaviest_node_16x16():
 
 
 def test_sweeps_16x16_track_oracle_golden():
-    # whole sweeps of the 16 x 16, m = 64 workload against the oracle's sweep
-    # energies (tests/golden, written by make_reference.py from the oracle only).
-    # Node by node the two agree to rounding (test above); over a sweep the
-    # single-site updates amplify rounding through ill-conditioned centre
-    # matricisations, so the bound is set well above the observed ~1e-6 per site
-    # and well below the ~1e-1 per site changes between sweeps
+    # Whole sweeps of the 16 x 16, m = 64 workload against the oracle's sweep
+    # energies (tests/golden, make_reference.py; oracle only).  How close two
+    # correct FP64 trajectories stay over whole sweeps is measured on the
+    # oracle itself (make_perturbed.py): runs whose initial tensors differ by
+    # 1e-15 and 1e-13 relative separate from the unperturbed run by up to
+    # 2.3e-6, 2.9e-6 and 1.5e-6 per site in sweeps 1-3 (node by node the
+    # separation grows from 1e-14 at the first node to 1e-12 by node 55,
+    # 1e-10 by node 114 and 1e-6 at the root: the single-tensor updates
+    # amplify rounding).  The GPU, whose matvec and eigenvalue agree with the
+    # oracle's to 1e-14 at every node of a sweep given the same tensors
+    # (test_sweep_16x16_every_node_with_resync), is held to four times the
+    # largest oracle-to-oracle separation seen up to each sweep.
     import json
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "ising16_m64_oracle.json")
-    ref = json.load(open(path))["energies"]
+    g = os.path.join(os.path.dirname(__file__), "golden")
+    ref = json.load(open(os.path.join(g, "ising16_m64_oracle.json")))["energies"]
+    env, sep = [], 0.0
+    for s_ in range(len(ref)):
+        for eps in ("1e-15", "1e-13"):
+            e = json.load(open(os.path.join(g, f"ising16_m64_oracle_eps{eps}.json")))["energies"]
+            sep = max(sep, abs(e[s_] - ref[s_]) / 256)
+        env.append(sep)
     p = config_problem("ising16_m64")
     from paper_2507_21236_amd import AttnHandle
     a = AttnHandle(p)
     a.init_state()
     e, _ = a.sweep(len(ref))
-    for s, (x, y) in enumerate(zip(e, ref)):
-        print(f"sweep {s}: GPU {x:.10f} oracle {y:.10f} |dE|/N {abs(x - y) / p.n_sites:.2e}")
-        assert abs(x - y) / p.n_sites < 1e-5, (s, x, y)
+    for s_, (x, y) in enumerate(zip(e, ref)):
+        d = abs(x - y) / p.n_sites
+        print(f"sweep {s_}: GPU {x:.10f} oracle {y:.10f} |dE|/N {d:.2e} (oracle vs perturbed oracle "
+              f"up to {env[s_]:.2e})")
+        assert d <= 4 * env[s_], (s_, x, y, env[s_])
 
 
 def test_sweeps_4x4_against_exact_diagonalisation():
