@@ -274,6 +274,69 @@ def compressed_form(sweeps):
     return out
 
 
+def attn_recipe(sweeps):
+    """The aTTN ground-state recipe of Sec. 4 on the 16 x 16 Ising workload
+    with the strict placement (48 gates, no term on two gates), starting
+    from identity gates: S_TTN = 1 (one plain TTN sweep, then the layer
+    optimised by the MERA-like update before every sweep, Sec. 6.3) against
+    plain TTN sweeps from the same state; and the observables of the final
+    state (one magnetisation, the 256 x 256 ZZ correlation matrix)."""
+    import numpy as np
+    import torch
+    from problems import config_problem
+    from problems.models import PZ, PX
+    from paper_2507_21236_amd import AttnHandle, solver_opts, de_opts
+    p = config_problem("ising16_m64", strict_only=True, identity_de=True)
+    N = p.n_sites
+    a = AttnHandle(p)
+    a.init_state()
+    t0 = time.perf_counter()
+    e_attn, s_attn = a.sweep_attn(sweeps, s_ttn=1, opts=solver_opts(krylov_k=20), dopts=de_opts())
+    torch.cuda.synchronize()
+    t_attn = time.perf_counter() - t0
+    # one more layer update alone, timed (environment on the GPU + update + rebuild)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    u, eb, ea, it = a.optimize_disentanglers(de_opts())
+    torch.cuda.synchronize()
+    t_opt = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    a.set_disentanglers(u)
+    torch.cuda.synchronize()
+    t_set = time.perf_counter() - t2
+    t3 = time.perf_counter()
+    mx = a.measure([[(s, PX)] for s in range(N)])
+    torch.cuda.synchronize()
+    t_meas = time.perf_counter() - t3
+    t4 = time.perf_counter()
+    C = a.correlation(PZ, PZ)
+    torch.cuda.synchronize()
+    t_corr = time.perf_counter() - t4
+    b = AttnHandle(p)
+    b.init_state()
+    t5 = time.perf_counter()
+    e_ttn, _ = b.sweep(sweeps, solver_opts(krylov_k=20))
+    torch.cuda.synchronize()
+    t_ttn = time.perf_counter() - t5
+    a.close()
+    b.close()
+    print(f"[bench] aTTN recipe: {sweeps} sweeps {t_attn:.2f} s, E/N {e_attn[-1] / N:.8f} vs TTN "
+          f"{e_ttn[-1] / N:.8f}; layer update {t_opt:.3f} s + rebuild {t_set:.3f} s; correlation "
+          f"matrix {t_corr:.2f} s", file=sys.stderr, flush=True)
+    return {"workload": "ising16x16_h3_m64_strict48_identity_start_seed16",
+            "sweeps": sweeps, "s_ttn": 1,
+            "attn_E_per_site": [float(x) / N for x in e_attn],
+            "ttn_E_per_site": [float(x) / N for x in e_ttn],
+            "attn_minus_ttn_final_per_site": float(e_attn[-1] - e_ttn[-1]) / N,
+            "attn_total_s": round(t_attn, 3), "ttn_total_s": round(t_ttn, 3),
+            "attn_sweep_s_incl_layer_update": [round(float(x), 4) for x in s_attn],
+            "layer_update_s": round(t_opt, 4), "layer_rebuild_s": round(t_set, 4),
+            "layer_update_gate_energy_change": float(np.sum(ea - eb)),
+            "magnetisation_x_per_site": float(np.mean(mx)), "measure_256_s": round(t_meas, 4),
+            "correlation_256x256_s": round(t_corr, 3),
+            "correlation_zz_mean_offdiag": float((C.sum() - np.trace(C)) / (N * N - N))}
+
+
 def learned_form(a, p, tol, n_nodes=2, pairs=6, steps=1500):
     """Davidson with Jacobi and with learned corrections vs the plain Lanczos
     sweep, from the state after one FP64 sweep.  The model is trained first on
@@ -414,6 +477,9 @@ def main():
                     help="timed sweeps of the batched-form comparison (0 to skip)")
     ap.add_argument("--converge-cap", type=int, default=150,
                     help="most sweeps of the time-to-target runs (0: no convergence leg)")
+    ap.add_argument("--attn-sweeps", type=int, default=8,
+                    help="sweeps of the aTTN recipe (layer optimisation before each sweep) vs plain "
+                         "TTN sweeps on the strict 16x16 placement (0 to skip)")
     ap.add_argument("--compress-sweeps", type=int, default=1,
                     help="sweeps of the term-compression comparison on the 16x16 triangular "
                          "Heisenberg model at m = 96 (0 to skip)")
@@ -631,6 +697,8 @@ def main():
     if args.compress_sweeps > 0:
         out["forms"] = out.get("forms", {})
         out["forms"]["compressed_terms"] = compressed_form(args.compress_sweeps)
+    if args.attn_sweeps > 0:
+        out["attn_recipe"] = attn_recipe(args.attn_sweeps)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)
