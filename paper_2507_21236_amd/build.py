@@ -16,7 +16,10 @@ LIB = os.path.join(HERE, "libattn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["model.cpp", "runtime.cpp", "state.cpp", "measure.cpp", "batch.cpp", "kernels.hip",
-           "measure_kernels.hip"]
+           "sandwich.hip", "measure_kernels.hip"]
+# per-source device flags: the sandwich kernels keep their MFMA accumulators in
+# ordinary VGPRs (see the header of sandwich.hip)
+EXTRA = {"sandwich.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 # packed FP32 instructions are kept out of the generated code
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
@@ -33,7 +36,7 @@ def build_library(verbose: bool = False) -> str:
     os.makedirs(build_dir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(build_dir, src + ".o")
-        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + COMMON + DEVICE_FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-c",
                                       os.path.join(CSRC, src), "-o", obj]

@@ -1,4 +1,4 @@
-// gfx950 kernels of the aTTN hot path.
+// gfx950 kernels of the aTTN hot path (the sandwich kernels are in sandwich.hip).
 //
 // Dense contractions run on the matrix cores with 16 x 16 x 4 MFMA tiles.
 // FP64 and FP32 share the operand layout (A lane l -> (row l%16, k l/16),
@@ -12,29 +12,9 @@
 
 #include "kernels.hpp"
 #include "launch.hpp"
+#include "mfma_common.hpp"
 
 namespace attn {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef double dv2 __attribute__((ext_vector_type(2)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-template <typename T> struct V4;
-template <> struct V4<double> { typedef d4 type; };
-template <> struct V4<float> { typedef f4 type; };
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 // A failure status of the eigensolver / QR state, also collected in the
 // sticky word that sweeps read once at their end.
@@ -42,569 +22,6 @@ __device__ __forceinline__ void fail_status(KrylovState* st, int v) {
   st->status = v;
   atomicOr(&st->sticky, v);
 }
-
-// accumulator row of item i in lane group g = lane / 16
-template <typename T> __device__ __forceinline__ int drow(int g, int i);
-template <> __device__ __forceinline__ int drow<double>(int g, int i) { return g + 4 * i; }
-template <> __device__ __forceinline__ int drow<float>(int g, int i) { return 4 * g + i; }
-
-// accumulator row of item i in lane group g for the 16x16x32 BF16 product
-__device__ __forceinline__ int drow_bf(int g, int i) { return 4 * g + i; }
-// column held at position pos of a permuted 32-wide chunk, and its inverse
-__device__ __forceinline__ int bf_perm(int pos) {
-  const int j = pos & 7, g = (pos >> 3) & 3;
-  return (pos & ~31) + 16 * (j >> 2) + drow_bf(g, j & 3);
-}
-__device__ __forceinline__ int bf_pinv(int a) {
-  const int r = a & 15, h = (a >> 4) & 1;
-  return (a & ~31) + 8 * (r >> 2) + 4 * h + (r & 3);
-}
-
-// ============================================================================ sandwich
-// One work unit = (task, slice s, first 16-row strip).  The WG stages X_s in LDS;
-// wave w owns rows [16 (strip0 + w), +16) of Y_s.  Per item:
-//   stage 1: T1^T[p][a'] = sum_a X_s[a][p] A[a'][a]           (or X_s^T if A = 1)
-//   stage 2: Y^T[p'][a'] += sum_p B[p'][p] T1^T[p][a']        (or T1^T if B = 1)
-// Stage 2 consumes the stage-1 accumulators directly as the B operand by
-// walking K = p in the order {16 tp + drow(j, i) : j = 0..3} for fixed (tp, i),
-// which is exactly how the accumulator layout spreads p over lane groups.
-// Loads of operator blocks through the global address space: the blocks
-// arrive as generic pointers, and flat loads would make every wait for them
-// also wait for LDS traffic (full drains instead of counted partial waits).
-template <typename T>
-__device__ __forceinline__ T gload(const T* p) {
-  return *(const __attribute__((address_space(1))) T*)p;
-}
-
-// The rows of Y_s owned by this wave for items [i0, i1), written to y.
-// Column order of a 16-wide tile as the products see it: tile row m of both
-// MFMA stages stands for column colperm(m).  FP64: the accumulator rows of a
-// lane, l/16 + 4 i, become the columns 2 (l/16) + {0, 1, 8, 9}, so that each
-// lane ends up with two pairs of adjacent columns and stores them as 16-byte
-// writes; FP32 lanes already hold 4 adjacent columns.
-template <typename T> __device__ __forceinline__ int colperm(int m);
-template <> __device__ __forceinline__ int colperm<double>(int m) { return 2 * (m & 3) + ((m >> 2) & 1) + 8 * (m >> 3); }
-template <> __device__ __forceinline__ int colperm<float>(int m) { return m; }
-
-template <typename T, int NB>
-__device__ __forceinline__ void sandwich_rows(const SWTask& t, const SWItem* __restrict__ items, int i0, int i1,
-                                              void* y, int accumulate, int s, int strip0, const T* lds) {
-  typedef typename V4<T>::type v4;
-  const int ma = t.ma;
-  constexpr int mb = 16 * NB;
-  constexpr int ld = mb + 2;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int strip = strip0 + wave;
-  if (strip * 16 >= ma) return;
-  const int l16 = lane & 15, l4 = lane >> 4;
-  const int arow = strip * 16 + l16;
-  const int pc = colperm<T>(l16);   // column read by this lane for an A operand
-  int pk[4];                        // column of the contraction index of item i
-#pragma unroll
-  for (int i = 0; i < 4; i++) pk[i] = colperm<T>(drow<T>(l4, i));
-  v4 acc[NB];
-#pragma unroll
-  for (int q = 0; q < NB; q++) acc[q] = v4{0, 0, 0, 0};
-  for (int it = i0; it < i1; it++) {
-    const T* A = (const T*)items[it].A;
-    const T* B = (const T*)items[it].B;
-    const T coef = (T)items[it].coef;
-    v4 t1[NB];
-    if (A) {
-#pragma unroll
-      for (int q = 0; q < NB; q++) t1[q] = v4{0, 0, 0, 0};
-      const T* Ap = A + arow;
-      for (int k0 = 0; k0 < ma; k0 += 4) {
-        const T bop = gload(Ap + (int64_t)(k0 + l4) * ma) * coef;
-        const T* xr = lds + (k0 + l4) * ld + pc;
-#pragma unroll
-        for (int q = 0; q < NB; q++) t1[q] = mfma16(xr[16 * q], bop, t1[q]);
-      }
-    } else {
-      const T* xr = lds + arow * ld;
-#pragma unroll
-      for (int q = 0; q < NB; q++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) t1[q][i] = xr[16 * q + pk[i]] * coef;
-    }
-    if (B) {
-#pragma unroll
-      for (int tp = 0; tp < NB; tp++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const T* Bp = B + (int64_t)(16 * tp + pk[i]) * mb + pc;
-#pragma unroll
-          for (int tq = 0; tq < NB; tq++) acc[tq] = mfma16(gload(Bp + 16 * tq), t1[tp][i], acc[tq]);
-        }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NB; q++) acc[q] += t1[q];
-    }
-  }
-  T* Y = (T*)y + (int64_t)s * t.ys_slice + (int64_t)arow * t.ys_row;
-  if constexpr (sizeof(T) == 8) {
-#pragma unroll
-    for (int q = 0; q < NB; q++) {
-      double2* p0 = (double2*)(Y + 16 * q + 2 * l4);
-      double2* p1 = (double2*)(Y + 16 * q + 8 + 2 * l4);
-      double2 v0 = make_double2(acc[q][0], acc[q][1]), v1 = make_double2(acc[q][2], acc[q][3]);
-      if (accumulate) {
-        const double2 o0 = *p0, o1 = *p1;
-        v0.x += o0.x; v0.y += o0.y; v1.x += o1.x; v1.y += o1.y;
-      }
-      // streaming stores: each output (a partial sum, a Z tensor) is read once
-      // by the next kernel, and not allocating it in L2 keeps the operator
-      // blocks there (matvec launches -2 %, effective-operator launches -5 %;
-      // the reduction of the partials reads them from HBM, +4 us)
-      __builtin_nontemporal_store(dv2{v0.x, v0.y}, (dv2*)p0);
-      __builtin_nontemporal_store(dv2{v1.x, v1.y}, (dv2*)p1);
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < NB; q++) {
-      float4* p0 = (float4*)(Y + 16 * q + 4 * l4);
-      float4 v = make_float4(acc[q][0], acc[q][1], acc[q][2], acc[q][3]);
-      if (accumulate) {
-        const float4 o = *p0;
-        v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
-      }
-      *p0 = v;
-    }
-  }
-}
-
-
-template <typename T, int NB>
-__device__ __forceinline__ void sandwich_mfma(const SWTask& t, const SWItem* __restrict__ items,
-                                              const int4 wu, const T* __restrict__ xbase,
-                                              unsigned char* smem_raw, const SWOut* __restrict__ outs = nullptr) {
-  T* lds = reinterpret_cast<T*>(smem_raw);
-  const int s = wu.y;
-  const int ma = t.ma;
-  constexpr int mb = 16 * NB;
-  constexpr int ld = mb + 2;
-  const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)s * t.xs_slice;
-  for (int e = threadIdx.x; e < ma * mb; e += 256) {
-    const int a = e / mb, b = e - a * mb;
-    lds[a * ld + b] = X[(int64_t)a * t.xs_row + b];
-  }
-  __syncthreads();
-  if (outs && t.pad) {   // several outputs: items of output o go to outs[o].y
-    for (int o = t.item0; o < t.item0 + t.nitem; o++)
-      sandwich_rows<T, NB>(t, items, outs[o].item0, outs[o].item0 + outs[o].nitem, outs[o].y, t.accumulate, s,
-                           wu.z, lds);
-  } else {
-    sandwich_rows<T, NB>(t, items, t.item0, t.item0 + t.nitem, t.y, t.accumulate, s, wu.z, lds);
-  }
-}
-
-template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_sandwich(const SWTask* __restrict__ tasks,
-                                                  const SWItem* __restrict__ items,
-                                                  const int4* __restrict__ wus,
-                                                  const T* __restrict__ xbase,
-                                                  const SWOut* __restrict__ outs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int4 wu = wus[blockIdx.x];
-  sandwich_mfma<T, NB>(tasks[wu.x], items, wu, xbase, smem_raw, outs);
-}
-
-// Generic sandwich for dimensions that are not multiples of 16: one thread per
-// output element of one slice.  wu = (task, slice, first element).
-template <typename T>
-__device__ __forceinline__ void sandwich_gen_elem(const SWTask& t, const SWItem* __restrict__ items,
-                                                  int s, int e, const T* __restrict__ xbase) {
-  const int ma = t.ma, mb = t.mb;
-  if (e >= ma * mb) return;
-  const int ap = e / mb, bp = e - ap * mb;
-  const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)s * t.xs_slice;
-  T acc = 0;
-  for (int it = t.item0; it < t.item0 + t.nitem; it++) {
-    const T* A = (const T*)items[it].A;
-    const T* B = (const T*)items[it].B;
-    T sum = 0;
-    for (int b = 0; b < mb; b++) {
-      const T bw = B ? B[(int64_t)b * mb + bp] : (b == bp ? (T)1 : (T)0);
-      if (bw == (T)0) continue;
-      T col = 0;
-      if (A) {
-        for (int a = 0; a < ma; a++) col += A[(int64_t)a * ma + ap] * X[(int64_t)a * t.xs_row + b];
-      } else {
-        col = X[(int64_t)ap * t.xs_row + b];
-      }
-      sum += bw * col;
-    }
-    acc += (T)items[it].coef * sum;
-  }
-  T* Y = (T*)t.y + (int64_t)s * t.ys_slice + (int64_t)ap * t.ys_row + bp;
-  if (t.accumulate) *Y += acc;
-  else *Y = acc;
-}
-
-// Small slices (ma mb <= 256, one work unit per slice): the slice, the stage-1
-// product and each item's blocks are staged in LDS, so an item costs a few
-// LDS passes instead of chains of dependent global loads.  Same arithmetic
-// and summation order as sandwich_gen_elem (a zero entry of B adds a zero).
-template <typename T>
-__device__ __forceinline__ void sandwich_gen_slice(const SWTask& t, const SWItem* __restrict__ items, int s,
-                                                   const T* __restrict__ xbase, T* lds) {
-  const int ma = t.ma, mb = t.mb, n = ma * mb;
-  T* Xs = lds;
-  T* T1 = Xs + n;
-  T* As = T1 + n;
-  T* Bs = As + ma * ma;
-  const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)s * t.xs_slice;
-  const int e = threadIdx.x;
-  const bool mine = e < n;
-  const int ap = mine ? e / mb : 0, bp = mine ? e - ap * mb : 0;
-  for (int q = threadIdx.x; q < n; q += blockDim.x) {
-    const int a = q / mb, b = q - a * mb;
-    Xs[q] = X[(int64_t)a * t.xs_row + b];
-  }
-  T acc = 0;
-  for (int it = t.item0; it < t.item0 + t.nitem; it++) {
-    const T* A = (const T*)items[it].A;
-    const T* B = (const T*)items[it].B;
-    __syncthreads();
-    if (A)
-      for (int q = threadIdx.x; q < ma * ma; q += blockDim.x) As[q] = A[q];
-    if (B)
-      for (int q = threadIdx.x; q < mb * mb; q += blockDim.x) Bs[q] = B[q];
-    __syncthreads();
-    if (mine) {   // stage 1: T1(ap, bp) = sum_a A(a, ap) X(a, bp)
-      T col = 0;
-      if (A) {
-        for (int a = 0; a < ma; a++) col += As[a * ma + ap] * Xs[a * mb + bp];
-      } else {
-        col = Xs[ap * mb + bp];
-      }
-      T1[e] = col;
-    }
-    __syncthreads();
-    if (mine) {   // stage 2: sum_b B(b, bp) T1(ap, b)
-      T sum = 0;
-      if (B) {
-        for (int b = 0; b < mb; b++) sum += Bs[b * mb + bp] * T1[ap * mb + b];
-      } else {
-        sum = T1[ap * mb + bp];
-      }
-      acc += (T)items[it].coef * sum;
-    }
-  }
-  if (!mine) return;
-  T* Y = (T*)t.y + (int64_t)s * t.ys_slice + (int64_t)ap * t.ys_row + bp;
-  if (t.accumulate) *Y += acc;
-  else *Y = acc;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_sandwich_gen(const SWTask* __restrict__ tasks,
-                                                      const SWItem* __restrict__ items,
-                                                      const int4* __restrict__ wus,
-                                                      const T* __restrict__ xbase) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int4 wu = wus[blockIdx.x];
-  const SWTask& t = tasks[wu.x];
-  if (gen_slice_lds(t.ma, t.mb, sizeof(T)))
-    sandwich_gen_slice<T>(t, items, wu.y, xbase, reinterpret_cast<T*>(smem_raw));
-  else
-    sandwich_gen_elem<T>(t, items, wu.y, wu.z + threadIdx.x, xbase);
-}
-
-// ============================================================================ split-BF16 sandwich
-// Same contraction as k_sandwich with every operand split as hi + lo BF16 and
-// three 16x16x32 BF16 products (hi.hi + hi.lo + lo.hi) accumulated in FP32.
-// The K index of every product walks a 32-wide chunk in the order
-//   slot (g, j) of lane group g -> 32 c + 16 (j / 4) + drow_bf(g, j % 4),
-// which is how the stage-1 accumulators spread p over lane groups: stage 2 then
-// takes them as its B operand straight from registers.  Operator blocks come in
-// that order already (fmt 2 of k_convert); X_s is split and permuted in LDS.
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ f4 mfma_bf(bf8 a, bf8 b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-template <int NB>
-__global__ __launch_bounds__(256) void k_sandwich_bf2(const SWTask* __restrict__ tasks,
-                                                      const SWItem* __restrict__ items,
-                                                      const int4* __restrict__ wus,
-                                                      const float* __restrict__ xbase) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int4 wu = wus[blockIdx.x];
-  const SWTask& t = tasks[wu.x];
-  const int s = wu.y;
-  const int ma = t.ma;
-  constexpr int mb = 16 * NB;
-  const int lda = ma + 8;                      // LDS row = one column b of X_s
-  __bf16* xh = reinterpret_cast<__bf16*>(smem_raw);
-  __bf16* xl = xh + mb * lda;
-  const float* X = (t.x ? (const float*)t.x : xbase) + (int64_t)s * t.xs_slice;
-  for (int e = threadIdx.x; e < ma * mb; e += 256) {
-    const int a = e / mb, b = e - a * mb;
-    const float v = X[(int64_t)a * t.xs_row + b];
-    const __bf16 hi = (__bf16)v;
-    const __bf16 lo = (__bf16)(v - (float)hi);
-    const int pos = bf_pinv(a);
-    xh[b * lda + pos] = hi;
-    xl[b * lda + pos] = lo;
-  }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int strip = wu.z + wave;
-  if (strip * 16 >= ma) return;
-  const int l16 = lane & 15, g = lane >> 4;
-  const int arow = strip * 16 + l16;
-  const int64_t mma = (int64_t)ma * ma, mmb = (int64_t)mb * mb;
-  f4 acc[NB];
-#pragma unroll
-  for (int q = 0; q < NB; q++) acc[q] = f4{0, 0, 0, 0};
-  const int iend = t.item0 + t.nitem;
-  for (int it = t.item0; it < iend; it++) {
-    const __bf16* A = (const __bf16*)items[it].A;
-    const __bf16* B = (const __bf16*)items[it].B;
-    const float coef = (float)items[it].coef;
-    f4 t1[NB];
-    if (A) {
-#pragma unroll
-      for (int q = 0; q < NB; q++) t1[q] = f4{0, 0, 0, 0};
-      const bf8* Ah = (const bf8*)(A + (int64_t)arow * ma + 8 * g);
-      const bf8* Al = (const bf8*)(A + mma + (int64_t)arow * ma + 8 * g);
-      for (int c = 0; c < ma / 32; c++) {
-        const bf8 ah = Ah[4 * c], al = Al[4 * c];
-#pragma unroll
-        for (int q = 0; q < NB; q++) {
-          const int off = (16 * q + l16) * lda + 32 * c + 8 * g;
-          const bf8 vh = *(const bf8*)(xh + off);
-          const bf8 vl = *(const bf8*)(xl + off);
-          t1[q] = mfma_bf(vh, ah, t1[q]);
-          t1[q] = mfma_bf(vh, al, t1[q]);
-          t1[q] = mfma_bf(vl, ah, t1[q]);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < NB; q++) t1[q] *= coef;
-    } else {
-      const int pa = bf_pinv(arow);
-#pragma unroll
-      for (int q = 0; q < NB; q++)
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          const int p = 16 * q + drow_bf(g, i);
-          t1[q][i] = ((float)xh[p * lda + pa] + (float)xl[p * lda + pa]) * coef;
-        }
-    }
-    if (B) {
-#pragma unroll
-      for (int c = 0; c < NB / 2; c++) {
-        bf8 th, tl;
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-          const float v = t1[2 * c + j / 4][j % 4];
-          th[j] = (__bf16)v;
-          tl[j] = (__bf16)(v - (float)th[j]);
-        }
-#pragma unroll
-        for (int tq = 0; tq < NB; tq++) {
-          const int64_t off = (int64_t)(16 * tq + l16) * mb + 32 * c + 8 * g;
-          const bf8 bh = *(const bf8*)(B + off);
-          const bf8 bl = *(const bf8*)(B + mmb + off);
-          acc[tq] = mfma_bf(bh, th, acc[tq]);
-          acc[tq] = mfma_bf(bl, th, acc[tq]);
-          acc[tq] = mfma_bf(bh, tl, acc[tq]);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NB; q++) acc[q] += t1[q];
-    }
-  }
-  float* Y = (float*)t.y + (int64_t)s * t.ys_slice + (int64_t)arow * t.ys_row;
-#pragma unroll
-  for (int q = 0; q < NB; q++)
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int c = 16 * q + drow_bf(g, i);
-      if (t.accumulate) Y[c] += acc[q][i];
-      else Y[c] = acc[q][i];
-    }
-}
-
-// Wave-per-slice form for legs <= 64 (ma = 16 MA, mb = 16 NB, both multiples
-// of 32): each wave computes a whole slice Y_s with all MA row strips in
-// registers, so every fragment of A and B serves MA (or NB) products instead
-// of one; the split X_s stays in registers for the whole item loop.  The four
-// waves (four slices) share the item's operator blocks through LDS: the blocks
-// of item i + 1 are loaded from memory into registers while item i is
-// computed from LDS, then written to the other LDS buffer (double buffering,
-// one barrier per item).  wu = (task, first slice, -, number of slices <= 4).
-template <int MA, int NB>
-__global__ __launch_bounds__(256) void k_sandwich_bf2w(const SWTask* __restrict__ tasks,
-                                                       const SWItem* __restrict__ items,
-                                                       const int4* __restrict__ wus,
-                                                       const float* __restrict__ xbase) {
-  constexpr int ma = 16 * MA, mb = 16 * NB, CA = ma / 32, CB = mb / 32;
-  constexpr int lda = ma + 8, ldb = mb + 8;         // padded LDS rows (conflict-free 16-byte reads)
-  constexpr int SA = ma * lda, SB = mb * ldb;       // bf16 per plane in LDS
-  constexpr int BUF = 2 * SA + 2 * SB;              // one item: A hi, A lo, B hi, B lo
-  constexpr int NA = ma * ma / 8, NBC = mb * mb / 8;  // 16-byte chunks per plane in memory
-  constexpr int NTOT = 2 * NA + 2 * NBC, NPT = (NTOT + 255) / 256;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __bf16* lds = reinterpret_cast<__bf16*>(smem_raw);
-  const int4 wu = wus[blockIdx.x];
-  const SWTask& t = tasks[wu.x];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const bool active = wave < wu.w;
-  const int s = wu.y + (active ? wave : 0);
-  const int l16 = lane & 15, g = lane >> 4;
-  const float* X = (t.x ? (const float*)t.x : xbase) + (int64_t)s * t.xs_slice;
-  bf8 xh[CA][NB], xl[CA][NB];
-#pragma unroll
-  for (int c = 0; c < CA; c++)
-#pragma unroll
-    for (int q = 0; q < NB; q++)
-#pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const float v = active ? X[(int64_t)bf_perm(32 * c + 8 * g + j) * t.xs_row + 16 * q + l16] : 0.0f;
-        const __bf16 hi = (__bf16)v;
-        xh[c][q][j] = hi;
-        xl[c][q][j] = (__bf16)(v - (float)hi);
-      }
-  bf8 pre[NPT];
-  auto fetch = [&](int it) {
-    const __bf16* A = (const __bf16*)items[it].A;
-    const __bf16* B = (const __bf16*)items[it].B;
-#pragma unroll
-    for (int r = 0; r < NPT; r++) {
-      const int ch = tid + 256 * r;
-      const __bf16* src = nullptr;
-      if (ch < 2 * NA) src = A ? A + (int64_t)ch * 8 : nullptr;
-      else if (ch < NTOT) src = B ? B + (int64_t)(ch - 2 * NA) * 8 : nullptr;
-      if (src) pre[r] = *(const bf8*)src;
-    }
-  };
-  auto store = [&](int buf) {
-    __bf16* L = lds + buf * BUF;
-#pragma unroll
-    for (int r = 0; r < NPT; r++) {
-      const int ch = tid + 256 * r;
-      if (ch < 2 * NA) {
-        const int e = ch * 8, plane = e / (ma * ma), w = e - plane * ma * ma;
-        *(bf8*)(L + plane * SA + (w / ma) * lda + w % ma) = pre[r];
-      } else if (ch < NTOT) {
-        const int e = (ch - 2 * NA) * 8, plane = e / (mb * mb), w = e - plane * mb * mb;
-        *(bf8*)(L + 2 * SA + plane * SB + (w / mb) * ldb + w % mb) = pre[r];
-      }
-    }
-  };
-  f4 acc[MA][NB];
-#pragma unroll
-  for (int a = 0; a < MA; a++)
-#pragma unroll
-    for (int q = 0; q < NB; q++) acc[a][q] = f4{0, 0, 0, 0};
-  const int i0 = t.item0, i1 = t.item0 + t.nitem;
-  if (i0 < i1) {
-    fetch(i0);
-    store(0);
-  }
-  __syncthreads();
-  for (int it = i0; it < i1; it++) {
-    const int buf = (it - i0) & 1;
-    if (it + 1 < i1) fetch(it + 1);
-    const bool hasA = items[it].A != nullptr, hasB = items[it].B != nullptr;
-    const float coef = (float)items[it].coef;
-    const __bf16* LA = lds + buf * BUF;
-    const __bf16* LB = LA + 2 * SA;
-    if (active) {
-      f4 t1[MA][NB];
-      if (hasA) {
-#pragma unroll
-        for (int a = 0; a < MA; a++)
-#pragma unroll
-          for (int q = 0; q < NB; q++) t1[a][q] = f4{0, 0, 0, 0};
-#pragma unroll
-        for (int c = 0; c < CA; c++) {
-          bf8 ah[MA], al[MA];
-#pragma unroll
-          for (int a = 0; a < MA; a++) {
-            const int off = (16 * a + l16) * lda + 32 * c + 8 * g;
-            ah[a] = *(const bf8*)(LA + off);
-            al[a] = *(const bf8*)(LA + SA + off);
-          }
-#pragma unroll
-          for (int a = 0; a < MA; a++)
-#pragma unroll
-            for (int q = 0; q < NB; q++) {
-              t1[a][q] = mfma_bf(xh[c][q], ah[a], t1[a][q]);
-              t1[a][q] = mfma_bf(xh[c][q], al[a], t1[a][q]);
-              t1[a][q] = mfma_bf(xl[c][q], ah[a], t1[a][q]);
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < MA; a++)
-#pragma unroll
-          for (int q = 0; q < NB; q++) t1[a][q] *= coef;
-      } else {
-#pragma unroll
-        for (int a = 0; a < MA; a++)
-#pragma unroll
-          for (int q = 0; q < NB; q++)
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-              t1[a][q][i] = coef * X[(int64_t)(16 * a + l16) * t.xs_row + 16 * q + drow_bf(g, i)];
-      }
-      if (hasB) {
-#pragma unroll
-        for (int c = 0; c < CB; c++) {
-          bf8 th[MA], tl[MA];
-#pragma unroll
-          for (int a = 0; a < MA; a++)
-#pragma unroll
-            for (int jj = 0; jj < 8; jj++) {
-              const float v = t1[a][2 * c + jj / 4][jj % 4];
-              th[a][jj] = (__bf16)v;
-              tl[a][jj] = (__bf16)(v - (float)th[a][jj]);
-            }
-#pragma unroll
-          for (int tq = 0; tq < NB; tq++) {
-            const int off = (16 * tq + l16) * ldb + 32 * c + 8 * g;
-            const bf8 bh = *(const bf8*)(LB + off);
-            const bf8 bl = *(const bf8*)(LB + SB + off);
-#pragma unroll
-            for (int a = 0; a < MA; a++) {
-              acc[a][tq] = mfma_bf(bh, th[a], acc[a][tq]);
-              acc[a][tq] = mfma_bf(bl, th[a], acc[a][tq]);
-              acc[a][tq] = mfma_bf(bh, tl[a], acc[a][tq]);
-            }
-          }
-        }
-      } else {
-#pragma unroll
-        for (int a = 0; a < MA; a++)
-#pragma unroll
-          for (int q = 0; q < NB; q++) acc[a][q] += t1[a][q];
-      }
-    }
-    if (it + 1 < i1) store(buf ^ 1);
-    __syncthreads();
-  }
-  if (!active) return;
-#pragma unroll
-  for (int a = 0; a < MA; a++) {
-    float* Y = (float*)t.y + (int64_t)s * t.ys_slice + (int64_t)(16 * a + l16) * t.ys_row;
-#pragma unroll
-    for (int q = 0; q < NB; q++)
-#pragma unroll
-      for (int i = 0; i < 4; i++) {
-        const int c = 16 * q + drow_bf(g, i);
-        if (t.accumulate) Y[c] += acc[a][q][i];
-        else Y[c] = acc[a][q][i];
-      }
-  }
-}
-
-template <int MA, int NB>
-constexpr size_t bf2w_lds() { return (size_t)2 * (2 * 16 * MA * (16 * MA + 8) + 2 * 16 * NB * (16 * NB + 8)) * 2; }
 
 // ============================================================================ mode product
 // Element (i, f) of a (d0, d1, d2) tensor contracted on leg j, where f runs over
@@ -776,29 +193,6 @@ __global__ __launch_bounds__(256) void k_mode_gen(const MPTask* __restrict__ tas
 // ============================================================================ mixed-shape launches
 // One launch over the work units of many tasks of different shapes (several
 // nodes of several problem instances): the kind of each unit selects the body.
-// Sandwich: wu.w = NB (legs multiples of 16, mb = 16 NB <= 64) or 0 (generic).
-template <typename T>
-__global__ __launch_bounds__(256) void k_batch_sandwich(const SWTask* __restrict__ tasks,
-                                                        const SWItem* __restrict__ items,
-                                                        const int4* __restrict__ wus) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int4 wu = wus[blockIdx.x];
-  const SWTask& t = tasks[wu.x];
-  switch (wu.w) {
-    case 0:
-      if (gen_slice_lds(t.ma, t.mb, sizeof(T)))
-        sandwich_gen_slice<T>(t, items, wu.y, nullptr, reinterpret_cast<T*>(smem_raw));
-      else
-        sandwich_gen_elem<T>(t, items, wu.y, wu.z + threadIdx.x, nullptr);
-      break;
-    case 1: sandwich_mfma<T, 1>(t, items, wu, nullptr, smem_raw); break;
-    case 2: sandwich_mfma<T, 2>(t, items, wu, nullptr, smem_raw); break;
-    case 3: sandwich_mfma<T, 3>(t, items, wu, nullptr, smem_raw); break;
-    case 4: sandwich_mfma<T, 4>(t, items, wu, nullptr, smem_raw); break;
-    default: break;
-  }
-}
-
 // Mode product: the task's kind (MPTask::pad) is NI (m_j = 16 NI <= 64) or 0 (generic).
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_mode(const MPTask* __restrict__ tasks,
@@ -3039,89 +2433,6 @@ __global__ __launch_bounds__(64) void k_small_matmul(const double* __restrict__ 
 // ============================================================================ launchers
 static inline unsigned grid1(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-template <typename T, int NB>
-static hipError_t sand_launch(const SWTask* tasks, const SWItem* items, const int4* wus, int nwu,
-                              int ma, const void* xbase, hipStream_t s, const SWOut* outs) {
-  const size_t lds = (size_t)ma * (16 * NB + 2) * sizeof(T);
-  hipLaunchKernelGGL((k_sandwich<T, NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus,
-                     (const T*)xbase, outs);
-  return hipGetLastError();
-}
-
-template <int NB>
-static hipError_t sand_bf2_launch(const SWTask* tasks, const SWItem* items, const int4* wus, int nwu,
-                                  int ma, const void* xbase, hipStream_t s) {
-  const size_t lds = (size_t)2 * (16 * NB) * (ma + 8) * sizeof(__bf16);
-  hipLaunchKernelGGL((k_sandwich_bf2<NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus,
-                     (const float*)xbase);
-  return hipGetLastError();
-}
-
-hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const SWItem* items,
-                           const int4* wus, int nwu, const void* xbase, hipStream_t s, const SWOut* outs) {
-  if (nwu == 0) return hipSuccess;
-  if (dtype == 3) {   // split BF16, one slice per wave (legs 32 or 64)
-#define BF2W(MA, NB)                                                                             \
-  {                                                                                              \
-    const size_t lds = bf2w_lds<MA, NB>();                                                       \
-    hipLaunchKernelGGL((k_sandwich_bf2w<MA, NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus, \
-                       (const float*)xbase);                                                     \
-    return hipGetLastError();                                                                    \
-  }
-    if (ma == 32 && mb == 32) BF2W(2, 2)
-    if (ma == 32 && mb == 64) BF2W(2, 4)
-    if (ma == 64 && mb == 32) BF2W(4, 2)
-    if (ma == 64 && mb == 64) BF2W(4, 4)
-#undef BF2W
-    return hipErrorInvalidValue;
-  }
-  if (dtype == 2) {
-    if (!(ma % 32 == 0 && mb % 32 == 0 && ma <= 128 && mb <= 128)) return hipErrorInvalidValue;
-    switch (mb / 32) {
-      case 1: return sand_bf2_launch<2>(tasks, items, wus, nwu, ma, xbase, s);
-      case 2: return sand_bf2_launch<4>(tasks, items, wus, nwu, ma, xbase, s);
-      case 3: return sand_bf2_launch<6>(tasks, items, wus, nwu, ma, xbase, s);
-      case 4: return sand_bf2_launch<8>(tasks, items, wus, nwu, ma, xbase, s);
-    }
-    return hipErrorInvalidValue;
-  }
-  const bool mf = (ma % 16 == 0) && (mb % 16 == 0) && ma <= 128 && mb <= 128;
-  if (dtype == 0) {
-    if (!mf) {
-      hipLaunchKernelGGL(k_sandwich_gen<double>, dim3(nwu), dim3(256), gen_slice_lds(ma, mb, 8), s, tasks, items,
-                         wus, (const double*)xbase);
-      return hipGetLastError();
-    }
-    switch (mb / 16) {
-      case 1: return sand_launch<double, 1>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 2: return sand_launch<double, 2>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 3: return sand_launch<double, 3>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 4: return sand_launch<double, 4>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 5: return sand_launch<double, 5>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 6: return sand_launch<double, 6>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 7: return sand_launch<double, 7>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 8: return sand_launch<double, 8>(tasks, items, wus, nwu, ma, xbase, s, outs);
-    }
-  } else {
-    if (!mf) {
-      hipLaunchKernelGGL(k_sandwich_gen<float>, dim3(nwu), dim3(256), gen_slice_lds(ma, mb, 4), s, tasks, items,
-                         wus, (const float*)xbase);
-      return hipGetLastError();
-    }
-    switch (mb / 16) {
-      case 1: return sand_launch<float, 1>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 2: return sand_launch<float, 2>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 3: return sand_launch<float, 3>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 4: return sand_launch<float, 4>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 5: return sand_launch<float, 5>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 6: return sand_launch<float, 6>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 7: return sand_launch<float, 7>(tasks, items, wus, nwu, ma, xbase, s, outs);
-      case 8: return sand_launch<float, 8>(tasks, items, wus, nwu, ma, xbase, s, outs);
-    }
-  }
-  return hipErrorInvalidValue;
-}
-
 template <typename T, int NI>
 static hipError_t mode_launch(const MPTask* tasks, const MPJob* jobs, const int2* wus, int nwu,
                               const void* xbase, hipStream_t s) {
@@ -3392,16 +2703,6 @@ hipError_t launch_small_matmul(const double* A, const double* B, double* C, int 
 }
 
 // ---------------------------------------------------------------- mixed-shape launchers
-hipError_t launch_batch_sandwich(int dtype, const SWTask* tasks, const SWItem* items, const int4* wus,
-                                 int nwu, size_t lds, hipStream_t s) {
-  if (nwu == 0) return hipSuccess;
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_batch_sandwich<double>, dim3(nwu), dim3(256), lds, s, tasks, items, wus);
-  else
-    hipLaunchKernelGGL(k_batch_sandwich<float>, dim3(nwu), dim3(256), lds, s, tasks, items, wus);
-  return hipGetLastError();
-}
-
 hipError_t launch_batch_mode(int dtype, const MPTask* tasks, const MPJob* jobs, const int2* wus, int nwu,
                              size_t lds, hipStream_t s) {
   if (nwu == 0) return hipSuccess;
@@ -3455,21 +2756,9 @@ hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s)
 // Raise the dynamic-LDS limit of every kernel that uses it (call before any
 // stream capture: attribute changes are not stream operations).
 hipError_t prepare_kernel_attributes() {
+  if (hipError_t e = prepare_sandwich_attributes()) return e;
   const void* fns[] = {
-      (const void*)k_batch_sandwich<double>, (const void*)k_batch_sandwich<float>,
       (const void*)k_batch_mode<double>, (const void*)k_batch_mode<float>,
-      (const void*)k_sandwich<double, 1>, (const void*)k_sandwich<double, 2>,
-      (const void*)k_sandwich<double, 3>, (const void*)k_sandwich<double, 4>,
-      (const void*)k_sandwich<double, 5>, (const void*)k_sandwich<double, 6>,
-      (const void*)k_sandwich<double, 7>, (const void*)k_sandwich<double, 8>,
-      (const void*)k_sandwich<float, 1>, (const void*)k_sandwich<float, 2>,
-      (const void*)k_sandwich<float, 3>, (const void*)k_sandwich<float, 4>,
-      (const void*)k_sandwich<float, 5>, (const void*)k_sandwich<float, 6>,
-      (const void*)k_sandwich<float, 7>, (const void*)k_sandwich<float, 8>,
-      (const void*)k_sandwich_bf2<2>, (const void*)k_sandwich_bf2<4>,
-      (const void*)k_sandwich_bf2w<2, 2>, (const void*)k_sandwich_bf2w<2, 4>,
-      (const void*)k_sandwich_bf2w<4, 2>, (const void*)k_sandwich_bf2w<4, 4>,
-      (const void*)k_sandwich_bf2<6>, (const void*)k_sandwich_bf2<8>,
       (const void*)k_mode<double, 1, mode_qs(1)>, (const void*)k_mode<double, 2, mode_qs(2)>,
       (const void*)k_mode<double, 3, mode_qs(3)>, (const void*)k_mode<double, 4, mode_qs(4)>,
       (const void*)k_mode<double, 5, mode_qs(5)>, (const void*)k_mode<double, 6, mode_qs(6)>,

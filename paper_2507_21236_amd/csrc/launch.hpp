@@ -61,6 +61,7 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t s);
 hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 hipError_t prepare_kernel_attributes();
+hipError_t prepare_sandwich_attributes();
 
 // Davidson form.  op: 0 init, 1 start (arg = phase 0/1), 2 dots of W[k-1],
 // 3 Rayleigh-Ritz (Jacobi eigensolver), 4 Ritz vector and residual, 5 Jacobi
