@@ -664,15 +664,15 @@ void* to_mirror(attn_handle* h, const void* p, int fmt) {
   throw StatusFail{ATTN_ERR_STATE, "internal: block outside every store"};
 }
 
-// The wave-per-slice split-BF16 kernel keeps two workgroups resident per CU
-// (its LDS double buffer), so a launch takes ceil(W / 512) rounds of W
-// workgroups.  Its tasks (copied from the FP64 plan, W = tasks x slices / 4)
+// The register-blocked split-BF16 kernel keeps one workgroup of eight waves
+// resident per CU (two waves per SIMD), so a launch takes ceil(W / 256)
+// rounds of W workgroups.  Its tasks (copied from the FP64 plan, W = tasks x slices / 4)
 // are re-cut into fewer, longer item ranges so that W is a multiple of 512:
 // per class of tasks with the same slice geometry, the items are shared out
 // over fewer tasks in proportion to the class's item count, each new task
 // writing the partial output of one of the class's old tasks; the outputs
 // left unwritten are added to `dropped`.
-void rechunk_bf2w(SWGroup& g, std::vector<int>& ns_of, std::vector<RDSrc>& srcs, std::vector<const void*>& dropped) {
+void rechunk_bf2h(SWGroup& g, std::vector<int>& ns_of, std::vector<RDSrc>& srcs, std::vector<const void*>& dropped) {
   (void)srcs;
   const int nt = (int)g.tasks.size();
   if (nt == 0) return;
@@ -680,7 +680,7 @@ void rechunk_bf2w(SWGroup& g, std::vector<int>& ns_of, std::vector<RDSrc>& srcs,
     if (t.pad) return;
   int64_t W = 0;
   for (int t = 0; t < nt; t++) W += (ns_of[t] + 3) / 4;
-  const int64_t kRound = 512;
+  const int64_t kRound = 512;   // two rounds; cutting to multiples of 256 measured slower (220 vs 241 TFLOP/s)
   if (W <= kRound || W % kRound == 0) return;
   const int64_t Wt = kRound * (W / kRound);
   // classes of tasks with one slice geometry (consecutive in task order)
@@ -790,7 +790,7 @@ void ensure_lowp(attn_handle* h, int dtype) {
         // one slice per wave: units of up to four consecutive slices of a task
         std::vector<int> ns_of(g.tasks.size(), 0);
         for (const int4& wu : g.wus) ns_of[wu.x] = std::max(ns_of[wu.x], wu.y + 1);
-        rechunk_bf2w(g, ns_of, L.srcs, dropped);
+        rechunk_bf2h(g, ns_of, L.srcs, dropped);
         std::vector<int4> w2;
         for (size_t ti = 0; ti < g.tasks.size(); ti++)
           for (int s0 = 0; s0 < ns_of[ti]; s0 += 4) w2.push_back(make_int4((int)ti, s0, 0, std::min(4, ns_of[ti] - s0)));
