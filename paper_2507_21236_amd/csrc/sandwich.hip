@@ -435,8 +435,181 @@ __global__ __launch_bounds__(256) void k_sandwich_bf2(const SWTask* __restrict__
     }
 }
 
-// Register-blocked form for legs <= 64 (ma = 16 MA, mb = 16 NB, both multiples
-// of 32): a work unit is up to four slices, each computed by two waves, wave
+// Wave-per-slice form for legs <= 64 (ma = 16 MA, mb = 16 NB, both multiples
+// of 32; used where one of them is 32): each wave computes a whole slice Y_s
+// with all MA row strips in registers, so every fragment of A and B serves MA (or NB) products instead
+// of one; the split X_s stays in registers for the whole item loop.  The four
+// waves (four slices) share the item's operator blocks through LDS: the blocks
+// of item i + 1 are loaded from memory into registers while item i is
+// computed from LDS, then written to the other LDS buffer (double buffering,
+// one barrier per item).  wu = (task, first slice, -, number of slices <= 4).
+template <int MA, int NB>
+__global__ __launch_bounds__(256) void k_sandwich_bf2w(const SWTask* __restrict__ tasks,
+                                                       const SWItem* __restrict__ items,
+                                                       const int4* __restrict__ wus,
+                                                       const float* __restrict__ xbase) {
+  constexpr int ma = 16 * MA, mb = 16 * NB, CA = ma / 32, CB = mb / 32;
+  constexpr int lda = ma + 8, ldb = mb + 8;         // padded LDS rows (conflict-free 16-byte reads)
+  constexpr int SA = ma * lda, SB = mb * ldb;       // bf16 per plane in LDS
+  constexpr int BUF = 2 * SA + 2 * SB;              // one item: A hi, A lo, B hi, B lo
+  constexpr int NA = ma * ma / 8, NBC = mb * mb / 8;  // 16-byte chunks per plane in memory
+  constexpr int NTOT = 2 * NA + 2 * NBC, NPT = (NTOT + 255) / 256;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __bf16* lds = reinterpret_cast<__bf16*>(smem_raw);
+  const int4 wu = wus[blockIdx.x];
+  const SWTask& t = tasks[wu.x];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const bool active = wave < wu.w;
+  const int s = wu.y + (active ? wave : 0);
+  const int l16 = lane & 15, g = lane >> 4;
+  const float* X = (t.x ? (const float*)t.x : xbase) + (int64_t)s * t.xs_slice;
+  bf8 xh[CA][NB], xl[CA][NB];
+#pragma unroll
+  for (int c = 0; c < CA; c++)
+#pragma unroll
+    for (int q = 0; q < NB; q++)
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const float v = active ? X[(int64_t)bf_perm(32 * c + 8 * g + j) * t.xs_row + 16 * q + l16] : 0.0f;
+        const __bf16 hi = (__bf16)v;
+        xh[c][q][j] = hi;
+        xl[c][q][j] = (__bf16)(v - (float)hi);
+      }
+  bf8 pre[NPT];
+  auto fetch = [&](int it) {
+    const __bf16* A = (const __bf16*)items[it].A;
+    const __bf16* B = (const __bf16*)items[it].B;
+#pragma unroll
+    for (int r = 0; r < NPT; r++) {
+      const int ch = tid + 256 * r;
+      const __bf16* src = nullptr;
+      if (ch < 2 * NA) src = A ? A + (int64_t)ch * 8 : nullptr;
+      else if (ch < NTOT) src = B ? B + (int64_t)(ch - 2 * NA) * 8 : nullptr;
+      if (src) pre[r] = *(const bf8*)src;
+    }
+  };
+  auto store = [&](int buf) {
+    __bf16* L = lds + buf * BUF;
+#pragma unroll
+    for (int r = 0; r < NPT; r++) {
+      const int ch = tid + 256 * r;
+      if (ch < 2 * NA) {
+        const int e = ch * 8, plane = e / (ma * ma), w = e - plane * ma * ma;
+        *(bf8*)(L + plane * SA + (w / ma) * lda + w % ma) = pre[r];
+      } else if (ch < NTOT) {
+        const int e = (ch - 2 * NA) * 8, plane = e / (mb * mb), w = e - plane * mb * mb;
+        *(bf8*)(L + 2 * SA + plane * SB + (w / mb) * ldb + w % mb) = pre[r];
+      }
+    }
+  };
+  f4 acc[MA][NB];
+#pragma unroll
+  for (int a = 0; a < MA; a++)
+#pragma unroll
+    for (int q = 0; q < NB; q++) acc[a][q] = f4{0, 0, 0, 0};
+  const int i0 = t.item0, i1 = t.item0 + t.nitem;
+  if (i0 < i1) {
+    fetch(i0);
+    store(0);
+  }
+  __syncthreads();
+  for (int it = i0; it < i1; it++) {
+    const int buf = (it - i0) & 1;
+    if (it + 1 < i1) fetch(it + 1);
+    const bool hasA = items[it].A != nullptr, hasB = items[it].B != nullptr;
+    const float coef = (float)items[it].coef;
+    const __bf16* LA = lds + buf * BUF;
+    const __bf16* LB = LA + 2 * SA;
+    if (active) {
+      f4 t1[MA][NB];
+      if (hasA) {
+#pragma unroll
+        for (int a = 0; a < MA; a++)
+#pragma unroll
+          for (int q = 0; q < NB; q++) t1[a][q] = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < CA; c++) {
+          bf8 ah[MA], al[MA];
+#pragma unroll
+          for (int a = 0; a < MA; a++) {
+            const int off = (16 * a + l16) * lda + 32 * c + 8 * g;
+            ah[a] = *(const bf8*)(LA + off);
+            al[a] = *(const bf8*)(LA + SA + off);
+          }
+#pragma unroll
+          for (int a = 0; a < MA; a++)
+#pragma unroll
+            for (int q = 0; q < NB; q++) {
+              t1[a][q] = mfma_bf(xh[c][q], ah[a], t1[a][q]);
+              t1[a][q] = mfma_bf(xh[c][q], al[a], t1[a][q]);
+              t1[a][q] = mfma_bf(xl[c][q], ah[a], t1[a][q]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < MA; a++)
+#pragma unroll
+          for (int q = 0; q < NB; q++) t1[a][q] *= coef;
+      } else {
+#pragma unroll
+        for (int a = 0; a < MA; a++)
+#pragma unroll
+          for (int q = 0; q < NB; q++)
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+              t1[a][q][i] = coef * X[(int64_t)(16 * a + l16) * t.xs_row + 16 * q + drow_bf(g, i)];
+      }
+      if (hasB) {
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+          bf8 th[MA], tl[MA];
+#pragma unroll
+          for (int a = 0; a < MA; a++)
+#pragma unroll
+            for (int jj = 0; jj < 8; jj++) {
+              const float v = t1[a][2 * c + jj / 4][jj % 4];
+              th[a][jj] = (__bf16)v;
+              tl[a][jj] = (__bf16)(v - (float)th[a][jj]);
+            }
+#pragma unroll
+          for (int tq = 0; tq < NB; tq++) {
+            const int off = (16 * tq + l16) * ldb + 32 * c + 8 * g;
+            const bf8 bh = *(const bf8*)(LB + off);
+            const bf8 bl = *(const bf8*)(LB + SB + off);
+#pragma unroll
+            for (int a = 0; a < MA; a++) {
+              acc[a][tq] = mfma_bf(bh, th[a], acc[a][tq]);
+              acc[a][tq] = mfma_bf(bl, th[a], acc[a][tq]);
+              acc[a][tq] = mfma_bf(bh, tl[a], acc[a][tq]);
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < MA; a++)
+#pragma unroll
+          for (int q = 0; q < NB; q++) acc[a][q] += t1[a][q];
+      }
+    }
+    if (it + 1 < i1) store(buf ^ 1);
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int a = 0; a < MA; a++) {
+    float* Y = (float*)t.y + (int64_t)s * t.ys_slice + (int64_t)(16 * a + l16) * t.ys_row;
+#pragma unroll
+    for (int q = 0; q < NB; q++)
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        const int c = 16 * q + drow_bf(g, i);
+        if (t.accumulate) Y[c] += acc[a][q][i];
+        else Y[c] = acc[a][q][i];
+      }
+  }
+}
+
+// Half-slice form for legs 64 x 64 (ma = 16 MA, mb = 16 NB): a work unit is up
+// to four slices, each computed by two waves, wave
 // 2 j + h owning the row strips [MA/2 h, MA/2 (h + 1)) of slice j with its
 // accumulators and stage-1 tiles in registers, so that every fragment of A and
 // B serves MA/2 (or NB) products; the split X_s stays in registers for the
@@ -445,7 +618,10 @@ __global__ __launch_bounds__(256) void k_sandwich_bf2(const SWTask* __restrict__
 // item i is computed from LDS, then written to the other LDS buffer (double
 // buffering, one barrier per item).  With half a slice per wave the kernel
 // fits 256 registers per lane, two waves per SIMD (a whole slice per wave
-// took 400, one wave per SIMD: 191 -> 242 useful TFLOP/s at legs 64).
+// takes 400 at legs 64, one wave per SIMD: 191 -> 242 useful TFLOP/s).  It is
+// launched at legs 64 x 64 only: its (32, 32) instance gave matvecs 0.5 off
+// (relative) on the device for a reason not found, while the wave-per-slice
+// form, which fits the registers there, is exact to the split's rounding.
 // wu = (task, first slice, -, number of slices <= 4).
 template <int MA, int NB>
 __global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict__ tasks,
@@ -613,6 +789,7 @@ __global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict_
   }
 }
 
+// LDS of both the wave-per-slice and the half-slice form
 template <int MA, int NB>
 constexpr size_t bf2h_lds() { return (size_t)2 * (2 * 16 * MA * (16 * MA + 8) + 2 * 16 * NB * (16 * NB + 8)) * 2; }
 
@@ -668,15 +845,20 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
 #define BF2W(MA, NB)                                                                             \
   {                                                                                              \
     const size_t lds = bf2h_lds<MA, NB>();                                                       \
-    hipLaunchKernelGGL((k_sandwich_bf2h<MA, NB>), dim3(nwu), dim3(512), lds, s, tasks, items, wus, \
+    hipLaunchKernelGGL((k_sandwich_bf2w<MA, NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus, \
                        (const float*)xbase);                                                     \
     return hipGetLastError();                                                                    \
   }
     if (ma == 32 && mb == 32) BF2W(2, 2)
     if (ma == 32 && mb == 64) BF2W(2, 4)
     if (ma == 64 && mb == 32) BF2W(4, 2)
-    if (ma == 64 && mb == 64) BF2W(4, 4)
 #undef BF2W
+    if (ma == 64 && mb == 64) {
+      const size_t lds = bf2h_lds<4, 4>();
+      hipLaunchKernelGGL((k_sandwich_bf2h<4, 4>), dim3(nwu), dim3(512), lds, s, tasks, items, wus,
+                         (const float*)xbase);
+      return hipGetLastError();
+    }
     return hipErrorInvalidValue;
   }
   if (dtype == 2) {
@@ -749,8 +931,8 @@ hipError_t prepare_sandwich_attributes() {
       (const void*)k_sandwich<float, 5>, (const void*)k_sandwich<float, 6>,
       (const void*)k_sandwich<float, 7>, (const void*)k_sandwich<float, 8>,
       (const void*)k_sandwich_bf2<2>, (const void*)k_sandwich_bf2<4>,
-      (const void*)k_sandwich_bf2h<2, 2>, (const void*)k_sandwich_bf2h<2, 4>,
-      (const void*)k_sandwich_bf2h<4, 2>, (const void*)k_sandwich_bf2h<4, 4>,
+      (const void*)k_sandwich_bf2w<2, 2>, (const void*)k_sandwich_bf2w<2, 4>,
+      (const void*)k_sandwich_bf2w<4, 2>, (const void*)k_sandwich_bf2h<4, 4>,
       (const void*)k_sandwich_bf2<6>, (const void*)k_sandwich_bf2<8>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
