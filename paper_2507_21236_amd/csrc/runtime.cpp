@@ -203,6 +203,13 @@ void upload_mp(attn_handle* h, std::vector<MPGroup>& gs) {
   }
 }
 
+#define ATTN_MV_TARGET 768
+// matvec work units per spectator group (three groups per node): 3 x 768 =
+// three rounds of the 768 workgroups resident at three per CU.  Measured
+// against 1024 (four rounds) and 512: sweep 0.581 vs 0.584 and 0.582 s, and a
+// quarter fewer partial outputs to write and sum than with 1024.
+constexpr int64_t kMvTarget = ATTN_MV_TARGET;
+
 void mv_chunks(const MatvecPlan& P, const int* dm, const int64_t target[3], int out[3]) {
   int64_t nit[3] = {0, 0, 0}, units[3] = {1, 1, 1};
   int ma[3], mb[3];
@@ -234,7 +241,7 @@ void build_mv_dev(attn_handle* h, int n, std::vector<int64_t>& comb_off_out) {
   for (size_t i = 0; i < P.combines.size(); i++) h->comb_blocks[n].push_back({off[i], P.combines[i].dim});
   int64_t part_used = 0;
   int nchs[3];
-  const int64_t target[3] = {1024, 1024, 1024};
+  const int64_t target[3] = {kMvTarget, kMvTarget, kMvTarget};
   mv_chunks(P, dm, target, nchs);
   // two-leg items and local operators, grouped by spectator
   for (int sp = 0; sp < 3; sp++) {
@@ -1359,7 +1366,7 @@ attn_status attn_build_tpo(const attn_problem* p, attn_handle** out) {
       const int64_t Msz = (int64_t)dm[0] * dm[1] * dm[2];
       const MatvecPlan& P = h->M.mv[n];
       int nparts = 0, nchs[3];
-      const int64_t target[3] = {1024, 1024, 1024};
+      const int64_t target[3] = {kMvTarget, kMvTarget, kMvTarget};
       mv_chunks(P, dm, target, nchs);
       for (int sp = 0; sp < 3; sp++) nparts += nchs[sp];
       part_need = std::max(part_need, nparts * Msz);
