@@ -19,7 +19,7 @@ struct attn_batch {
   std::vector<hipEvent_t> evs;
   // autotuned work split: target workgroups per sandwich launch group, by (ma, mb)
   std::vector<std::pair<std::pair<int, int>, int>> tuned;
-  int default_target = 1024;   // the single-handle split
+  int default_target = (int)kMvTarget;   // the single-handle split
 
   struct Merged {
     std::vector<SWTask> sw_tasks;
@@ -398,7 +398,7 @@ void autotune(attn_batch* b) {
       }
     }
   }
-  const int cands[4] = {64, 256, 1024, 4096};
+  const int cands[4] = {64, 256, (int)kMvTarget, 4096};   // the single-handle split among them
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

@@ -203,12 +203,6 @@ void upload_mp(attn_handle* h, std::vector<MPGroup>& gs) {
   }
 }
 
-#define ATTN_MV_TARGET 768
-// matvec work units per spectator group (three groups per node): 3 x 768 =
-// three rounds of the 768 workgroups resident at three per CU.  Measured
-// against 1024 (four rounds) and 512: sweep 0.581 vs 0.584 and 0.582 s, and a
-// quarter fewer partial outputs to write and sum than with 1024.
-constexpr int64_t kMvTarget = ATTN_MV_TARGET;
 
 void mv_chunks(const MatvecPlan& P, const int* dm, const int64_t target[3], int out[3]) {
   int64_t nit[3] = {0, 0, 0}, units[3] = {1, 1, 1};

@@ -291,6 +291,12 @@ double* block_ptr(attn_handle* h, const BRef& b, double* comb_base, const std::v
 void slice_geom(int spect, const int* dm, int& ma, int& mb, int& ns, int64_t& sl, int64_t& row);
 // item chunks per spectator of the matvec plan of a node with dims dm
 // (target workgroups per launch, per spectator's slice shape)
+// matvec work units per spectator group (three groups per node): 3 x 768 =
+// three rounds of the 768 workgroups resident at three per CU.  Measured
+// against 1024 (four rounds) and 512: sweep 0.581 vs 0.584 and 0.582 s, and a
+// quarter fewer partial outputs to write and sum than with 1024.  The batched
+// form takes the same split unless it is autotuned.
+constexpr int64_t kMvTarget = 768;
 void mv_chunks(const MatvecPlan& P, const int* dm, const int64_t target[3], int out[3]);
 bool sw_mfma(int ma, int mb);
 // Doubles of the QR matrices of a handle whose widest link is mmax: G, R0, R1,

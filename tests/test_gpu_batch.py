@@ -68,21 +68,33 @@ def test_batch_fp64_matches_oracle_4x4():
 
 
 def test_batch_autotuned_without_graphs():
-    # the autotuned split changes only the summation grouping: FP32 energies
-    # after one sweep stay within FP32 rounding of the untuned run
-    from paper_2507_21236_amd import AttnBatch, ATTN_F32
+    # the autotuned split changes only the summation grouping of the FP32
+    # partial outputs.  From the random start such differences are amplified
+    # over a sweep like any rounding difference (measured 1e-5 to 1e-3 per site
+    # after one sweep), so both batches start from the state after four FP64
+    # sweeps, where the sweep is close to stationary and the two runs agree to
+    # 3e-9 per site (measured); held to 1e-7 per site over two sweeps
+    from paper_2507_21236_amd import AttnBatch, solver_opts, ATTN_F32, ATTN_F64
     insts = batch_instances(32)
     ps = [insts[i] for i in MIXED[:3]]
-    ref = AttnBatch(_handles(ps), precision=ATTN_F32)
-    e_ref, _ = ref.sweep(1)
-    hs = _handles(ps)
-    b = AttnBatch(hs, precision=ATTN_F32, use_graphs=False, autotune=True)
+
+    def started():
+        hs = _handles(ps)
+        for a in hs:
+            a.sweep(4, solver_opts(krylov_k=20, precision=ATTN_F64))
+        return hs
+
+    ref = AttnBatch(started(), precision=ATTN_F32)
+    e_ref, _ = ref.sweep(2)
+    b = AttnBatch(started(), precision=ATTN_F32, use_graphs=False, autotune=True)
     n_steps, n_units, tuned = b.info()
     print("tuned splits (ma, mb, target):", tuned, "steps", n_steps, "units", n_units)
     assert n_steps == max(p.n_sites - 1 for p in ps)
     assert len(tuned) > 0
-    e, _ = b.sweep(1)
+    e, _ = b.sweep(2)
     for i, p in enumerate(ps):
-        assert abs(e[i, 0] - e_ref[i, 0]) / p.n_sites < 1e-6, (i, e[i, 0], e_ref[i, 0])
+        d = np.abs(e[i] - e_ref[i]) / p.n_sites
+        print(f"instance {MIXED[i]}: |dE|/N {d}")
+        assert np.all(d < 1e-7), (i, e[i], e_ref[i])
     b.close()
     ref.close()
