@@ -48,10 +48,10 @@ PEAK_FP64 = 78.6   # TFLOP/s, MI355X dense FP64 (vector and matrix)
 # products per useful product, so its useful-flop ceiling is a third of 2.5 PF
 PEAKS = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0 / 3}
 KERNELS = {"f64": "k_sandwich<double,4>", "f32": "k_sandwich<float,4>",
-           "bf16x2": "k_sandwich_bf2w<4,4>"}
+           "bf16x2": "k_sandwich_bf2h<4,4>"}
 # HBM bytes per launch of the FP64 contraction kernel at legs of dimension 64,
 # averaged like the live timing over the 620 matvec launches of a sweep of
-# this workload (600 launches of 3072 workgroups at the (64,64,64) nodes, 20
+# this workload (600 launches of 2304 workgroups at the (64,64,64) nodes, 20
 # at the root):
 # rocprofv3 --pmc FETCH_SIZE (x 2) and WRITE_SIZE (x 1) on
 # `bench.py --traffic-probe`, the factors read off a plain 1 GiB device copy
@@ -59,7 +59,7 @@ KERNELS = {"f64": "k_sandwich<double,4>", "f32": "k_sandwich<float,4>",
 # kernel's partial outputs (one per item chunk, streaming stores); the reads
 # are X and the operator blocks.  Valid for the kernel as measured: None once
 # it changes.
-TRAFFIC_F64 = {"read": 64.4e6, "write": 108.2e6}
+TRAFFIC_F64 = {"read": 82.4e6, "write": 83.3e6}
 
 
 def host_info():
