@@ -665,7 +665,7 @@ void* to_mirror(attn_handle* h, const void* p, int fmt) {
   throw StatusFail{ATTN_ERR_STATE, "internal: block outside every store"};
 }
 
-// The register-blocked split-BF16 kernel keeps one workgroup of eight waves
+// The split-BF16 kernel at legs 64 x 64 keeps one workgroup of eight waves
 // resident per CU (two waves per SIMD), so a launch takes ceil(W / 256)
 // rounds of W workgroups.  Its tasks (copied from the FP64 plan, W = tasks x slices / 4)
 // are re-cut into fewer, longer item ranges so that W is a multiple of 512:
@@ -673,7 +673,7 @@ void* to_mirror(attn_handle* h, const void* p, int fmt) {
 // over fewer tasks in proportion to the class's item count, each new task
 // writing the partial output of one of the class's old tasks; the outputs
 // left unwritten are added to `dropped`.
-void rechunk_bf2h(SWGroup& g, std::vector<int>& ns_of, std::vector<RDSrc>& srcs, std::vector<const void*>& dropped) {
+void rechunk_bf16(SWGroup& g, std::vector<int>& ns_of, std::vector<RDSrc>& srcs, std::vector<const void*>& dropped) {
   (void)srcs;
   const int nt = (int)g.tasks.size();
   if (nt == 0) return;
@@ -791,7 +791,7 @@ void ensure_lowp(attn_handle* h, int dtype) {
         // one slice per wave: units of up to four consecutive slices of a task
         std::vector<int> ns_of(g.tasks.size(), 0);
         for (const int4& wu : g.wus) ns_of[wu.x] = std::max(ns_of[wu.x], wu.y + 1);
-        rechunk_bf2h(g, ns_of, L.srcs, dropped);
+        rechunk_bf16(g, ns_of, L.srcs, dropped);
         std::vector<int4> w2;
         for (size_t ti = 0; ti < g.tasks.size(); ti++)
           for (int s0 = 0; s0 < ns_of[ti]; s0 += 4) w2.push_back(make_int4((int)ti, s0, 0, std::min(4, ns_of[ti] - s0)));

@@ -608,34 +608,49 @@ __global__ __launch_bounds__(256) void k_sandwich_bf2w(const SWTask* __restrict_
   }
 }
 
-// Half-slice form for legs 64 x 64 (ma = 16 MA, mb = 16 NB): a work unit is up
-// to four slices, each computed by two waves, wave
-// 2 j + h owning the row strips [MA/2 h, MA/2 (h + 1)) of slice j with its
-// accumulators and stage-1 tiles in registers, so that every fragment of A and
-// B serves MA/2 (or NB) products; the split X_s stays in registers for the
-// whole item loop.  The eight waves share the item's operator blocks through
-// LDS: the blocks of item i + 1 are loaded from memory into registers while
-// item i is computed from LDS, then written to the other LDS buffer (double
-// buffering, one barrier per item).  With half a slice per wave the kernel
-// fits 256 registers per lane, two waves per SIMD (a whole slice per wave
-// takes 400 at legs 64, one wave per SIMD: 191 -> 242 useful TFLOP/s).  It is
-// launched at legs 64 x 64 only: its (32, 32) instance gave matvecs 0.5 off
-// (relative) on the device for a reason not found, while the wave-per-slice
-// form, which fits the registers there, is exact to the split's rounding.
-// wu = (task, first slice, -, number of slices <= 4).
+// s_waitcnt vmcnt(n) for n = 0 .. 4, the other counters left alone
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(0x0F70); break;
+    case 1: __builtin_amdgcn_s_waitcnt(0x0F71); break;
+    case 2: __builtin_amdgcn_s_waitcnt(0x0F72); break;
+    case 3: __builtin_amdgcn_s_waitcnt(0x0F73); break;
+    default: __builtin_amdgcn_s_waitcnt(0x0F74); break;
+  }
+}
+
+// Half-slice form at legs 64 x 64: a work unit is up to four slices, each
+// computed by two waves, wave 2 j + h owning the row strips [2 h, 2 h + 2) of
+// slice j with its accumulators and stage-1 tiles in registers (every A or B
+// fragment serves two or four products; the split X_s stays in registers for
+// the whole item loop), so that two waves per SIMD fit (a whole 64 x 64 slice
+// per wave takes 400 registers, one wave per SIMD: 191 useful TFLOP/s, half a
+// slice per wave with the blocks brought through registers 241, this form
+// 291).  The eight waves share every item's operator blocks, moved from memory
+// straight into LDS (the gfx950 loads that write LDS, 16 bytes per lane), so
+// that no registers hold them in flight and the blocks of item i + 2 load
+// while item i is computed (three LDS buffers of 32 KiB: A hi, A lo, B hi,
+// B lo).  It is launched at legs 64 x 64 only: a (32, 32) instance of the
+// half-slice form gave matvecs 0.5 off (relative) on the device, for a reason
+// not found, while the wave-per-slice form fits the registers at legs 32.  A plane is stored without padding, the 16-byte column k of row r
+// at position k ^ ((r >> 1) & 7): a load instruction fills 1 KiB of LDS
+// contiguously (8 rows), each lane fetching the global column that belongs
+// at its position, and the 16 rows read by one MFMA operand fall on distinct
+// banks.  Waits are explicit: the compiler does not order these loads
+// against the LDS reads of other buffers, and needs not; the loads of item
+// i + 1 are older than the ones of item i + 2, so a wave waits until at most
+// the latter are outstanding, then all waves meet at a barrier.  Same
+// products in the same order as the wave-per-slice form.
 template <int MA, int NB>
-__global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict__ tasks,
+__global__ __launch_bounds__(512) void k_sandwich_bf2d(const SWTask* __restrict__ tasks,
                                                        const SWItem* __restrict__ items,
                                                        const int4* __restrict__ wus,
                                                        const float* __restrict__ xbase) {
-  constexpr int ma = 16 * MA, mb = 16 * NB, CA = ma / 32, CB = mb / 32, MW = MA / 2;
-  constexpr int lda = ma + 8, ldb = mb + 8;
-  constexpr int SA = ma * lda, SB = mb * ldb;
-  constexpr int BUF = 2 * SA + 2 * SB;
-  constexpr int NA = ma * ma / 8, NBC = mb * mb / 8;
-  constexpr int NTOT = 2 * NA + 2 * NBC, NPT = (NTOT + 511) / 512;
+  static_assert(MA == 4 && NB == 4, "legs 64 x 64 only");
+  constexpr int m = 64, CA = 2, CB = 2, MW = 2;
+  constexpr int PLANE = m * m * 2;   // bytes of one 64 x 64 BF16 plane
+  constexpr int BUFB = 4 * PLANE;    // one item
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __bf16* lds = reinterpret_cast<__bf16*>(smem_raw);
   const int4 wu = wus[blockIdx.x];
   const SWTask& t = tasks[wu.x];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -656,32 +671,28 @@ __global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict_
         xh[c][q][j] = hi;
         xl[c][q][j] = (__bf16)(v - (float)hi);
       }
-  bf8 pre[NPT];
-  auto fetch = [&](int it) {
-    const __bf16* A = (const __bf16*)items[it].A;
-    const __bf16* B = (const __bf16*)items[it].B;
+  // wave w moves 1-KiB chunks 4 w .. 4 w + 3 of an item: plane w / 2, row blocks
+  // 4 (w % 2) .. + 3; lane L takes row L / 8 of the block and LDS position L % 8
+  const int wv = __builtin_amdgcn_readfirstlane(wave);   // wave-uniform: block pointers in scalar registers
+  const int pl = wv >> 1, drow = lane >> 3, dpos = lane & 7;
+  auto dma = [&](int it, int buf) -> int {
+    const void* pa = items[it].A;
+    const void* pb = items[it].B;
+    const __bf16* base = (const __bf16*)(pl < 2 ? pa : pb);
+    if (!base) return 0;
+    base += (pl & 1) * m * m;
+    unsigned char* dst = smem_raw + buf * BUFB + pl * PLANE;
 #pragma unroll
-    for (int r = 0; r < NPT; r++) {
-      const int ch = tid + 512 * r;
-      const __bf16* src = nullptr;
-      if (ch < 2 * NA) src = A ? A + (int64_t)ch * 8 : nullptr;
-      else if (ch < NTOT) src = B ? B + (int64_t)(ch - 2 * NA) * 8 : nullptr;
-      if (src) pre[r] = *(const bf8*)src;
+    for (int r = 0; r < 4; r++) {
+      const int rb = 4 * (wv & 1) + r, row = 8 * rb + drow;
+      const __bf16* src = base + row * m + 8 * (dpos ^ ((row >> 1) & 7));
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                       (__attribute__((address_space(3))) void*)(dst + rb * 1024), 16, 0, 0);
     }
+    return 4;
   };
-  auto store = [&](int buf) {
-    __bf16* L = lds + buf * BUF;
-#pragma unroll
-    for (int r = 0; r < NPT; r++) {
-      const int ch = tid + 512 * r;
-      if (ch < 2 * NA) {
-        const int e = ch * 8, plane = e / (ma * ma), w = e - plane * ma * ma;
-        *(bf8*)(L + plane * SA + (w / ma) * lda + w % ma) = pre[r];
-      } else if (ch < NTOT) {
-        const int e = (ch - 2 * NA) * 8, plane = e / (mb * mb), w = e - plane * mb * mb;
-        *(bf8*)(L + 2 * SA + plane * SB + (w / mb) * ldb + w % mb) = pre[r];
-      }
-    }
+  auto frag = [&](const unsigned char* plane, int row, int k) -> bf8 {
+    return *(const bf8*)(plane + row * 128 + ((k ^ ((row >> 1) & 7)) << 4));
   };
   f4 acc[MW][NB];
 #pragma unroll
@@ -689,20 +700,30 @@ __global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict_
 #pragma unroll
     for (int q = 0; q < NB; q++) acc[a][q] = f4{0, 0, 0, 0};
   const int i0 = t.item0, i1 = t.item0 + t.nitem;
-  if (i0 < i1) {
-    fetch(i0);
-    store(0);
-  }
-  __syncthreads();
+  if (i0 < i1) dma(i0, 0);
+  const int n1 = i0 + 1 < i1 ? dma(i0 + 1, 1) : 0;
+  wait_vm(n1);
+  __builtin_amdgcn_s_barrier();
   for (int it = i0; it < i1; it++) {
-    const int buf = (it - i0) & 1;
-    if (it + 1 < i1) fetch(it + 1);
+    const int k0 = it - i0;
     const bool hasA = items[it].A != nullptr, hasB = items[it].B != nullptr;
     const float coef = (float)items[it].coef;
-    const __bf16* LA = lds + buf * BUF;
-    const __bf16* LB = LA + 2 * SA;
+    const unsigned char* LB = smem_raw + (k0 % 3) * BUFB;
+    f4 t1[MW][NB];
+    // without A the stage-1 result is the scaled slice itself, read from memory
+    // before this iteration's block loads are issued (so that waiting for it
+    // does not wait for them)
+    if (active && !hasA) {
+#pragma unroll
+      for (int a = 0; a < MW; a++)
+#pragma unroll
+        for (int q = 0; q < NB; q++)
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+            t1[a][q][i] = coef * X[(int64_t)(16 * (a0 + a) + l16) * t.xs_row + 16 * q + drow_bf(g, i)];
+    }
+    const int n2 = it + 2 < i1 ? dma(it + 2, (k0 + 2) % 3) : 0;
     if (active) {
-      f4 t1[MW][NB];
       if (hasA) {
 #pragma unroll
         for (int a = 0; a < MW; a++)
@@ -713,9 +734,9 @@ __global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict_
           bf8 ah[MW], al[MW];
 #pragma unroll
           for (int a = 0; a < MW; a++) {
-            const int off = (16 * (a0 + a) + l16) * lda + 32 * c + 8 * g;
-            ah[a] = *(const bf8*)(LA + off);
-            al[a] = *(const bf8*)(LA + SA + off);
+            const int row = 16 * (a0 + a) + l16;
+            ah[a] = frag(LB, row, 4 * c + g);
+            al[a] = frag(LB + PLANE, row, 4 * c + g);
           }
 #pragma unroll
           for (int a = 0; a < MW; a++)
@@ -730,14 +751,6 @@ __global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict_
         for (int a = 0; a < MW; a++)
 #pragma unroll
           for (int q = 0; q < NB; q++) t1[a][q] *= coef;
-      } else {
-#pragma unroll
-        for (int a = 0; a < MW; a++)
-#pragma unroll
-          for (int q = 0; q < NB; q++)
-#pragma unroll
-            for (int i = 0; i < 4; i++)
-              t1[a][q][i] = coef * X[(int64_t)(16 * (a0 + a) + l16) * t.xs_row + 16 * q + drow_bf(g, i)];
       }
       if (hasB) {
 #pragma unroll
@@ -753,9 +766,9 @@ __global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict_
             }
 #pragma unroll
           for (int tq = 0; tq < NB; tq++) {
-            const int off = (16 * tq + l16) * ldb + 32 * c + 8 * g;
-            const bf8 bh = *(const bf8*)(LB + off);
-            const bf8 bl = *(const bf8*)(LB + SB + off);
+            const int row = 16 * tq + l16;
+            const bf8 bh = frag(LB + 2 * PLANE, row, 4 * c + g);
+            const bf8 bl = frag(LB + 3 * PLANE, row, 4 * c + g);
 #pragma unroll
             for (int a = 0; a < MW; a++) {
               acc[a][tq] = mfma_bf(bh, th[a], acc[a][tq]);
@@ -771,8 +784,12 @@ __global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict_
           for (int q = 0; q < NB; q++) acc[a][q] += t1[a][q];
       }
     }
-    if (it + 1 < i1) store(buf ^ 1);
-    __syncthreads();
+    // the blocks of item it + 1 (issued one iteration ago) have landed once at
+    // most the n2 loads of item it + 2 are outstanding; then nobody reads buffer
+    // k0 % 3 any more either, which item it + 3 will overwrite
+    wait_vm(n2);
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS reads are done
+    __builtin_amdgcn_s_barrier();
   }
   if (!active) return;
 #pragma unroll
@@ -789,9 +806,9 @@ __global__ __launch_bounds__(512) void k_sandwich_bf2h(const SWTask* __restrict_
   }
 }
 
-// LDS of both the wave-per-slice and the half-slice form
+// LDS of the wave-per-slice form: two buffers of one item's four padded planes
 template <int MA, int NB>
-constexpr size_t bf2h_lds() { return (size_t)2 * (2 * 16 * MA * (16 * MA + 8) + 2 * 16 * NB * (16 * NB + 8)) * 2; }
+constexpr size_t bf2w_lds() { return (size_t)2 * (2 * 16 * MA * (16 * MA + 8) + 2 * 16 * NB * (16 * NB + 8)) * 2; }
 
 // ============================================================================ mixed-shape launches
 // One launch over the work units of many tasks of different shapes (several
@@ -844,7 +861,7 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
   if (dtype == 3) {   // split BF16, one slice per wave (legs 32 or 64)
 #define BF2W(MA, NB)                                                                             \
   {                                                                                              \
-    const size_t lds = bf2h_lds<MA, NB>();                                                       \
+    const size_t lds = bf2w_lds<MA, NB>();                                                       \
     hipLaunchKernelGGL((k_sandwich_bf2w<MA, NB>), dim3(nwu), dim3(256), lds, s, tasks, items, wus, \
                        (const float*)xbase);                                                     \
     return hipGetLastError();                                                                    \
@@ -854,8 +871,8 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
     if (ma == 64 && mb == 32) BF2W(4, 2)
 #undef BF2W
     if (ma == 64 && mb == 64) {
-      const size_t lds = bf2h_lds<4, 4>();
-      hipLaunchKernelGGL((k_sandwich_bf2h<4, 4>), dim3(nwu), dim3(512), lds, s, tasks, items, wus,
+      const size_t lds = 3 * 4 * 64 * 64 * sizeof(__bf16);   // three buffers of one item's four planes
+      hipLaunchKernelGGL((k_sandwich_bf2d<4, 4>), dim3(nwu), dim3(512), lds, s, tasks, items, wus,
                          (const float*)xbase);
       return hipGetLastError();
     }
@@ -932,7 +949,7 @@ hipError_t prepare_sandwich_attributes() {
       (const void*)k_sandwich<float, 7>, (const void*)k_sandwich<float, 8>,
       (const void*)k_sandwich_bf2<2>, (const void*)k_sandwich_bf2<4>,
       (const void*)k_sandwich_bf2w<2, 2>, (const void*)k_sandwich_bf2w<2, 4>,
-      (const void*)k_sandwich_bf2w<4, 2>, (const void*)k_sandwich_bf2h<4, 4>,
+      (const void*)k_sandwich_bf2w<4, 2>, (const void*)k_sandwich_bf2d<4, 4>,
       (const void*)k_sandwich_bf2<6>, (const void*)k_sandwich_bf2<8>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
