@@ -405,6 +405,64 @@ def learned_form(a, p, tol, n_nodes=2, pairs=6, steps=1500):
         out[name]["dE_per_site_vs_lanczos_k20"] = (out[name]["energy"] - out["lanczos_k20"]["energy"]) / N
     out["speedup_learned_vs_jacobi"] = round(out["davidson_jacobi"]["sweep_s"] /
                                              out["davidson_learned"]["sweep_s"], 3)
+    out["_weights"] = w
+    return out
+
+
+def learned_form_32x32(w, tol=1e-7, n_nodes=2):
+    """The learned form where it is meant to pay: 32 x 32 Ising, m = 128 (1023
+    nodes, H_eff applications up to 2.6 TFLOP).  At the heaviest full nodes,
+    from the seeded initial tensors: the k = 20 Lanczos eigensolve, and Davidson
+    (subspace 32, restart to 8) with Jacobi and with learned corrections, both
+    to ||r|| <= tol (matched residual); the model is the one trained on the
+    16 x 16, m = 64 harvest.  Times are per eigensolve with the device
+    synchronised around it."""
+    import torch
+    from problems import config_problem
+    from paper_2507_21236_amd import (AttnHandle, solver_opts, ATTN_SOLVER_DAVIDSON,
+                                      ATTN_PRECOND_JACOBI, ATTN_PRECOND_LEARNED)
+    t0 = time.time()
+    p = config_problem("ising32_m128")
+    a = AttnHandle(p)
+    a.init_state()
+    t_build = time.time() - t0
+    a.set_precond_weights(w)
+    full = [n for n in range(a.n_nodes) if tuple(a.node_info(n)[0]) == (128, 128, 128)]
+    nodes = sorted(full, key=lambda q: -a.node_info(q)[2])[:n_nodes]
+    runs = {"lanczos_k20": solver_opts(krylov_k=20),
+            "davidson_jacobi": solver_opts(solver=ATTN_SOLVER_DAVIDSON, krylov_k=32, tol=tol,
+                                           precond=ATTN_PRECOND_JACOBI, max_iter=400, restart=8),
+            "davidson_learned": solver_opts(solver=ATTN_SOLVER_DAVIDSON, krylov_k=32, tol=tol,
+                                            precond=ATTN_PRECOND_LEARNED, max_iter=400, restart=8)}
+    out = {"workload": "ising32x32_h3.05_m128_de256_seed5", "build_s": round(t_build, 1),
+           "tol_residual": tol, "nodes": []}
+    tot = {k: 0.0 for k in runs}
+    for n in nodes:
+        a.move_center(n)
+        T0 = a.get_tensor(n)
+        rec = {"node": int(n), "gflop_per_matvec": round(a.node_info(n)[2] / 1e9, 1)}
+        for name, o in runs.items():
+            a.set_tensor(n, T0)
+            nmv0 = a.counters()[0]
+            it0, fb0, _, _ = a.solver_stats()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            th, _ = a.eigsolve(n, o)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            it1, fb1, res, _ = a.solver_stats()
+            rec[name] = {"s": round(dt, 3), "matvecs": int(a.counters()[0] - nmv0), "theta": float(th)}
+            if name != "lanczos_k20":
+                rec[name]["residual"] = float(res)
+                rec[name]["fallbacks_to_jacobi"] = int(fb1 - fb0)
+            tot[name] += dt
+            print(f"[bench] 32x32 m=128 node {n} {name}: {dt:.2f} s, theta {th:.12f}, "
+                  f"matvecs {rec[name]['matvecs']}", file=sys.stderr, flush=True)
+        out["nodes"].append(rec)
+        a.set_tensor(n, T0)
+    out["total_s"] = {k: round(v, 3) for k, v in tot.items()}
+    out["speedup_learned_vs_jacobi"] = round(tot["davidson_jacobi"] / tot["davidson_learned"], 3)
+    a.close()
     return out
 
 
@@ -473,6 +531,8 @@ def main():
                     help="timed H_eff applications per full node after the sweeps (0 to skip)")
     ap.add_argument("--learned-tol", type=float, default=1e-5,
                     help="Davidson residual tolerance of the learned-form comparison (0 to skip)")
+    ap.add_argument("--learned-32x32", type=int, default=1,
+                    help="also time the learned form at the heaviest 32 x 32 m = 128 nodes (0 = skip)")
     ap.add_argument("--batch-sweeps", type=int, default=2,
                     help="timed sweeps of the batched-form comparison (0 to skip)")
     ap.add_argument("--converge-cap", type=int, default=150,
@@ -691,6 +751,9 @@ def main():
     if args.learned_tol > 0:
         out["forms"] = out.get("forms", {})
         out["forms"]["learned"] = learned_form(a, p, args.learned_tol)
+        w = out["forms"]["learned"].pop("_weights")
+        if args.learned_32x32:
+            out["forms"]["learned"]["ising32x32_m128"] = learned_form_32x32(w)
     if args.batch_sweeps > 0:
         out["forms"] = out.get("forms", {})
         out["forms"]["batched"] = batched_form(args.batch_sweeps, 1)
