@@ -48,7 +48,7 @@ PEAK_FP64 = 78.6   # TFLOP/s, MI355X dense FP64 (vector and matrix)
 # products per useful product, so its useful-flop ceiling is a third of 2.5 PF
 PEAKS = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0 / 3}
 KERNELS = {"f64": "k_sandwich<double,4>", "f32": "k_sandwich<float,4>",
-           "bf16x2": "k_sandwich_bf2h<4,4>"}
+           "bf16x2": "k_sandwich_bf2d<4,4>"}
 # HBM bytes per launch of the FP64 contraction kernel at legs of dimension 64,
 # averaged like the live timing over the 620 matvec launches of a sweep of
 # this workload (600 launches of 2304 workgroups at the (64,64,64) nodes, 20
