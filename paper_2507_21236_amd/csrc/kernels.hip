@@ -2771,8 +2771,12 @@ hipError_t prepare_kernel_attributes() {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
   }
-  hipError_t e = hipFuncSetAttribute((const void*)k_tiny_lanczos_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)kTinyWaveLds);
+  // the LDS form of the Cholesky kernel keeps n (n + 1) doubles: 74 KiB at n = 96, 129 KiB at n = 128
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_inv<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     128 * 129 * (int)sizeof(double));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_tiny_lanczos_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)kTinyWaveLds);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_tiny_lanczos_block<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)kTinyLdsMax);
