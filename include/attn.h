@@ -54,7 +54,7 @@ typedef int32_t attn_status;
 #define ATTN_ERR_STATE          -8   /* call not valid in the current state (see each call) */
 #define ATTN_ERR_SHAPE          -9   /* buffer length does not match the tensor size */
 #define ATTN_ERR_NUMERIC       -10   /* NaN / Inf, or a factorisation broke down */
-#define ATTN_ERR_UNSUPPORTED   -11   /* valid input outside what this build implements */
+#define ATTN_ERR_UNSUPPORTED   -11   /* valid input outside what this library implements */
 #define ATTN_ERR_IO            -12   /* a file cannot be opened, read or written, or is corrupt */
 #define ATTN_ERR_MISMATCH      -13   /* a checkpoint belongs to another problem */
 
