@@ -94,7 +94,9 @@ def cpu_baseline(problem, sample_matvecs=3, plan_sweeps=5):
     matvecs there (after one untimed warm-up matvec) with the BLAS limited to
     4 threads (the paper's per-simulation allocation) and with all of its
     threads; then `plan_sweeps` whole oracle sweeps of the 4 x 4 m = 8 Ising
-    instance.  Returns the dict for the JSON line (value: all threads)."""
+    instance and one of the 8 x 8 m = 32 instance (the oracle sweep of the
+    16 x 16 workload itself takes about 1000 s and is left out).  Returns the
+    dict for the JSON line (value: all threads)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle.ttn import OracleTTN
@@ -127,6 +129,12 @@ def cpu_baseline(problem, sample_matvecs=3, plan_sweeps=5):
     t2 = time.time()
     e4 = [o4.sweep() for _ in range(plan_sweeps)]
     t4 = (time.time() - t2) / plan_sweeps
+    q8 = config_problem("ising8_m32")
+    o8 = OracleTTN(q8.n_sites, q8.d, q8.m, q8.leaf_order, q8.terms, q8.de_sites, q8.de_u, q8.raw_tensors)
+    t2 = time.time()
+    e8 = o8.sweep()
+    t8 = time.time() - t2
+    print(f"[bench] oracle sweeps: 4x4 m=8 {t4:.3f} s, 8x8 m=32 {t8:.1f} s", file=sys.stderr, flush=True)
     return {"value": by_threads[str(all_threads)], "unit": "TFLOP/s", "cores": all_threads,
             "kind": "oracle",
             "sample": (f"{sample_matvecs} FP64 oracle matvecs (after one warm-up) at the heaviest "
@@ -136,6 +144,8 @@ def cpu_baseline(problem, sample_matvecs=3, plan_sweeps=5):
             "tflops_by_blas_threads": by_threads,
             "ising4_m8_oracle_sweep_s": round(t4, 4),
             "ising4_m8_oracle_energies": e4,
+            "ising8_m32_oracle_sweep_s": round(t8, 2),
+            "ising8_m32_oracle_energy_sweep1": e8,
             "host": hi}
 
 
@@ -506,6 +516,56 @@ def node_matvec_timing(a, warm=10, reps=100):
             "per_node": per}
 
 
+def small_leg_matvecs(warm=10, reps=100):
+    """H_eff matvec at the full nodes of the 8 x 8 Ising workload at m = 16 and
+    m = 32 (legs (16,16,16) and (32,32,32): small contractions, bound by
+    latency rather than the matrix cores), FP64 and FP32 operands, timed like
+    the full nodes of the main workload (HIP events, median per node); the
+    aggregate is sum F / sum of the median times."""
+    import torch
+    from problems import config_problem
+    from paper_2507_21236_amd import AttnHandle, ATTN_F64, ATTN_F32
+    stream = torch.cuda.current_stream()
+    gen = torch.Generator(device="cuda").manual_seed(2)
+    out = {}
+    for key in ("ising8_m16", "ising8_m32"):
+        p = config_problem(key)
+        a = AttnHandle(p)
+        a.init_state()
+        full = [n for n in range(a.n_nodes) if tuple(a.node_info(n)[0]) == (p.m,) * 3]
+        rec = {"full_nodes": len(full)}
+        for name, dt, tdt in (("f64", ATTN_F64, torch.float64), ("f32", ATTN_F32, torch.float32)):
+            tot_f, tot_t, meds = 0.0, 0.0, []
+            for n in full:
+                a.move_center(n)
+                dims, _, flops = a.node_info(n)
+                x = torch.randn(int(dims[0]) * int(dims[1]) * int(dims[2]), dtype=tdt, device="cuda",
+                                generator=gen)
+                y = torch.empty_like(x)
+                for _ in range(warm):
+                    a.heff_apply(n, x, y, dtype=dt, stream=stream.cuda_stream)
+                evs = []
+                for _ in range(reps):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    a.heff_apply(n, x, y, dtype=dt, stream=stream.cuda_stream)
+                    e1.record(stream)
+                    evs.append((e0, e1))
+                torch.cuda.synchronize()
+                ts = sorted(e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs)
+                med = ts[len(ts) // 2]
+                meds.append(round(med * 1e6, 1))
+                tot_f += flops
+                tot_t += med
+            rec[name] = {"median_us_per_node": meds, "aggregate_tflops": round(tot_f / tot_t / 1e12, 3),
+                         "gflop_per_node": round(tot_f / len(full) / 1e9, 3)}
+        out[key] = rec
+        print(f"[bench] {key}: FP64 {rec['f64']['aggregate_tflops']} TFLOP/s, FP32 "
+              f"{rec['f32']['aggregate_tflops']} TFLOP/s over {len(full)} full nodes", file=sys.stderr, flush=True)
+        a.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,6 +591,8 @@ def main():
                     help="timed H_eff applications per full node after the sweeps (0 to skip)")
     ap.add_argument("--learned-tol", type=float, default=1e-5,
                     help="Davidson residual tolerance of the learned-form comparison (0 to skip)")
+    ap.add_argument("--small-legs", type=int, default=1,
+                    help="time the matvec at the full nodes of 8 x 8 m = 16 and 32 (0 = skip)")
     ap.add_argument("--learned-32x32", type=int, default=1,
                     help="also time the learned form at the heaviest 32 x 32 m = 128 nodes (0 = skip)")
     ap.add_argument("--batch-sweeps", type=int, default=2,
@@ -754,6 +816,8 @@ def main():
         w = out["forms"]["learned"].pop("_weights")
         if args.learned_32x32:
             out["forms"]["learned"]["ising32x32_m128"] = learned_form_32x32(w)
+    if args.small_legs:
+        out["matvec_small_legs"] = small_leg_matvecs()
     if args.batch_sweeps > 0:
         out["forms"] = out.get("forms", {})
         out["forms"]["batched"] = batched_form(args.batch_sweeps, 1)
