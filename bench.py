@@ -152,7 +152,8 @@ def cpu_baseline(problem, sample_matvecs=3, plan_sweeps=5):
 def batched_form(sweeps, warmup):
     """32 uneven instances (L in {8, 12, 16}, m in {16, 32, 48, 64}, seeded):
     plain per-instance FP64 sweeps vs lock-step batched sweeps (mixed-shape
-    launches, HIP graphs, autotuned splits) in FP32 and FP64."""
+    launches or one persistent launch per matvec, HIP graphs, autotuned
+    splits) in FP32 and FP64."""
     import numpy as np
     import torch
     from problems import batch_instances
@@ -179,11 +180,12 @@ def batched_form(sweeps, warmup):
             es.append(e)
         return tot / sweeps, es
 
-    def batched(prec, autotune):
+    def batched(prec, autotune, persistent=False):
         for a in hs:
             a.init_state()
         t = time.perf_counter()
-        b = AttnBatch(hs, krylov_k=20, precision=prec, use_graphs=True, autotune=autotune)
+        b = AttnBatch(hs, krylov_k=20, precision=prec, use_graphs=True, autotune=autotune,
+                      persistent=persistent)
         t_create = time.perf_counter() - t
         for _ in range(warmup):   # also captures the step graphs
             b.sweep(1)
@@ -213,6 +215,12 @@ def batched_form(sweeps, warmup):
     b32t, e_b32t, c32t, tuned = batched(ATTN_F32, True)
     print(f"[bench] batched FP32 sweeps, autotuned splits: {b32t:.3f} s (create + autotune {c32t:.1f} s)",
           file=sys.stderr, flush=True)
+    # one persistent launch per matvec: the same unit bodies and reduction
+    # order as the staged launches, so the same energies bit for bit
+    p64, e_p64, _, _ = batched(ATTN_F64, False, True)
+    print(f"[bench] batched FP64 sweeps, persistent matvec: {p64:.3f} s", file=sys.stderr, flush=True)
+    p32, e_p32, _, _ = batched(ATTN_F32, False, True)
+    print(f"[bench] batched FP32 sweeps, persistent matvec: {p32:.3f} s", file=sys.stderr, flush=True)
     n_sites = np.array([p.n_sites for p in ps], dtype=float)
 
     def maxdev(ea, eb):
@@ -232,6 +240,13 @@ def batched_form(sweeps, warmup):
            "max_abs_dE_per_site_batched_f64_vs_per_instance_f64": maxdev(e_b64, e_seq64),
            "max_abs_dE_per_site_batched_f32_vs_per_instance_f32": maxdev(e_b32, e_seq32),
            "max_abs_dE_per_site_batched_f32_autotuned_vs_per_instance_f32": maxdev(e_b32t, e_seq32),
+           "batched_f64_persistent_s_per_sweep": round(p64, 4),
+           "batched_f32_persistent_s_per_sweep": round(p32, 4),
+           "speedup_persistent_vs_staged_f64": round(b64 / p64, 3),
+           "speedup_persistent_vs_staged_f32": round(b32 / p32, 3),
+           "speedup_batched_f32_persistent_vs_per_instance_f64": round(seq64 / p32, 3),
+           "persistent_energies_identical_to_staged": bool(np.array_equal(e_p64, e_b64)
+                                                           and np.array_equal(e_p32, e_b32)),
            "autotuned_splits_ma_mb_target": tuned,
            "batch_create_autotune_s": round(c32t, 2)}
     for a in hs:

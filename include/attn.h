@@ -344,7 +344,12 @@ attn_status attn_mlp_eval(const float* params, const float* feats, float* out, i
  * over one work list (all terms of every active node: two-leg terms and local
  * operators in one launch, each stage of the three-leg chains in one launch,
  * every Krylov vector step in one launch); the centre moves of different
- * instances run concurrently on four streams.  With use_graphs each step is
+ * instances run concurrently on four streams.  With persistent, each matvec
+ * of a step is instead ONE launch: a resident grid takes the units of all
+ * instances (transposes, chain stages, two-leg tiles, reduction tiles) from
+ * one ordered work list by ticket, and a unit that needs earlier results waits
+ * on a per-instance counter of the units it depends on, which always come
+ * earlier in the list.  With use_graphs each step is
  * captured once as a HIP graph and replayed in later sweeps.  With autotune the
  * work split of the two-leg launches is chosen per leg shape (ma, mb) by timing
  * candidate splits over all steps at creation.  Without autotuning the split is
@@ -361,9 +366,12 @@ typedef struct attn_batch_opts {
   int32_t precision;   /* ATTN_F64 or ATTN_F32 operands; Krylov steps stay FP64 */
   int32_t use_graphs;  /* 1: capture every step as a HIP graph */
   int32_t autotune;    /* 1: time candidate work splits per leg shape at creation */
+  int32_t persistent;  /* 1: each matvec of a step is one launch of a resident grid
+                          over an ordered work list of all instances' units
+                          (same results bit for bit as the staged launches) */
 } attn_batch_opts;
 
-/* opts may be NULL (k = 20, FP32, graphs, no autotuning).  *out is owned by the
+/* opts may be NULL (k = 20, FP32, graphs, no autotuning, staged launches).  *out is owned by the
  * caller (attn_batch_destroy).  Errors: ARG, STATE (handle not on a device),
  * UNSUPPORTED (mixed d or devices, legs above 64, BF16X2), HIP, OOM. */
 attn_status attn_batch_create(attn_handle* const* hs, int32_t n, const attn_batch_opts* opts,
@@ -372,7 +380,8 @@ attn_status attn_batch_create(attn_handle* const* hs, int32_t n, const attn_batc
 /* n_sweeps lock-step sweeps.  energies[i * n_sweeps + s] = theta at the last
  * node (root) of instance i in sweep s; seconds[s] = wall time of sweep s.
  * Either array may be NULL.  Errors: STATE (a handle is not in the sweep start
- * state), NUMERIC, HIP. */
+ * state), NUMERIC, HIP (also when a wait inside a persistent matvec ran past
+ * its limit of about a second; the batch is then unusable). */
 attn_status attn_batch_sweep(attn_batch* b, int32_t n_sweeps, double* energies, double* seconds);
 
 /* Number of steps, sandwich work units per sweep-step matvec summed over steps,

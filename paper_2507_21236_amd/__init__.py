@@ -154,10 +154,11 @@ class AttnBatch:
     """Lock-step sweeps of several AttnHandle instances (borrowed: keep them
     alive and do not use them while the batch sweeps)."""
 
-    def __init__(self, handles, krylov_k=20, precision=ATTN_F32, use_graphs=True, autotune=False):
+    def __init__(self, handles, krylov_k=20, precision=ATTN_F32, use_graphs=True, autotune=False,
+                 persistent=False):
         self.handles = list(handles)
         self.b = _lib.attn_batch_create([a.h for a in self.handles], krylov_k, precision,
-                                        use_graphs, autotune)
+                                        use_graphs, autotune, persistent)
 
     def sweep(self, n_sweeps):
         """(energies [n_instances][n_sweeps], seconds [n_sweeps])"""

@@ -80,7 +80,8 @@ ATTN_DE_MERA, ATTN_DE_RCG = 0, 1
 
 class attn_batch_opts(ctypes.Structure):
     _fields_ = [("krylov_k", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("use_graphs", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("use_graphs", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("persistent", ctypes.c_int32)]
 
 
 _H = ctypes.c_void_p
@@ -293,9 +294,10 @@ def _bcheck(code, b):
         raise AttnError(code, (_lib.attn_batch_last_error(b) or b"").decode())
 
 
-def attn_batch_create(handles, krylov_k=20, precision=ATTN_F32, use_graphs=True, autotune=False):
+def attn_batch_create(handles, krylov_k=20, precision=ATTN_F32, use_graphs=True, autotune=False,
+                      persistent=False):
     arr = (_H * len(handles))(*handles)
-    o = attn_batch_opts(krylov_k, precision, int(use_graphs), int(autotune))
+    o = attn_batch_opts(krylov_k, precision, int(use_graphs), int(autotune), int(persistent))
     b = _H()
     _bcheck(_lib.attn_batch_create(arr, len(handles), ctypes.byref(o), ctypes.byref(b)), None)
     return b.value

@@ -1,8 +1,10 @@
 // Batched form: many independent problem instances (each its own handle, of
 // any size) swept in lock step.  Step t moves every instance's isometry centre
 // to its node t (post-order) and solves that node; the eigensolver work of all
-// instances in a step is merged into mixed-shape launches over one work list,
-// and each step is captured once as a HIP graph and replayed in later sweeps.
+// instances in a step is merged into mixed-shape launches over one work list
+// (or, in the persistent form, each matvec of the step into one launch over an
+// ordered work list), and each step is captured once as a HIP graph and
+// replayed in later sweeps.
 #include "runtime.hpp"
 
 struct attn_batch {
@@ -12,7 +14,10 @@ struct attn_batch {
   int precision = ATTN_F32;
   int krylov_k = 20;
   bool use_graphs = true;
+  bool persistent = false;
   bool dead = false;
+  int n_cu = 0;
+  int32_t* d_pm = nullptr;   // [0] abort word, then the counters of the persistent matvec
   std::vector<void*> owned;
   std::vector<double*> x64;   // FP64 form: per-instance copy of the newest basis vector
   hipStream_t s[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -35,6 +40,13 @@ struct attn_batch {
     std::vector<RDSrc> rd_srcs;
     std::vector<RDTask> rd;
     int64_t rd_max = 0;
+    // instance of every task (persistent form)
+    std::vector<int> sw_inst, mp_inst[3], tr_inst, rd_inst;
+    std::vector<PUnit> pu;
+    std::vector<int32_t> tickets;
+    int pm_grid = 0;
+    size_t pm_lds = 0;
+    PMArgs pm;
     // device copies
     SWTask* d_sw_tasks = nullptr;
     SWItem* d_sw_items = nullptr;
@@ -45,6 +57,8 @@ struct attn_batch {
     TRTask* d_tr = nullptr;
     RDSrc* d_rd_srcs = nullptr;
     RDTask* d_rd = nullptr;
+    PUnit* d_pu = nullptr;
+    int32_t* d_tickets = nullptr;
   };
 
   struct Step {
@@ -232,6 +246,99 @@ void upload_merged(attn_batch* b, attn_batch::Merged& m) {
   m.d_rd_srcs = bupload(b, m.rd_srcs);
   for (RDTask& t : m.rd) t.srcs = m.d_rd_srcs + (size_t)(uintptr_t)t.srcs;   // offsets -> pointers
   m.d_rd = bupload(b, m.rd);
+  m.d_pu = bupload(b, m.pu);
+  m.d_tickets = bupload(b, m.tickets);
+  std::memset(&m.pm, 0, sizeof(m.pm));
+  m.pm.units = m.d_pu;
+  m.pm.tickets = m.d_tickets;
+  m.pm.n_tickets = m.tickets.empty() ? 0 : (int32_t)m.tickets.size() - 1;
+  m.pm.n_units = (int32_t)m.pu.size();
+  m.pm.n_cnt = kPmFirst + 4 * (int32_t)b->hs.size();
+  m.pm.cnt = b->d_pm ? b->d_pm + 1 : nullptr;
+  m.pm.abort = b->d_pm;
+  m.pm.sw_tasks = m.d_sw_tasks;
+  m.pm.sw_items = m.d_sw_items;
+  for (int k = 0; k < 3; k++) {
+    m.pm.mp_tasks[k] = m.d_mp_tasks[k];
+    m.pm.mp_jobs[k] = m.d_mp_jobs[k];
+  }
+  m.pm.tr = m.d_tr;
+  m.pm.rd = m.d_rd;
+}
+
+// Ordered work list of the persistent matvec.  Counters per instance i:
+// 4 i + {0: transposes, 1: chain stage 1, 2: chain stage 2, 3: partial and
+// chain outputs}.  Order: transposes, chain stage 1, sandwiches, stage 2,
+// stage 3, reductions, so that every wait points at units earlier in the list.
+void build_units(attn_batch* b, attn_batch::Merged& m) {
+  const int ni = (int)b->hs.size();
+  auto ctr = [](int i, int k) { return kPmFirst + 4 * i + k; };
+  std::vector<int> n(4 * ni, 0);
+  m.pu.clear();
+  auto push = [&](int kind, int a, int bb, int c, int d, int wait, int sig) {
+    PUnit u;
+    u.kind = kind; u.a = a; u.b = bb; u.c = c; u.d = d;
+    u.wait = wait;
+    u.need = wait >= 0 ? n[wait - kPmFirst] : 0;
+    u.signal = sig;
+    m.pu.push_back(u);
+    if (sig >= 0) n[sig - kPmFirst]++;
+  };
+  std::vector<char> has_tr(ni, 0);
+  for (size_t r = 0; r < m.tr.size(); r++) {
+    const int i = m.tr_inst[r];
+    const int64_t M = (int64_t)m.tr[r].ml * m.tr[r].mr * m.tr[r].mp;
+    for (int64_t e = 0; e < M; e += kPmTile) push(PU_TRANSPOSE, (int)r, (int)e, 0, 0, -1, ctr(i, 0));
+    has_tr[i] = 1;
+  }
+  for (const int2& wu : m.mp_wus[0]) push(PU_MODE, 0, wu.x, wu.y, 0, -1, ctr(m.mp_inst[0][wu.x], 1));
+  for (const int4& wu : m.sw_wus) {
+    const int i = m.sw_inst[wu.x];
+    const bool tr = m.sw_tasks[wu.x].x == (const void*)b->hs[i]->d_xt;
+    if (tr && !has_tr[i]) throw BatchFail{ATTN_ERR_STATE, "internal: transposed input without its transpose"};
+    push(PU_SANDWICH, wu.x, wu.y, wu.z, wu.w, tr ? ctr(i, 0) : -1, ctr(i, 3));
+  }
+  for (const int2& wu : m.mp_wus[1]) {
+    const int i = m.mp_inst[1][wu.x];
+    push(PU_MODE, 1, wu.x, wu.y, 0, ctr(i, 1), ctr(i, 2));
+  }
+  for (const int2& wu : m.mp_wus[2]) {
+    const int i = m.mp_inst[2][wu.x];
+    push(PU_MODE, 2, wu.x, wu.y, 0, ctr(i, 2), ctr(i, 3));
+  }
+  for (size_t r = 0; r < m.rd.size(); r++) {
+    const int i = m.rd_inst[r];
+    const int64_t M = (int64_t)m.rd[r].ml * m.rd[r].mr * m.rd[r].mp;
+    for (int64_t e = 0; e < M; e += kPmTile) push(PU_REDUCE, (int)r, (int)e, 0, 0, ctr(i, 3), -1);
+  }
+  // counters nobody waits on are not signalled (each signal costs a release)
+  std::vector<char> waited(4 * ni, 0);
+  for (const PUnit& u : m.pu)
+    if (u.wait >= 0) waited[u.wait - kPmFirst] = 1;
+  for (PUnit& u : m.pu)
+    if (u.signal >= 0 && !waited[u.signal - kPmFirst]) u.signal = -1;
+  m.pm_lds = m.sw_lds;
+  for (int k = 0; k < 3; k++) m.pm_lds = std::max(m.pm_lds, m.mp_lds[k]);
+  if (m.pm_lds > (size_t)kPmMaxLds) throw BatchFail{ATTN_ERR_UNSUPPORTED, "persistent matvec: LDS above its limit"};
+  int per_cu = 0;
+  HIPCHK(batch_matvec_occupancy(b->precision == ATTN_F64 ? 0 : 1, m.pm_lds, &per_cu));
+  if (per_cu < 1) throw BatchFail{ATTN_ERR_UNSUPPORTED, "persistent matvec does not fit a CU"};
+  const int64_t slots = (int64_t)per_cu * b->n_cu;
+  // tickets: runs of up to K consecutive units with the same wait and signal,
+  // K chosen so that every workgroup takes about kTicketsPerWG tickets
+  constexpr int64_t kTicketsPerWG = 4, kMaxRun = 16;
+  const int64_t K = std::max<int64_t>(1, std::min<int64_t>(kMaxRun, (int64_t)m.pu.size() / (kTicketsPerWG * slots)));
+  m.tickets.clear();
+  for (size_t u = 0; u < m.pu.size(); u++) {
+    const PUnit& q = m.pu[u];
+    const bool start = m.tickets.empty() || (int64_t)(u - m.tickets.back()) >= K ||
+                       m.pu[m.tickets.back()].wait != q.wait || m.pu[m.tickets.back()].need != q.need ||
+                       m.pu[m.tickets.back()].signal != q.signal;
+    if (start) m.tickets.push_back((int32_t)u);
+  }
+  const int64_t nt = (int64_t)m.tickets.size();
+  m.tickets.push_back((int32_t)m.pu.size());
+  m.pm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(slots, nt));
 }
 
 void build_step(attn_batch* b, int t) {
@@ -288,6 +395,10 @@ void build_step(attn_batch* b, int t) {
       S.mv.tr.push_back({x, h->d_xt, D.dims[0], D.dims[1], D.dims[2], 0});
       S.mv.tr_max = std::max(S.mv.tr_max, Msz);
     }
+    S.mv.sw_inst.resize(S.mv.sw_tasks.size(), i);
+    for (int k = 0; k < 3; k++) S.mv.mp_inst[k].resize(S.mv.mp_tasks[k].size(), i);
+    S.mv.tr_inst.resize(S.mv.tr.size(), i);
+    S.mv.rd_inst.push_back(i);
     RDTask rt;
     rt.srcs = (const RDSrc*)(uintptr_t)S.mv.rd_srcs.size();   // offset, made a pointer at upload
     rt.y = h->d_w;
@@ -302,11 +413,16 @@ void build_step(attn_batch* b, int t) {
   S.d_cv = bupload(b, S.cv);
   S.d_tj = bupload(b, S.tj);
   S.d_kj = bupload(b, S.kj);
+  if (b->persistent) build_units(b, S.mv);
   upload_merged(b, S.mv);
 }
 
 void run_matvec(attn_batch* b, attn_batch::Merged& m, hipStream_t s) {
   const int dt = b->precision == ATTN_F64 ? 0 : 1;
+  if (b->persistent) {
+    HIPCHK(launch_batch_matvec(dt, m.pm, m.pm_grid, m.pm_lds, s));
+    return;
+  }
   HIPCHK(launch_transpose_list(dt, m.d_tr, (int)m.tr.size(), m.tr_max, s));
   for (int k = 0; k < 3; k++)
     HIPCHK(launch_batch_mode(dt, m.d_mp_tasks[k], m.d_mp_jobs[k], m.d_mp_wus[k], (int)m.mp_wus[k].size(),
@@ -490,9 +606,16 @@ attn_status attn_batch_create(attn_handle* const* hs, int32_t n, const attn_batc
   b->precision = o.precision;
   b->krylov_k = o.krylov_k;
   b->use_graphs = o.use_graphs != 0;
+  b->persistent = o.persistent != 0;
   try {
     HIPCHK(hipSetDevice(b->device));
     HIPCHK(prepare_kernel_attributes());
+    HIPCHK(hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, b->device));
+    if (b->persistent) {
+      const size_t bytes = (size_t)(1 + kPmFirst + 4 * n) * sizeof(int32_t);
+      b->d_pm = (int32_t*)balloc(b, bytes);
+      HIPCHK(hipMemset(b->d_pm, 0, bytes));
+    }
     for (int q = 0; q < 4; q++) HIPCHK(hipStreamCreate(&b->s[q]));
     b->evs.resize(4);
     for (auto& e : b->evs) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -560,6 +683,15 @@ attn_status attn_batch_sweep(attn_batch* b, int32_t n_sweeps, double* energies, 
       }
       HIPCHK(hipStreamSynchronize(s0));
       auto t1 = std::chrono::steady_clock::now();
+      if (b->persistent) {
+        int32_t ab = 0;
+        HIPCHK(hipMemcpy(&ab, b->d_pm, sizeof(ab), hipMemcpyDeviceToHost));
+        if (ab) {
+          b->dead = true;
+          b->err = "persistent matvec: a wait for earlier units exceeded its limit";
+          return ATTN_ERR_HIP;
+        }
+      }
       for (int i = 0; i < ni; i++) {
         attn_handle* h = b->hs[i];
         KrylovState st;

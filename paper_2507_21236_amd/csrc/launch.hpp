@@ -52,6 +52,10 @@ hipError_t launch_tiny(const TJob* jobs, int nj, int minM, int maxM, int kreq, h
 // (LDS in bytes: the largest any unit of the launch needs).
 hipError_t launch_batch_sandwich(int dtype, const SWTask* tasks, const SWItem* items, const int4* wus,
                                  int nwu, size_t lds, hipStream_t s);
+// One persistent launch of a whole batched matvec (grid workgroups; the
+// counters of a.cnt must be zero, and are zero again when it ends).
+hipError_t launch_batch_matvec(int dtype, const PMArgs& a, int grid, size_t lds, hipStream_t s);
+hipError_t batch_matvec_occupancy(int dtype, size_t lds, int* per_cu);
 hipError_t launch_batch_mode(int dtype, const MPTask* tasks, const MPJob* jobs, const int2* wus, int nwu,
                              size_t lds, hipStream_t s);
 hipError_t launch_transpose_list(int dtype, const TRTask* tasks, int ntask, int64_t maxM, hipStream_t s);

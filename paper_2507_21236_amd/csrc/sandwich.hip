@@ -2,8 +2,8 @@
 // spectator slices s of a node tensor, for the H_eff matvec (two-leg terms and
 // local operators) and the effective-operator updates; FP64 / FP32 on the
 // 16 x 16 x 4 matrix cores, split BF16 on the 16 x 16 x 32 ones, a generic
-// form for legs that are not multiples of 16, and the mixed-shape launch of
-// the batched form.
+// form for legs that are not multiples of 16, and the mixed-shape and
+// persistent launches of the batched form.
 //
 // This file is compiled with the MFMA accumulators in ordinary VGPRs (the
 // build passes -amdgpu-mfma-vgpr-form for it alone): with accumulation
@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 #include "mfma_common.hpp"
+#include "mode_body.hpp"
 
 namespace attn {
 
@@ -836,6 +837,179 @@ __global__ __launch_bounds__(256) void k_batch_sandwich(const SWTask* __restrict
   }
 }
 
+// ============================================================================ persistent batched matvec
+// The staged batched matvec is six launches (transposes, three chain stages,
+// sandwiches, reduction); here one launch of a resident grid runs them all
+// from one ordered work list (PUnit), so later stages start while earlier
+// units of other instances still run.  Every unit runs the same body as in
+// the staged launches, and the reduction sums in the same fixed order, so the
+// results are the same bit for bit.
+//
+// Ordering across the chip: a finishing unit makes its stores visible at
+// device scope (release fence in every wave) before one lane bumps its
+// counter; a waiting unit polls the counter from one lane, then every wave
+// takes an acquire fence before reading what the producers wrote.
+template <typename T>
+__device__ __forceinline__ void pm_transpose(const TRTask& t, int64_t e0) {
+  const int64_t M = (int64_t)t.ml * t.mr * t.mp;
+  const int64_t e1 = e0 + kPmTile < M ? e0 + kPmTile : M;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int64_t l = e / ((int64_t)t.mr * t.mp);
+    const int64_t rem = e - l * t.mr * t.mp;
+    const int64_t r = rem / t.mp, p = rem - r * t.mp;
+    ((T*)t.xt)[p * t.ml * t.mr + l * t.mr + r] = ((const T*)t.x)[e];
+  }
+}
+
+// same per-element sum as k_reduce_list
+template <typename TI>
+__device__ __forceinline__ void pm_reduce(const RDTask& t, int64_t e0) {
+  const int64_t M = (int64_t)t.ml * t.mr * t.mp;
+  const int64_t e1 = e0 + kPmTile < M ? e0 + kPmTile : M;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int64_t l = e / ((int64_t)t.mr * t.mp);
+    const int64_t rem = e - l * t.mr * t.mp;
+    const int64_t r = rem / t.mp, p = rem - r * t.mp;
+    const int64_t et = p * t.ml * t.mr + l * t.mr + r;
+    double acc = 0;
+    for (int k = 0; k < t.nsrc; k++) acc += (double)((const TI*)t.srcs[k].p)[t.srcs[k].layout ? et : e];
+    ((double*)t.y)[e] = acc;
+  }
+}
+
+// One mode-product or sandwich unit.  Not inlined: inside the persistent
+// loop the compiler would otherwise keep the lane-dependent set-up of every
+// body live at once (over 300 registers for FP64).  As calls under the
+// occupancy cap of the kernel below, they save a few registers at entry and
+// exit and spill nothing inside.  Arguments of a call arrive in vector
+// registers, so each is made wave-uniform again (scalar loads of the task and
+// item descriptors, uniform branches), and the LDS buffer is named here, not
+// passed, so that it is addressed as LDS rather than through flat pointers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// a descriptor list (read-only while the kernel runs) at a wave-uniform
+// address, read through the constant address space: scalar loads
+template <typename P>
+__device__ __forceinline__ const P* uni(const P* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (const P*)(const __attribute__((address_space(4))) P*)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __noinline__ void pm_mode(const MPTask* tp, const MPJob* jobs_, int task_, int c_) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const MPTask& t = *uni(tp);
+  const MPJob* jobs = uni(jobs_);
+  const int task = uni(task_), c = uni(c_);
+  const int2 wu = make_int2(task, c);
+  switch (t.pad) {
+    case 0: mode_gen_elem<T>(t, jobs, (int64_t)c + threadIdx.x, nullptr); break;
+    case 1: mode_mfma<T, 1>(t, jobs, wu, nullptr, smem_raw); break;
+    case 2: mode_mfma<T, 2>(t, jobs, wu, nullptr, smem_raw); break;
+    case 3: mode_mfma<T, 3>(t, jobs, wu, nullptr, smem_raw); break;
+    case 4: mode_mfma<T, 4>(t, jobs, wu, nullptr, smem_raw); break;
+    default: break;
+  }
+}
+
+template <typename T>
+__device__ __noinline__ void pm_sandwich(const SWTask* tp, const SWItem* items_, int task_, int s_, int z_,
+                                         int body_) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const SWTask& t = *uni(tp);
+  const SWItem* items = uni(items_);
+  const int task = uni(task_), s = uni(s_), z = uni(z_), body = uni(body_);
+  const int4 wu = make_int4(task, s, z, body);
+  switch (body) {
+    case 0:
+      if (gen_slice_lds(t.ma, t.mb, sizeof(T)))
+        sandwich_gen_slice<T>(t, items, s, nullptr, reinterpret_cast<T*>(smem_raw));
+      else
+        sandwich_gen_elem<T>(t, items, s, z + threadIdx.x, nullptr);
+      break;
+    case 1: sandwich_mfma<T, 1>(t, items, wu, nullptr, smem_raw); break;
+    case 2: sandwich_mfma<T, 2>(t, items, wu, nullptr, smem_raw); break;
+    case 3: sandwich_mfma<T, 3>(t, items, wu, nullptr, smem_raw); break;
+    case 4: sandwich_mfma<T, 4>(t, items, wu, nullptr, smem_raw); break;
+    default: break;
+  }
+}
+
+// Three (FP64) or four (FP32) workgroups per CU, as many as the staged
+// sandwich launches keep resident.
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4)))
+void k_batch_matvec(const PMArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_ticket, s_flag;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const bool stop = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+      s_ticket = stop ? a.n_tickets
+                      : __hip_atomic_fetch_add(a.cnt + kPmHead, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const int tk = uni(s_ticket);
+    if (tk >= a.n_tickets) break;
+    // a ticket is a run of consecutive units with the same wait and signal
+    const int32_t* tickets = uni(a.tickets);
+    const PUnit* units = uni(a.units);
+    const int u0 = tickets[tk], u1 = tickets[tk + 1];
+    const int wait = units[u0].wait, need = units[u0].need, signal = units[u0].signal;
+    if (wait >= 0) {
+      if (threadIdx.x == 0) {
+        int ok = 1;
+        for (int it = 0;; it++) {
+          if (__hip_atomic_load(a.cnt + wait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) break;
+          if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+          if (it >= kPmSpin) {
+            __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(4);
+        }
+        // pairs with the producers' release; the CU's vector cache is shared
+        // by the workgroup's waves, so one wave's acquire serves all of them
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_flag = ok;
+      }
+      __syncthreads();
+      if (!s_flag) continue;   // aborted: skip the bodies (their counter is never needed again)
+    }
+    for (int ui = u0; ui < u1; ui++) {
+      const PUnit u = units[ui];
+      if (ui > u0) __syncthreads();   // LDS of the previous unit
+      switch (u.kind) {
+        case PU_TRANSPOSE: pm_transpose<T>(a.tr[u.a], u.b); break;
+        case PU_REDUCE: pm_reduce<T>(a.rd[u.a], u.b); break;
+        case PU_MODE: pm_mode<T>(a.mp_tasks[u.a] + u.b, a.mp_jobs[u.a], u.b, u.c); break;
+        case PU_SANDWICH: pm_sandwich<T>(a.sw_tasks + u.a, a.sw_items, u.a, u.b, u.c, u.d); break;
+        default: break;
+      }
+    }
+    // Every wave waits until its own stores have reached the L2 of its XCD;
+    // after the barrier one release by lane 0 writes that L2 back, which
+    // covers the stores of all four waves, and publishes the count.  (A
+    // release fence in every wave would write the L2 back four more times;
+    // each write-back walks the whole cache, and a matvec has thousands of
+    // signalling tickets.)
+    if (signal >= 0) wait_vm(0);
+    __syncthreads();   // also frees LDS and s_ticket for the next ticket
+    if (signal >= 0 && threadIdx.x == 0)
+      __hip_atomic_fetch_add(a.cnt + signal, u1 - u0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // the last workgroup out leaves every counter at zero for the next launch
+  if (threadIdx.x == 0)
+    s_flag = __hip_atomic_fetch_add(a.cnt + kPmExit, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+             (int)gridDim.x - 1;
+  __syncthreads();
+  if (s_flag)
+    for (int i = threadIdx.x; i < a.n_cnt; i += 256)
+      __hip_atomic_store(a.cnt + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ============================================================================ launchers
 template <typename T, int NB>
 static hipError_t sand_launch(const SWTask* tasks, const SWItem* items, const int4* wus, int nwu,
@@ -935,6 +1109,22 @@ hipError_t launch_batch_sandwich(int dtype, const SWTask* tasks, const SWItem* i
   return hipGetLastError();
 }
 
+hipError_t launch_batch_matvec(int dtype, const PMArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (a.n_units == 0) return hipSuccess;
+  if (grid < 1) return hipErrorInvalidValue;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_batch_matvec<double>, dim3(grid), dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_batch_matvec<float>, dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+// Resident workgroups per CU of the persistent batched matvec at `lds` bytes.
+hipError_t batch_matvec_occupancy(int dtype, size_t lds, int* per_cu) {
+  const void* f = dtype == 0 ? (const void*)k_batch_matvec<double> : (const void*)k_batch_matvec<float>;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, 256, lds);
+}
+
 // Dynamic-LDS limit of the sandwich kernels (called by prepare_kernel_attributes).
 hipError_t prepare_sandwich_attributes() {
   const void* fns[] = {
@@ -953,6 +1143,10 @@ hipError_t prepare_sandwich_attributes() {
       (const void*)k_sandwich_bf2<6>, (const void*)k_sandwich_bf2<8>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  for (const void* f : {(const void*)k_batch_matvec<double>, (const void*)k_batch_matvec<float>}) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kPmMaxLds);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

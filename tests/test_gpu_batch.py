@@ -54,17 +54,42 @@ def test_batch_reproduces_single_handle_sweeps(form):
     b.close()
 
 
-def test_batch_fp64_matches_oracle_4x4():
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_fp64_matches_oracle_4x4(persistent):
     from paper_2507_21236_amd import AttnBatch, ATTN_F64
     p = config_problem("ising4_m8")
     a, o = make_pair(p)
     other = _handles([batch_instances(32)[2]])
-    b = AttnBatch([a] + other, krylov_k=20, precision=ATTN_F64)
+    b = AttnBatch([a] + other, krylov_k=20, precision=ATTN_F64, persistent=persistent)
     e_b, _ = b.sweep(3)
     for s in range(3):
         e_o = o.sweep()
         assert abs(e_b[0, s] - e_o) / p.n_sites < 1e-10, (s, e_b[0, s], e_o)
     b.close()
+
+
+@pytest.mark.parametrize("form", ["f32", "f64"])
+@pytest.mark.parametrize("graphs", [False, True])
+def test_persistent_matvec_reproduces_staged_launches(form, graphs):
+    # one launch per matvec over the ordered work list (transposes, chain
+    # stages, sandwich tiles, reduction tiles of all instances) runs the same
+    # unit bodies and the same fixed-order reduction as the staged launches,
+    # so the sweeps give the same energies bit for bit; with graphs, sweep 0
+    # captures the steps and sweep 1 replays them (the launch leaves its
+    # counters at zero for the next one)
+    from paper_2507_21236_amd import AttnBatch, ATTN_F32, ATTN_F64
+    prec = ATTN_F32 if form == "f32" else ATTN_F64
+    insts = batch_instances(32)
+    ps = [insts[i] for i in MIXED]
+    staged = AttnBatch(_handles(ps), krylov_k=20, precision=prec, use_graphs=False)
+    e_s, _ = staged.sweep(2)
+    staged.close()
+    pers = AttnBatch(_handles(ps), krylov_k=20, precision=prec, use_graphs=graphs, persistent=True)
+    e_p, _ = pers.sweep(2)
+    for i, p in enumerate(ps):
+        print(f"instance {MIXED[i]} L={p.meta['L']} m={p.m}: persistent {e_p[i]} staged {e_s[i]}")
+    assert np.array_equal(e_p, e_s)
+    pers.close()
 
 
 def test_batch_autotuned_without_graphs():
