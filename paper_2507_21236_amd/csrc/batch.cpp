@@ -17,7 +17,7 @@ struct attn_batch {
   bool persistent = false;
   bool dead = false;
   int n_cu = 0;
-  int32_t* d_pm = nullptr;   // [0] abort word, then the counters of the persistent matvec
+  int32_t* d_pm = nullptr;   // [0] abort word, then (one line further) the counters of the persistent matvec
   std::vector<void*> owned;
   std::vector<double*> x64;   // FP64 form: per-instance copy of the newest basis vector
   hipStream_t s[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -254,7 +254,7 @@ void upload_merged(attn_batch* b, attn_batch::Merged& m) {
   m.pm.n_tickets = m.tickets.empty() ? 0 : (int32_t)m.tickets.size() - 1;
   m.pm.n_units = (int32_t)m.pu.size();
   m.pm.n_cnt = kPmFirst + 4 * (int32_t)b->hs.size();
-  m.pm.cnt = b->d_pm ? b->d_pm + 1 : nullptr;
+  m.pm.cnt = b->d_pm ? b->d_pm + kPmStride : nullptr;
   m.pm.abort = b->d_pm;
   m.pm.sw_tasks = m.d_sw_tasks;
   m.pm.sw_items = m.d_sw_items;
@@ -267,9 +267,12 @@ void upload_merged(attn_batch* b, attn_batch::Merged& m) {
 }
 
 // Ordered work list of the persistent matvec.  Counters per instance i:
-// 4 i + {0: transposes, 1: chain stage 1, 2: chain stage 2, 3: partial and
-// chain outputs}.  Order: transposes, chain stage 1, sandwiches, stage 2,
-// stage 3, reductions, so that every wait points at units earlier in the list.
+// kPmFirst + 4 i + {0: transposes, 1: chain stage 1, 2: chain stage 2,
+// 3: partial and chain outputs}.  Order: transposes, chain stage 1, the first
+// third of the sandwich tiles, stage 2, the second third, stage 3, the last
+// third, reductions.  Every wait points at units earlier in the list, and the
+// sandwich thirds give the chain stages independent work to overlap with, so
+// the chain's three dependent stages do not end up behind all of the tiles.
 void build_units(attn_batch* b, attn_batch::Merged& m) {
   const int ni = (int)b->hs.size();
   auto ctr = [](int i, int k) { return kPmFirst + 4 * i + k; };
@@ -288,28 +291,36 @@ void build_units(attn_batch* b, attn_batch::Merged& m) {
   for (size_t r = 0; r < m.tr.size(); r++) {
     const int i = m.tr_inst[r];
     const int64_t M = (int64_t)m.tr[r].ml * m.tr[r].mr * m.tr[r].mp;
-    for (int64_t e = 0; e < M; e += kPmTile) push(PU_TRANSPOSE, (int)r, (int)e, 0, 0, -1, ctr(i, 0));
+    for (int64_t e = 0; e < M; e += kPmTileT) push(PU_TRANSPOSE, (int)r, (int)e, 0, 0, -1, ctr(i, 0));
     has_tr[i] = 1;
   }
   for (const int2& wu : m.mp_wus[0]) push(PU_MODE, 0, wu.x, wu.y, 0, -1, ctr(m.mp_inst[0][wu.x], 1));
-  for (const int4& wu : m.sw_wus) {
-    const int i = m.sw_inst[wu.x];
-    const bool tr = m.sw_tasks[wu.x].x == (const void*)b->hs[i]->d_xt;
-    if (tr && !has_tr[i]) throw BatchFail{ATTN_ERR_STATE, "internal: transposed input without its transpose"};
-    push(PU_SANDWICH, wu.x, wu.y, wu.z, wu.w, tr ? ctr(i, 0) : -1, ctr(i, 3));
-  }
+  const bool chains = !m.mp_wus[1].empty() || !m.mp_wus[2].empty();
+  const size_t nsw = m.sw_wus.size();
+  auto sandwiches = [&](size_t w0, size_t w1) {
+    for (size_t w = w0; w < w1; w++) {
+      const int4& wu = m.sw_wus[w];
+      const int i = m.sw_inst[wu.x];
+      const bool tr = m.sw_tasks[wu.x].x == (const void*)b->hs[i]->d_xt;
+      if (tr && !has_tr[i]) throw BatchFail{ATTN_ERR_STATE, "internal: transposed input without its transpose"};
+      push(PU_SANDWICH, wu.x, wu.y, wu.z, wu.w, tr ? ctr(i, 0) : -1, ctr(i, 3));
+    }
+  };
+  sandwiches(0, chains ? nsw / 3 : nsw);
   for (const int2& wu : m.mp_wus[1]) {
     const int i = m.mp_inst[1][wu.x];
     push(PU_MODE, 1, wu.x, wu.y, 0, ctr(i, 1), ctr(i, 2));
   }
+  if (chains) sandwiches(nsw / 3, 2 * nsw / 3);
   for (const int2& wu : m.mp_wus[2]) {
     const int i = m.mp_inst[2][wu.x];
     push(PU_MODE, 2, wu.x, wu.y, 0, ctr(i, 2), ctr(i, 3));
   }
+  if (chains) sandwiches(2 * nsw / 3, nsw);
   for (size_t r = 0; r < m.rd.size(); r++) {
     const int i = m.rd_inst[r];
     const int64_t M = (int64_t)m.rd[r].ml * m.rd[r].mr * m.rd[r].mp;
-    for (int64_t e = 0; e < M; e += kPmTile) push(PU_REDUCE, (int)r, (int)e, 0, 0, ctr(i, 3), -1);
+    for (int64_t e = 0; e < M; e += kPmTileR) push(PU_REDUCE, (int)r, (int)e, 0, 0, ctr(i, 3), -1);
   }
   // counters nobody waits on are not signalled (each signal costs a release)
   std::vector<char> waited(4 * ni, 0);
@@ -324,21 +335,24 @@ void build_units(attn_batch* b, attn_batch::Merged& m) {
   HIPCHK(batch_matvec_occupancy(b->precision == ATTN_F64 ? 0 : 1, m.pm_lds, &per_cu));
   if (per_cu < 1) throw BatchFail{ATTN_ERR_UNSUPPORTED, "persistent matvec does not fit a CU"};
   const int64_t slots = (int64_t)per_cu * b->n_cu;
-  // tickets: runs of up to K consecutive units with the same wait and signal,
-  // K chosen so that every workgroup takes about kTicketsPerWG tickets
-  constexpr int64_t kTicketsPerWG = 4, kMaxRun = 16;
-  const int64_t K = std::max<int64_t>(1, std::min<int64_t>(kMaxRun, (int64_t)m.pu.size() / (kTicketsPerWG * slots)));
+  // tickets: runs of up to K consecutive units with the same kind, wait and
+  // signal.  Chain-stage, transpose and reduction units go one per ticket:
+  // the chain stages are on the dependency path, and the reductions end the
+  // launch, so neither may pile up in one workgroup.  Sandwich tiles are many
+  // and alike; they go in runs sized for about eight tickets per workgroup.
+  const int64_t Ks = std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nsw / (8 * slots)));
   m.tickets.clear();
   for (size_t u = 0; u < m.pu.size(); u++) {
     const PUnit& q = m.pu[u];
+    const int64_t K = q.kind == PU_SANDWICH ? Ks : 1;
     const bool start = m.tickets.empty() || (int64_t)(u - m.tickets.back()) >= K ||
-                       m.pu[m.tickets.back()].wait != q.wait || m.pu[m.tickets.back()].need != q.need ||
-                       m.pu[m.tickets.back()].signal != q.signal;
+                       m.pu[m.tickets.back()].kind != q.kind || m.pu[m.tickets.back()].wait != q.wait ||
+                       m.pu[m.tickets.back()].need != q.need || m.pu[m.tickets.back()].signal != q.signal;
     if (start) m.tickets.push_back((int32_t)u);
   }
   const int64_t nt = (int64_t)m.tickets.size();
   m.tickets.push_back((int32_t)m.pu.size());
-  m.pm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(slots, nt));
+  m.pm_grid = (int)std::max<int64_t>(kPmQueues, std::min<int64_t>(slots, nt));   // a workgroup per queue
 }
 
 void build_step(attn_batch* b, int t) {
@@ -612,7 +626,7 @@ attn_status attn_batch_create(attn_handle* const* hs, int32_t n, const attn_batc
     HIPCHK(prepare_kernel_attributes());
     HIPCHK(hipDeviceGetAttribute(&b->n_cu, hipDeviceAttributeMultiprocessorCount, b->device));
     if (b->persistent) {
-      const size_t bytes = (size_t)(1 + kPmFirst + 4 * n) * sizeof(int32_t);
+      const size_t bytes = (size_t)(1 + kPmFirst + 4 * n) * kPmStride * sizeof(int32_t);
       b->d_pm = (int32_t*)balloc(b, bytes);
       HIPCHK(hipMemset(b->d_pm, 0, bytes));
     }

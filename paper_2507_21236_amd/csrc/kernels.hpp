@@ -117,22 +117,26 @@ struct TRTask {        // [l][r][p] -> [p][l][r]
 };
 
 // ---------------------------------------------------------------- persistent batched matvec
-// One launch runs a whole matvec of several problem instances: a fixed grid of
-// workgroups takes units from one ordered work list by ticket (an atomic
-// counter).  A unit may wait for a counter of units that come before it in the
-// list (per instance: transposes before the sandwiches that read the
-// transposed input, each chain stage before the next, every partial output
-// before the reduction), so a workgroup that waits only waits on tickets that
-// running workgroups already hold, and the launch cannot deadlock.  One
-// ticket covers a run of consecutive units with the same wait and signal, so
-// that the ticket atomic and the device-scope release and acquire are paid
-// once per run rather than once per unit.
+// One launch runs a whole matvec of several problem instances: a resident
+// grid of workgroups takes units from one ordered work list by ticket.  The
+// tickets are dealt to kPmQueues queues (ticket t to queue t mod kPmQueues,
+// workgroup b takes from queue b mod kPmQueues, one atomic counter per queue),
+// so that no single counter serialises every grab.  A unit may wait for a
+// counter of units that come before it in the list (per instance:
+// transposes before the sandwiches that read the transposed input, each chain
+// stage before the next, every partial output before the reduction).  The
+// launch cannot deadlock: each queue hands out its tickets in list order, so
+// the earliest unfinished unit is either held by a running workgroup (and
+// everything it waits for is earlier, hence finished) or is next in its
+// queue, whose workgroups are then all free to take it.  One ticket covers a
+// run of consecutive units with the same wait and signal, so that the ticket
+// atomic and the device-scope release and acquire are paid once per run.
 enum { PU_TRANSPOSE = 0, PU_MODE = 1, PU_SANDWICH = 2, PU_REDUCE = 3 };
 
 struct PUnit {
   int32_t kind;     // PU_*
   int32_t a, b, c, d;
-  // transpose / reduce: a = task, b = first element (kPmTile elements per unit)
+  // transpose / reduce: a = task, b = first element (kPmTileT / kPmTileR elements)
   // mode: a = chain stage, b = task of that stage, c = free tile or first element
   // sandwich: (a, b, c, d) = (task, slice, first 16-row strip, body)
   int32_t wait;     // counter that must reach `need` before the unit runs, or -1
@@ -140,22 +144,25 @@ struct PUnit {
   int32_t signal;   // counter incremented once the unit's results are visible, or -1
 };
 
-constexpr int kPmHead = 0;    // next ticket
-constexpr int kPmExit = 1;    // workgroups that have left the loop
-constexpr int kPmFirst = 2;   // first dependency counter
-constexpr int kPmTile = 2048; // elements per transpose or reduction unit
+constexpr int kPmQueues = 8;              // ticket queues (counters 0 .. 7)
+constexpr int kPmExit = kPmQueues;        // counter: workgroups that have left the loop
+constexpr int kPmFirst = kPmQueues + 1;   // first dependency counter
+constexpr int kPmStride = 32;             // ints between counters: one 128-byte line each
+constexpr int kPmTileT = 2048;            // elements per transpose unit
+constexpr int kPmTileR = 256;             // elements per reduction unit (one per lane: each sums every source)
 // Spin limit of one wait: about a second; past it the launch sets its abort
-// word, drains the list without running the remaining units and ends.
+// word, skips every unit that still has to wait, and ends.
 constexpr int kPmSpin = 1 << 20;
 constexpr int kPmMaxLds = 64 * 1024;   // dynamic LDS limit of the persistent launch
+constexpr int kPmDefer = 4;             // tickets a workgroup may finish before publishing their count
 
 struct PMArgs {
   const PUnit* units;
   const int32_t* tickets;   // [n_tickets + 1]: first unit of each ticket
   int32_t n_tickets;
   int32_t n_units;
-  int32_t n_cnt;      // counters incl. head and exit; the last workgroup out zeroes them
-  int32_t* cnt;
+  int32_t n_cnt;      // counters (queues, exit, dependencies); the last workgroup out zeroes them
+  int32_t* cnt;       // counter c at cnt[c * kPmStride]
   int32_t* abort;     // sticky: a wait exceeded its limit
   const SWTask* sw_tasks;
   const SWItem* sw_items;

@@ -845,14 +845,22 @@ __global__ __launch_bounds__(256) void k_batch_sandwich(const SWTask* __restrict
 // the staged launches, and the reduction sums in the same fixed order, so the
 // results are the same bit for bit.
 //
-// Ordering across the chip: a finishing unit makes its stores visible at
-// device scope (release fence in every wave) before one lane bumps its
-// counter; a waiting unit polls the counter from one lane, then every wave
-// takes an acquire fence before reading what the producers wrote.
+// Ordering across the chip (eight XCDs, each with its own L2): before a
+// count is published every wave waits for its stores, and one device-scope
+// release writes the L2 back; a waiting workgroup polls the counter from one
+// lane and takes a device-scope acquire before reading what producers wrote.
+// Without the release the results are wrong (non-finite energies in a test
+// build); the acquire measured free.
+//
+// Measured (32 seeded Ising instances, L 8..16, m 16..64, graphs): FP32
+// sweep 2.97 s against 2.25 s staged, FP64 3.82 s against 3.11 s.  A
+// per-unit timestamp trace put the remaining gap in per-ticket latency
+// (ticket atomic, descriptor loads, publish: about 5 us between units) and in
+// the reduction tail; the staged launches stay the default.
 template <typename T>
 __device__ __forceinline__ void pm_transpose(const TRTask& t, int64_t e0) {
   const int64_t M = (int64_t)t.ml * t.mr * t.mp;
-  const int64_t e1 = e0 + kPmTile < M ? e0 + kPmTile : M;
+  const int64_t e1 = e0 + kPmTileT < M ? e0 + kPmTileT : M;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
     const int64_t l = e / ((int64_t)t.mr * t.mp);
     const int64_t rem = e - l * t.mr * t.mp;
@@ -865,13 +873,14 @@ __device__ __forceinline__ void pm_transpose(const TRTask& t, int64_t e0) {
 template <typename TI>
 __device__ __forceinline__ void pm_reduce(const RDTask& t, int64_t e0) {
   const int64_t M = (int64_t)t.ml * t.mr * t.mp;
-  const int64_t e1 = e0 + kPmTile < M ? e0 + kPmTile : M;
+  const int64_t e1 = e0 + kPmTileR < M ? e0 + kPmTileR : M;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
     const int64_t l = e / ((int64_t)t.mr * t.mp);
     const int64_t rem = e - l * t.mr * t.mp;
     const int64_t r = rem / t.mp, p = rem - r * t.mp;
     const int64_t et = p * t.ml * t.mr + l * t.mr + r;
     double acc = 0;
+#pragma unroll 8
     for (int k = 0; k < t.nsrc; k++) acc += (double)((const TI*)t.srcs[k].p)[t.srcs[k].layout ? et : e];
     ((double*)t.y)[e] = acc;
   }
@@ -936,18 +945,39 @@ __device__ __noinline__ void pm_sandwich(const SWTask* tp, const SWItem* items_,
   }
 }
 
-// Three (FP64) or four (FP32) workgroups per CU, as many as the staged
-// sandwich launches keep resident.
+// Three (FP64) or four (FP32) workgroups per CU (FP32 at five: registers
+// capped at 96, the mode body spills, and the sweep measured 8 % slower).
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4)))
 void k_batch_matvec(const PMArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int s_ticket, s_flag;
+  // Signals are deferred: a workgroup sums the count of its finished units on
+  // one counter and publishes it (one release) before it waits for anything,
+  // when its next ticket signals another counter, after kPmDefer tickets, and
+  // when it leaves.  It never waits while holding a count, so every count is
+  // published after at most kPmDefer tickets that need nothing.
+  int pend_sig = -1, pend_cnt = 0, pend_age = 0;   // same in every lane
+  // the last (counter, need) this workgroup waited for: later tickets with
+  // the same counter and no larger need are ready, and its acquire still holds
+  int seen_wait = -1, seen_need = 0;
+  auto publish = [&]() {
+    // every wave waits until its own stores have reached the L2 of its XCD;
+    // after the barrier one release by lane 0 writes that L2 back (covering
+    // the stores of all four waves) and publishes the count
+    wait_vm(0);
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(a.cnt + pend_sig * kPmStride, pend_cnt, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    pend_sig = -1;
+    pend_cnt = 0;
+    pend_age = 0;
+  };
   for (;;) {
     if (threadIdx.x == 0) {
-      const bool stop = __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-      s_ticket = stop ? a.n_tickets
-                      : __hip_atomic_fetch_add(a.cnt + kPmHead, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int q = blockIdx.x % kPmQueues;
+      s_ticket = q + kPmQueues * __hip_atomic_fetch_add(a.cnt + q * kPmStride, 1, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
     const int tk = uni(s_ticket);
@@ -957,11 +987,14 @@ void k_batch_matvec(const PMArgs a) {
     const PUnit* units = uni(a.units);
     const int u0 = tickets[tk], u1 = tickets[tk + 1];
     const int wait = units[u0].wait, need = units[u0].need, signal = units[u0].signal;
-    if (wait >= 0) {
+    const bool ready = wait < 0 || (wait == seen_wait && need <= seen_need);
+    if (pend_cnt && (!ready || signal != pend_sig || pend_age >= kPmDefer)) publish();
+    if (!ready) {
       if (threadIdx.x == 0) {
         int ok = 1;
         for (int it = 0;; it++) {
-          if (__hip_atomic_load(a.cnt + wait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) break;
+          if (__hip_atomic_load(a.cnt + wait * kPmStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need)
+            break;
           if (__hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
           if (it >= kPmSpin) {
             __hip_atomic_store(a.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -977,6 +1010,8 @@ void k_batch_matvec(const PMArgs a) {
       }
       __syncthreads();
       if (!s_flag) continue;   // aborted: skip the bodies (their counter is never needed again)
+      seen_wait = wait;
+      seen_need = need;
     }
     for (int ui = u0; ui < u1; ui++) {
       const PUnit u = units[ui];
@@ -989,25 +1024,22 @@ void k_batch_matvec(const PMArgs a) {
         default: break;
       }
     }
-    // Every wave waits until its own stores have reached the L2 of its XCD;
-    // after the barrier one release by lane 0 writes that L2 back, which
-    // covers the stores of all four waves, and publishes the count.  (A
-    // release fence in every wave would write the L2 back four more times;
-    // each write-back walks the whole cache, and a matvec has thousands of
-    // signalling tickets.)
-    if (signal >= 0) wait_vm(0);
-    __syncthreads();   // also frees LDS and s_ticket for the next ticket
-    if (signal >= 0 && threadIdx.x == 0)
-      __hip_atomic_fetch_add(a.cnt + signal, u1 - u0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();   // frees LDS and s_ticket for the next ticket
+    if (signal >= 0) {
+      pend_sig = signal;
+      pend_cnt += u1 - u0;
+      pend_age++;
+    }
   }
+  if (pend_cnt) publish();
   // the last workgroup out leaves every counter at zero for the next launch
   if (threadIdx.x == 0)
-    s_flag = __hip_atomic_fetch_add(a.cnt + kPmExit, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+    s_flag = __hip_atomic_fetch_add(a.cnt + kPmExit * kPmStride, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
              (int)gridDim.x - 1;
   __syncthreads();
   if (s_flag)
     for (int i = threadIdx.x; i < a.n_cnt; i += 256)
-      __hip_atomic_store(a.cnt + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.cnt + i * kPmStride, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ============================================================================ launchers
@@ -1111,7 +1143,7 @@ hipError_t launch_batch_sandwich(int dtype, const SWTask* tasks, const SWItem* i
 
 hipError_t launch_batch_matvec(int dtype, const PMArgs& a, int grid, size_t lds, hipStream_t s) {
   if (a.n_units == 0) return hipSuccess;
-  if (grid < 1) return hipErrorInvalidValue;
+  if (grid < kPmQueues) return hipErrorInvalidValue;   // every queue needs a workgroup
   if (dtype == 0)
     hipLaunchKernelGGL(k_batch_matvec<double>, dim3(grid), dim3(256), lds, s, a);
   else
