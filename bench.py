@@ -197,6 +197,8 @@ def batched_form(sweeps, warmup):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / sweeps
         tuned = b.info()[2]
+        if persistent == 2:
+            tuned = b.forms()
         b.close()
         return dt, e, t_create, tuned
 
@@ -221,6 +223,13 @@ def batched_form(sweeps, warmup):
     print(f"[bench] batched FP64 sweeps, persistent matvec: {p64:.3f} s", file=sys.stderr, flush=True)
     p32, e_p32, _, _ = batched(ATTN_F32, False, True)
     print(f"[bench] batched FP32 sweeps, persistent matvec: {p32:.3f} s", file=sys.stderr, flush=True)
+    # per step the faster of the two forms, timed at creation
+    c64, e_c64, cc64, f64 = batched(ATTN_F64, False, 2)
+    print(f"[bench] batched FP64 sweeps, form per step: {c64:.3f} s ({f64[1]} of {f64[0]} steps persistent, "
+          f"create {cc64:.1f} s)", file=sys.stderr, flush=True)
+    c32, e_c32, cc32, f32 = batched(ATTN_F32, False, 2)
+    print(f"[bench] batched FP32 sweeps, form per step: {c32:.3f} s ({f32[1]} of {f32[0]} steps persistent, "
+          f"create {cc32:.1f} s)", file=sys.stderr, flush=True)
     n_sites = np.array([p.n_sites for p in ps], dtype=float)
 
     def maxdev(ea, eb):
@@ -247,6 +256,15 @@ def batched_form(sweeps, warmup):
            "speedup_batched_f32_persistent_vs_per_instance_f64": round(seq64 / p32, 3),
            "persistent_energies_identical_to_staged": bool(np.array_equal(e_p64, e_b64)
                                                            and np.array_equal(e_p32, e_b32)),
+           "batched_f64_form_per_step_s_per_sweep": round(c64, 4),
+           "batched_f32_form_per_step_s_per_sweep": round(c32, 4),
+           "form_per_step_persistent_steps_f64": f64[1],
+           "form_per_step_persistent_steps_f32": f32[1],
+           "form_per_step_matvec_steps": f64[0],
+           "speedup_form_per_step_vs_staged_f64": round(b64 / c64, 3),
+           "speedup_form_per_step_vs_staged_f32": round(b32 / c32, 3),
+           "form_per_step_energies_identical_to_staged": bool(np.array_equal(e_c64, e_b64)
+                                                              and np.array_equal(e_c32, e_b32)),
            "autotuned_splits_ma_mb_target": tuned,
            "batch_create_autotune_s": round(c32t, 2)}
     for a in hs:

@@ -349,7 +349,9 @@ attn_status attn_mlp_eval(const float* params, const float* feats, float* out, i
  * instances (transposes, chain stages, two-leg tiles, reduction tiles) from
  * one ordered work list by ticket, and a unit that needs earlier results waits
  * on a per-instance counter of the units it depends on, which always come
- * earlier in the list.  With use_graphs each step is
+ * earlier in the list (persistent = 2: each step takes whichever of the two
+ * forms ran its matvec faster when timed at creation).  With use_graphs each
+ * step is
  * captured once as a HIP graph and replayed in later sweeps.  With autotune the
  * work split of the two-leg launches is chosen per leg shape (ma, mb) by timing
  * candidate splits over all steps at creation.  Without autotuning the split is
@@ -366,14 +368,17 @@ typedef struct attn_batch_opts {
   int32_t precision;   /* ATTN_F64 or ATTN_F32 operands; Krylov steps stay FP64 */
   int32_t use_graphs;  /* 1: capture every step as a HIP graph */
   int32_t autotune;    /* 1: time candidate work splits per leg shape at creation */
-  int32_t persistent;  /* 1: each matvec of a step is one launch of a resident grid
-                          over an ordered work list of all instances' units
-                          (same results bit for bit as the staged launches) */
+  int32_t persistent;  /* 0: staged launches; 1: each matvec of a step is one
+                          launch of a resident grid over an ordered work list
+                          of all instances' units; 2: per step, whichever of
+                          the two timed faster at creation (every choice gives
+                          the same results bit for bit) */
 } attn_batch_opts;
 
-/* opts may be NULL (k = 20, FP32, graphs, no autotuning, staged launches).  *out is owned by the
- * caller (attn_batch_destroy).  Errors: ARG, STATE (handle not on a device),
- * UNSUPPORTED (mixed d or devices, legs above 64, BF16X2), HIP, OOM. */
+/* opts may be NULL (k = 20, FP32, graphs, no autotuning, staged launches).
+ * *out is owned by the caller (attn_batch_destroy).  Errors: ARG (also
+ * persistent outside 0..2), STATE (handle not on a device), UNSUPPORTED (mixed
+ * d or devices, legs above 64, BF16X2), HIP, OOM. */
 attn_status attn_batch_create(attn_handle* const* hs, int32_t n, const attn_batch_opts* opts,
                               attn_batch** out);
 
@@ -388,6 +393,9 @@ attn_status attn_batch_sweep(attn_batch* b, int32_t n_sweeps, double* energies, 
  * and the autotuned splits: tuned[3k..3k+2] = (ma, mb, target workgroups). */
 attn_status attn_batch_info(const attn_batch* b, int32_t* n_steps, int64_t* n_launch_units,
                             int32_t* n_tuned, int32_t* tuned, int32_t cap);
+
+/* Steps that run matvecs, and how many of them use the persistent launch. */
+attn_status attn_batch_forms(const attn_batch* b, int32_t* n_matvec_steps, int32_t* n_persistent_steps);
 
 /* Message of the last error of b (of the last failed attn_batch_create when b
  * is NULL); owned by the library. */

@@ -155,7 +155,9 @@ class AttnBatch:
     alive and do not use them while the batch sweeps)."""
 
     def __init__(self, handles, krylov_k=20, precision=ATTN_F32, use_graphs=True, autotune=False,
-                 persistent=False):
+                 persistent=0):
+        """persistent: 0 staged launches, 1 one persistent launch per matvec,
+        2 per step whichever of the two timed faster at creation."""
         self.handles = list(handles)
         self.b = _lib.attn_batch_create([a.h for a in self.handles], krylov_k, precision,
                                         use_graphs, autotune, persistent)
@@ -166,6 +168,10 @@ class AttnBatch:
 
     def info(self):
         return _lib.attn_batch_info(self.b)
+
+    def forms(self):
+        """(steps that run matvecs, steps among them on the persistent launch)"""
+        return _lib.attn_batch_forms(self.b)
 
     def close(self):
         if self.b:

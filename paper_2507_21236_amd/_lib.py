@@ -127,6 +127,7 @@ _proto = {
     "attn_batch_sweep": (ctypes.c_int32, [_H, ctypes.c_int32, _f64p, _f64p]),
     "attn_batch_info": (ctypes.c_int32, [_H, _i32p, ctypes.POINTER(ctypes.c_int64), _i32p, _i32p,
                                          ctypes.c_int32]),
+    "attn_batch_forms": (ctypes.c_int32, [_H, _i32p, _i32p]),
     "attn_batch_last_error": (ctypes.c_char_p, [_H]),
     "attn_batch_destroy": (ctypes.c_int32, [_H]),
     "attn_mlp_train_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -317,6 +318,13 @@ def attn_batch_info(b, cap=64):
     _bcheck(_lib.attn_batch_info(b, ctypes.byref(ns), ctypes.byref(nu), ctypes.byref(nt), tuned, cap), b)
     t = [tuple(tuned[3 * k:3 * k + 3]) for k in range(min(nt.value, cap))]
     return ns.value, nu.value, t
+
+
+def attn_batch_forms(b):
+    """(steps that run matvecs, of them the steps that use the persistent launch)"""
+    nm, npers = ctypes.c_int32(0), ctypes.c_int32(0)
+    _bcheck(_lib.attn_batch_forms(b, ctypes.byref(nm), ctypes.byref(npers)), b)
+    return nm.value, npers.value
 
 
 def attn_batch_last_error(b):

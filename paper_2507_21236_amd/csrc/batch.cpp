@@ -14,7 +14,7 @@ struct attn_batch {
   int precision = ATTN_F32;
   int krylov_k = 20;
   bool use_graphs = true;
-  bool persistent = false;
+  int persistent = 0;         // 0 staged launches, 1 persistent launch, 2 per step the faster of the two
   bool dead = false;
   int n_cu = 0;
   int32_t* d_pm = nullptr;   // [0] abort word, then (one line further) the counters of the persistent matvec
@@ -47,6 +47,7 @@ struct attn_batch {
     int pm_grid = 0;
     size_t pm_lds = 0;
     PMArgs pm;
+    bool use_pm = false;   // this step's matvec runs as the persistent launch
     // device copies
     SWTask* d_sw_tasks = nullptr;
     SWItem* d_sw_items = nullptr;
@@ -427,13 +428,16 @@ void build_step(attn_batch* b, int t) {
   S.d_cv = bupload(b, S.cv);
   S.d_tj = bupload(b, S.tj);
   S.d_kj = bupload(b, S.kj);
-  if (b->persistent) build_units(b, S.mv);
+  if (b->persistent && !S.kj.empty()) {
+    build_units(b, S.mv);
+    S.mv.use_pm = true;
+  }
   upload_merged(b, S.mv);
 }
 
 void run_matvec(attn_batch* b, attn_batch::Merged& m, hipStream_t s) {
   const int dt = b->precision == ATTN_F64 ? 0 : 1;
-  if (b->persistent) {
+  if (m.use_pm) {
     HIPCHK(launch_batch_matvec(dt, m.pm, m.pm_grid, m.pm_lds, s));
     return;
   }
@@ -495,6 +499,33 @@ void enqueue_step(attn_batch* b, int t, hipStream_t s0) {
   HIPCHK(launch_ktridiag(J, nj, s0));
   HIPCHK(launch_kritz(J, nj, s0));
   HIPCHK(launch_kscale(J, nj, S.kj_max, 1, s0));
+}
+
+// Per step, time the step's matvec as staged launches and as the persistent
+// launch (one warm-up, then three of each; the inputs are whatever the
+// buffers hold, which does not change the time of the contractions) and keep
+// the faster.  Both forms give the same results bit for bit.
+void choose_forms(attn_batch* b) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  hipStream_t s = b->s[0];
+  for (auto& S : b->steps) {
+    if (S.kj.empty()) continue;
+    float t[2] = {0, 0};
+    for (int f = 0; f < 2; f++) {
+      S.mv.use_pm = f == 1;
+      run_matvec(b, S.mv, s);
+      HIPCHK(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; r++) run_matvec(b, S.mv, s);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipEventElapsedTime(&t[f], e0, e1));
+    }
+    S.mv.use_pm = t[1] < t[0];
+  }
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
 }
 
 // Handles must sit in the state a sweep starts from (and ends in): centre at
@@ -620,7 +651,12 @@ attn_status attn_batch_create(attn_handle* const* hs, int32_t n, const attn_batc
   b->precision = o.precision;
   b->krylov_k = o.krylov_k;
   b->use_graphs = o.use_graphs != 0;
-  b->persistent = o.persistent != 0;
+  if (o.persistent < 0 || o.persistent > 2) {
+    g_batch_error = "persistent must be 0, 1 or 2";
+    delete b;
+    return ATTN_ERR_ARG;
+  }
+  b->persistent = o.persistent;
   try {
     HIPCHK(hipSetDevice(b->device));
     HIPCHK(prepare_kernel_attributes());
@@ -642,6 +678,7 @@ attn_status attn_batch_create(attn_handle* const* hs, int32_t n, const attn_batc
     b->steps.resize(maxn);
     if (o.autotune) autotune(b);
     for (int t = 0; t < maxn; t++) build_step(b, t);
+    if (b->persistent == 2) choose_forms(b);
     HIPCHK(hipDeviceSynchronize());
   } catch (const HipFail& e) {
     g_batch_error = std::string("HIP error in ") + e.what + ": " + hipGetErrorString(e.e);
@@ -761,6 +798,19 @@ attn_status attn_batch_info(const attn_batch* b, int32_t* n_steps, int64_t* n_la
       tuned[3 * k + 1] = b->tuned[k].first.second;
       tuned[3 * k + 2] = b->tuned[k].second;
     }
+  return ATTN_OK;
+}
+
+attn_status attn_batch_forms(const attn_batch* b, int32_t* n_matvec_steps, int32_t* n_persistent_steps) {
+  if (!b) return ATTN_ERR_ARG;
+  int32_t nm = 0, np = 0;
+  for (auto& S : b->steps) {
+    if (S.kj.empty()) continue;
+    nm++;
+    np += S.mv.use_pm ? 1 : 0;
+  }
+  if (n_matvec_steps) *n_matvec_steps = nm;
+  if (n_persistent_steps) *n_persistent_steps = np;
   return ATTN_OK;
 }
 

@@ -92,6 +92,27 @@ def test_persistent_matvec_reproduces_staged_launches(form, graphs):
     pers.close()
 
 
+@pytest.mark.parametrize("form", ["f32", "f64"])
+def test_per_step_form_choice_reproduces_staged_launches(form):
+    # persistent = 2 times each step's matvec both ways at creation and keeps
+    # the faster; any mix of the two forms gives the staged energies bit for bit
+    from paper_2507_21236_amd import AttnBatch, ATTN_F32, ATTN_F64
+    prec = ATTN_F32 if form == "f32" else ATTN_F64
+    insts = batch_instances(32)
+    ps = [insts[i] for i in MIXED]
+    staged = AttnBatch(_handles(ps), krylov_k=20, precision=prec, use_graphs=False)
+    e_s, _ = staged.sweep(2)
+    staged.close()
+    mixed = AttnBatch(_handles(ps), krylov_k=20, precision=prec, use_graphs=True, persistent=2)
+    n_mv, n_pers = mixed.forms()
+    print(f"steps with matvecs {n_mv}, on the persistent launch {n_pers}")
+    assert 0 < n_mv <= max(p.n_sites - 1 for p in ps)
+    assert 0 <= n_pers <= n_mv
+    e_m, _ = mixed.sweep(2)
+    assert np.array_equal(e_m, e_s)
+    mixed.close()
+
+
 def test_batch_autotuned_without_graphs():
     # the autotuned split changes only the summation grouping of the FP32
     # partial outputs.  From the random start such differences are amplified
