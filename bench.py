@@ -94,9 +94,10 @@ def cpu_baseline(problem, sample_matvecs=3, plan_sweeps=5):
     matvecs there (after one untimed warm-up matvec) with the BLAS limited to
     4 threads (the paper's per-simulation allocation) and with all of its
     threads; then `plan_sweeps` whole oracle sweeps of the 4 x 4 m = 8 Ising
-    instance and one of the 8 x 8 m = 32 instance (the oracle sweep of the
-    16 x 16 workload itself takes about 1000 s and is left out).  Returns the
-    dict for the JSON line (value: all threads)."""
+    instance and one of the 8 x 8 m = 32 instance, and matvecs at the
+    heaviest full node of each of the two (the oracle sweep of the 16 x 16
+    workload itself takes 730-820 s and is left out).  Returns the dict for
+    the JSON line (value: all threads)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle.ttn import OracleTTN
@@ -135,6 +136,24 @@ def cpu_baseline(problem, sample_matvecs=3, plan_sweeps=5):
     e8 = o8.sweep()
     t8 = time.time() - t2
     print(f"[bench] oracle sweeps: 4x4 m=8 {t4:.3f} s, 8x8 m=32 {t8:.1f} s", file=sys.stderr, flush=True)
+    small = {}
+    for name, oo, mm, reps in (("ising4_m8", o4, 8, 50), ("ising8_m32", o8, 32, 5)):
+        fulls = [n for n in range(oo.tree.n_nodes) if oo.tree.dims[n] == (mm,) * 3]
+        if not fulls:
+            continue
+        nd = max(fulls, key=oo.flops)
+        oo.move_center(nd)
+        pr = oo.prepare(nd)
+        xs = np.random.default_rng(1).standard_normal(oo.T[nd].shape)
+        oo.matvec(nd, xs, pr)
+        t3 = time.time()
+        for _ in range(reps):
+            oo.matvec(nd, xs, pr)
+        dt3 = (time.time() - t3) / reps
+        small[name] = {"node": f"({mm},{mm},{mm})", "gflop": round(oo.flops(nd) / 1e9, 4),
+                       "s_per_matvec": round(dt3, 6), "tflops": round(oo.flops(nd) / dt3 / 1e12, 5),
+                       "blas_threads": all_threads}
+    print(f"[bench] oracle matvecs at smaller full nodes: {small}", file=sys.stderr, flush=True)
     return {"value": by_threads[str(all_threads)], "unit": "TFLOP/s", "cores": all_threads,
             "kind": "oracle",
             "sample": (f"{sample_matvecs} FP64 oracle matvecs (after one warm-up) at the heaviest "
@@ -146,6 +165,7 @@ def cpu_baseline(problem, sample_matvecs=3, plan_sweeps=5):
             "ising4_m8_oracle_energies": e4,
             "ising8_m32_oracle_sweep_s": round(t8, 2),
             "ising8_m32_oracle_energy_sweep1": e8,
+            "oracle_matvec_smaller_full_nodes": small,
             "host": hi}
 
 
