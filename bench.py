@@ -47,7 +47,7 @@ PEAK_FP64 = 78.6   # TFLOP/s, MI355X dense FP64 (vector and matrix)
 # dense matrix-core peaks per form (TFLOP/s); split BF16 spends three BF16
 # products per useful product, so its useful-flop ceiling is a third of 2.5 PF
 PEAKS = {"f64": 78.6, "f32": 157.3, "bf16x2": 2500.0 / 3}
-KERNELS = {"f64": "k_sandwich<double,4>", "f32": "k_sandwich<float,4>",
+KERNELS = {"f64": "k_sandwich<double,4>", "f32": "k_sandwich_w2<float>",
            "bf16x2": "k_sandwich_bf2d<4,4>"}
 # HBM bytes per launch of the FP64 contraction kernel at legs of dimension 64,
 # averaged like the live timing over the 620 matvec launches of a sweep of
@@ -235,7 +235,7 @@ def batched_form(sweeps, warmup):
     b32, e_b32, c32, _ = batched(ATTN_F32, False)
     print(f"[bench] batched FP32 sweeps: {b32:.3f} s", file=sys.stderr, flush=True)
     b32t, e_b32t, c32t, tuned = batched(ATTN_F32, True)
-    print(f"[bench] batched FP32 sweeps, autotuned splits: {b32t:.3f} s (create + autotune {c32t:.1f} s)",
+    print(f"[bench] batched FP32 sweeps, autotuned splits and tiles: {b32t:.3f} s (create + autotune {c32t:.1f} s)",
           file=sys.stderr, flush=True)
     # one persistent launch per matvec: the same unit bodies and reduction
     # order as the staged launches, so the same energies bit for bit
@@ -285,7 +285,7 @@ def batched_form(sweeps, warmup):
            "speedup_form_per_step_vs_staged_f32": round(b32 / c32, 3),
            "form_per_step_energies_identical_to_staged": bool(np.array_equal(e_c64, e_b64)
                                                               and np.array_equal(e_c32, e_b32)),
-           "autotuned_splits_ma_mb_target": tuned,
+           "autotuned_ma_mb_target_rows_per_wave": tuned,
            "batch_create_autotune_s": round(c32t, 2)}
     for a in hs:
         a.close()

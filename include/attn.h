@@ -351,12 +351,13 @@ attn_status attn_mlp_eval(const float* params, const float* feats, float* out, i
  * on a per-instance counter of the units it depends on, which always come
  * earlier in the list (persistent = 2: each step takes whichever of the two
  * forms ran its matvec faster when timed at creation).  With use_graphs each
- * step is
- * captured once as a HIP graph and replayed in later sweeps.  With autotune the
- * work split of the two-leg launches is chosen per leg shape (ma, mb) by timing
- * candidate splits over all steps at creation.  Without autotuning the split is
- * the one the single-handle path uses, and batch sweeps then reproduce
- * attn_sweep of each handle bit for bit.
+ * step is captured once as a HIP graph and replayed in later sweeps.  With
+ * autotune the work split of the two-leg launches (and, for FP32 legs 64 x 64
+ * in the staged launches, the tile of a wave: one or two 16-row strips) is
+ * chosen per leg shape (ma, mb) by timing the candidates over all steps at
+ * creation.  Without autotuning the split is the one the single-handle path
+ * uses, and batch sweeps then reproduce attn_sweep of each handle bit for
+ * bit.
  * The batch borrows the handles (they must outlive it and must not be used
  * while it sweeps).  Each handle must be in the sweep start state: after
  * attn_init_state or after full sweeps.
@@ -367,7 +368,7 @@ typedef struct attn_batch_opts {
   int32_t krylov_k;    /* Lanczos matvecs per node (20) */
   int32_t precision;   /* ATTN_F64 or ATTN_F32 operands; Krylov steps stay FP64 */
   int32_t use_graphs;  /* 1: capture every step as a HIP graph */
-  int32_t autotune;    /* 1: time candidate work splits per leg shape at creation */
+  int32_t autotune;    /* 1: time candidate work splits (and FP32 tiles) per leg shape at creation */
   int32_t persistent;  /* 0: staged launches; 1: each matvec of a step is one
                           launch of a resident grid over an ordered work list
                           of all instances' units; 2: per step, whichever of
@@ -390,7 +391,9 @@ attn_status attn_batch_create(attn_handle* const* hs, int32_t n, const attn_batc
 attn_status attn_batch_sweep(attn_batch* b, int32_t n_sweeps, double* energies, double* seconds);
 
 /* Number of steps, sandwich work units per sweep-step matvec summed over steps,
- * and the autotuned splits: tuned[3k..3k+2] = (ma, mb, target workgroups). */
+ * and the autotuned choices per leg shape: tuned[4k..4k+3] = (ma, mb, target
+ * workgroups, rows per wave: 16, or 32 for the two-strip FP32 tile at legs
+ * 64 x 64).  tuned holds 4 * cap values. */
 attn_status attn_batch_info(const attn_batch* b, int32_t* n_steps, int64_t* n_launch_units,
                             int32_t* n_tuned, int32_t* tuned, int32_t cap);
 

@@ -314,9 +314,9 @@ def attn_batch_sweep(b, n_inst, n_sweeps):
 def attn_batch_info(b, cap=64):
     ns, nt = ctypes.c_int32(), ctypes.c_int32()
     nu = ctypes.c_int64()
-    tuned = (ctypes.c_int32 * (3 * cap))()
+    tuned = (ctypes.c_int32 * (4 * cap))()
     _bcheck(_lib.attn_batch_info(b, ctypes.byref(ns), ctypes.byref(nu), ctypes.byref(nt), tuned, cap), b)
-    t = [tuple(tuned[3 * k:3 * k + 3]) for k in range(min(nt.value, cap))]
+    t = [tuple(tuned[4 * k:4 * k + 4]) for k in range(min(nt.value, cap))]
     return ns.value, nu.value, t
 
 

@@ -22,8 +22,13 @@ struct attn_batch {
   std::vector<double*> x64;   // FP64 form: per-instance copy of the newest basis vector
   hipStream_t s[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> evs;
-  // autotuned work split: target workgroups per sandwich launch group, by (ma, mb)
-  std::vector<std::pair<std::pair<int, int>, int>> tuned;
+  // autotuned per leg shape (ma, mb): target workgroups per sandwich launch
+  // group, and the tile of a wave (1: one 16-row strip; 2: two strips, FP32
+  // legs 64 in the staged launches only, as a launch of its own)
+  struct Tune {
+    int ma, mb, target, tile;
+  };
+  std::vector<Tune> tuned;
   int default_target = (int)kMvTarget;   // the single-handle split
 
   struct Merged {
@@ -40,6 +45,8 @@ struct attn_batch {
     std::vector<RDSrc> rd_srcs;
     std::vector<RDTask> rd;
     int64_t rd_max = 0;
+    std::vector<int4> sw_wus2;   // two-strip units (task, first slice, 0, slices)
+    int4* d_sw_wus2 = nullptr;
     // instance of every task (persistent form)
     std::vector<int> sw_inst, mp_inst[3], tr_inst, rd_inst;
     std::vector<PUnit> pu;
@@ -110,8 +117,19 @@ T* bupload(attn_batch* b, const std::vector<T>& v) {
 
 int target_for(const attn_batch* b, int ma, int mb) {
   for (auto& t : b->tuned)
-    if (t.first.first == ma && t.first.second == mb) return t.second;
+    if (t.ma == ma && t.mb == mb) return t.target;
   return b->default_target;
+}
+
+int tile_for(const attn_batch* b, int ma, int mb) {
+  for (auto& t : b->tuned)
+    if (t.ma == ma && t.mb == mb) return t.tile;
+  return 1;
+}
+
+// two-strip tiles apply to FP32 legs 64 x 64 in the staged launches
+bool w2_allowed(const attn_batch* b, int ma, int mb) {
+  return b->precision == ATTN_F32 && ma == 64 && mb == 64 && b->persistent == 0;
 }
 
 // Link-by-link centre path from a to c (up to the common ancestor, then down).
@@ -189,7 +207,9 @@ void add_sandwich(attn_batch* b, attn_handle* h, int n, const void* x, attn_batc
       }
       const int ti = (int)m.sw_tasks.size();
       m.sw_tasks.push_back(t);
-      if (mf) {
+      if (mf && w2_allowed(b, ma, mb) && tile_for(b, ma, mb) == 2) {
+        for (int s = 0; s < ns; s += 2) m.sw_wus2.push_back(make_int4(ti, s, 0, std::min(2, ns - s)));
+      } else if (mf) {
         for (int s = 0; s < ns; s++)
           for (int st = 0; st < ma / 16; st += 4) m.sw_wus.push_back(make_int4(ti, s, st, mb / 16));
         m.sw_lds = std::max(m.sw_lds, (size_t)ma * (mb + 2) * esz);
@@ -238,6 +258,7 @@ void upload_merged(attn_batch* b, attn_batch::Merged& m) {
   m.d_sw_tasks = bupload(b, m.sw_tasks);
   m.d_sw_items = bupload(b, m.sw_items);
   m.d_sw_wus = bupload(b, m.sw_wus);
+  m.d_sw_wus2 = bupload(b, m.sw_wus2);
   for (int k = 0; k < 3; k++) {
     m.d_mp_tasks[k] = bupload(b, m.mp_tasks[k]);
     m.d_mp_jobs[k] = bupload(b, m.mp_jobs[k]);
@@ -446,6 +467,9 @@ void run_matvec(attn_batch* b, attn_batch::Merged& m, hipStream_t s) {
     HIPCHK(launch_batch_mode(dt, m.d_mp_tasks[k], m.d_mp_jobs[k], m.d_mp_wus[k], (int)m.mp_wus[k].size(),
                              m.mp_lds[k], s));
   HIPCHK(launch_batch_sandwich(dt, m.d_sw_tasks, m.d_sw_items, m.d_sw_wus, (int)m.sw_wus.size(), m.sw_lds, s));
+  if (!m.sw_wus2.empty())
+    HIPCHK(launch_sandwich(4, 64, 64, m.d_sw_tasks, m.d_sw_items, m.d_sw_wus2, (int)m.sw_wus2.size(), nullptr, s,
+                           nullptr));
   HIPCHK(launch_reduce_list(dt, m.d_rd, (int)m.rd.size(), m.rd_max, s));
 }
 
@@ -566,41 +590,47 @@ void autotune(attn_batch* b) {
   const int nsteps = (int)b->steps.size();
   for (auto& sh : shapes) {
     float best = 1e30f;
-    int best_c = b->default_target;
-    for (int c : cands) {
-      b->tuned.push_back({sh, c});
-      std::vector<attn_batch::Merged> ms(nsteps);
-      bool fits = true;
-      for (int t = 0; t < nsteps && fits; t++) {
-        for (int i = 0; i < (int)b->hs.size() && fits; i++) {
-          attn_handle* h = b->hs[i];
-          if (t >= (int)h->M.tree.nodes.size() || h->mv[t].d_tiny) continue;
-          std::vector<RDSrc> srcs;
-          const void* x = b->precision == ATTN_F64 ? (const void*)b->x64[i] : (const void*)h->d_x32;
-          add_sandwich(b, h, t, x, ms[t], srcs, &sh, &fits);
+    int best_c = b->default_target, best_tile = 1;
+    const int ntile = w2_allowed(b, sh.first, sh.second) ? 2 : 1;
+    for (int tile = 1; tile <= ntile; tile++)
+      for (int c : cands) {
+        b->tuned.push_back({sh.first, sh.second, c, tile});
+        std::vector<attn_batch::Merged> ms(nsteps);
+        bool fits = true;
+        for (int t = 0; t < nsteps && fits; t++) {
+          for (int i = 0; i < (int)b->hs.size() && fits; i++) {
+            attn_handle* h = b->hs[i];
+            if (t >= (int)h->M.tree.nodes.size() || h->mv[t].d_tiny) continue;
+            std::vector<RDSrc> srcs;
+            const void* x = b->precision == ATTN_F64 ? (const void*)b->x64[i] : (const void*)h->d_x32;
+            add_sandwich(b, h, t, x, ms[t], srcs, &sh, &fits);
+          }
         }
+        b->tuned.pop_back();
+        if (!fits) continue;
+        std::vector<void*> mark(b->owned);
+        for (auto& m : ms) upload_merged(b, m);
+        const int dt = b->precision == ATTN_F64 ? 0 : 1;
+        float ms_tot = 0;
+        for (int rep = 0; rep < 2; rep++) {   // first pass warms up
+          HIPCHK(hipEventRecord(e0, b->s[0]));
+          for (auto& m : ms) {
+            HIPCHK(launch_batch_sandwich(dt, m.d_sw_tasks, m.d_sw_items, m.d_sw_wus, (int)m.sw_wus.size(),
+                                         m.sw_lds, b->s[0]));
+            if (!m.sw_wus2.empty())
+              HIPCHK(launch_sandwich(4, 64, 64, m.d_sw_tasks, m.d_sw_items, m.d_sw_wus2, (int)m.sw_wus2.size(),
+                                     nullptr, b->s[0], nullptr));
+          }
+          HIPCHK(hipEventRecord(e1, b->s[0]));
+          HIPCHK(hipEventSynchronize(e1));
+          HIPCHK(hipEventElapsedTime(&ms_tot, e0, e1));
+        }
+        // free the trial lists
+        for (size_t k = mark.size(); k < b->owned.size(); k++) HIPCHK(hipFree(b->owned[k]));
+        b->owned.resize(mark.size());
+        if (ms_tot < best) { best = ms_tot; best_c = c; best_tile = tile; }
       }
-      b->tuned.pop_back();
-      if (!fits) continue;
-      std::vector<void*> mark(b->owned);
-      for (auto& m : ms) upload_merged(b, m);
-      const int dt = b->precision == ATTN_F64 ? 0 : 1;
-      float ms_tot = 0;
-      for (int rep = 0; rep < 2; rep++) {   // first pass warms up
-        HIPCHK(hipEventRecord(e0, b->s[0]));
-        for (auto& m : ms)
-          HIPCHK(launch_batch_sandwich(dt, m.d_sw_tasks, m.d_sw_items, m.d_sw_wus, (int)m.sw_wus.size(),
-                                       m.sw_lds, b->s[0]));
-        HIPCHK(hipEventRecord(e1, b->s[0]));
-        HIPCHK(hipEventSynchronize(e1));
-        HIPCHK(hipEventElapsedTime(&ms_tot, e0, e1));
-      }
-      // free the trial lists
-      for (size_t k = mark.size(); k < b->owned.size(); k++) HIPCHK(hipFree(b->owned[k]));
-      b->owned.resize(mark.size());
-      if (ms_tot < best) { best = ms_tot; best_c = c; }
-    }
-    b->tuned.push_back({sh, best_c});
+    b->tuned.push_back({sh.first, sh.second, best_c, best_tile});
   }
   HIPCHK(hipEventDestroy(e0));
   HIPCHK(hipEventDestroy(e1));
@@ -783,20 +813,22 @@ attn_status attn_batch_sweep(attn_batch* b, int32_t n_sweeps, double* energies, 
 }
 
 attn_status attn_batch_info(const attn_batch* b, int32_t* n_steps, int64_t* n_launch_units,
-                            int32_t* n_tuned, int32_t* tuned /* [n][3] = ma, mb, target */, int32_t cap) {
+                            int32_t* n_tuned, int32_t* tuned /* [n][4] = ma, mb, target, rows per wave */,
+                            int32_t cap) {
   if (!b) return ATTN_ERR_ARG;
   if (n_steps) *n_steps = (int32_t)b->steps.size();
   if (n_launch_units) {
     int64_t u = 0;
-    for (auto& S : b->steps) u += (int64_t)S.mv.sw_wus.size();
+    for (auto& S : b->steps) u += (int64_t)(S.mv.sw_wus.size() + S.mv.sw_wus2.size());
     *n_launch_units = u;
   }
   if (n_tuned) *n_tuned = (int32_t)b->tuned.size();
   if (tuned)
     for (int k = 0; k < (int)b->tuned.size() && k < cap; k++) {
-      tuned[3 * k] = b->tuned[k].first.first;
-      tuned[3 * k + 1] = b->tuned[k].first.second;
-      tuned[3 * k + 2] = b->tuned[k].second;
+      tuned[4 * k] = b->tuned[k].ma;
+      tuned[4 * k + 1] = b->tuned[k].mb;
+      tuned[4 * k + 2] = b->tuned[k].target;
+      tuned[4 * k + 3] = 16 * b->tuned[k].tile;
     }
   return ATTN_OK;
 }

@@ -798,6 +798,16 @@ void ensure_lowp(attn_handle* h, int dtype) {
         g.wus.swap(w2);
         g.fmt = 3;
       }
+      if (dtype == 1 && g.ma == 64 && g.mb == 64) {
+        // FP32 at legs 64: two row strips per wave, units of up to two slices
+        std::vector<int> ns_of(g.tasks.size(), 0);
+        for (const int4& wu : g.wus) ns_of[wu.x] = std::max(ns_of[wu.x], wu.y + 1);
+        std::vector<int4> w2;
+        for (size_t ti = 0; ti < g.tasks.size(); ti++)
+          for (int s0 = 0; s0 < ns_of[ti]; s0 += 2) w2.push_back(make_int4((int)ti, s0, 0, std::min(2, ns_of[ti] - s0)));
+        g.wus.swap(w2);
+        g.fmt = 4;
+      }
     }
     const std::vector<MPGroup>* src[3] = {&D.chainA, &D.chainB, &D.chainC};
     std::vector<MPGroup>* dst[3] = {&L.chainA, &L.chainB, &L.chainC};
@@ -2306,17 +2316,18 @@ extern "C" attn_status attn_validate(const attn_handle* h) {
       const int64_t M = (int64_t)D.dims[0] * D.dims[1] * D.dims[2];
       for (auto& g : D.sw) {
         c.sw(g, M, 4);
-        if (g.fmt == 3)
+        if (g.fmt == 3 || g.fmt == 4)
           for (const int4& wu : g.wus) {
             const SWTask& t = g.tasks[wu.x];
-            if (wu.w < 1 || wu.w > 4) c.fail("split-BF16 unit slice count");
+            if (wu.w < 1 || wu.w > (g.fmt == 3 ? 4 : 2)) c.fail("several-slice unit: slice count");
             // the last slice of the unit, whole (ma x mb) slab
             const int64_t last = (int64_t)(wu.y + wu.w - 1);
-            if (t.x) c.span(t.x, (last * t.xs_slice + (t.ma - 1) * t.xs_row + t.mb) * 4, "split-BF16 x");
-            else if (last * t.xs_slice + (t.ma - 1) * t.xs_row + t.mb > M) c.fail("split-BF16 x beyond the input");
-            c.span(t.y, (last * t.ys_slice + (t.ma - 1) * t.ys_row + t.mb) * 4, "split-BF16 y");
+            if (t.x) c.span(t.x, (last * t.xs_slice + (t.ma - 1) * t.xs_row + t.mb) * 4, "several-slice unit x");
+            else if (last * t.xs_slice + (t.ma - 1) * t.xs_row + t.mb > M) c.fail("several-slice unit: x beyond the input");
+            c.span(t.y, (last * t.ys_slice + (t.ma - 1) * t.ys_row + t.mb) * 4, "several-slice unit y");
+            if (g.fmt == 4 && (t.ma != 64 || t.mb != 64 || t.pad)) c.fail("two-strip unit: legs or outputs");
           }
-        if (g.fmt >= 2) {
+        if (g.fmt == 2 || g.fmt == 3) {
           if (!sw_bf16(g.ma, g.mb)) c.fail("split-BF16 group with legs not multiples of 32");
           for (auto& it : g.items)
             if ((uintptr_t)it.A % 16 || (uintptr_t)it.B % 16) c.fail("split-BF16 block not 16-byte aligned");

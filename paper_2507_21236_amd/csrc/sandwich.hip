@@ -811,6 +811,147 @@ __global__ __launch_bounds__(512) void k_sandwich_bf2d(const SWTask* __restrict_
 template <int MA, int NB>
 constexpr size_t bf2w_lds() { return (size_t)2 * (2 * 16 * MA * (16 * MA + 8) + 2 * 16 * NB * (16 * NB + 8)) * 2; }
 
+// ============================================================================ two strips per wave
+// FP32 at legs 64 x 64: a work unit is up to two slices, wave w computing rows
+// [32 (w % 2), +32) of slice w / 2 as two 16-row strips.  Each operand value
+// then feeds two products: the slice element read from LDS in stage 1 serves
+// both strips' A rows, and each B element loaded in stage 2 serves both
+// strips' stage-1 tiles, so the operand loads per MFMA halve (the FP32 MFMA
+// runs twice as fast as the FP64 one and the one-strip form waits for its
+// operands).  Per output element the same products in the same order as
+// sandwich_rows, so the results are the same bit for bit.
+// slices s0 .. s0 + ns - 1 (ns <= 2) of task t
+template <typename T>
+__device__ __forceinline__ void sandwich_w2(const SWTask& t, const SWItem* __restrict__ items, int s0, int ns,
+                                            const T* __restrict__ xbase, unsigned char* smem_raw) {
+  typedef typename V4<T>::type v4;
+  constexpr int NB = 4, mb = 64, ld = mb + 2, KS = mb / 4, PA = 2, PB = 2;
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  for (int j = 0; j < ns; j++) {
+    const T* X = (t.x ? (const T*)t.x : xbase) + (int64_t)(s0 + j) * t.xs_slice;
+    T* L = lds + j * mb * ld;
+    for (int e = threadIdx.x; e < mb * mb; e += 256) {
+      const int a = e / mb, b = e - a * mb;
+      L[a * ld + b] = X[(int64_t)a * t.xs_row + b];
+    }
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = wave >> 1;
+  if (j >= ns) return;   // no barrier below
+  const int s = s0 + j;
+  const T* L = lds + j * mb * ld;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int r0 = 32 * (wave & 1);
+  const int pc = colperm<T>(l16);
+  int pk[4];
+#pragma unroll
+  for (int i = 0; i < 4; i++) pk[i] = colperm<T>(drow<T>(l4, i));
+  v4 acc[2][NB];
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int q = 0; q < NB; q++) acc[a][q] = v4{0, 0, 0, 0};
+  for (int it = t.item0; it < t.item0 + t.nitem; it++) {
+    const T* A = (const T*)items[it].A;
+    const T* B = (const T*)items[it].B;
+    const T coef = (T)items[it].coef;
+    v4 t1[2][NB];
+    if (A) {
+#pragma unroll
+      for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int q = 0; q < NB; q++) t1[a][q] = v4{0, 0, 0, 0};
+      const T* Ap = A + r0 + l16;
+      T ab[PA][2];
+#pragma unroll
+      for (int k = 0; k < PA; k++)
+#pragma unroll
+        for (int a = 0; a < 2; a++) ab[k][a] = gload(Ap + 16 * a + (int64_t)(4 * k + l4) * mb);
+#pragma unroll
+      for (int ks = 0; ks < KS; ks++) {
+        T bop[2];
+#pragma unroll
+        for (int a = 0; a < 2; a++) bop[a] = ab[ks % PA][a] * coef;
+        if (ks + PA < KS)
+#pragma unroll
+          for (int a = 0; a < 2; a++) ab[ks % PA][a] = gload(Ap + 16 * a + (int64_t)(4 * (ks + PA) + l4) * mb);
+        const T* xr = L + (4 * ks + l4) * ld + pc;
+#pragma unroll
+        for (int q = 0; q < NB; q++) {
+          const T xv = xr[16 * q];
+#pragma unroll
+          for (int a = 0; a < 2; a++) t1[a][q] = mfma16(xv, bop[a], t1[a][q]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 2; a++) {
+        const T* xr = L + (r0 + 16 * a + l16) * ld;
+#pragma unroll
+        for (int q = 0; q < NB; q++)
+#pragma unroll
+          for (int i = 0; i < 4; i++) t1[a][q][i] = xr[16 * q + pk[i]] * coef;
+      }
+    }
+    if (B) {
+      T bb[PB][NB];
+#pragma unroll
+      for (int g = 0; g < PB; g++)
+#pragma unroll
+        for (int tq = 0; tq < NB; tq++)
+          bb[g][tq] = gload(B + (int64_t)(16 * (g / 4) + pk[g % 4]) * mb + pc + 16 * tq);
+#pragma unroll
+      for (int g = 0; g < 4 * NB; g++) {
+        T bv[NB];
+#pragma unroll
+        for (int tq = 0; tq < NB; tq++) bv[tq] = bb[g % PB][tq];
+        if (g + PB < 4 * NB) {
+          const int gn = g + PB;
+#pragma unroll
+          for (int tq = 0; tq < NB; tq++)
+            bb[g % PB][tq] = gload(B + (int64_t)(16 * (gn / 4) + pk[gn % 4]) * mb + pc + 16 * tq);
+        }
+#pragma unroll
+        for (int tq = 0; tq < NB; tq++)
+#pragma unroll
+          for (int a = 0; a < 2; a++) acc[a][tq] = mfma16(bv[tq], t1[a][g / 4][g % 4], acc[a][tq]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int q = 0; q < NB; q++) acc[a][q] += t1[a][q];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; a++) {
+    T* Y = (T*)t.y + (int64_t)s * t.ys_slice + (int64_t)(r0 + 16 * a + l16) * t.ys_row;
+#pragma unroll
+    for (int q = 0; q < NB; q++) {
+      float4* p0 = (float4*)(Y + 16 * q + 4 * l4);
+      float4 v = make_float4(acc[a][q][0], acc[a][q][1], acc[a][q][2], acc[a][q][3]);
+      if (t.accumulate) {
+        const float4 o = *p0;
+        v.x += o.x; v.y += o.y; v.z += o.z; v.w += o.w;
+      }
+      *p0 = v;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sandwich_w2(const SWTask* __restrict__ tasks,
+                                                     const SWItem* __restrict__ items,
+                                                     const int4* __restrict__ wus,
+                                                     const T* __restrict__ xbase) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int4 wu = wus[blockIdx.x];
+  sandwich_w2<T>(tasks[wu.x], items, wu.y, wu.w, xbase, smem_raw);
+}
+
 // ============================================================================ mixed-shape launches
 // One launch over the work units of many tasks of different shapes (several
 // nodes of several problem instances): the kind of each unit selects the body.
@@ -1084,6 +1225,12 @@ hipError_t launch_sandwich(int dtype, int ma, int mb, const SWTask* tasks, const
     }
     return hipErrorInvalidValue;
   }
+  if (dtype == 4) {   // FP32, legs 64 x 64, two strips per wave, units of up to two slices
+    if (ma != 64 || mb != 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sandwich_w2<float>, dim3(nwu), dim3(256), (size_t)2 * 64 * 66 * sizeof(float), s, tasks,
+                       items, wus, (const float*)xbase);
+    return hipGetLastError();
+  }
   if (dtype == 2) {
     if (!(ma % 32 == 0 && mb % 32 == 0 && ma <= 128 && mb <= 128)) return hipErrorInvalidValue;
     switch (mb / 32) {
@@ -1172,7 +1319,7 @@ hipError_t prepare_sandwich_attributes() {
       (const void*)k_sandwich_bf2<2>, (const void*)k_sandwich_bf2<4>,
       (const void*)k_sandwich_bf2w<2, 2>, (const void*)k_sandwich_bf2w<2, 4>,
       (const void*)k_sandwich_bf2w<4, 2>, (const void*)k_sandwich_bf2d<4, 4>,
-      (const void*)k_sandwich_bf2<6>, (const void*)k_sandwich_bf2<8>};
+      (const void*)k_sandwich_bf2<6>, (const void*)k_sandwich_bf2<8>, (const void*)k_sandwich_w2<float>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;

@@ -134,7 +134,8 @@ def test_batch_autotuned_without_graphs():
     e_ref, _ = ref.sweep(2)
     b = AttnBatch(started(), precision=ATTN_F32, use_graphs=False, autotune=True)
     n_steps, n_units, tuned = b.info()
-    print("tuned splits (ma, mb, target):", tuned, "steps", n_steps, "units", n_units)
+    print("tuned (ma, mb, target, rows per wave):", tuned, "steps", n_steps, "units", n_units)
+    assert all(r in (16, 32) for (_, _, _, r) in tuned)
     assert n_steps == max(p.n_sites - 1 for p in ps)
     assert len(tuned) > 0
     e, _ = b.sweep(2)
