@@ -54,6 +54,22 @@ def test_batch_reproduces_single_handle_sweeps(form):
     b.close()
 
 
+def test_two_strip_fp32_tile_matches_one_strip():
+    # an 8 x 8, m = 64 instance: the single-handle FP32 path runs its legs
+    # 64 x 64 with two row strips per wave, the batch without autotuning with
+    # one; the same products in the same order, so the sweeps agree bit for bit
+    from paper_2507_21236_amd import AttnBatch, solver_opts, ATTN_F32
+    p = batch_instances(32)[1]
+    assert (p.meta["L"], p.m) == (8, 64)
+    single = _handles([p])[0]
+    e_s, _ = single.sweep(2, solver_opts(krylov_k=20, precision=ATTN_F32))
+    b = AttnBatch(_handles([p]), krylov_k=20, precision=ATTN_F32, use_graphs=False)
+    e_b, _ = b.sweep(2)
+    print("single", e_s, "batch", e_b[0])
+    assert np.array_equal(e_b[0], e_s)
+    b.close()
+
+
 @pytest.mark.parametrize("persistent", [False, True])
 def test_batch_fp64_matches_oracle_4x4(persistent):
     from paper_2507_21236_amd import AttnBatch, ATTN_F64
